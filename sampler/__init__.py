@@ -1,0 +1,13 @@
+"""Seeded synthetic coefficient fields for the RVE corrector problem.
+
+This module only draws random inputs. It holds none of the method's
+arithmetic (no operator, right-hand side, solver or homogenized matrix), so
+both the CPU oracle and the GPU path may take their inputs from it.
+"""
+from .boolean_model import (  # noqa: F401
+    SEED_ROOT,
+    BooleanModel,
+    realization,
+    batch,
+    uneven_batch,
+)
