@@ -1,0 +1,199 @@
+/*
+ * rve.h -- C ABI of librve: the RVE corrector path on one AMD Instinct MI355X
+ * (gfx950), hand-written HIP kernels.
+ *
+ * Problem (Khoromskaia, Khoromskij, Otto, "Numerical study in stochastic
+ * homogenization for elliptic PDEs", Sec. 2 eqns. RHS_grad1/scaled_setting
+ * and Sec. 4.3 eqn. wg03): on the periodic n x n grid of Q1 finite elements,
+ * for a per-cell coefficient field a > 0, find the correctors phi_1, phi_2
+ * with  int grad psi . a (e_i + grad phi_i) = 0  for every test function psi,
+ * then the homogenized 2x2 matrix (Sec. 4.1 eqns. A_hom_m, Ahom_m_entry;
+ * Sec. 4.3 eqn. wg01 and the symmetry argument for wg02).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grid: n periodic nodes and n cells per axis. Cell (i, j) spans nodes
+ *   i..i+1 along x1 and j..j+1 along x2 (mod n). Arrays are row-major
+ *   [i][j] with x2 contiguous (the paper's big-endian index map, Sec. 3.2).
+ * - Supported n: multiples of 64 from 64 to 4096.
+ * - The discrete problem depends only on the cell array a: the Q1 stiffness
+ *   is h-independent in 2D, so the library solves in grid units and returns
+ *   phi multiplied by the mesh width h. A_hom does not depend on h.
+ * - A_hom is reported in the energy form
+ *     A_ij = < (e_j + grad phi_j) . a (e_i + grad phi_i) >
+ *   (symmetric by construction; its error is quadratic in the solver error),
+ *   optionally beside the flux form A_ij = < a (delta_ij + d_j phi_i) > of
+ *   eqn. Ahom_m_entry. < . > is the average over the torus.
+ * - Solver (Sec. 3.5, eqn. DD_Eqn): preconditioned CG from x0 = 0 with the
+ *   constant-coefficient periodic Q1 operator a0 * A_Delta as preconditioner,
+ *   a0 = (max a + min a) / 2 (proof of Lemma Cond_Number), applied as its
+ *   pseudo-inverse (the paper's shift delta -> 0 on the mean-zero subspace).
+ *   Stop when ||r||_2 / ||f||_2 <= tol. phi is returned with zero mean.
+ * - Memory: every pointer argument named *_dev is device memory owned by the
+ *   caller, on the context's device; *_host is host memory. The library
+ *   allocates only inside the context (workspace, transform tables), grows
+ *   that workspace on demand, and frees it in rve_destroy.
+ * - Streams: all work is enqueued on the context's stream, in order. Calls
+ *   return after enqueueing, except where a host output or a convergence
+ *   poll needs the device (documented per call).
+ * - Errors: every call returns an int status (enum rve_status); nothing
+ *   throws across the ABI. Argument errors are detected on the host before
+ *   any work is enqueued. Batch calls also write a per-item status.
+ * - Threads: a context must not be used by two host threads at once.
+ *   Contexts are independent of each other.
+ */
+#ifndef RVE_H
+#define RVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rve_status {
+  RVE_OK = 0,             /* converged */
+  RVE_NOT_CONVERGED = 1,  /* maxit reached; outputs and relres still written */
+  RVE_BREAKDOWN = 2,      /* p^T A p <= 0 or not finite during PCG */
+  RVE_EINVAL = -1,        /* invalid argument (host), or a coefficient <= 0 / NaN (device) */
+  RVE_EHIP = -2,          /* a HIP runtime error */
+  RVE_ENOMEM = -3         /* device allocation failed */
+};
+
+/* Arithmetic of the preconditioner's transform GEMMs (Q X Q on MFMA). The
+ * residual update, the search directions, the CG dot products, the stencil
+ * apply and the A_hom reductions are FP64 in every mode. */
+enum rve_precision {
+  RVE_FP64 = 0,      /* FP64 MFMA, FP64 intermediates */
+  RVE_MIX_FP32 = 1,  /* FP32 MFMA, FP32 intermediates */
+  RVE_MIX_BF16 = 2   /* BF16 MFMA operands, FP32 accumulation, BF16 intermediates */
+};
+
+typedef struct rve_opts {
+  double tol;        /* relative residual target ||r||_2/||f||_2, > 0 */
+  int maxit;         /* maximum PCG iterations per system, >= 1 */
+  int prec;          /* enum rve_precision */
+  int flexible;      /* 1: flexible (Polak-Ribiere) beta; 0: standard beta.
+                        Negative: automatic (flexible unless prec == RVE_FP64). */
+  int check_every;   /* host polls the all-converged flag every this many
+                        iterations; <= 0 selects a default */
+} rve_opts;
+
+typedef struct rve_ctx rve_ctx;
+
+/* Fill *opts with defaults: tol 1e-10, maxit 2000, FP64, automatic beta,
+ * automatic polling. */
+void rve_default_opts(rve_opts* opts);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream). */
+int rve_create(rve_ctx** out, int device, void* hip_stream);
+int rve_destroy(rve_ctx* ctx);
+int rve_set_stream(rve_ctx* ctx, void* hip_stream);
+
+/*
+ * Solve B independent realizations of equal size n (one batch: every kernel
+ * launch covers all 2B corrector systems).
+ *
+ *   a_dev         [B][n][n] FP64 per-cell coefficients, each > 0
+ *   h             mesh width (> 0); phi is returned in physical units (x h)
+ *   phi_dev       [B][2][n][n] FP64 correctors phi_1, phi_2 (mean zero), or NULL
+ *   ahom_dev      [B][2][2] FP64 energy-form A_hom (required)
+ *   ahom_flux_dev [B][2][2] FP64 flux-form A_hom, or NULL
+ *   iters_dev     [B][2] int PCG iterations per direction, or NULL
+ *   relres_dev    [B][2] FP64 final recursive relative residual, or NULL
+ *   status_dev    [B] int per-item status (enum rve_status), or NULL
+ *
+ * Returns the worst status over items (EINVAL/EHIP/ENOMEM before warnings).
+ * Blocks the host on polls of the convergence flag (every check_every
+ * iterations) and at the end, when it reads the per-item statuses.
+ */
+int rve_solve_batch(rve_ctx* ctx, int B, int n, double h, const double* a_dev,
+                    const rve_opts* opts, double* phi_dev, double* ahom_dev,
+                    double* ahom_flux_dev, int* iters_dev, double* relres_dev,
+                    int* status_dev);
+
+/*
+ * Realizations of different sizes in one call (packed input).
+ *
+ *   n_host[B]          grid size of item b (host)
+ *   cell_off_host[B+1] element offsets of item b's cells in a_dev (host);
+ *                      item b occupies a_dev[cell_off[b] .. cell_off[b]+n_b^2)
+ *   phi_dev            packed like a_dev but with 2 n_b^2 nodes per item at
+ *                      offset 2*cell_off[b], or NULL
+ *   other outputs      as rve_solve_batch, indexed by item
+ * Items of equal n are solved together; offsets must be non-overlapping.
+ */
+int rve_solve_uneven(rve_ctx* ctx, int B, const int* n_host,
+                     const int64_t* cell_off_host, double h, const double* a_dev,
+                     const rve_opts* opts, double* phi_dev, double* ahom_dev,
+                     double* ahom_flux_dev, int* iters_dev, double* relres_dev,
+                     int* status_dev);
+
+/*
+ * Derivative of the energy-form A_hom with respect to every cell value
+ * (vector-Jacobian product). The energy form is stationary in the
+ * correctors (eqn. wg03), so d A_ij / d a_e = (1/n^2) int_e (e_i + grad
+ * phi_i) . (e_j + grad phi_j) and no adjoint solve is needed.
+ *
+ *   a_dev        [B][n][n] coefficients used for the solve
+ *   phi_dev      [B][2][n][n] correctors as returned by rve_solve_batch (x h)
+ *   h            the same mesh width
+ *   G_dev        [B][2][2] upstream weights G_ij
+ *   grad_a_dev   [B][n][n] output: sum_ij G_ij d A_ij / d a_e
+ *   a_in         coefficient value of the inclusion cells
+ *   grad_in_dev  [B] output: sum_ij G_ij d A_ij / d a_in, where every cell
+ *                with a_e == a_in moves with a_in; or NULL
+ */
+int rve_grad(rve_ctx* ctx, int B, int n, const double* a_dev,
+             const double* phi_dev, double h, const double* G_dev,
+             double* grad_a_dev, double a_in, double* grad_in_dev);
+
+/*
+ * Ensemble statistics of N homogenized matrices at RVE size L (Sec. 4.2
+ * eqn. A_hom_Empir; Sec. 5 eqns. Var1, Var2; Sec. 5.3 eqn. quartic).
+ *
+ *   ahom_dev [N][2][2] FP64, N >= 2
+ *   out_dev  [26] FP64: mean[4] (A11 A12 A21 A22), centred variance[4]
+ *            (1/(N-1)), std_a12 and std_(a11-a22) (uncentred, 1/N), then
+ *            the 4x4 quartic tensor q[(i,k),(j,l)] = L^2 cov(A_ij, A_kl),
+ *            row-major.
+ */
+int rve_stats(rve_ctx* ctx, int N, double L, const double* ahom_dev, double* out_dev);
+
+/*
+ * The two linear maps of the PCG, one call each, for checking them alone.
+ *
+ * rve_apply_operator: out = A u for the Q1 stiffness of each field (grid
+ * units; Sec. 3.1 eqn. FEM_discr, assembled there by the Kronecker sums of
+ * Sec. 3.2, applied here matrix-free as a 9-point stencil).
+ *   a_dev [B][n][n] cells; u_dev, out_dev [B][2][n][n] nodes (distinct).
+ *
+ * rve_apply_precond: z = (a0 A_Delta)^+ r (Sec. 3.5) with a0 = (max a +
+ * min a)/2 of each field and the transform GEMMs in precision `prec`
+ * (enum rve_precision).
+ *   a_dev [B][n][n]; r_dev, z_dev [B][2][n][n] (distinct).
+ */
+int rve_apply_operator(rve_ctx* ctx, int B, int n, const double* a_dev, const double* u_dev,
+                       double* out_dev);
+int rve_apply_precond(rve_ctx* ctx, int B, int n, const double* a_dev, const double* r_dev,
+                      double* z_dev, int prec);
+
+/* Static string for a status code. */
+const char* rve_status_string(int status);
+
+/* Event timing of kernel classes on the context's stream. rve_set_timing
+ * turns recording on (1) or off (0) and clears the accumulators; while it is
+ * on, every launch of a class is bracketed by HIP events.
+ * rve_last_timing returns the totals since the last rve_set_timing in
+ * out_ms[4] and out_counts[4]: [0] stencil applies (one kernel launch each),
+ * [1] preconditioner applies (four transform GEMM launches each), [2] x/r
+ * updates, [3] search-direction updates; counts are bracketed applies. */
+int rve_set_timing(rve_ctx* ctx, int enable);
+int rve_last_timing(rve_ctx* ctx, double* out_ms, long long* out_counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_H */

@@ -1,0 +1,18 @@
+"""MI355X-native RVE corrector path for stochastic homogenization.
+
+Hot path of Khoromskaia, Khoromskij, Otto, "Numerical study in stochastic
+homogenization for elliptic PDEs: convergence rate in the size of
+representative volume elements": for each realization of a two-valued
+periodic coefficient field, solve the two corrector problems of the periodic
+Q1 discretisation by preconditioned CG and reduce them to the homogenized
+2x2 matrix A_hom; over many realizations, form the ensemble statistics.
+
+All arithmetic runs in librve (hand-written HIP kernels for gfx950, C ABI in
+include/rve.h); this package only marshals torch tensors into it.
+"""
+from ._native import FP64, MIX_FP32, MIX_BF16, LIB_PATH, RveError  # noqa: F401
+from .api import (  # noqa: F401
+    Context, Options, Result, context, solve_batch, solve_uneven, grad, stats,
+    apply_operator, apply_precond,
+)
+from .autograd import RveAhom, RveAhomContrast, ahom  # noqa: F401

@@ -1,0 +1,248 @@
+"""Python binding of librve: argument marshalling only.
+
+Every step of the corrector path runs in librve's HIP kernels; this module
+checks shapes/dtypes/devices of torch tensors, passes their device pointers
+through the C ABI (include/rve.h) on torch's current HIP stream, and wraps
+the results. PyTorch provides device memory and streams, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+from ._native import FP64, MIX_BF16, MIX_FP32  # noqa: F401
+
+
+@dataclass
+class Options:
+    tol: float = 1e-10          # relative residual target ||r||/||f||
+    maxit: int = 2000
+    prec: int = FP64            # FP64, MIX_FP32 or MIX_BF16 (preconditioner GEMMs)
+    flexible: int = -1          # -1 automatic, 0 standard beta, 1 flexible beta
+    check_every: int = 0        # convergence poll period (0 = library default)
+
+    def to_c(self) -> N.RveOpts:
+        return N.RveOpts(float(self.tol), int(self.maxit), int(self.prec), int(self.flexible),
+                         int(self.check_every))
+
+
+@dataclass
+class Result:
+    ahom: torch.Tensor                  # (B, 2, 2) energy form
+    ahom_flux: Optional[torch.Tensor]   # (B, 2, 2) flux form
+    phi: Optional[torch.Tensor]         # (B, 2, n, n) correctors x h, mean zero
+    iters: torch.Tensor                 # (B, 2) int32
+    relres: torch.Tensor                # (B, 2) float64
+    status: torch.Tensor                # (B,) int32
+    code: int                           # worst status of the call
+
+
+class Context:
+    """Owns one rve_ctx bound to a device; enqueues on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("librve needs a HIP device; none is visible")
+        self.device = int(device)
+        self._lib = N.lib()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            N.check(self._lib.rve_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream)),
+                    "rve_create")
+        self.handle = h
+
+    def bind_stream(self):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        N.check(self._lib.rve_set_stream(self.handle, ctypes.c_void_p(stream)), "rve_set_stream")
+        return self.handle
+
+    def set_timing(self, enable: bool):
+        N.check(self._lib.rve_set_timing(self.handle, int(bool(enable))), "rve_set_timing")
+
+    def timing(self):
+        """Accumulated event timing since set_timing(True): dict of class ->
+        (total ms, applies) for 'stencil', 'precond' (four GEMM launches per
+        apply), 'update_xr', 'update_p'."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_longlong * 4)()
+        N.check(self._lib.rve_last_timing(self.handle, ms, cnt), "rve_last_timing")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(("stencil", "precond", "update_xr", "update_p"))}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.rve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    ctx = _contexts.get(dev)
+    if ctx is None:
+        ctx = Context(dev)
+        _contexts[dev] = ctx
+    return ctx
+
+
+_UNSET = 127   # status sentinel: items the library never reached
+
+
+def _check_batch(code: int, status: torch.Tensor, what: str) -> int:
+    """Errors raise unless they are per-item outcomes written into `status`
+    (a coefficient <= 0 or NaN found on the device); warnings pass through."""
+    if code >= 0:
+        return code
+    if code == N.EINVAL and not bool(torch.any(status == _UNSET)):
+        return code
+    return N.check(code, what)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a HIP device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def solve_batch(a: torch.Tensor, h: float = 1.0, opts: Optional[Options] = None, *,
+                want_phi: bool = True, want_flux: bool = True,
+                ctx: Optional[Context] = None) -> Result:
+    """Correctors and A_hom of B equal-size realizations a (B, n, n) FP64."""
+    _need(a, "a")
+    if a.dim() == 2:
+        a = a.unsqueeze(0)
+    if a.dim() != 3 or a.shape[1] != a.shape[2]:
+        raise ValueError("a must have shape (B, n, n)")
+    B, n = a.shape[0], a.shape[1]
+    opts = opts or Options()
+    ctx = ctx or context(a.device.index)
+    dev = a.device
+    ahom = torch.empty((B, 2, 2), dtype=torch.float64, device=dev)
+    flux = torch.empty((B, 2, 2), dtype=torch.float64, device=dev) if want_flux else None
+    phi = torch.empty((B, 2, n, n), dtype=torch.float64, device=dev) if want_phi else None
+    iters = torch.empty((B, 2), dtype=torch.int32, device=dev)
+    relres = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    status = torch.full((B,), _UNSET, dtype=torch.int32, device=dev)
+    c_opts = opts.to_c()
+    code = ctx._lib.rve_solve_batch(ctx.bind_stream(), B, n, float(h), _p(a), ctypes.byref(c_opts),
+                                    _p(phi), _p(ahom), _p(flux), _p(iters), _p(relres), _p(status))
+    _check_batch(code, status, "rve_solve_batch")
+    return Result(ahom, flux, phi, iters, relres, status, code)
+
+
+def solve_uneven(fields: Sequence[torch.Tensor], h: float = 1.0, opts: Optional[Options] = None, *,
+                 want_phi: bool = False, want_flux: bool = True,
+                 ctx: Optional[Context] = None):
+    """Realizations of different sizes in one call. Returns a Result whose
+    ahom/flux/iters/relres/status are stacked per item and whose phi (if
+    requested) is a list of (2, n_b, n_b) tensors."""
+    if len(fields) == 0:
+        raise ValueError("no realizations")
+    dev = fields[0].device
+    for k, f in enumerate(fields):
+        _need(f, f"fields[{k}]")
+        if f.dim() != 2 or f.shape[0] != f.shape[1] or f.device != dev:
+            raise ValueError("each field must be (n, n) on one device")
+    B = len(fields)
+    ns = [int(f.shape[0]) for f in fields]
+    offs = [0]
+    for n in ns:
+        offs.append(offs[-1] + n * n)
+    packed = torch.cat([f.reshape(-1) for f in fields])
+    opts = opts or Options()
+    ctx = ctx or context(dev.index)
+    ahom = torch.empty((B, 2, 2), dtype=torch.float64, device=dev)
+    flux = torch.empty((B, 2, 2), dtype=torch.float64, device=dev) if want_flux else None
+    phi = torch.empty(2 * offs[-1], dtype=torch.float64, device=dev) if want_phi else None
+    iters = torch.empty((B, 2), dtype=torch.int32, device=dev)
+    relres = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    status = torch.full((B,), _UNSET, dtype=torch.int32, device=dev)
+    n_c = (ctypes.c_int * B)(*ns)
+    off_c = (ctypes.c_int64 * (B + 1))(*offs)
+    c_opts = opts.to_c()
+    code = ctx._lib.rve_solve_uneven(ctx.bind_stream(), B, n_c, off_c, float(h), _p(packed),
+                                     ctypes.byref(c_opts), _p(phi), _p(ahom), _p(flux), _p(iters),
+                                     _p(relres), _p(status))
+    _check_batch(code, status, "rve_solve_uneven")
+    phis = None
+    if want_phi:
+        phis = [phi[2 * offs[b]: 2 * offs[b + 1]].view(2, ns[b], ns[b]) for b in range(B)]
+    return Result(ahom, flux, phis, iters, relres, status, code)
+
+
+def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
+         a_in: Optional[float] = None, ctx: Optional[Context] = None):
+    """sum_ij G_ij dA_ij/da per cell, (B, n, n); and, if a_in is given, the
+    derivative with respect to the common value of the cells equal to a_in."""
+    _need(a, "a")
+    _need(phi, "phi")
+    _need(G, "G")
+    B, n = a.shape[0], a.shape[1]
+    if phi.shape != (B, 2, n, n) or G.shape != (B, 2, 2):
+        raise ValueError("phi must be (B, 2, n, n) and G (B, 2, 2)")
+    ctx = ctx or context(a.device.index)
+    out = torch.empty_like(a)
+    gin = torch.empty((B,), dtype=torch.float64, device=a.device) if a_in is not None else None
+    N.check(ctx._lib.rve_grad(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out),
+                              float(a_in if a_in is not None else 0.0), _p(gin)), "rve_grad")
+    return out, gin
+
+
+def stats(ahom: torch.Tensor, L: float, ctx: Optional[Context] = None) -> dict:
+    """Mean, centred variance, Var1/Var2 standard deviations and the 4x4
+    quartic tensor of N homogenized matrices (N, 2, 2)."""
+    _need(ahom, "ahom")
+    Nn = ahom.shape[0]
+    ctx = ctx or context(ahom.device.index)
+    out = torch.empty(26, dtype=torch.float64, device=ahom.device)
+    N.check(ctx._lib.rve_stats(ctx.bind_stream(), Nn, float(L), _p(ahom), _p(out)), "rve_stats")
+    return {"mean": out[0:4].view(2, 2), "var": out[4:8].view(2, 2), "std_a12": out[8],
+            "std_a11_minus_a22": out[9], "quartic": out[10:26].view(4, 4)}
+
+
+def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+    """A u for the Q1 operator of each field: a (B, n, n), u (B, 2, n, n)."""
+    _need(a, "a")
+    _need(u, "u")
+    B, n = a.shape[0], a.shape[1]
+    if u.shape != (B, 2, n, n):
+        raise ValueError("u must be (B, 2, n, n)")
+    ctx = ctx or context(a.device.index)
+    out = torch.empty_like(u)
+    N.check(ctx._lib.rve_apply_operator(ctx.bind_stream(), B, n, _p(a), _p(u), _p(out)),
+            "rve_apply_operator")
+    return out
+
+
+def apply_precond(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
+                  ctx: Optional[Context] = None) -> torch.Tensor:
+    """(a0 A_Delta)^+ r with a0 from each field a: a (B, n, n), r (B, 2, n, n)."""
+    _need(a, "a")
+    _need(r, "r")
+    B, n = a.shape[0], a.shape[1]
+    if r.shape != (B, 2, n, n):
+        raise ValueError("r must be (B, 2, n, n)")
+    ctx = ctx or context(a.device.index)
+    z = torch.empty_like(r)
+    N.check(ctx._lib.rve_apply_precond(ctx.bind_stream(), B, n, _p(a), _p(r), _p(z), int(prec)),
+            "rve_apply_precond")
+    return z

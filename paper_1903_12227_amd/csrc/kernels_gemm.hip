@@ -1,0 +1,267 @@
+// Preconditioner apply z = (a0 A_Delta)^+ r by Kronecker diagonalisation,
+// as dense transform GEMMs on the MFMA units (gfx950).
+//
+// A_Delta = K (x) M + M (x) K is the constant-coefficient periodic Q1
+// operator (grid units): K = circ(-1, 2, -1), M = circ(1, 4, 1)/6. Both are
+// symmetric circulants, so the symmetric orthogonal Hartley matrix
+// Q[k][j] = cas(2 pi k j / n)/sqrt(n) (cas = cos + sin, Q = Q^T, Q^2 = I)
+// diagonalises both factors, and for an n x n residual R
+//     Z = Q [ (Q R Q) ./ (a0 E) ] Q,  E[k][l] = (8 - 2c_k - 2c_l - 4 c_k c_l)/3,
+// c_k = cos(2 pi k / n), with the (0,0) entry of 1/E set to zero (the
+// pseudo-inverse on the mean-zero subspace; Sec. 3.5 uses B = a0 A_Delta +
+// delta I with delta -> 0).
+//
+// Every GEMM here has the same shape: out_s = (X_s Q)^T for each system s,
+// X_s row-major with the contraction index contiguous. Since Q is symmetric,
+// two such GEMMs give ((X Q)^T Q)^T = Q X Q, so the four transforms are four
+// launches of one kernel; the first reads the FP64 residual and converts,
+// the second scales by 1/(a0 E), the fourth writes z in FP64 and emits
+// partial sums of r.z.
+//
+// Tiling: 256 threads (2 x 2 waves) per 64 x 64 output tile; each wave owns
+// a 32 x 32 block = 2 x 2 MFMA 16x16 tiles. Operand tiles are staged through
+// LDS with the next K slice prefetched into registers; the output tile is
+// transposed through LDS so global stores are contiguous. Tiles are ordered
+// so that the n/64 tiles sharing one A row-block are consecutive and land on
+// one XCD (its L2 then holds that row-block once).
+#include <type_traits>
+
+#include "launch.h"
+
+namespace rve {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64;
+
+// MFMA precision traits. Lane layouts (wave64, 16x16 output):
+//   operands: lane l supplies row/column l%16 at contraction slice l/16
+//             (FP64/FP32: one value; BF16: 8 consecutive values);
+//   FP64 accumulator register i of lane l: row (l/16) + 4i, column l%16;
+//   FP32 accumulator register i of lane l: row 4(l/16) + i, column l%16.
+struct TrF64 {
+  using op_t = double;
+  using acc_t = double;
+  using accv_t = v4d;
+  static constexpr int BK = 16, KM = 4, PAD = 1;
+  __device__ static accv_t mma(const op_t* a, const op_t* b, accv_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(*a, *b, c, 0, 0, 0);
+  }
+  __device__ static int acc_row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+struct TrF32 {
+  using op_t = float;
+  using acc_t = float;
+  using accv_t = v4f;
+  static constexpr int BK = 16, KM = 4, PAD = 1;
+  __device__ static accv_t mma(const op_t* a, const op_t* b, accv_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+  }
+  __device__ static int acc_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+struct TrBF16 {
+  using op_t = __bf16;
+  using acc_t = float;
+  using accv_t = v4f;
+  static constexpr int BK = 64, KM = 32, PAD = 8;
+  __device__ static accv_t mma(const op_t* a, const op_t* b, accv_t c) {
+    const v8bf av = *reinterpret_cast<const v8bf*>(a);
+    const v8bf bv = *reinterpret_cast<const v8bf*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+  __device__ static int acc_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+template <class T> __device__ inline T cvt(double v);
+template <> __device__ inline double cvt<double>(double v) { return v; }
+template <> __device__ inline float cvt<float>(double v) { return (float)v; }
+template <> __device__ inline __bf16 cvt<__bf16>(double v) { return (__bf16)(float)v; }
+template <class T> __device__ inline T cvtf(float v);
+template <> __device__ inline float cvtf<float>(float v) { return v; }
+template <> __device__ inline __bf16 cvtf<__bf16>(float v) { return (__bf16)v; }
+
+enum Epi { kEpiStore = 0, kEpiEinv = 1, kEpiZ = 2 };
+
+// Elements of one K-slice per thread: (BM x BK) / 256.
+template <class Tr> struct Stage {
+  static constexpr int PER = (BM * Tr::BK) / kBlock;   // 4 (FP64/FP32) or 16 (BF16)
+  static constexpr int TPR = Tr::BK / PER;              // threads per row: 4
+};
+
+template <class Tr, class InT, int EPI>
+__global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, const typename Tr::op_t* __restrict__ Qm,
+                                                     void* __restrict__ out_v, int n, int S, const SysState* sys,
+                                                     const RealState* real, const void* __restrict__ einv_v,
+                                                     const double* __restrict__ rres, double* __restrict__ part) {
+  using op_t = typename Tr::op_t;
+  using acc_t = typename Tr::acc_t;
+  using accv_t = typename Tr::accv_t;
+  constexpr int BK = Tr::BK, KM = Tr::KM, LDA = BK + Tr::PAD;
+  constexpr int PER = Stage<Tr>::PER, TPR = Stage<Tr>::TPR;
+  constexpr int LDC = BM + 1;
+  constexpr size_t kOpBytes = 2 * (size_t)BM * LDA * sizeof(op_t);
+  constexpr size_t kCBytes = (size_t)BN * LDC * sizeof(acc_t);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kCBytes ? kOpBytes : kCBytes];
+  __shared__ double red[4];
+  op_t* As = reinterpret_cast<op_t*>(smem);
+  op_t* Bs = As + BM * LDA;
+  acc_t* Cs = reinterpret_cast<acc_t*>(smem);
+
+  const int NB = n / BN, MB = n / BM;
+  const long long T = (long long)S * MB * NB;
+  long long t = blockIdx.x;
+  if ((T & 7) == 0) t = (t & 7) * (T >> 3) + (t >> 3);   // XCD-contiguous tile ranges
+  const int nb = (int)(t % NB);
+  const long long rest = t / NB;
+  const int mb = (int)(rest % MB);
+  const int s = (int)(rest / MB);
+  if (sys && !sys[s].active) return;
+
+  const long long N2 = (long long)n * n;
+  const InT* Xs = X + (long long)s * N2 + (long long)mb * BM * n;
+  const op_t* Qs = Qm + (long long)nb * BN * n;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int ld_row = tid / TPR, ld_col = (tid % TPR) * PER;
+
+  InT ra[PER];
+  op_t rb[PER];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      ra[e] = Xs[(long long)ld_row * n + k0 + ld_col + e];
+      rb[e] = Qs[(long long)ld_row * n + k0 + ld_col + e];
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      if constexpr (sizeof(InT) == sizeof(op_t)) As[ld_row * LDA + ld_col + e] = (op_t)ra[e];
+      else As[ld_row * LDA + ld_col + e] = cvt<op_t>((double)ra[e]);
+      Bs[ld_row * LDA + ld_col + e] = rb[e];
+    }
+  };
+
+  accv_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+  // operand fragment base: row (l%16), contraction offset (l/16) * (KM/4)
+  const int frow = lane & 15, fk = (lane >> 4) * (KM / 4);
+
+  gload(0);
+  sstore();
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += BK) {
+    const bool more = k0 + BK < n;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += KM) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const op_t* pa = As + (wm * 32 + i * 16 + frow) * LDA + kk + fk;
+          const op_t* pb = Bs + (wn * 32 + j * 16 + frow) * LDA + kk + fk;
+          acc[i][j] = Tr::mma(pa, pb, acc[i][j]);
+        }
+    }
+    __syncthreads();
+    if (more) {
+      sstore();
+      __syncthreads();
+    }
+  }
+
+  // accumulators -> LDS, transposed: Cs[col][row]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wm * 32 + i * 16 + Tr::acc_row(lane, e);
+        const int col = wn * 32 + j * 16 + (lane & 15);
+        Cs[col * LDC + row] = acc[i][j][e];
+      }
+  __syncthreads();
+
+  // output tile: BN rows (l) of BM contiguous values (m); 4 threads per row
+  const int orow = tid >> 2, oc0 = (tid & 3) * 16;
+  const long long obase = (long long)s * N2 + (long long)(nb * BN + orow) * n + mb * BM + oc0;
+  double dot = 0.0;
+  acc_t scale = (acc_t)1;
+  if constexpr (EPI == kEpiEinv) scale = (acc_t)real[s >> 1].inv_a0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acc_t v = Cs[orow * LDC + oc0 + e];
+    if constexpr (EPI == kEpiEinv) {
+      const acc_t* einv = reinterpret_cast<const acc_t*>(einv_v);
+      v = v * einv[(long long)(nb * BN + orow) * n + mb * BM + oc0 + e] * scale;
+    }
+    if constexpr (EPI == kEpiZ) {
+      double* out = reinterpret_cast<double*>(out_v);
+      const double zv = (double)v;
+      out[obase + e] = zv;
+      dot += zv * rres[obase + e];
+    } else {
+      op_t* out = reinterpret_cast<op_t*>(out_v);
+      if constexpr (sizeof(acc_t) == sizeof(op_t)) out[obase + e] = (op_t)v;
+      else out[obase + e] = cvtf<op_t>(v);
+    }
+  }
+  if constexpr (EPI == kEpiZ) {
+    double d[1] = {dot};
+    block_sum<1>(d, red);
+    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = d[0];
+  }
+}
+
+template <class Tr>
+void run_precond(const Work& w, const GemmTables& t, hipStream_t st) {
+  using op_t = typename Tr::op_t;
+  const int n = w.n;
+  const long long T = (long long)w.S * (n / BM) * (n / BN);
+  const dim3 grid((unsigned)T), block(kBlock);
+  const op_t* Q = reinterpret_cast<const op_t*>(t.q);
+  const void* einv = std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv64 : (const void*)t.einv32;
+  op_t* u1 = reinterpret_cast<op_t*>(w.u1);
+  op_t* u2 = reinterpret_cast<op_t*>(w.u2);
+  // T1 = (R Q)^T
+  hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S, w.sys,
+                     w.real, nullptr, nullptr, nullptr);
+  // W = (Q R Q) ./ (a0 E)
+  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+                     w.real, einv, nullptr, nullptr);
+  // T3 = (W Q)^T
+  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+                     w.real, nullptr, nullptr, nullptr);
+  // z = Q W Q (FP64), partial sums of r.z
+  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ>), grid, block, 0, st, u1, Q, (void*)w.z, n, w.S, w.sys,
+                     w.real, nullptr, w.r, w.part_rz);
+}
+
+}  // namespace
+
+size_t gemm_elem_size(int prec) {
+  return prec == kGemmF64 ? sizeof(double) : prec == kGemmF32 ? sizeof(float) : sizeof(__bf16);
+}
+
+int gemm_tiles_per_system(int n, int /*prec*/) { return (n / BM) * (n / BN); }
+
+void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st) {
+  if (prec == kGemmF64) run_precond<TrF64>(w, t, st);
+  else if (prec == kGemmF32) run_precond<TrF32>(w, t, st);
+  else run_precond<TrBF16>(w, t, st);
+}
+
+}  // namespace rve

@@ -1,0 +1,716 @@
+// Stencil-shaped and elementwise kernels of the RVE corrector path.
+//
+// Grid units (h = 1). Cell (i, j) spans nodes i..i+1 (x1) and j..j+1 (x2),
+// mod n; arrays are [i][j] with x2 contiguous. A realization b owns the two
+// corrector systems s = 2b (direction e1) and s = 2b + 1 (direction e2).
+//
+// Tile-shaped kernels (RHS, operator apply, A_hom, gradient) use one
+// 256-thread workgroup per 64 x 64 tile of a realization: lane = column, the
+// four waves take 16-row strips and slide a register window down their
+// strip, so every value is loaded from HBM about once and the +-1 column
+// neighbours come from the same cache lines. All reductions are written as
+// per-workgroup partials and finished in a fixed order (deterministic, no
+// floating-point atomics).
+#include "launch.h"
+
+namespace rve {
+
+namespace {
+
+constexpr double kSixth = 1.0 / 6.0;
+constexpr double kThird = 1.0 / 3.0;
+constexpr double kTwoThirds = 2.0 / 3.0;
+
+__global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B,
+                                                        int* count, int count_len) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int stride = gridDim.x * kBlock;
+  for (int i = t; i < S; i += stride) sys[i] = SysState{};
+  for (int i = t; i < B; i += stride) real[i] = RealState{};
+  for (int i = t; i < count_len; i += stride) count[i] = 0;
+}
+
+// Galerkin right-hand sides f_i = -int a d(psi)/dx_i, integrated exactly per
+// cell (eqn. FEM_discr_RHS): with a11 = a[p][q], a10 = a[p][q-1],
+// a01 = a[p-1][q], a00 = a[p-1][q-1],
+//   f_1[p][q] = (a11 + a10 - a01 - a00)/2,  f_2[p][q] = (a11 + a01 - a10 - a00)/2.
+// Also gathers per-tile sum/min/max of a and a count of invalid cells.
+__global__ void __launch_bounds__(kBlock) k_rhs(const double* __restrict__ a, double* __restrict__ r,
+                                                 int n, double* __restrict__ part) {
+  __shared__ double sh[4 * 6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.z;
+  const long long N2 = (long long)n * n;
+  const int col = blockIdx.x * kTile + lane, cm = wrap_dec(col, n);
+  const int row0 = blockIdx.y * kTile + w * kStrip;
+  const double* A = a + (long long)b * N2;
+  double* F1 = r + (2LL * b) * N2;
+  double* F2 = F1 + N2;
+  int rr = wrap_dec(row0, n);
+  double a00 = A[(long long)rr * n + cm], a01 = A[(long long)rr * n + col];
+  double s[3] = {0.0, 0.0, 0.0};
+  double amin = 1.0e308, amax = -1.0e308;
+  int bad = 0;
+  for (int j = 0; j < kStrip; ++j) {
+    const int row = row0 + j;
+    const double a10 = A[(long long)row * n + cm], a11 = A[(long long)row * n + col];
+    const double f1 = 0.5 * ((a11 + a10) - (a01 + a00));
+    const double f2 = 0.5 * ((a11 + a01) - (a10 + a00));
+    F1[(long long)row * n + col] = f1;
+    F2[(long long)row * n + col] = f2;
+    s[0] += f1;
+    s[1] += f2;
+    s[2] += a11;
+    amin = fmin(amin, a11);
+    amax = fmax(amax, a11);
+    bad += !(a11 > 0.0);   // also catches NaN
+    a00 = a10;
+    a01 = a11;
+  }
+  const double vmin = wave_min(amin), vmax = wave_max(amax);
+  double badd = (double)bad;
+  double v[4] = {s[0], s[1], s[2], badd};
+  block_sum<4>(v, sh);
+  __shared__ double mm[8];
+  if (lane == 0) { mm[w] = vmin; mm[4 + w] = vmax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int P = gridDim.x * gridDim.y;
+    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    double* o = part + ((long long)b * P + tile) * kMiscNV;
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = fmin(fmin(mm[0], mm[1]), fmin(mm[2], mm[3]));
+    o[4] = fmax(fmax(mm[4], mm[5]), fmax(mm[6], mm[7]));
+    o[5] = v[3];
+  }
+}
+
+// Per realization: finish the RHS partials (one wave per realization).
+__global__ void k_scalar_init(SysState* sys, RealState* real, const double* __restrict__ part, int P,
+                              int n) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  double s1 = 0, s2 = 0, sa = 0, bad = 0, mn = 1.0e308, mx = -1.0e308;
+  for (int t = lane; t < P; t += kWave) {
+    const double* o = part + ((long long)b * P + t) * kMiscNV;
+    s1 += o[0];
+    s2 += o[1];
+    sa += o[2];
+    mn = fmin(mn, o[3]);
+    mx = fmax(mx, o[4]);
+    bad += o[5];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  sa = wave_sum(sa);
+  bad = wave_sum(bad);
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    const double N2 = (double)n * (double)n;
+    RealState rs;
+    rs.a_sum = sa;
+    rs.a_min = mn;
+    rs.a_max = mx;
+    rs.inv_a0 = 2.0 / (mx + mn);
+    rs.bad = (int)bad;
+    rs.pad = 0;
+    real[b] = rs;
+    const int valid = (bad == 0.0) && isfinite(sa);
+    sys[2 * b].mean_f = s1 / N2;
+    sys[2 * b + 1].mean_f = s2 / N2;
+    sys[2 * b].valid = valid;
+    sys[2 * b + 1].valid = valid;
+  }
+}
+
+// r <- r - mean(f), x <- 0 (the initial iterate); partial sums of r.r.
+__global__ void __launch_bounds__(kBlock) k_meansub(double* __restrict__ r, double* __restrict__ x,
+                                                     const SysState* sys, long long N2,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int s = blockIdx.y;
+  const double m = sys[s].mean_f;
+  double* R = r + (long long)s * N2;
+  double* X = x + (long long)s * N2;
+  double acc[1] = {0.0};
+  const long long stride = (long long)gridDim.x * kBlock * 2;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
+    double2 v = *reinterpret_cast<double2*>(R + i);
+    v.x -= m;
+    v.y -= m;
+    *reinterpret_cast<double2*>(R + i) = v;
+    *reinterpret_cast<double2*>(X + i) = make_double2(0.0, 0.0);
+    acc[0] += v.x * v.x + v.y * v.y;
+  }
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = acc[0];
+}
+
+__global__ void k_scalar_fnorm(SysState* sys, const double* __restrict__ part, int P) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  double v = 0;
+  for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
+  v = wave_sum(v);
+  if (lane == 0) {
+    SysState& S = sys[s];
+    S.fnorm = sqrt(v);
+    S.iters = 0;
+    S.relres = 0.0;
+    if (!S.valid) {
+      S.active = 0;
+      S.status = -1;   // RVE_EINVAL
+    } else if (!(S.fnorm > 0.0)) {
+      S.active = 0;    // f = 0 (e.g. a constant field): phi = 0, done
+      S.status = 0;
+    } else {
+      S.active = 1;
+      S.status = 0;
+    }
+  }
+}
+
+// q = A p for both systems of a realization (9-point Q1 stencil), with
+// partial sums of p.q.
+//
+// Node (p,q) touches cells (p-1,q-1)=a00, (p-1,q)=a01, (p,q-1)=a10,
+// (p,q)=a11. Each cell contributes (a_e/6)(4 u_self - u_x1nbr - u_x2nbr -
+// 2 u_diag): the consistent Q1 element matrix a_e (k (x) m + m (x) k) of
+// the rank-2 Kronecker form (Sec. 3.2). Collected per neighbour:
+//   centre (2/3)(a00+a01+a10+a11); (p+-1, q): -(a10+a11)/6, -(a00+a01)/6;
+//   (p, q+-1): -(a01+a11)/6, -(a00+a10)/6; diagonals -a_e/3 of the one
+//   cell they share with the node.
+__device__ inline double q1_apply(double a00, double a01, double a10, double a11, const double (&um)[3],
+                                  const double (&uc)[3], const double (&up)[3]) {
+  double v = kTwoThirds * ((a00 + a01) + (a10 + a11)) * uc[1];
+  v -= kSixth * ((a10 + a11) * up[1] + (a00 + a01) * um[1] + (a01 + a11) * uc[2] + (a00 + a10) * uc[0]);
+  v -= kThird * (a11 * up[2] + a01 * um[2] + a10 * up[0] + a00 * um[0]);
+  return v;
+}
+
+template <bool DOT>
+__global__ void __launch_bounds__(kBlock) k_stencil(const double* __restrict__ a, const double* __restrict__ p,
+                                                     double* __restrict__ q, int n, const SysState* sys,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4 * 2];
+  const int b = blockIdx.z;
+  const int s0 = 2 * b, s1 = s0 + 1;
+  const int act0 = DOT ? sys[s0].active : 1, act1 = DOT ? sys[s1].active : 1;
+  if (!act0 && !act1) return;   // uniform over the workgroup
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long N2 = (long long)n * n;
+  const int col = blockIdx.x * kTile + lane, cm = wrap_dec(col, n), cp = wrap_inc(col, n);
+  const int row0 = blockIdx.y * kTile + w * kStrip;
+  const double* A = a + (long long)b * N2;
+  const double* P0 = p + (long long)s0 * N2;
+  const double* P1 = P0 + N2;
+  double* Q0 = q + (long long)s0 * N2;
+  double* Q1 = Q0 + N2;
+
+  const int rm = wrap_dec(row0, n);
+  double um0[3], uc0[3], up0[3], um1[3], uc1[3], up1[3];
+  {
+    const long long om = (long long)rm * n, oc = (long long)row0 * n;
+    um0[0] = P0[om + cm]; um0[1] = P0[om + col]; um0[2] = P0[om + cp];
+    uc0[0] = P0[oc + cm]; uc0[1] = P0[oc + col]; uc0[2] = P0[oc + cp];
+    um1[0] = P1[om + cm]; um1[1] = P1[om + col]; um1[2] = P1[om + cp];
+    uc1[0] = P1[oc + cm]; uc1[1] = P1[oc + col]; uc1[2] = P1[oc + cp];
+  }
+  double a00 = A[(long long)rm * n + cm], a01 = A[(long long)rm * n + col];
+  double d[2] = {0.0, 0.0};
+  for (int j = 0; j < kStrip; ++j) {
+    const int row = row0 + j;
+    const long long op = (long long)wrap_inc(row, n) * n, oc = (long long)row * n;
+    up0[0] = P0[op + cm]; up0[1] = P0[op + col]; up0[2] = P0[op + cp];
+    up1[0] = P1[op + cm]; up1[1] = P1[op + col]; up1[2] = P1[op + cp];
+    const double a10 = A[oc + cm], a11 = A[oc + col];
+    const double v0 = q1_apply(a00, a01, a10, a11, um0, uc0, up0);
+    const double v1 = q1_apply(a00, a01, a10, a11, um1, uc1, up1);
+    if (act0) Q0[oc + col] = v0;
+    if (act1) Q1[oc + col] = v1;
+    d[0] += uc0[1] * v0;
+    d[1] += uc1[1] * v1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      um0[k] = uc0[k]; uc0[k] = up0[k];
+      um1[k] = uc1[k]; uc1[k] = up1[k];
+    }
+    a00 = a10;
+    a01 = a11;
+  }
+  if (DOT) {
+    block_sum<2>(d, sh);
+    if (threadIdx.x == 0) {
+      const int P = gridDim.x * gridDim.y;
+      const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+      part[(long long)s0 * P + tile] = d[0];
+      part[(long long)s1 * P + tile] = d[1];
+    }
+  }
+}
+
+__global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, int P) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  if (!sys[s].active) return;
+  double v = 0;
+  for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
+  v = wave_sum(v);
+  if (lane == 0) {
+    SysState& S = sys[s];
+    if (!(v > 0.0) || !isfinite(v)) {
+      S.active = 0;
+      S.status = 2;   // RVE_BREAKDOWN
+      S.alpha = 0.0;
+    } else {
+      S.alpha = S.rz / v;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, partial sums of r.r (and of r.z_old for the
+// flexible beta).
+__global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p,
+                                                       const double* __restrict__ q,
+                                                       const double* __restrict__ z, const SysState* sys,
+                                                       long long N2, double* __restrict__ part_rr,
+                                                       double* __restrict__ part_rzo, int flexible) {
+  __shared__ double sh[4 * 2];
+  const int s = blockIdx.y;
+  if (!sys[s].active) return;
+  const double al = sys[s].alpha;
+  const long long off = (long long)s * N2;
+  double acc[2] = {0.0, 0.0};
+  const long long stride = (long long)gridDim.x * kBlock * 2;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
+    double2 xv = *reinterpret_cast<const double2*>(x + off + i);
+    double2 rv = *reinterpret_cast<const double2*>(r + off + i);
+    const double2 pv = *reinterpret_cast<const double2*>(p + off + i);
+    const double2 qv = *reinterpret_cast<const double2*>(q + off + i);
+    xv.x = fma(al, pv.x, xv.x);
+    xv.y = fma(al, pv.y, xv.y);
+    rv.x = fma(-al, qv.x, rv.x);
+    rv.y = fma(-al, qv.y, rv.y);
+    *reinterpret_cast<double2*>(x + off + i) = xv;
+    *reinterpret_cast<double2*>(r + off + i) = rv;
+    acc[0] += rv.x * rv.x + rv.y * rv.y;
+    if (flexible) {
+      const double2 zv = *reinterpret_cast<const double2*>(z + off + i);
+      acc[1] += rv.x * zv.x + rv.y * zv.y;
+    }
+  }
+  block_sum<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    part_rr[(long long)s * gridDim.x + blockIdx.x] = acc[0];
+    part_rzo[(long long)s * gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+__global__ void k_scalar_conv(SysState* sys, const double* __restrict__ part, int P, double tol, int maxit,
+                              int* count_slot, int S) {
+  // one wave per system; blockDim = 64
+  const int s = blockIdx.x, lane = threadIdx.x;
+  if (!sys[s].active) return;
+  double v = 0;
+  for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
+  v = wave_sum(v);
+  if (lane == 0) {
+    SysState& S0 = sys[s];
+    S0.iters += 1;
+    S0.relres = sqrt(v) / S0.fnorm;
+    if (S0.relres <= tol) {
+      S0.active = 0;
+      S0.status = 0;
+    } else if (!isfinite(S0.relres)) {
+      S0.active = 0;
+      S0.status = 2;
+    } else if (S0.iters >= maxit) {
+      S0.active = 0;
+      S0.status = 1;   // RVE_NOT_CONVERGED
+    } else {
+      atomicAdd(count_slot, 1);
+    }
+  }
+}
+
+__global__ void k_scalar_beta(SysState* sys, const double* __restrict__ part_rz, int Pz,
+                              const double* __restrict__ part_rzo, int Po, int flexible, int first) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  if (!sys[s].active) return;
+  double v = 0, o = 0;
+  for (int t = lane; t < Pz; t += kWave) v += part_rz[(long long)s * Pz + t];
+  if (flexible && !first)
+    for (int t = lane; t < Po; t += kWave) o += part_rzo[(long long)s * Po + t];
+  v = wave_sum(v);
+  o = wave_sum(o);
+  if (lane == 0) {
+    SysState& S = sys[s];
+    S.beta = first ? 0.0 : (v - o) / S.rz;
+    S.rz = v;
+    if (!(v > 0.0) || !isfinite(v)) {   // the preconditioner must stay positive
+      S.active = 0;
+      S.status = 2;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_update_p(double* __restrict__ p, const double* __restrict__ z,
+                                                      const SysState* sys, long long N2, int first) {
+  const int s = blockIdx.y;
+  if (!sys[s].active) return;
+  const double be = sys[s].beta;
+  const long long off = (long long)s * N2;
+  const long long stride = (long long)gridDim.x * kBlock * 2;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
+    const double2 zv = *reinterpret_cast<const double2*>(z + off + i);
+    double2 pv;
+    if (first) {
+      pv = zv;
+    } else {
+      pv = *reinterpret_cast<const double2*>(p + off + i);
+      pv.x = fma(be, pv.x, zv.x);
+      pv.y = fma(be, pv.y, zv.y);
+    }
+    *reinterpret_cast<double2*>(p + off + i) = pv;
+  }
+}
+
+// Exact cell integrals for bilinear phi on the unit cell, corners
+// u00 = phi[i][j], u01 = phi[i][j+1], u10 = phi[i+1][j], u11 = phi[i+1][j+1]:
+// d1 phi is linear in the x2-local coordinate t between b1 = u10 - u00 (t=0)
+// and t1 = u11 - u01 (t=1), so int d1u d1v = (b1u b1v + t1u t1v)/3 +
+// (b1u t1v + t1u b1v)/6 and int d1u = (b1u + t1u)/2; d2 likewise.
+struct CellGrad {
+  double b1, t1, b2, t2;
+  __device__ CellGrad(double u00, double u01, double u10, double u11)
+      : b1(u10 - u00), t1(u11 - u01), b2(u01 - u00), t2(u11 - u10) {}
+  __device__ double D1() const { return 0.5 * (b1 + t1); }
+  __device__ double D2() const { return 0.5 * (b2 + t2); }
+};
+__device__ inline double grad_dot(const CellGrad& u, const CellGrad& v) {
+  return kThird * ((u.b1 * v.b1 + u.t1 * v.t1) + (u.b2 * v.b2 + u.t2 * v.t2)) +
+         kSixth * ((u.b1 * v.t1 + u.t1 * v.b1) + (u.b2 * v.t2 + u.t2 * v.b2));
+}
+// E_ij(e) = int_e (e_i + grad phi_i).(e_j + grad phi_j).
+struct CellEnergy {
+  double e11, e12, e22;
+  __device__ CellEnergy(const CellGrad& u, const CellGrad& v) {
+    e11 = 1.0 + 2.0 * u.D1() + grad_dot(u, u);
+    e12 = u.D2() + v.D1() + grad_dot(u, v);
+    e22 = 1.0 + 2.0 * v.D2() + grad_dot(v, v);
+  }
+};
+
+// Per-tile partials of sum_e a_e E_ij(e) (energy form), of the flux-form
+// integrands a(delta_ij + d_j phi_i), and of sum phi_i.
+__global__ void __launch_bounds__(kBlock) k_ahom(const double* __restrict__ a, const double* __restrict__ x,
+                                                  int n, double* __restrict__ part) {
+  __shared__ double sh[4 * 9];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.z;
+  const long long N2 = (long long)n * n;
+  const int col = blockIdx.x * kTile + lane, cp = wrap_inc(col, n);
+  const int row0 = blockIdx.y * kTile + w * kStrip;
+  const double* A = a + (long long)b * N2;
+  const double* X0 = x + (2LL * b) * N2;
+  const double* X1 = X0 + N2;
+  long long o = (long long)row0 * n;
+  double u00 = X0[o + col], u01 = X0[o + cp], v00 = X1[o + col], v01 = X1[o + cp];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < kStrip; ++j) {
+    const int row = row0 + j;
+    const long long on = (long long)wrap_inc(row, n) * n;
+    const double u10 = X0[on + col], u11 = X0[on + cp], v10 = X1[on + col], v11 = X1[on + cp];
+    const double ae = A[(long long)row * n + col];
+    const CellGrad gu(u00, u01, u10, u11), gv(v00, v01, v10, v11);
+    const CellEnergy E(gu, gv);
+    acc[0] += ae * E.e11;
+    acc[1] += ae * E.e12;
+    acc[2] += ae * E.e22;
+    acc[3] += ae * (1.0 + gu.D1());
+    acc[4] += ae * gu.D2();
+    acc[5] += ae * gv.D1();
+    acc[6] += ae * (1.0 + gv.D2());
+    acc[7] += u00;
+    acc[8] += v00;
+    u00 = u10; u01 = u11; v00 = v10; v01 = v11;
+  }
+  block_sum<9>(acc, sh);
+  if (threadIdx.x == 0) {
+    const int P = gridDim.x * gridDim.y;
+    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    double* out = part + ((long long)b * P + tile) * kMiscNV;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = acc[k];
+  }
+}
+
+__global__ void k_scalar_ahom(SysState* sys, const double* __restrict__ part, int P, int n,
+                              double* __restrict__ ahom, double* __restrict__ ahom_flux) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int t = lane; t < P; t += kWave) {
+    const double* o = part + ((long long)b * P + t) * kMiscNV;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] += o[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+    const double inv = 1.0 / ((double)n * (double)n);
+    double* A = ahom + 4LL * b;
+    A[0] = v[0] * inv;
+    A[1] = v[1] * inv;
+    A[2] = v[1] * inv;
+    A[3] = v[2] * inv;
+    if (ahom_flux) {
+      double* F = ahom_flux + 4LL * b;
+      F[0] = v[3] * inv;
+      F[1] = v[4] * inv;
+      F[2] = v[5] * inv;
+      F[3] = v[6] * inv;
+    }
+    sys[2 * b].mean_x = v[7] * inv;
+    sys[2 * b + 1].mean_x = v[8] * inv;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_phi_out(const double* __restrict__ x, double* __restrict__ phi,
+                                                     const SysState* sys, long long N2, double h) {
+  const int s = blockIdx.y;
+  const double m = sys[s].mean_x;
+  const long long off = (long long)s * N2;
+  const long long stride = (long long)gridDim.x * kBlock * 2;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
+    const double2 xv = *reinterpret_cast<const double2*>(x + off + i);
+    double2 o;
+    o.x = h * (xv.x - m);
+    o.y = h * (xv.y - m);
+    *reinterpret_cast<double2*>(phi + off + i) = o;
+  }
+}
+
+__global__ void k_finalize(const SysState* sys, int B, int* iters, double* relres, int* status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const SysState& s0 = sys[2 * b];
+  const SysState& s1 = sys[2 * b + 1];
+  if (iters) {
+    iters[2 * b] = s0.iters;
+    iters[2 * b + 1] = s1.iters;
+  }
+  if (relres) {
+    relres[2 * b] = s0.relres;
+    relres[2 * b + 1] = s1.relres;
+  }
+  if (status) {
+    // errors (negative codes) dominate; otherwise the larger warning code
+    const int c0 = s0.status, c1 = s1.status;
+    status[b] = (c0 < 0 || c1 < 0) ? min(c0, c1) : max(c0, c1);
+  }
+}
+
+// grad[e] = sum_ij G_ij dA_ij/da_e = (G11 E11 + (G12 + G21) E12 + G22 E22)/n^2,
+// plus per-tile partial sums over the cells with a_e == a_in.
+__global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ a, const double* __restrict__ phi,
+                                                  double inv_h, const double* __restrict__ G,
+                                                  double* __restrict__ grad, double a_in, int n,
+                                                  double* __restrict__ part, int want_in) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.z;
+  const long long N2 = (long long)n * n;
+  const int col = blockIdx.x * kTile + lane, cp = wrap_inc(col, n);
+  const int row0 = blockIdx.y * kTile + w * kStrip;
+  const double* A = a + (long long)b * N2;
+  const double* X0 = phi + (2LL * b) * N2;
+  const double* X1 = X0 + N2;
+  double* Gr = grad + (long long)b * N2;
+  const double inv_n2 = 1.0 / ((double)n * (double)n);
+  const double g11 = G[4 * b] * inv_n2, g12 = (G[4 * b + 1] + G[4 * b + 2]) * inv_n2, g22 = G[4 * b + 3] * inv_n2;
+  long long o = (long long)row0 * n;
+  double u00 = X0[o + col] * inv_h, u01 = X0[o + cp] * inv_h;
+  double v00 = X1[o + col] * inv_h, v01 = X1[o + cp] * inv_h;
+  double acc[1] = {0.0};
+  for (int j = 0; j < kStrip; ++j) {
+    const int row = row0 + j;
+    const long long on = (long long)wrap_inc(row, n) * n;
+    const double u10 = X0[on + col] * inv_h, u11 = X0[on + cp] * inv_h;
+    const double v10 = X1[on + col] * inv_h, v11 = X1[on + cp] * inv_h;
+    const CellEnergy E(CellGrad(u00, u01, u10, u11), CellGrad(v00, v01, v10, v11));
+    const double g = g11 * E.e11 + g12 * E.e12 + g22 * E.e22;
+    const long long oc = (long long)row * n + col;
+    Gr[oc] = g;
+    if (A[oc] == a_in) acc[0] += g;
+    u00 = u10; u01 = u11; v00 = v10; v01 = v11;
+  }
+  if (want_in) {
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) {
+      const int P = gridDim.x * gridDim.y;
+      part[(long long)b * P + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+    }
+  }
+}
+
+__global__ void k_scalar_grad(const double* __restrict__ part, int P, double* grad_in) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  double v = 0;
+  for (int t = lane; t < P; t += kWave) v += part[(long long)b * P + t];
+  v = wave_sum(v);
+  if (lane == 0) grad_in[b] = v;
+}
+
+// Ensemble statistics in one workgroup (fixed-order reductions).
+__global__ void __launch_bounds__(kBlock) k_stats(const double* __restrict__ A, int N, double L,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[4 * 18];
+  __shared__ double mean[4];
+  double s[4] = {0, 0, 0, 0};
+  for (int t = threadIdx.x; t < N; t += kBlock)
+    for (int k = 0; k < 4; ++k) s[k] += A[4LL * t + k];
+  block_sum<4>(s, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) mean[k] = s[k] / N;
+  __syncthreads();
+  double c[18];
+  for (int k = 0; k < 18; ++k) c[k] = 0.0;
+  for (int t = threadIdx.x; t < N; t += kBlock) {
+    double d[4], raw[4];
+    for (int k = 0; k < 4; ++k) {
+      raw[k] = A[4LL * t + k];
+      d[k] = raw[k] - mean[k];
+    }
+    // q[(i,k),(j,l)] = cov(A_ij, A_kl): row (i,k) -> 2i+k, col (j,l) -> 2j+l
+    for (int i = 0; i < 2; ++i)
+      for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+          for (int l = 0; l < 2; ++l) c[(2 * i + k) * 4 + (2 * j + l)] += d[2 * i + j] * d[2 * k + l];
+    c[16] += raw[1] * raw[1];
+    const double dd = raw[0] - raw[3];
+    c[17] += dd * dd;
+  }
+  block_sum<18>(c, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) out[k] = mean[k];
+    // centred variances are the diagonal covariances cov(A_ij, A_ij)
+    // var(A_ij) = cov(A_ij, A_ij) sits at row (i,i), column (j,j)
+    out[4] = c[0 * 4 + 0] / (N - 1);            // A11: row (0,0), col (0,0)
+    out[5] = c[0 * 4 + 3] / (N - 1);            // A12: row (0,0), col (1,1)
+    out[6] = c[3 * 4 + 0] / (N - 1);            // A21: row (1,1), col (0,0)
+    out[7] = c[3 * 4 + 3] / (N - 1);            // A22: row (1,1), col (1,1)
+    out[8] = sqrt(c[16] / N);
+    out[9] = sqrt(c[17] / N);
+    const double scale = L * L / (N - 1);
+    for (int k = 0; k < 16; ++k) out[10 + k] = scale * c[k];
+  }
+}
+
+inline int vec_blocks(long long N2) {
+  long long nb = (N2 + 2LL * kBlock * 2 - 1) / (2LL * kBlock * 2);
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void launch_init_state(const Work& w, int count_len, hipStream_t st) {
+  int m = w.S > count_len ? w.S : count_len;
+  int blocks = (m + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(kBlock), 0, st, w.sys, w.real, w.S, w.B, w.count,
+                     count_len);
+}
+
+void launch_rhs(const Work& w, hipStream_t st) {
+  dim3 g(w.n / kTile, w.n / kTile, w.B);
+  hipLaunchKernelGGL(k_rhs, g, dim3(kBlock), 0, st, w.a, w.r, w.n, w.part_misc);
+}
+
+void launch_scalar_init(const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_init, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, w.P_tile, w.n);
+}
+
+void launch_meansub(const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_meansub, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.r, w.x, w.sys, w.N2, w.part_rr);
+}
+
+void launch_scalar_fnorm(const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_fnorm, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec);
+}
+
+void launch_stencil_dot(const Work& w, hipStream_t st) {
+  dim3 g(w.n / kTile, w.n / kTile, w.B);
+  hipLaunchKernelGGL(k_stencil<true>, g, dim3(kBlock), 0, st, w.a, w.p, w.q, w.n, w.sys, w.part_pq);
+}
+
+void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
+  dim3 g(n / kTile, n / kTile, B);
+  hipLaunchKernelGGL(k_stencil<false>, g, dim3(kBlock), 0, st, a, u, out, n, (const SysState*)nullptr,
+                     (double*)nullptr);
+}
+
+void launch_scalar_alpha(const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_tile);
+}
+
+void launch_update_xr(const Work& w, int flexible, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.x, w.r, w.p, w.q, w.z, w.sys,
+                     w.N2, w.part_rr, w.part_rzo, flexible);
+}
+
+void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec, tol, maxit,
+                     w.count + slot, w.S);
+}
+
+void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_beta, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rz, w.P_gemm, w.part_rzo,
+                     w.P_vec, flexible, first);
+}
+
+void launch_update_p(const Work& w, int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.p, w.z, w.sys, w.N2, first);
+}
+
+void launch_ahom(const Work& w, hipStream_t st) {
+  dim3 g(w.n / kTile, w.n / kTile, w.B);
+  hipLaunchKernelGGL(k_ahom, g, dim3(kBlock), 0, st, w.a, w.x, w.n, w.part_misc);
+}
+
+void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_ahom, dim3(w.B), dim3(kWave), 0, st, w.sys, w.part_misc, w.P_tile, w.n, ahom,
+                     ahom_flux);
+}
+
+void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st) {
+  hipLaunchKernelGGL(k_phi_out, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.x, phi, w.sys, w.N2, h);
+}
+
+void launch_finalize(const Work& w, int* iters, double* relres, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3((w.B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, w.sys, w.B, iters,
+                     relres, status);
+}
+
+void launch_grad(int B, int n, const double* a, const double* phi, double inv_h, const double* G,
+                 double* grad, double a_in, double* part, int want_in, hipStream_t st) {
+  dim3 g(n / kTile, n / kTile, B);
+  hipLaunchKernelGGL(k_grad, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
+}
+
+void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st) {
+  const int P = (n / kTile) * (n / kTile);
+  hipLaunchKernelGGL(k_scalar_grad, dim3(B), dim3(kWave), 0, st, part, P, grad_in);
+}
+
+void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(kBlock), 0, st, ahom, N, L, out);
+}
+
+int vec_blocks_per_system(long long N2) { return vec_blocks(N2); }
+
+}  // namespace rve

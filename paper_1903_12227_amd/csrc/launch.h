@@ -1,0 +1,76 @@
+// Host-side launchers of the librve kernels. Each kernel source file defines
+// its kernels and the launchers below; the API layer calls only these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace rve {
+
+// Device pointers and sizes of one equal-n batch of B realizations
+// (S = 2B corrector systems, system s = 2b + i for direction i).
+struct Work {
+  int B = 0, n = 0, S = 0;
+  long long N2 = 0;          // n*n
+  const double* a = nullptr; // [B][n][n] cells
+  double* x = nullptr;       // [S][n][n] iterate (grid units)
+  double* r = nullptr;       // residual
+  double* p = nullptr;       // search direction
+  double* q = nullptr;       // A p
+  double* z = nullptr;       // preconditioned residual
+  void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
+  void* u2 = nullptr;
+  SysState* sys = nullptr;   // [S]
+  RealState* real = nullptr; // [B]
+  double* part_pq = nullptr;   // [S][P] partial sums of p.Ap
+  double* part_rr = nullptr;   // [S][P] partial sums of r.r
+  double* part_rzo = nullptr;  // [S][P] partial sums of r_new.z_old (flexible beta)
+  double* part_rz = nullptr;   // [S][P] partial sums of r.z
+  double* part_misc = nullptr; // [B][P][kMiscNV] per-realization partials
+  int* count = nullptr;        // [maxit+1] active-system counts per iteration
+  int P_tile = 0;   // workgroups per realization of the stencil-shaped kernels
+  int P_vec = 0;    // workgroups per system of the vector kernels
+  int P_gemm = 0;   // output tiles per system of the transform GEMMs
+};
+
+constexpr int kMiscNV = 9;
+
+// Elementwise and stencil kernels (kernels_vec.hip).
+void launch_init_state(const Work& w, int count_len, hipStream_t st);
+void launch_rhs(const Work& w, hipStream_t st);
+void launch_scalar_init(const Work& w, hipStream_t st);
+void launch_meansub(const Work& w, hipStream_t st);
+void launch_scalar_fnorm(const Work& w, hipStream_t st);
+void launch_stencil_dot(const Work& w, hipStream_t st);
+void launch_scalar_alpha(const Work& w, hipStream_t st);
+void launch_update_xr(const Work& w, int flexible, hipStream_t st);
+void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
+void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
+void launch_update_p(const Work& w, int first, hipStream_t st);
+void launch_ahom(const Work& w, hipStream_t st);
+void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
+void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st);
+void launch_finalize(const Work& w, int* iters, double* relres, int* status, hipStream_t st);
+void launch_grad(int B, int n, const double* a, const double* phi, double inv_h,
+                 const double* G, double* grad, double a_in, double* part, int want_in,
+                 hipStream_t st);
+void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st);
+void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t st);
+void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out,
+                          hipStream_t st);
+
+// Transform GEMMs of the preconditioner (kernels_gemm.hip).
+enum GemmPrec { kGemmF64 = 0, kGemmF32 = 1, kGemmBF16 = 2 };
+struct GemmTables {
+  const void* q = nullptr;        // [n][n] Hartley matrix in the GEMM operand type
+  const double* einv64 = nullptr; // [n][n] 1/E, (0,0) entry 0
+  const float* einv32 = nullptr;
+};
+size_t gemm_elem_size(int prec);
+// z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.
+void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st);
+int gemm_tiles_per_system(int n, int prec);
+
+}  // namespace rve

@@ -1,0 +1,616 @@
+// librve C ABI: context, workspace, transform tables and the PCG driver.
+//
+// The driver enqueues every step of the corrector path as HIP kernels on the
+// context's stream; the host only sequences launches and polls a pinned
+// all-converged counter once per chunk of iterations, keeping one chunk of
+// launches queued ahead so the GPU does not drain while the host waits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "launch.h"
+
+using namespace rve;
+
+namespace {
+
+constexpr int kMinN = 64, kMaxN = 4096;
+
+struct Tables {
+  double* q64 = nullptr;
+  float* q32 = nullptr;
+  __bf16* q16 = nullptr;
+  double* einv64 = nullptr;
+  float* einv32 = nullptr;
+};
+
+// Timed kernel classes: 0 stencil apply, 1 preconditioner apply (four
+// transform GEMMs), 2 x/r update, 3 search-direction update.
+constexpr int kTimedClasses = 4;
+
+struct EventTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> pairs;   // (class, first event index)
+  size_t used = 0;
+  double ms[kTimedClasses] = {0, 0, 0, 0};
+  long long count[kTimedClasses] = {0, 0, 0, 0};
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+}  // namespace
+
+struct rve_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::map<int, Tables> tables;
+  int* h_count = nullptr;   // pinned, 2 slots
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  bool timing = false;
+  EventTimer timer;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) {                             \
+      fprintf(stderr, "librve: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
+      return RVE_EHIP;                                  \
+    }                                                   \
+  } while (0)
+
+inline void ignore(hipError_t) {}
+
+bool n_supported(int n) { return n >= kMinN && n <= kMaxN && n % 64 == 0; }
+
+// Errors (negative codes) dominate warnings; among equals the larger magnitude.
+int worse(int x, int y) { return (x < 0 || y < 0) ? std::min(x, y) : std::max(x, y); }
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Host tables for the Hartley transform of size n, in FP64: exact integer
+// reduction of k*j mod n before the angle, host libm cos/sin.
+int build_tables(rve_ctx* ctx, int n, Tables** out) {
+  auto it = ctx->tables.find(n);
+  if (it != ctx->tables.end()) {
+    *out = &it->second;
+    return RVE_OK;
+  }
+  const size_t N2 = (size_t)n * n;
+  std::vector<double> q(N2), einv(N2);
+  std::vector<float> q32(N2), einv32(N2);
+  std::vector<__bf16> q16(N2);
+  const double two_pi = 6.283185307179586476925286766559;
+  const double inv_sqrt = 1.0 / std::sqrt((double)n);
+  std::vector<double> cas(n), c(n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = two_pi * (double)m / (double)n;
+    cas[m] = (std::cos(ang) + std::sin(ang)) * inv_sqrt;
+    c[m] = std::cos(ang);
+  }
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) {
+      const double v = cas[(size_t)((long long)k * j % n)];
+      q[(size_t)k * n + j] = v;
+      q32[(size_t)k * n + j] = (float)v;
+      q16[(size_t)k * n + j] = (__bf16)(float)v;
+    }
+  for (int k = 0; k < n; ++k)
+    for (int l = 0; l < n; ++l) {
+      const double E = (8.0 - 2.0 * c[k] - 2.0 * c[l] - 4.0 * c[k] * c[l]) / 3.0;
+      const double inv = (k == 0 && l == 0) ? 0.0 : 1.0 / E;
+      einv[(size_t)k * n + l] = inv;
+      einv32[(size_t)k * n + l] = (float)inv;
+    }
+  Tables t;
+  if (hipMalloc(&t.q64, N2 * 8) != hipSuccess || hipMalloc(&t.q32, N2 * 4) != hipSuccess ||
+      hipMalloc(&t.q16, N2 * 2) != hipSuccess || hipMalloc(&t.einv64, N2 * 8) != hipSuccess ||
+      hipMalloc(&t.einv32, N2 * 4) != hipSuccess) {
+    ignore(hipFree(t.q64)); ignore(hipFree(t.q32)); ignore(hipFree(t.q16));
+    ignore(hipFree(t.einv64)); ignore(hipFree(t.einv32));
+    return RVE_ENOMEM;
+  }
+  HIP_TRY(hipMemcpy(t.q64, q.data(), N2 * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.q32, q32.data(), N2 * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.q16, q16.data(), N2 * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einv64, einv.data(), N2 * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einv32, einv32.data(), N2 * 4, hipMemcpyHostToDevice));
+  ctx->tables[n] = t;
+  *out = &ctx->tables[n];
+  return RVE_OK;
+}
+
+// Carve the workspace of one equal-n batch; grows the arena if needed.
+struct Layout {
+  size_t off_x, off_r, off_p, off_q, off_z, off_u1, off_u2, off_sys, off_real;
+  size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_count, off_status, total;
+};
+
+Layout plan(int B, int n, int prec, int maxit, Work* w) {
+  Layout L{};
+  const long long S = 2LL * B, N2 = (long long)n * n;
+  const int P_tile = (n / kTile) * (n / kTile);
+  long long vb = N2 / 1024;
+  if (vb > 256) vb = 256;
+  if (vb < 1) vb = 1;
+  const int P_vec = (int)vb;
+  const int P_gemm = gemm_tiles_per_system(n, prec);
+  const size_t vec = align_up((size_t)(S * N2) * 8);
+  const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(prec));
+  size_t o = 0;
+  L.off_x = o; o += vec;
+  L.off_r = o; o += vec;
+  L.off_p = o; o += vec;
+  L.off_q = o; o += vec;
+  L.off_z = o; o += vec;
+  L.off_u1 = o; o += uvec;
+  L.off_u2 = o; o += uvec;
+  L.off_sys = o; o += align_up(S * sizeof(SysState));
+  L.off_real = o; o += align_up(B * sizeof(RealState));
+  L.off_pq = o; o += align_up(S * P_tile * 8);
+  L.off_rr = o; o += align_up(S * P_vec * 8);
+  L.off_rzo = o; o += align_up(S * P_vec * 8);
+  L.off_rz = o; o += align_up(S * P_gemm * 8);
+  L.off_misc = o; o += align_up((size_t)B * P_tile * kMiscNV * 8);
+  L.off_count = o; o += align_up((size_t)(maxit + 2) * sizeof(int));
+  L.off_status = o; o += align_up((size_t)B * sizeof(int));
+  L.total = o;
+  w->B = B;
+  w->n = n;
+  w->S = (int)S;
+  w->N2 = N2;
+  w->P_tile = P_tile;
+  w->P_vec = P_vec;
+  w->P_gemm = P_gemm;
+  return L;
+}
+
+int ensure_ws(rve_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return RVE_OK;
+  if (ctx->ws) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ignore(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return RVE_ENOMEM;
+  }
+  ctx->ws_bytes = bytes;
+  return RVE_OK;
+}
+
+void bind(rve_ctx* ctx, const Layout& L, Work* w) {
+  char* base = static_cast<char*>(ctx->ws);
+  w->x = reinterpret_cast<double*>(base + L.off_x);
+  w->r = reinterpret_cast<double*>(base + L.off_r);
+  w->p = reinterpret_cast<double*>(base + L.off_p);
+  w->q = reinterpret_cast<double*>(base + L.off_q);
+  w->z = reinterpret_cast<double*>(base + L.off_z);
+  w->u1 = base + L.off_u1;
+  w->u2 = base + L.off_u2;
+  w->sys = reinterpret_cast<SysState*>(base + L.off_sys);
+  w->real = reinterpret_cast<RealState*>(base + L.off_real);
+  w->part_pq = reinterpret_cast<double*>(base + L.off_pq);
+  w->part_rr = reinterpret_cast<double*>(base + L.off_rr);
+  w->part_rzo = reinterpret_cast<double*>(base + L.off_rzo);
+  w->part_rz = reinterpret_cast<double*>(base + L.off_rz);
+  w->part_misc = reinterpret_cast<double*>(base + L.off_misc);
+  w->count = reinterpret_cast<int*>(base + L.off_count);
+}
+
+int check_opts(const rve_opts* o) {
+  if (!o) return RVE_EINVAL;
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RVE_EINVAL;
+  if (o->maxit < 1 || o->maxit > 1000000) return RVE_EINVAL;
+  if (o->prec < RVE_FP64 || o->prec > RVE_MIX_BF16) return RVE_EINVAL;
+  return RVE_OK;
+}
+
+// Kernel-class timing with event pairs on the context stream.
+struct Timed {
+  rve_ctx* ctx;
+  int cls;
+  Timed(rve_ctx* c, int k) : ctx(c), cls(k) {
+    if (ctx->timing) {
+      hipEvent_t e = ctx->timer.next();
+      if (e) {
+        ctx->timer.pairs.push_back({cls, (int)ctx->timer.used - 1});
+        ignore(hipEventRecord(e, ctx->stream));
+      }
+    }
+  }
+  ~Timed() {
+    if (ctx->timing) {
+      hipEvent_t e = ctx->timer.next();
+      if (e) ignore(hipEventRecord(e, ctx->stream));
+    }
+  }
+};
+
+int harvest_timing(rve_ctx* ctx) {
+  if (!ctx->timing) return RVE_OK;
+  EventTimer& T = ctx->timer;
+  for (auto& pr : T.pairs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, T.pool[pr.second], T.pool[pr.second + 1]) == hipSuccess) {
+      T.ms[pr.first] += ms;
+      T.count[pr.first] += 1;
+    }
+  }
+  T.pairs.clear();
+  T.used = 0;
+  return RVE_OK;
+}
+
+// Solve B equal-size realizations whose coefficients sit at a_dev.
+// `status_host` (optional) receives the per-item statuses.
+int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const rve_opts* o,
+                double* phi, double* ahom, double* flux, int* iters, double* relres, int* status_dev,
+                std::vector<int>* status_host) {
+  Work w;
+  const Layout L = plan(B, n, o->prec, o->maxit, &w);
+  int rc = ensure_ws(ctx, L.total);
+  if (rc) return rc;
+  bind(ctx, L, &w);
+  w.a = a_dev;
+  Tables* tb = nullptr;
+  rc = build_tables(ctx, n, &tb);
+  if (rc) return rc;
+  GemmTables gt;
+  gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
+                                                                                : (const void*)tb->q16;
+  gt.einv64 = tb->einv64;
+  gt.einv32 = tb->einv32;
+  const int prec = o->prec == RVE_FP64 ? kGemmF64 : o->prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  const int flexible = o->flexible < 0 ? (o->prec != RVE_FP64) : (o->flexible != 0);
+  int chunk = o->check_every > 0 ? o->check_every : 8;
+  hipStream_t st = ctx->stream;
+
+  launch_init_state(w, o->maxit + 2, st);
+  launch_rhs(w, st);
+  launch_scalar_init(w, st);
+  launch_meansub(w, st);
+  launch_scalar_fnorm(w, st);
+  {
+    Timed t(ctx, 1);
+    launch_precond(w, prec, gt, st);
+  }
+  launch_scalar_beta(w, flexible, 1, st);
+  {
+    Timed t(ctx, 3);
+    launch_update_p(w, 1, st);
+  }
+
+  int enq = 0, chunk_idx = 0;
+  for (;;) {
+    const int end = std::min(enq + chunk, o->maxit);
+    for (; enq < end; ++enq) {
+      {
+        Timed t(ctx, 0);
+        launch_stencil_dot(w, st);
+      }
+      launch_scalar_alpha(w, st);
+      {
+        Timed t(ctx, 2);
+        launch_update_xr(w, flexible, st);
+      }
+      launch_scalar_conv(w, o->tol, o->maxit, enq, st);
+      if (enq + 1 < o->maxit) {
+        {
+          Timed t(ctx, 1);
+          launch_precond(w, prec, gt, st);
+        }
+        launch_scalar_beta(w, flexible, 0, st);
+        {
+          Timed t(ctx, 3);
+          launch_update_p(w, 0, st);
+        }
+      }
+    }
+    const int slot = chunk_idx & 1;
+    HIP_TRY(hipMemcpyAsync(ctx->h_count + slot, w.count + (enq - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(ctx->chunk_ev[slot], st));
+    if (enq >= o->maxit) {
+      HIP_TRY(hipEventSynchronize(ctx->chunk_ev[slot]));
+      break;
+    }
+    if (chunk_idx > 0) {
+      const int prev = slot ^ 1;
+      HIP_TRY(hipEventSynchronize(ctx->chunk_ev[prev]));
+      if (ctx->h_count[prev] == 0) break;
+    }
+    ++chunk_idx;
+  }
+
+  launch_ahom(w, st);
+  launch_scalar_ahom(w, ahom, flux, st);
+  if (phi) launch_phi_out(w, phi, h, st);
+  int* stat = status_dev ? status_dev : reinterpret_cast<int*>(static_cast<char*>(ctx->ws) + L.off_status);
+  launch_finalize(w, iters, relres, stat, st);
+  HIP_TRY(hipGetLastError());
+  std::vector<int> hs(B);
+  HIP_TRY(hipMemcpyAsync(hs.data(), stat, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  harvest_timing(ctx);
+  int worst = RVE_OK;
+  for (int b = 0; b < B; ++b) worst = worse(worst, hs[b]);
+  if (status_host) *status_host = hs;
+  return worst;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+void rve_default_opts(rve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->maxit = 2000;
+  o->prec = RVE_FP64;
+  o->flexible = -1;
+  o->check_every = 0;
+}
+
+const char* rve_status_string(int s) {
+  switch (s) {
+    case RVE_OK: return "RVE_OK: converged";
+    case RVE_NOT_CONVERGED: return "RVE_NOT_CONVERGED: maxit reached";
+    case RVE_BREAKDOWN: return "RVE_BREAKDOWN: non-positive or non-finite curvature in PCG";
+    case RVE_EINVAL: return "RVE_EINVAL: invalid argument or coefficient";
+    case RVE_EHIP: return "RVE_EHIP: HIP runtime error";
+    case RVE_ENOMEM: return "RVE_ENOMEM: device allocation failed";
+    default: return "unknown rve status";
+  }
+}
+
+int rve_create(rve_ctx** out, int device, void* hip_stream) {
+  if (!out) return RVE_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(device));
+  rve_ctx* c = new (std::nothrow) rve_ctx();
+  if (!c) return RVE_ENOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_count), 2 * sizeof(int), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return RVE_ENOMEM;
+  }
+  if (hipEventCreateWithFlags(&c->chunk_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->chunk_ev[1], hipEventDisableTiming) != hipSuccess) {
+    ignore(hipHostFree(c->h_count));
+    delete c;
+    return RVE_EHIP;
+  }
+  *out = c;
+  return RVE_OK;
+}
+
+int rve_destroy(rve_ctx* c) {
+  if (!c) return RVE_EINVAL;
+  ignore(hipSetDevice(c->device));
+  ignore(hipStreamSynchronize(c->stream));
+  for (auto& kv : c->tables) {
+    ignore(hipFree(kv.second.q64));
+    ignore(hipFree(kv.second.q32));
+    ignore(hipFree(kv.second.q16));
+    ignore(hipFree(kv.second.einv64));
+    ignore(hipFree(kv.second.einv32));
+  }
+  if (c->ws) ignore(hipFree(c->ws));
+  for (auto e : c->timer.pool) ignore(hipEventDestroy(e));
+  ignore(hipEventDestroy(c->chunk_ev[0]));
+  ignore(hipEventDestroy(c->chunk_ev[1]));
+  ignore(hipHostFree(c->h_count));
+  delete c;
+  return RVE_OK;
+}
+
+int rve_set_stream(rve_ctx* c, void* hip_stream) {
+  if (!c) return RVE_EINVAL;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  return RVE_OK;
+}
+
+int rve_solve_batch(rve_ctx* c, int B, int n, double h, const double* a_dev, const rve_opts* o,
+                    double* phi_dev, double* ahom_dev, double* ahom_flux_dev, int* iters_dev,
+                    double* relres_dev, int* status_dev) {
+  if (!c || B < 1 || !n_supported(n) || !(h > 0.0) || !std::isfinite(h) || !a_dev || !ahom_dev)
+    return RVE_EINVAL;
+  if (check_opts(o)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  return solve_equal(c, B, n, h, a_dev, o, phi_dev, ahom_dev, ahom_flux_dev, iters_dev, relres_dev,
+                     status_dev, nullptr);
+}
+
+int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, double h,
+                     const double* a_dev, const rve_opts* o, double* phi_dev, double* ahom_dev,
+                     double* ahom_flux_dev, int* iters_dev, double* relres_dev, int* status_dev) {
+  if (!c || B < 1 || !n_host || !off || !(h > 0.0) || !std::isfinite(h) || !a_dev || !ahom_dev)
+    return RVE_EINVAL;
+  if (check_opts(o)) return RVE_EINVAL;
+  // validate sizes and offsets: supported n, increasing, non-overlapping
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) {
+    if (!n_supported(n_host[b]) || off[b] < 0) return RVE_EINVAL;
+    order[b] = b;
+  }
+  // off[B] is the total extent of a_dev in elements; items must fit in it and
+  // must not overlap each other
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return off[x] < off[y]; });
+  for (int k = 0; k < B; ++k) {
+    const int b = order[k];
+    const int64_t end = off[b] + (int64_t)n_host[b] * n_host[b];
+    if (end > off[B]) return RVE_EINVAL;
+    if (k + 1 < B && end > off[order[k + 1]]) return RVE_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  // group items by size
+  std::map<int, std::vector<int>> groups;
+  for (int b = 0; b < B; ++b) groups[n_host[b]].push_back(b);
+  int worst = RVE_OK;
+  for (auto& g : groups) {
+    const int n = g.first;
+    const std::vector<int>& items = g.second;
+    const int Bg = (int)items.size();
+    const size_t N2 = (size_t)n * n;
+    // staging: a [Bg][N2], phi [Bg][2][N2], small outputs
+    double *a_g = nullptr, *phi_g = nullptr, *ah_g = nullptr, *fl_g = nullptr, *rr_g = nullptr;
+    int *it_g = nullptr, *st_g = nullptr;
+    const size_t bytes = Bg * N2 * 8 + (phi_dev ? 2 * Bg * N2 * 8 : 0) + Bg * (4 + 4 + 2) * 8 + Bg * 3 * 4 + 1024;
+    char* stage = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&stage), bytes, c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return RVE_ENOMEM;
+    }
+    size_t o2 = 0;
+    auto take = [&](size_t b) { char* p = stage + o2; o2 += align_up(b); return p; };
+    o2 = 0;
+    a_g = reinterpret_cast<double*>(take(Bg * N2 * 8));
+    if (phi_dev) phi_g = reinterpret_cast<double*>(take(2 * Bg * N2 * 8));
+    ah_g = reinterpret_cast<double*>(take(Bg * 4 * 8));
+    fl_g = reinterpret_cast<double*>(take(Bg * 4 * 8));
+    rr_g = reinterpret_cast<double*>(take(Bg * 2 * 8));
+    it_g = reinterpret_cast<int*>(take(Bg * 2 * 4));
+    st_g = reinterpret_cast<int*>(take(Bg * 4));
+    (void)o2;
+    for (int k = 0; k < Bg; ++k)
+      HIP_TRY(hipMemcpyAsync(a_g + k * N2, a_dev + off[items[k]], N2 * 8, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int> hs;
+    const int rc = solve_equal(c, Bg, n, h, a_g, o, phi_g, ah_g, fl_g, it_g, rr_g, st_g, &hs);
+    if (rc == RVE_EHIP || rc == RVE_ENOMEM) {
+      ignore(hipFreeAsync(stage, c->stream));
+      return rc;
+    }
+    for (int k = 0; k < Bg; ++k) {
+      const int b = items[k];
+      HIP_TRY(hipMemcpyAsync(ahom_dev + 4 * b, ah_g + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
+      if (ahom_flux_dev)
+        HIP_TRY(hipMemcpyAsync(ahom_flux_dev + 4 * b, fl_g + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
+      if (relres_dev)
+        HIP_TRY(hipMemcpyAsync(relres_dev + 2 * b, rr_g + 2 * k, 16, hipMemcpyDeviceToDevice, c->stream));
+      if (iters_dev)
+        HIP_TRY(hipMemcpyAsync(iters_dev + 2 * b, it_g + 2 * k, 8, hipMemcpyDeviceToDevice, c->stream));
+      if (status_dev)
+        HIP_TRY(hipMemcpyAsync(status_dev + b, st_g + k, 4, hipMemcpyDeviceToDevice, c->stream));
+      if (phi_dev)
+        HIP_TRY(hipMemcpyAsync(phi_dev + 2 * off[b], phi_g + 2 * k * N2, 2 * N2 * 8, hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    HIP_TRY(hipFreeAsync(stage, c->stream));
+    worst = worse(worst, rc);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return worst;
+}
+
+int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
+             const double* G_dev, double* grad_a_dev, double a_in, double* grad_in_dev) {
+  if (!c || B < 1 || !n_supported(n) || !(h > 0.0) || !a_dev || !phi_dev || !G_dev || !grad_a_dev)
+    return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  const int P = (n / kTile) * (n / kTile);
+  const int rc = ensure_ws(c, align_up((size_t)B * P * 8));
+  if (rc) return rc;
+  double* part = static_cast<double*>(c->ws);
+  launch_grad(B, n, a_dev, phi_dev, 1.0 / h, G_dev, grad_a_dev, a_in, part, grad_in_dev != nullptr, c->stream);
+  if (grad_in_dev) launch_scalar_grad(B, n, part, grad_in_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_stats(rve_ctx* c, int N, double L, const double* ahom_dev, double* out_dev) {
+  if (!c || N < 2 || !(L > 0.0) || !ahom_dev || !out_dev) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_stats(N, L, ahom_dev, out_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_apply_operator(rve_ctx* c, int B, int n, const double* a_dev, const double* u_dev, double* out_dev) {
+  if (!c || B < 1 || !n_supported(n) || !a_dev || !u_dev || !out_dev || u_dev == out_dev) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_apply_stencil(B, n, a_dev, u_dev, out_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const double* r_dev, double* z_dev,
+                      int prec) {
+  if (!c || B < 1 || !n_supported(n) || !a_dev || !r_dev || !z_dev || r_dev == z_dev) return RVE_EINVAL;
+  if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  Work w;
+  const Layout L = plan(B, n, prec, 1, &w);
+  int rc = ensure_ws(c, L.total);
+  if (rc) return rc;
+  bind(c, L, &w);
+  w.a = a_dev;
+  Tables* tb = nullptr;
+  rc = build_tables(c, n, &tb);
+  if (rc) return rc;
+  // a0 of each realization, exactly as the solver derives it
+  launch_init_state(w, 1, c->stream);
+  launch_rhs(w, c->stream);
+  launch_scalar_init(w, c->stream);
+  GemmTables gt;
+  gt.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
+                                                                         : (const void*)tb->q16;
+  gt.einv64 = tb->einv64;
+  gt.einv32 = tb->einv32;
+  w.r = const_cast<double*>(r_dev);
+  w.z = z_dev;
+  w.sys = nullptr;
+  launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_set_timing(rve_ctx* c, int enable) {
+  if (!c) return RVE_EINVAL;
+  c->timing = enable != 0;
+  for (int k = 0; k < kTimedClasses; ++k) {
+    c->timer.ms[k] = 0;
+    c->timer.count[k] = 0;
+  }
+  c->timer.pairs.clear();
+  c->timer.used = 0;
+  return RVE_OK;
+}
+
+int rve_last_timing(rve_ctx* c, double* out_ms, long long* out_counts) {
+  if (!c || !out_ms || !out_counts) return RVE_EINVAL;
+  for (int k = 0; k < kTimedClasses; ++k) {
+    out_ms[k] = c->timer.ms[k];
+    out_counts[k] = c->timer.count[k];
+  }
+  return RVE_OK;
+}
+
+}  // extern "C"

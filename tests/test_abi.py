@@ -1,0 +1,78 @@
+"""The C ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rve.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rve_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1903_12227_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.fail("librve.so is not built (run __graft_entry__.build())")
+    return _native.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1903_12227_amd import _native
+    assert set(_native.EXPORTS) == set(names)
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_1903_12227_amd import _native as N
+    for code in (N.OK, N.NOT_CONVERGED, N.BREAKDOWN, N.EINVAL, N.EHIP, N.ENOMEM):
+        assert N.status_string(code).startswith("RVE_")
+    o = N.RveOpts()
+    lib.rve_default_opts(ctypes.byref(o))
+    assert o.tol == 1e-10 and o.maxit == 2000 and o.prec == N.FP64 and o.flexible == -1
+
+
+def test_host_argument_validation(lib):
+    from paper_1903_12227_amd import _native as N
+    o = N.RveOpts()
+    lib.rve_default_opts(ctypes.byref(o))
+    fake = ctypes.c_void_p(1)
+    # null context, bad n (not a multiple of 64 / too small), bad h, bad opts
+    assert lib.rve_solve_batch(None, 1, 64, 0.125, fake, ctypes.byref(o), None, fake, None, None, None,
+                               None) == N.EINVAL
+    for n in (0, 32, 96, 8192):
+        assert lib.rve_solve_batch(fake, 1, n, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                   None, None) == N.EINVAL
+    assert lib.rve_solve_batch(fake, 1, 64, -1.0, fake, ctypes.byref(o), None, fake, None, None, None,
+                               None) == N.EINVAL
+    bad = N.RveOpts(-1.0, 10, 0, -1, 0)
+    assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                               None, None) == N.EINVAL
+    bad = N.RveOpts(1e-10, 0, 0, -1, 0)
+    assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                               None, None) == N.EINVAL
+    bad = N.RveOpts(1e-10, 10, 7, -1, 0)
+    assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                               None, None) == N.EINVAL
+    # uneven: overlapping offsets and extents beyond the total are rejected
+    ns = (ctypes.c_int * 2)(64, 64)
+    offs = (ctypes.c_int64 * 3)(0, 100, 8192)
+    assert lib.rve_solve_uneven(fake, 2, ns, offs, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                None, None) == N.EINVAL
+    offs = (ctypes.c_int64 * 3)(0, 4096, 4096)
+    assert lib.rve_solve_uneven(fake, 2, ns, offs, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                None, None) == N.EINVAL
+    assert lib.rve_stats(fake, 1, 16.0, fake, fake) == N.EINVAL
+    assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, 10.0, None) == N.EINVAL
+    assert lib.rve_apply_operator(fake, 1, 64, fake, fake, fake) == N.EINVAL   # u aliases out
+    assert lib.rve_apply_precond(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL
