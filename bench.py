@@ -160,7 +160,7 @@ def main():
 
     log("plain per-realization FP64 leg")
     single = batches[0][: args.plain]
-    run_step(rve, single[0:1].contiguous(), h, fp64, G[0:1], args.contrast, L)
+    rve.solve_batch(single[0:1].contiguous(), h, fp64, want_phi=True, want_flux=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b in range(args.plain):
