@@ -71,6 +71,30 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
     return (t1 - t0), it, tim, codes
 
 
+def bytes_per_node(prec_name, flexible):
+    """Algorithmic HBM bytes per node of each kernel class.
+
+    FP64 path: every vector FP64. Mixed paths: p and z are stored in FP32 and
+    the residual has a copy in the GEMM precision (s_g bytes) that the first
+    transform reads; x, r, q stay FP64.
+      stencil   (per realization, both systems): read p x2, write q x2, read a
+      update_xr (per system): read x, r, p, q [+ z for flexible beta], write x, r [+ r copy]
+      update_p  (per system): read z, p, write p
+      precond   (per system, four transforms): read r (copy), write/read three
+                intermediates, write z, re-read r (FP64) for r.z
+    """
+    sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
+    sp = 8 if prec_name == "fp64" else 4
+    lo = 0 if prec_name == "fp64" else sg
+    first_in = 8 if prec_name == "fp64" else sg
+    return {
+        "stencil": 2 * sp + 2 * 8 + 8,
+        "update_xr": 8 + 8 + sp + 8 + (sp if flexible else 0) + 8 + 8 + lo,
+        "update_p": 3 * sp,
+        "precond": first_in + 6 * sg + sp + 8,
+    }
+
+
 def roofline_entries(tim, it_all, n, B, prec_name, flexible):
     """Achieved rates of the timed kernel classes from algorithmic bytes/flops.
 
@@ -81,20 +105,22 @@ def roofline_entries(tim, it_all, n, B, prec_name, flexible):
     N2 = n * n
     stencil_applies = float(it_all.max(dim=2).values.sum())       # realization-launch units
     sys_iters = float(it_all.sum())
-    elem = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
+    bpn = bytes_per_node(prec_name, flexible)
     out = {}
     ms, cnt = tim["stencil"]
-    out["stencil"] = {"bound": "hbm", "bytes": stencil_applies * 40.0 * N2, "ms": ms, "launches": cnt}
+    out["stencil"] = {"bound": "hbm", "bytes": stencil_applies * bpn["stencil"] * N2, "ms": ms,
+                      "launches": cnt, "bytes_per_node": bpn["stencil"]}
     ms, cnt = tim["update_xr"]
-    out["update_xr"] = {"bound": "hbm", "bytes": sys_iters * (56.0 if flexible else 48.0) * N2, "ms": ms,
-                        "launches": cnt}
+    out["update_xr"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_xr"] * N2, "ms": ms,
+                        "launches": cnt, "bytes_per_node": bpn["update_xr"]}
     ms, cnt = tim["update_p"]
-    out["update_p"] = {"bound": "hbm", "bytes": sys_iters * 24.0 * N2, "ms": ms, "launches": cnt}
+    out["update_p"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_p"] * N2, "ms": ms,
+                       "launches": cnt, "bytes_per_node": bpn["update_p"]}
     ms, cnt = tim["precond"]
-    # four transforms of 2 n^3 flops per system-apply; bytes: r in (8), three
-    # intermediates written and read, z out (8) and r re-read for r.z (8)
+    # four transforms of 2 n^3 flops each per system-apply
     out["precond"] = {"bound": "mfma", "flops": sys_iters * 8.0 * n * N2,
-                      "bytes": sys_iters * (24.0 + 6 * elem) * N2, "ms": ms, "launches": 4 * cnt}
+                      "bytes": sys_iters * bpn["precond"] * N2, "ms": ms, "launches": 4 * cnt,
+                      "bytes_per_node": bpn["precond"]}
     return out
 
 
@@ -184,7 +210,7 @@ def main():
                 "avg_launch_ms": e["ms"] / max(e["launches"], 1)}
     kernels = {}
     for k, v in ent.items():
-        rec = {"ms_total": v["ms"], "launches": v["launches"],
+        rec = {"ms_total": v["ms"], "launches": v["launches"], "bytes_per_node": v["bytes_per_node"],
                "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
         if "flops" in v:
             rec["TFLOPs"] = v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else None

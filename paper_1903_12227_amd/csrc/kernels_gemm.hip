@@ -92,7 +92,7 @@ template <class Tr> struct Stage {
   static constexpr int TPR = Tr::BK / PER;              // threads per row: 4
 };
 
-template <class Tr, class InT, int EPI>
+template <class Tr, class InT, int EPI, class ZT = double>
 __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, const typename Tr::op_t* __restrict__ Qm,
                                                      void* __restrict__ out_v, int n, int S, const SysState* sys,
                                                      const RealState* real, const void* __restrict__ einv_v,
@@ -209,10 +209,10 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
       v = v * einv[(long long)(nb * BN + orow) * n + mb * BM + oc0 + e] * scale;
     }
     if constexpr (EPI == kEpiZ) {
-      double* out = reinterpret_cast<double*>(out_v);
-      const double zv = (double)v;
-      out[obase + e] = zv;
-      dot += zv * rres[obase + e];
+      ZT* out = reinterpret_cast<ZT*>(out_v);
+      const ZT zs = (ZT)v;
+      out[obase + e] = zs;
+      dot += (double)zs * rres[obase + e];
     } else {
       op_t* out = reinterpret_cast<op_t*>(out_v);
       if constexpr (sizeof(acc_t) == sizeof(op_t)) out[obase + e] = (op_t)v;
@@ -226,7 +226,175 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   }
 }
 
-template <class Tr>
+// Pure-BF16 transform GEMM with a 128 x 128 output tile (n % 128 == 0):
+// 2 x 2 waves of 64 x 64, i.e. 4 x 4 MFMA 16x16x32 blocks per wave, so each
+// operand fragment read from LDS feeds four MFMAs. Operand tiles (128 x 64
+// BF16, row stride 144 B: conflict-free 16-byte fragment reads) are loaded
+// with 16-byte global loads, the next K slice prefetched into registers.
+// The transposed output goes through LDS in two halves of 64 rows.
+constexpr int TM = 128, TN = 128, TK = 64, TLDA = TK + 8, TLDC = TM + 4;
+
+template <int EPI, class ZT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_hartley_bf16(const __bf16* __restrict__ X, const __bf16* __restrict__ Qm,
+                                                          void* __restrict__ out_v, int n, int S,
+                                                          const SysState* sys, const RealState* real,
+                                                          const float* __restrict__ einv,
+                                                          const double* __restrict__ rres,
+                                                          double* __restrict__ part) {
+  constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(__bf16);
+  constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
+  static_assert(kCBytes <= kOpBytes, "staging must fit in the operand buffers");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
+  __shared__ double red[4];
+  __bf16* As = reinterpret_cast<__bf16*>(smem);
+  __bf16* Bs = As + TM * TLDA;
+  float* Cs = reinterpret_cast<float*>(smem);
+
+  const int NB = n / TN, MB = n / TM;
+  const long long T = (long long)S * MB * NB;
+  long long t = blockIdx.x;
+  if ((T & 7) == 0) t = (t & 7) * (T >> 3) + (t >> 3);   // XCD-contiguous tile ranges
+  const int nb = (int)(t % NB);
+  const long long rest = t / NB;
+  const int mb = (int)(rest % MB);
+  const int s = (int)(rest / MB);
+  if (sys && !sys[s].active) return;
+
+  const long long N2 = (long long)n * n;
+  const __bf16* Xs = X + (long long)s * N2 + (long long)mb * TM * n;
+  const __bf16* Qs = Qm + (long long)nb * TN * n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int lr = tid >> 3, lc = (tid & 7) * 8;
+
+  // register staging of the next K slice (kept out of lambdas so that it
+  // stays in VGPRs)
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  const __bf16* xa = Xs + (long long)lr * n + lc;
+  const __bf16* qa = Qs + (long long)lr * n + lc;
+  const long long r32 = 32LL * n;
+#define RVE_GLOAD(k0)                                                        \
+  do {                                                                      \
+    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                       \
+    ra1 = *reinterpret_cast<const uint4*>(xa + r32 + (k0));                 \
+    ra2 = *reinterpret_cast<const uint4*>(xa + 2 * r32 + (k0));             \
+    ra3 = *reinterpret_cast<const uint4*>(xa + 3 * r32 + (k0));             \
+    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                       \
+    rb1 = *reinterpret_cast<const uint4*>(qa + r32 + (k0));                 \
+    rb2 = *reinterpret_cast<const uint4*>(qa + 2 * r32 + (k0));             \
+    rb3 = *reinterpret_cast<const uint4*>(qa + 3 * r32 + (k0));             \
+  } while (0)
+#define RVE_SSTORE()                                                         \
+  do {                                                                      \
+    *reinterpret_cast<uint4*>(As + (lr + 0) * TLDA + lc) = ra0;             \
+    *reinterpret_cast<uint4*>(As + (lr + 32) * TLDA + lc) = ra1;            \
+    *reinterpret_cast<uint4*>(As + (lr + 64) * TLDA + lc) = ra2;            \
+    *reinterpret_cast<uint4*>(As + (lr + 96) * TLDA + lc) = ra3;            \
+    *reinterpret_cast<uint4*>(Bs + (lr + 0) * TLDA + lc) = rb0;             \
+    *reinterpret_cast<uint4*>(Bs + (lr + 32) * TLDA + lc) = rb1;            \
+    *reinterpret_cast<uint4*>(Bs + (lr + 64) * TLDA + lc) = rb2;            \
+    *reinterpret_cast<uint4*>(Bs + (lr + 96) * TLDA + lc) = rb3;            \
+  } while (0)
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.f;
+
+  const int frow = lane & 15, fk = (lane >> 4) * 8;
+  RVE_GLOAD(0);
+  RVE_SSTORE();
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += TK) {
+    const bool more = k0 + TK < n;
+    if (more) RVE_GLOAD(k0 + TK);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 32) {
+      v8bf bf[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bf[j] = *reinterpret_cast<const v8bf*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const v8bf af = *reinterpret_cast<const v8bf*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      RVE_SSTORE();
+      __syncthreads();
+    }
+  }
+#undef RVE_GLOAD
+#undef RVE_SSTORE
+
+  float scale = 1.f;
+  if constexpr (EPI == kEpiEinv) scale = (float)real[s >> 1].inv_a0;
+  double dot = 0.0;
+  const int orow = tid >> 2, oc0 = (tid & 3) * 32;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (wn == h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            Cs[(j * 16 + (lane & 15)) * TLDC + wm * 64 + i * 16 + 4 * (lane >> 4) + e] = acc[i][j][e];
+    }
+    __syncthreads();
+    const long long l = (long long)nb * TN + h * 64 + orow;
+    const long long m0 = (long long)mb * TM + oc0;
+    const long long obase = (long long)s * N2 + l * n + m0;
+    float v[32];
+#pragma unroll
+    for (int e = 0; e < 32; e += 4) {
+      const float4 c = *reinterpret_cast<const float4*>(Cs + orow * TLDC + oc0 + e);
+      v[e] = c.x; v[e + 1] = c.y; v[e + 2] = c.z; v[e + 3] = c.w;
+    }
+    if constexpr (EPI == kEpiEinv) {
+#pragma unroll
+      for (int e = 0; e < 32; e += 4) {
+        const float4 g = *reinterpret_cast<const float4*>(einv + l * n + m0 + e);
+        v[e] *= g.x * scale; v[e + 1] *= g.y * scale; v[e + 2] *= g.z * scale; v[e + 3] *= g.w * scale;
+      }
+    }
+    if constexpr (EPI == kEpiZ) {
+      ZT* out = reinterpret_cast<ZT*>(out_v) + obase;
+#pragma unroll
+      for (int e = 0; e < 32; ++e) {
+        const ZT zs = (ZT)v[e];
+        out[e] = zs;
+        dot += (double)zs * rres[obase + e];
+      }
+    } else {
+      __bf16* out = reinterpret_cast<__bf16*>(out_v) + obase;
+#pragma unroll
+      for (int e = 0; e < 32; e += 8) {
+        v8bf pk;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pk[k] = (__bf16)v[e + k];
+        *reinterpret_cast<v8bf*>(out + e) = pk;
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (EPI == kEpiZ) {
+    double d[1] = {dot};
+    block_sum<1>(d, red);
+    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = d[0];
+  }
+}
+
+bool big_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % TM == 0; }
+
+template <class Tr, class ZT>
 void run_precond(const Work& w, const GemmTables& t, hipStream_t st) {
   using op_t = typename Tr::op_t;
   const int n = w.n;
@@ -236,18 +404,40 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st) {
   const void* einv = std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv64 : (const void*)t.einv32;
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
-  // T1 = (R Q)^T
-  hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S, w.sys,
-                     w.real, nullptr, nullptr, nullptr);
+  // T1 = (R Q)^T, from the FP64 residual or from its GEMM-precision copy
+  if (w.rlo)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, (const op_t*)w.rlo, Q, (void*)u1,
+                       n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S,
+                       w.sys, w.real, nullptr, nullptr, nullptr);
   // W = (Q R Q) ./ (a0 E)
   hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
                      w.real, einv, nullptr, nullptr);
   // T3 = (W Q)^T
   hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
                      w.real, nullptr, nullptr, nullptr);
-  // z = Q W Q (FP64), partial sums of r.z
-  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ>), grid, block, 0, st, u1, Q, (void*)w.z, n, w.S, w.sys,
-                     w.real, nullptr, w.r, w.part_rz);
+  // z = Q W Q, partial sums of r.z
+  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+                     nullptr, w.r, w.part_rz);
+}
+
+template <class ZT>
+void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st) {
+  const int n = w.n;
+  const long long T = (long long)w.S * (n / TM) * (n / TN);
+  const dim3 grid((unsigned)T), block(kBlock);
+  const __bf16* Q = reinterpret_cast<const __bf16*>(t.q);
+  __bf16* u1 = reinterpret_cast<__bf16*>(w.u1);
+  __bf16* u2 = reinterpret_cast<__bf16*>(w.u2);
+  hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, Q,
+                     (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((k_hartley_bf16<kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+                     w.real, t.einv32, nullptr, nullptr);
+  hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+                     w.real, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+                     nullptr, w.r, w.part_rz);
 }
 
 }  // namespace
@@ -256,12 +446,23 @@ size_t gemm_elem_size(int prec) {
   return prec == kGemmF64 ? sizeof(double) : prec == kGemmF32 ? sizeof(float) : sizeof(__bf16);
 }
 
-int gemm_tiles_per_system(int n, int /*prec*/) { return (n / BM) * (n / BN); }
+int gemm_tiles_per_system(int n, int prec) {
+  return big_bf16_tiles(n, prec) ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
+}
+
+int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
 
 void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st) {
-  if (prec == kGemmF64) run_precond<TrF64>(w, t, st);
-  else if (prec == kGemmF32) run_precond<TrF32>(w, t, st);
-  else run_precond<TrBF16>(w, t, st);
+  // z is FP64 with FP64 transforms and FP32 in the mixed modes
+  if (prec == kGemmF64) {
+    run_precond<TrF64, double>(w, t, st);
+  } else if (prec == kGemmF32) {
+    run_precond<TrF32, float>(w, t, st);
+  } else if (big_bf16_tiles(w.n, prec)) {
+    run_precond_bf16_big<float>(w, t, st);
+  } else {
+    run_precond<TrBF16, float>(w, t, st);
+  }
 }
 
 }  // namespace rve

@@ -21,6 +21,37 @@ constexpr double kSixth = 1.0 / 6.0;
 constexpr double kThird = 1.0 / 3.0;
 constexpr double kTwoThirds = 2.0 / 3.0;
 
+// Four consecutive elements of a vector in its storage type, widened to or
+// rounded from FP64 (the element index is a multiple of 4).
+template <class T> struct V4;
+template <> struct V4<double> {
+  __device__ static void load(const double* p, double (&v)[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p), b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+  __device__ static void store(double* p, const double (&v)[4]) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+  }
+};
+template <> struct V4<float> {
+  __device__ static void load(const float* p, double (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  __device__ static void store(float* p, const double (&v)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  }
+};
+template <> struct V4<__bf16> {
+  __device__ static void store(__bf16* p, const double (&v)[4]) {
+    struct alignas(8) Pack { __bf16 e[4]; } pk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pk.e[k] = (__bf16)(float)v[k];
+    *reinterpret_cast<Pack*>(p) = pk;
+  }
+};
+
 __global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B,
                                                         int* count, int count_len) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -125,24 +156,30 @@ __global__ void k_scalar_init(SysState* sys, RealState* real, const double* __re
   }
 }
 
-// r <- r - mean(f), x <- 0 (the initial iterate); partial sums of r.r.
+// r <- r - mean(f), x <- 0 (the initial iterate), and in mixed modes the
+// GEMM-precision copy of r; partial sums of r.r.
+template <class LoT, bool LO>
 __global__ void __launch_bounds__(kBlock) k_meansub(double* __restrict__ r, double* __restrict__ x,
-                                                     const SysState* sys, long long N2,
+                                                     LoT* __restrict__ rlo, const SysState* sys, long long N2,
                                                      double* __restrict__ part) {
   __shared__ double sh[4];
   const int s = blockIdx.y;
   const double m = sys[s].mean_f;
-  double* R = r + (long long)s * N2;
-  double* X = x + (long long)s * N2;
+  const long long off = (long long)s * N2;
   double acc[1] = {0.0};
-  const long long stride = (long long)gridDim.x * kBlock * 2;
-  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
-    double2 v = *reinterpret_cast<double2*>(R + i);
-    v.x -= m;
-    v.y -= m;
-    *reinterpret_cast<double2*>(R + i) = v;
-    *reinterpret_cast<double2*>(X + i) = make_double2(0.0, 0.0);
-    acc[0] += v.x * v.x + v.y * v.y;
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double v[4];
+    V4<double>::load(r + off + i, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] -= m;
+      acc[0] += v[k] * v[k];
+    }
+    V4<double>::store(r + off + i, v);
+    V4<double>::store(x + off + i, zero);
+    if constexpr (LO) V4<LoT>::store(rlo + off + i, v);
   }
   block_sum<1>(acc, sh);
   if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = acc[0];
@@ -189,8 +226,8 @@ __device__ inline double q1_apply(double a00, double a01, double a10, double a11
   return v;
 }
 
-template <bool DOT>
-__global__ void __launch_bounds__(kBlock) k_stencil(const double* __restrict__ a, const double* __restrict__ p,
+template <bool DOT, class PT>
+__global__ void __launch_bounds__(kBlock) k_stencil(const double* __restrict__ a, const PT* __restrict__ p,
                                                      double* __restrict__ q, int n, const SysState* sys,
                                                      double* __restrict__ part) {
   __shared__ double sh[4 * 2];
@@ -203,8 +240,8 @@ __global__ void __launch_bounds__(kBlock) k_stencil(const double* __restrict__ a
   const int col = blockIdx.x * kTile + lane, cm = wrap_dec(col, n), cp = wrap_inc(col, n);
   const int row0 = blockIdx.y * kTile + w * kStrip;
   const double* A = a + (long long)b * N2;
-  const double* P0 = p + (long long)s0 * N2;
-  const double* P1 = P0 + N2;
+  const PT* P0 = p + (long long)s0 * N2;
+  const PT* P1 = P0 + N2;
   double* Q0 = q + (long long)s0 * N2;
   double* Q1 = Q0 + N2;
 
@@ -269,12 +306,13 @@ __global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, i
 }
 
 // x += alpha p, r -= alpha q, partial sums of r.r (and of r.z_old for the
-// flexible beta).
+// flexible beta); in mixed modes also the GEMM-precision copy of the new r.
+template <class PT, class ZT, class LoT, bool LO>
 __global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                       const double* __restrict__ p,
-                                                       const double* __restrict__ q,
-                                                       const double* __restrict__ z, const SysState* sys,
-                                                       long long N2, double* __restrict__ part_rr,
+                                                       const PT* __restrict__ p, const double* __restrict__ q,
+                                                       const ZT* __restrict__ z, LoT* __restrict__ rlo,
+                                                       const SysState* sys, long long N2,
+                                                       double* __restrict__ part_rr,
                                                        double* __restrict__ part_rzo, int flexible) {
   __shared__ double sh[4 * 2];
   const int s = blockIdx.y;
@@ -282,22 +320,27 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, do
   const double al = sys[s].alpha;
   const long long off = (long long)s * N2;
   double acc[2] = {0.0, 0.0};
-  const long long stride = (long long)gridDim.x * kBlock * 2;
-  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
-    double2 xv = *reinterpret_cast<const double2*>(x + off + i);
-    double2 rv = *reinterpret_cast<const double2*>(r + off + i);
-    const double2 pv = *reinterpret_cast<const double2*>(p + off + i);
-    const double2 qv = *reinterpret_cast<const double2*>(q + off + i);
-    xv.x = fma(al, pv.x, xv.x);
-    xv.y = fma(al, pv.y, xv.y);
-    rv.x = fma(-al, qv.x, rv.x);
-    rv.y = fma(-al, qv.y, rv.y);
-    *reinterpret_cast<double2*>(x + off + i) = xv;
-    *reinterpret_cast<double2*>(r + off + i) = rv;
-    acc[0] += rv.x * rv.x + rv.y * rv.y;
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double xv[4], rv[4], pv[4], qv[4];
+    V4<double>::load(x + off + i, xv);
+    V4<double>::load(r + off + i, rv);
+    V4<PT>::load(p + off + i, pv);
+    V4<double>::load(q + off + i, qv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = fma(al, pv[k], xv[k]);
+      rv[k] = fma(-al, qv[k], rv[k]);
+      acc[0] += rv[k] * rv[k];
+    }
+    V4<double>::store(x + off + i, xv);
+    V4<double>::store(r + off + i, rv);
+    if constexpr (LO) V4<LoT>::store(rlo + off + i, rv);
     if (flexible) {
-      const double2 zv = *reinterpret_cast<const double2*>(z + off + i);
-      acc[1] += rv.x * zv.x + rv.y * zv.y;
+      double zv[4];
+      V4<ZT>::load(z + off + i, zv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[1] += rv[k] * zv[k];
     }
   }
   block_sum<2>(acc, sh);
@@ -355,24 +398,51 @@ __global__ void k_scalar_beta(SysState* sys, const double* __restrict__ part_rz,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_update_p(double* __restrict__ p, const double* __restrict__ z,
+// rlo = r rounded to the GEMM precision (for applying the preconditioner to a
+// caller's residual outside the solver).
+template <class LoT>
+__global__ void __launch_bounds__(kBlock) k_round_lo(const double* __restrict__ r, LoT* __restrict__ rlo,
+                                                      long long total) {
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < total; i += stride) {
+    double v[4];
+    V4<double>::load(r + i, v);
+    V4<LoT>::store(rlo + i, v);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_widen(const float* __restrict__ in, double* __restrict__ out,
+                                                   long long total) {
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < total; i += stride) {
+    double v[4];
+    V4<float>::load(in + i, v);
+    V4<double>::store(out + i, v);
+  }
+}
+
+// p = z + beta p (p = z on the first direction), computed in FP64 and stored
+// in the direction's storage type.
+template <class PT, class ZT>
+__global__ void __launch_bounds__(kBlock) k_update_p(PT* __restrict__ p, const ZT* __restrict__ z,
                                                       const SysState* sys, long long N2, int first) {
   const int s = blockIdx.y;
   if (!sys[s].active) return;
   const double be = sys[s].beta;
   const long long off = (long long)s * N2;
-  const long long stride = (long long)gridDim.x * kBlock * 2;
-  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 2; i < N2; i += stride) {
-    const double2 zv = *reinterpret_cast<const double2*>(z + off + i);
-    double2 pv;
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double zv[4], pv[4];
+    V4<ZT>::load(z + off + i, zv);
     if (first) {
-      pv = zv;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pv[k] = zv[k];
     } else {
-      pv = *reinterpret_cast<const double2*>(p + off + i);
-      pv.x = fma(be, pv.x, zv.x);
-      pv.y = fma(be, pv.y, zv.y);
+      V4<PT>::load(p + off + i, pv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pv[k] = fma(be, pv[k], zv[k]);
     }
-    *reinterpret_cast<double2*>(p + off + i) = pv;
+    V4<PT>::store(p + off + i, pv);
   }
 }
 
@@ -608,7 +678,7 @@ __global__ void __launch_bounds__(kBlock) k_stats(const double* __restrict__ A, 
 }
 
 inline int vec_blocks(long long N2) {
-  long long nb = (N2 + 2LL * kBlock * 2 - 1) / (2LL * kBlock * 2);
+  long long nb = (N2 + 4LL * kBlock - 1) / (4LL * kBlock);
   if (nb > 256) nb = 256;
   if (nb < 1) nb = 1;
   return (int)nb;
@@ -636,7 +706,16 @@ void launch_scalar_init(const Work& w, hipStream_t st) {
 }
 
 void launch_meansub(const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_meansub, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.r, w.x, w.sys, w.N2, w.part_rr);
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_meansub<double, false>), g, blk, 0, st, w.r, w.x, (double*)nullptr, w.sys, w.N2,
+                       w.part_rr);
+  else if (w.mixed == 1)
+    hipLaunchKernelGGL((k_meansub<float, true>), g, blk, 0, st, w.r, w.x, (float*)w.rlo, w.sys, w.N2,
+                       w.part_rr);
+  else
+    hipLaunchKernelGGL((k_meansub<__bf16, true>), g, blk, 0, st, w.r, w.x, (__bf16*)w.rlo, w.sys, w.N2,
+                       w.part_rr);
 }
 
 void launch_scalar_fnorm(const Work& w, hipStream_t st) {
@@ -645,13 +724,18 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st) {
 
 void launch_stencil_dot(const Work& w, hipStream_t st) {
   dim3 g(w.n / kTile, w.n / kTile, w.B);
-  hipLaunchKernelGGL(k_stencil<true>, g, dim3(kBlock), 0, st, w.a, w.p, w.q, w.n, w.sys, w.part_pq);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_stencil<true, double>), g, dim3(kBlock), 0, st, w.a, (const double*)w.p, w.q, w.n,
+                       w.sys, w.part_pq);
+  else
+    hipLaunchKernelGGL((k_stencil<true, float>), g, dim3(kBlock), 0, st, w.a, (const float*)w.p, w.q, w.n,
+                       w.sys, w.part_pq);
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
   dim3 g(n / kTile, n / kTile, B);
-  hipLaunchKernelGGL(k_stencil<false>, g, dim3(kBlock), 0, st, a, u, out, n, (const SysState*)nullptr,
-                     (double*)nullptr);
+  hipLaunchKernelGGL((k_stencil<false, double>), g, dim3(kBlock), 0, st, a, u, out, n,
+                     (const SysState*)nullptr, (double*)nullptr);
 }
 
 void launch_scalar_alpha(const Work& w, hipStream_t st) {
@@ -659,8 +743,17 @@ void launch_scalar_alpha(const Work& w, hipStream_t st) {
 }
 
 void launch_update_xr(const Work& w, int flexible, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_xr, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.x, w.r, w.p, w.q, w.z, w.sys,
-                     w.N2, w.part_rr, w.part_rzo, flexible);
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_update_xr<double, double, double, false>), g, blk, 0, st, w.x, w.r,
+                       (const double*)w.p, w.q, (const double*)w.z, (double*)nullptr, w.sys, w.N2, w.part_rr,
+                       w.part_rzo, flexible);
+  else if (w.mixed == 1)
+    hipLaunchKernelGGL((k_update_xr<float, float, float, true>), g, blk, 0, st, w.x, w.r, (const float*)w.p,
+                       w.q, (const float*)w.z, (float*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+  else
+    hipLaunchKernelGGL((k_update_xr<float, float, __bf16, true>), g, blk, 0, st, w.x, w.r, (const float*)w.p,
+                       w.q, (const float*)w.z, (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
 }
 
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st) {
@@ -673,8 +766,31 @@ void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) 
                      w.P_vec, flexible, first);
 }
 
+void launch_round_lo(const Work& w, hipStream_t st) {
+  const long long total = (long long)w.S * w.N2;
+  long long nb = (total + 4LL * kBlock - 1) / (4LL * kBlock);
+  if (nb > 4096) nb = 4096;
+  if (w.mixed == 1)
+    hipLaunchKernelGGL((k_round_lo<float>), dim3((unsigned)nb), dim3(kBlock), 0, st, w.r, (float*)w.rlo, total);
+  else if (w.mixed == 2)
+    hipLaunchKernelGGL((k_round_lo<__bf16>), dim3((unsigned)nb), dim3(kBlock), 0, st, w.r, (__bf16*)w.rlo,
+                       total);
+}
+
+void launch_widen(const float* in, double* out, long long total, hipStream_t st) {
+  long long nb = (total + 4LL * kBlock - 1) / (4LL * kBlock);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, total);
+}
+
 void launch_update_p(const Work& w, int first, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_p, dim3(w.P_vec, w.S), dim3(kBlock), 0, st, w.p, w.z, w.sys, w.N2, first);
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_update_p<double, double>), g, blk, 0, st, (double*)w.p, (const double*)w.z, w.sys,
+                       w.N2, first);
+  else
+    hipLaunchKernelGGL((k_update_p<float, float>), g, blk, 0, st, (float*)w.p, (const float*)w.z, w.sys, w.N2,
+                       first);
 }
 
 void launch_ahom(const Work& w, hipStream_t st) {

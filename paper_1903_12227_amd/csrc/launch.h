@@ -17,11 +17,17 @@ struct Work {
   const double* a = nullptr; // [B][n][n] cells
   double* x = nullptr;       // [S][n][n] iterate (grid units)
   double* r = nullptr;       // residual
-  double* p = nullptr;       // search direction
+  // Search direction p and preconditioned residual z are FP64 when the
+  // transform GEMMs are FP64 and FP32 otherwise (mixed modes); they only
+  // steer the iteration, while x, r and q = A p stay FP64, so r = f - A x
+  // holds to FP64 rounding in every mode.
+  void* p = nullptr;
   double* q = nullptr;       // A p
-  double* z = nullptr;       // preconditioned residual
+  void* z = nullptr;
+  void* rlo = nullptr;       // mixed modes: r rounded to the GEMM type, the first GEMM's input
   void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
   void* u2 = nullptr;
+  int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
   double* part_pq = nullptr;   // [S][P] partial sums of p.Ap
@@ -49,6 +55,8 @@ void launch_update_xr(const Work& w, int flexible, hipStream_t st);
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
 void launch_update_p(const Work& w, int first, hipStream_t st);
+void launch_round_lo(const Work& w, hipStream_t st);
+void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
 void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st);
@@ -70,7 +78,10 @@ struct GemmTables {
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.
+// In the mixed modes the first transform reads w.rlo, which must hold r in
+// the GEMM precision; w.P_gemm must equal gemm_tiles_per_system(n, prec).
 void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st);
 int gemm_tiles_per_system(int n, int prec);
+int gemm_tiles_per_system_max(int n);
 
 }  // namespace rve

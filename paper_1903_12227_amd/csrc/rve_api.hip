@@ -141,7 +141,7 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
 
 // Carve the workspace of one equal-n batch; grows the arena if needed.
 struct Layout {
-  size_t off_x, off_r, off_p, off_q, off_z, off_u1, off_u2, off_sys, off_real;
+  size_t off_x, off_r, off_p, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_count, off_status, total;
 };
 
@@ -153,15 +153,18 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
   const int P_vec = (int)vb;
-  const int P_gemm = gemm_tiles_per_system(n, prec);
+  const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  const int P_gemm = gemm_tiles_per_system(n, gp);
   const size_t vec = align_up((size_t)(S * N2) * 8);
-  const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(prec));
+  const size_t pzvec = align_up((size_t)(S * N2) * (prec == RVE_FP64 ? 8 : 4));
+  const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(gp));
   size_t o = 0;
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
-  L.off_p = o; o += vec;
+  L.off_p = o; o += pzvec;
   L.off_q = o; o += vec;
-  L.off_z = o; o += vec;
+  L.off_z = o; o += pzvec;
+  L.off_rlo = o; o += prec == RVE_FP64 ? 0 : uvec;
   L.off_u1 = o; o += uvec;
   L.off_u2 = o; o += uvec;
   L.off_sys = o; o += align_up(S * sizeof(SysState));
@@ -169,7 +172,7 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   L.off_pq = o; o += align_up(S * P_tile * 8);
   L.off_rr = o; o += align_up(S * P_vec * 8);
   L.off_rzo = o; o += align_up(S * P_vec * 8);
-  L.off_rz = o; o += align_up(S * P_gemm * 8);
+  L.off_rz = o; o += align_up(S * gemm_tiles_per_system_max(n) * 8);
   L.off_misc = o; o += align_up((size_t)B * P_tile * kMiscNV * 8);
   L.off_count = o; o += align_up((size_t)(maxit + 2) * sizeof(int));
   L.off_status = o; o += align_up((size_t)B * sizeof(int));
@@ -181,6 +184,7 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   w->P_tile = P_tile;
   w->P_vec = P_vec;
   w->P_gemm = P_gemm;
+  w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
   return L;
 }
 
@@ -204,9 +208,10 @@ void bind(rve_ctx* ctx, const Layout& L, Work* w) {
   char* base = static_cast<char*>(ctx->ws);
   w->x = reinterpret_cast<double*>(base + L.off_x);
   w->r = reinterpret_cast<double*>(base + L.off_r);
-  w->p = reinterpret_cast<double*>(base + L.off_p);
+  w->p = base + L.off_p;
   w->q = reinterpret_cast<double*>(base + L.off_q);
-  w->z = reinterpret_cast<double*>(base + L.off_z);
+  w->z = base + L.off_z;
+  w->rlo = w->mixed ? base + L.off_rlo : nullptr;
   w->u1 = base + L.off_u1;
   w->u2 = base + L.off_u2;
   w->sys = reinterpret_cast<SysState*>(base + L.off_sys);
@@ -585,9 +590,13 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   gt.einv64 = tb->einv64;
   gt.einv32 = tb->einv32;
   w.r = const_cast<double*>(r_dev);
-  w.z = z_dev;
   w.sys = nullptr;
+  if (w.mixed) launch_round_lo(w, c->stream);
+  // the solver keeps z in FP32 in the mixed modes; the caller wants FP64
+  void* z_solver = w.z;
+  w.z = w.mixed ? z_solver : (void*)z_dev;
   launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
+  if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
 }

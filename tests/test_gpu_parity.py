@@ -107,10 +107,11 @@ def test_constant_field_and_laminate(dev):
     assert abs(A[1, 0, 1]) <= 1e-12 and abs(A[2, 0, 1]) <= 1e-12
 
 
+@pytest.mark.parametrize("n", [128, 192])
 @pytest.mark.parametrize("prec", [1, 2])
-def test_mixed_precision_matches_oracle(dev, prec):
+def test_mixed_precision_matches_oracle(dev, prec, n):
     rve = _rve()
-    n, B = 128, 3
+    B = 3
     a = _fields(n, B, 4)
     res = rve.solve_batch(_to(a, dev), 1.0 / 8, rve.Options(tol=1e-10, prec=prec))
     assert res.code == 0
