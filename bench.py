@@ -74,24 +74,26 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
 def bytes_per_node(prec_name, flexible):
     """Algorithmic HBM bytes per node of each kernel class.
 
-    FP64 path: every vector FP64. Mixed paths: p and z are stored in FP32 and
-    the residual has a copy in the GEMM precision (s_g bytes) that the first
-    transform reads; x, r, q stay FP64.
-      stencil   (per realization, both systems): read p x2, write q x2, read a
-      update_xr (per system): read x, r, p, q [+ z for flexible beta], write x, r [+ r copy]
-      update_p  (per system): read z, p, write p
-      precond   (per system, four transforms): read r (copy), write/read three
-                intermediates, write z, re-read r (FP64) for r.z
+    FP64 path: every vector FP64. Mixed paths: the directions p and z are
+    stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
+    precision (s_g bytes) that the first transform reads; x, r, q stay FP64.
+      stencil   fused direction step + operator apply, per realization (both
+                systems): read z, p_old, x; write p_new, x, q; read a
+      update_r  per system: read r, q [+ z for flexible beta]; write r [+ r copy]
+      precond   per system, four transforms: read the r copy (FP64 r on the
+                FP64 path), write/read three intermediates, write z, re-read r
+                (FP64) for r.z
+      finalize  per system, once per solve: x += alpha p
     """
     sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": 2 * sp + 2 * 8 + 8,
-        "update_xr": 8 + 8 + sp + 8 + (sp if flexible else 0) + 8 + 8 + lo,
-        "update_p": 3 * sp,
+        "stencil": 2 * (sp + sp + 16 + sp + 8) + 8,
+        "update_r": 8 + 8 + 8 + lo + (sp if flexible else 0),
         "precond": first_in + 6 * sg + sp + 8,
+        "finalize": 8 + sp + 8,
     }
 
 
@@ -110,12 +112,9 @@ def roofline_entries(tim, it_all, n, B, prec_name, flexible):
     ms, cnt = tim["stencil"]
     out["stencil"] = {"bound": "hbm", "bytes": stencil_applies * bpn["stencil"] * N2, "ms": ms,
                       "launches": cnt, "bytes_per_node": bpn["stencil"]}
-    ms, cnt = tim["update_xr"]
-    out["update_xr"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_xr"] * N2, "ms": ms,
-                        "launches": cnt, "bytes_per_node": bpn["update_xr"]}
-    ms, cnt = tim["update_p"]
-    out["update_p"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_p"] * N2, "ms": ms,
-                       "launches": cnt, "bytes_per_node": bpn["update_p"]}
+    ms, cnt = tim["update_r"]
+    out["update_r"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_r"] * N2, "ms": ms,
+                       "launches": cnt, "bytes_per_node": bpn["update_r"]}
     ms, cnt = tim["precond"]
     # four transforms of 2 n^3 flops each per system-apply
     out["precond"] = {"bound": "mfma", "flops": sys_iters * 8.0 * n * N2,
@@ -195,7 +194,7 @@ def main():
     v_plain = args.plain / (time.perf_counter() - t0)
 
     # roofline of the dominant kernel class of the headline leg
-    ent = roofline_entries(tim_mix, it_mix_t, n, B, "bf16", flexible=True)
+    ent = roofline_entries(tim_mix, it_mix_t, n, B, "bf16", flexible=False)
     dom = max(ent, key=lambda k: ent[k]["ms"])
     e = ent[dom]
     if e["bound"] == "hbm" or dom != "precond":
@@ -234,6 +233,7 @@ def main():
                    "L": L, "n": n, "batch": B, "contrast": args.contrast, "tol": args.tol,
                    "precision": "mixed-bf16"},
         "iters_mean": float(it_mix.mean()),
+        "tuned": ctx.tuned(n, rve.MIX_BF16, B),
         "fp64_batched": {"value": v64, "ms_per_step": 1e3 * t64 / args.fp64_steps,
                          "iters_mean": float(it64.mean()), "gemm_TFLOPs": fp64_gemm_tfs},
         "plain_fp64_per_realization": {"value": v_plain, "realizations": args.plain},

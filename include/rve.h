@@ -74,7 +74,7 @@ typedef struct rve_opts {
   int maxit;         /* maximum PCG iterations per system, >= 1 */
   int prec;          /* enum rve_precision */
   int flexible;      /* 1: flexible (Polak-Ribiere) beta; 0: standard beta.
-                        Negative: automatic (flexible unless prec == RVE_FP64). */
+                        Negative: automatic (standard). */
   int check_every;   /* host polls the all-converged flag every this many
                         iterations; <= 0 selects a default */
 } rve_opts;
@@ -182,13 +182,31 @@ int rve_apply_precond(rve_ctx* ctx, int B, int n, const double* a_dev, const dou
 /* Static string for a status code. */
 const char* rve_status_string(int status);
 
+/*
+ * Autotuner. With mode 1 (the default), the first solve of each
+ * (n, precision, floor(log2 B)) times the candidate kernel variants on the
+ * live data and keeps the fastest: the number of grid columns per lane of
+ * the operator apply (1, 2 or 4) and the transform-GEMM tile (64 x 64, or
+ * 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
+ * and, if the environment variable RVE_TUNE_CACHE names a file, appended
+ * there as JSON lines and read back by rve_create. Mode 0 uses fixed
+ * defaults. Results do not depend on the choice beyond rounding order.
+ *
+ * rve_get_tuned: *choice for kind 0 (columns per lane) or 1 (GEMM variant)
+ * of a shape, or -1 with return value RVE_NOT_CONVERGED if not tuned yet.
+ */
+int rve_set_autotune(rve_ctx* ctx, int mode);
+int rve_get_tuned(rve_ctx* ctx, int kind, int n, int prec, int B, int* choice);
+
 /* Event timing of kernel classes on the context's stream. rve_set_timing
  * turns recording on (1) or off (0) and clears the accumulators; while it is
  * on, every launch of a class is bracketed by HIP events.
  * rve_last_timing returns the totals since the last rve_set_timing in
- * out_ms[4] and out_counts[4]: [0] stencil applies (one kernel launch each),
- * [1] preconditioner applies (four transform GEMM launches each), [2] x/r
- * updates, [3] search-direction updates; counts are bracketed applies. */
+ * out_ms[4] and out_counts[4]: [0] operator applies fused with the
+ * search-direction and iterate updates (one kernel launch each),
+ * [1] preconditioner applies (four transform GEMM launches each),
+ * [2] residual updates, [3] final iterate updates (one per solve); counts
+ * are bracketed applies. */
 int rve_set_timing(rve_ctx* ctx, int enable);
 int rve_last_timing(rve_ctx* ctx, double* out_ms, long long* out_counts);
 

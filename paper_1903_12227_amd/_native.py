@@ -16,7 +16,7 @@ EXPORTS = (
     "rve_default_opts", "rve_create", "rve_destroy", "rve_set_stream",
     "rve_solve_batch", "rve_solve_uneven", "rve_grad", "rve_stats",
     "rve_status_string", "rve_set_timing", "rve_last_timing",
-    "rve_apply_operator", "rve_apply_precond",
+    "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
 )
 
 
@@ -50,6 +50,8 @@ def _declare(lib):
     lib.rve_last_timing.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)]
     lib.rve_apply_operator.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
     lib.rve_apply_precond.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
+    lib.rve_set_autotune.argtypes = [_vp, _i]
+    lib.rve_get_tuned.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(_i)]
     for name in EXPORTS:
         if name not in ("rve_default_opts", "rve_status_string"):
             getattr(lib, name).restype = _i

@@ -66,12 +66,26 @@ class Context:
 
     def timing(self):
         """Accumulated event timing since set_timing(True): dict of class ->
-        (total ms, applies) for 'stencil', 'precond' (four GEMM launches per
-        apply), 'update_xr', 'update_p'."""
+        (total ms, applies) for 'stencil' (fused direction step and operator
+        apply), 'precond' (four GEMM launches per apply), 'update_r',
+        'finalize' (last x update, once per solve)."""
         ms = (ctypes.c_double * 4)()
         cnt = (ctypes.c_longlong * 4)()
         N.check(self._lib.rve_last_timing(self.handle, ms, cnt), "rve_last_timing")
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(("stencil", "precond", "update_xr", "update_p"))}
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(("stencil", "precond", "update_r", "finalize"))}
+
+    def set_autotune(self, enable: bool):
+        N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
+
+    def tuned(self, n: int, prec: int, B: int) -> dict:
+        """The autotuner's choices for a shape: columns per lane of the
+        operator apply and the transform-GEMM tile variant (-1: not tuned)."""
+        out = {}
+        for kind, name in ((0, "stencil_columns_per_lane"), (1, "gemm_variant")):
+            c = ctypes.c_int(-1)
+            self._lib.rve_get_tuned(self.handle, kind, int(n), int(prec), int(B), ctypes.byref(c))
+            out[name] = c.value
+        return out
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -446,8 +446,12 @@ size_t gemm_elem_size(int prec) {
   return prec == kGemmF64 ? sizeof(double) : prec == kGemmF32 ? sizeof(float) : sizeof(__bf16);
 }
 
-int gemm_tiles_per_system(int n, int prec) {
-  return big_bf16_tiles(n, prec) ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
+bool gemm_variant_valid(int n, int prec, int variant) {
+  return variant == 0 || (variant == 1 && big_bf16_tiles(n, prec));
+}
+
+int gemm_tiles_per_system(int n, int prec, int variant) {
+  return variant == 1 ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
 }
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
@@ -458,7 +462,7 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond<TrF64, double>(w, t, st);
   } else if (prec == kGemmF32) {
     run_precond<TrF32, float>(w, t, st);
-  } else if (big_bf16_tiles(w.n, prec)) {
+  } else if (w.gemm_variant == 1) {
     run_precond_bf16_big<float>(w, t, st);
   } else {
     run_precond<TrBF16, float>(w, t, st);

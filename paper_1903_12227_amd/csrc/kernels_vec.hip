@@ -226,57 +226,176 @@ __device__ inline double q1_apply(double a00, double a01, double a10, double a11
   return v;
 }
 
-template <bool DOT, class PT>
-__global__ void __launch_bounds__(kBlock) k_stencil(const double* __restrict__ a, const PT* __restrict__ p,
-                                                     double* __restrict__ q, int n, const SysState* sys,
-                                                     double* __restrict__ part) {
+// V consecutive elements of a row, widened to FP64 / rounded from FP64.
+template <class T, int V> struct VecIO;
+template <int V> struct VecIO<double, V> {
+  __device__ static void load(const double* p, double* v) {
+    if constexpr (V == 1) {
+      v[0] = p[0];
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; k += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(p + k);
+        v[k] = t.x; v[k + 1] = t.y;
+      }
+    }
+  }
+  __device__ static void store(double* p, const double* v) {
+    if constexpr (V == 1) {
+      p[0] = v[0];
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; k += 2) *reinterpret_cast<double2*>(p + k) = make_double2(v[k], v[k + 1]);
+    }
+  }
+};
+template <int V> struct VecIO<float, V> {
+  __device__ static void load(const float* p, double* v) {
+    if constexpr (V == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (V == 2) {
+      const float2 t = *reinterpret_cast<const float2*>(p);
+      v[0] = t.x; v[1] = t.y;
+    } else {
+      v[0] = p[0];
+    }
+  }
+  __device__ static void store(float* p, const double* v) {
+    if constexpr (V == 4) {
+      *reinterpret_cast<float4*>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    } else if constexpr (V == 2) {
+      *reinterpret_cast<float2*>(p) = make_float2((float)v[0], (float)v[1]);
+    } else {
+      p[0] = (float)v[0];
+    }
+  }
+};
+
+// Operator apply over V consecutive columns per lane (a 64V x 64 tile per
+// workgroup, each wave sliding down a 16-row strip), for both systems of a
+// realization. FUSED: the operand is the new search direction
+// p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on the fly for the V
+// nodes and their neighbours; p_k goes to a buffer different from p_{k-1}
+// (neighbouring workgroups still read p_{k-1} at tile edges), the deferred
+// update x += alpha_{k-1} p_{k-1} is applied, and q = A p_k is written with
+// partial sums of p_k.q (active systems only). Not FUSED: q = A u for a
+// caller's u (the plain operator apply).
+template <bool FUSED, class PT, class ZT, int V>
+__global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a,
+                                                       const PT* __restrict__ p_old, PT* __restrict__ p_new,
+                                                       const ZT* __restrict__ z, double* __restrict__ x,
+                                                       double* __restrict__ q, int n, const SysState* sys,
+                                                       double* __restrict__ part, int first) {
   __shared__ double sh[4 * 2];
   const int b = blockIdx.z;
   const int s0 = 2 * b, s1 = s0 + 1;
-  const int act0 = DOT ? sys[s0].active : 1, act1 = DOT ? sys[s1].active : 1;
+  const int act0 = FUSED ? sys[s0].active : 1, act1 = FUSED ? sys[s1].active : 1;
   if (!act0 && !act1) return;   // uniform over the workgroup
+  const double be[2] = {FUSED && !first ? sys[s0].beta : 0.0, FUSED && !first ? sys[s1].beta : 0.0};
+  const double al[2] = {FUSED && !first ? sys[s0].alpha : 0.0, FUSED && !first ? sys[s1].alpha : 0.0};
+  const int act[2] = {act0, act1};
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long N2 = (long long)n * n;
-  const int col = blockIdx.x * kTile + lane, cm = wrap_dec(col, n), cp = wrap_inc(col, n);
+  const int c0 = (blockIdx.x * kWave + lane) * V;
+  const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = blockIdx.y * kTile + w * kStrip;
   const double* A = a + (long long)b * N2;
-  const PT* P0 = p + (long long)s0 * N2;
-  const PT* P1 = P0 + N2;
-  double* Q0 = q + (long long)s0 * N2;
-  double* Q1 = Q0 + N2;
+  const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
+  const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
+
+  // operand row (V + 2 values: column c0-1, c0..c0+V-1, c0+V) of system i at row offset o;
+  // the previous direction at the V centre columns is kept in pc (for the x update)
+  auto load_row = [&](int i, long long o, double* u, double* pc) {
+    double pv[V + 2];
+    VecIO<PT, V>::load(Pold[i] + o + c0, pv + 1);
+    if (!FUSED || !first) {
+      pv[0] = (double)Pold[i][o + cl];
+      pv[V + 1] = (double)Pold[i][o + cr];
+    }
+    if constexpr (FUSED) {
+      double zv[V + 2];
+      VecIO<ZT, V>::load(Zs[i] + o + c0, zv + 1);
+      zv[0] = (double)Zs[i][o + cl];
+      zv[V + 1] = (double)Zs[i][o + cr];
+#pragma unroll
+      for (int k = 0; k < V; ++k) pc[k] = first ? 0.0 : pv[k + 1];
+#pragma unroll
+      for (int k = 0; k < V + 2; ++k) u[k] = first ? zv[k] : fma(be[i], pv[k], zv[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < V + 2; ++k) u[k] = pv[k];
+    }
+  };
 
   const int rm = wrap_dec(row0, n);
-  double um0[3], uc0[3], up0[3], um1[3], uc1[3], up1[3];
+  double um[2][V + 2], uc[2][V + 2], up[2][V + 2];
+  double pcur[2][V], pnxt[2][V], pdummy[V];
   {
     const long long om = (long long)rm * n, oc = (long long)row0 * n;
-    um0[0] = P0[om + cm]; um0[1] = P0[om + col]; um0[2] = P0[om + cp];
-    uc0[0] = P0[oc + cm]; uc0[1] = P0[oc + col]; uc0[2] = P0[oc + cp];
-    um1[0] = P1[om + cm]; um1[1] = P1[om + col]; um1[2] = P1[om + cp];
-    uc1[0] = P1[oc + cm]; uc1[1] = P1[oc + col]; uc1[2] = P1[oc + cp];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      load_row(i, om, um[i], pdummy);
+      load_row(i, oc, uc[i], pcur[i]);
+    }
   }
-  double a00 = A[(long long)rm * n + cm], a01 = A[(long long)rm * n + col];
+  double am[V + 1];   // a[row-1][c0-1 .. c0+V-1]
+  {
+    const long long om = (long long)rm * n;
+    am[0] = A[om + cl];
+    VecIO<double, V>::load(A + om + c0, am + 1);
+  }
   double d[2] = {0.0, 0.0};
   for (int j = 0; j < kStrip; ++j) {
     const int row = row0 + j;
     const long long op = (long long)wrap_inc(row, n) * n, oc = (long long)row * n;
-    up0[0] = P0[op + cm]; up0[1] = P0[op + col]; up0[2] = P0[op + cp];
-    up1[0] = P1[op + cm]; up1[1] = P1[op + col]; up1[2] = P1[op + cp];
-    const double a10 = A[oc + cm], a11 = A[oc + col];
-    const double v0 = q1_apply(a00, a01, a10, a11, um0, uc0, up0);
-    const double v1 = q1_apply(a00, a01, a10, a11, um1, uc1, up1);
-    if (act0) Q0[oc + col] = v0;
-    if (act1) Q1[oc + col] = v1;
-    d[0] += uc0[1] * v0;
-    d[1] += uc1[1] * v1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      um0[k] = uc0[k]; uc0[k] = up0[k];
-      um1[k] = uc1[k]; uc1[k] = up1[k];
+    for (int i = 0; i < 2; ++i) load_row(i, op, up[i], pnxt[i]);
+    double ac[V + 1];
+    ac[0] = A[oc + cl];
+    VecIO<double, V>::load(A + oc + c0, ac + 1);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      double qv[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const double sm[3] = {um[i][k], um[i][k + 1], um[i][k + 2]};
+        const double sc[3] = {uc[i][k], uc[i][k + 1], uc[i][k + 2]};
+        const double sp[3] = {up[i][k], up[i][k + 1], up[i][k + 2]};
+        qv[k] = q1_apply(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
+      }
+      if (act[i]) {
+        double* Q = q + (long long)(s0 + i) * N2 + oc + c0;
+        VecIO<double, V>::store(Q, qv);
+        if constexpr (FUSED) {
+          double pn[V];
+#pragma unroll
+          for (int k = 0; k < V; ++k) pn[k] = uc[i][k + 1];
+          VecIO<PT, V>::store(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
+          if (!first) {
+            double* X = x + (long long)(s0 + i) * N2 + oc + c0;
+            double xv[V];
+            VecIO<double, V>::load(X, xv);
+#pragma unroll
+            for (int k = 0; k < V; ++k) xv[k] = fma(al[i], pcur[i][k], xv[k]);
+            VecIO<double, V>::store(X, xv);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) d[i] += (double)(PT)uc[i][k + 1] * qv[k];
+#pragma unroll
+      for (int k = 0; k < V + 2; ++k) {
+        um[i][k] = uc[i][k];
+        uc[i][k] = up[i][k];
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) pcur[i][k] = pnxt[i][k];
     }
-    a00 = a10;
-    a01 = a11;
+#pragma unroll
+    for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
   }
-  if (DOT) {
+  if constexpr (FUSED) {
     block_sum<2>(d, sh);
     if (threadIdx.x == 0) {
       const int P = gridDim.x * gridDim.y;
@@ -305,15 +424,15 @@ __global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, i
   }
 }
 
-// x += alpha p, r -= alpha q, partial sums of r.r (and of r.z_old for the
-// flexible beta); in mixed modes also the GEMM-precision copy of the new r.
-template <class PT, class ZT, class LoT, bool LO>
-__global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                       const PT* __restrict__ p, const double* __restrict__ q,
-                                                       const ZT* __restrict__ z, LoT* __restrict__ rlo,
-                                                       const SysState* sys, long long N2,
-                                                       double* __restrict__ part_rr,
-                                                       double* __restrict__ part_rzo, int flexible) {
+// r -= alpha q, partial sums of r.r (and of r.z for the flexible beta); in
+// mixed modes also the GEMM-precision copy of the new r. (Used with the fused
+// stencil, which applies the x update.)
+template <class ZT, class LoT, bool LO>
+__global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, const double* __restrict__ q,
+                                                      const ZT* __restrict__ z, LoT* __restrict__ rlo,
+                                                      const SysState* sys, long long N2,
+                                                      double* __restrict__ part_rr,
+                                                      double* __restrict__ part_rzo, int flexible) {
   __shared__ double sh[4 * 2];
   const int s = blockIdx.y;
   if (!sys[s].active) return;
@@ -322,18 +441,14 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, do
   double acc[2] = {0.0, 0.0};
   const long long stride = (long long)gridDim.x * kBlock * 4;
   for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
-    double xv[4], rv[4], pv[4], qv[4];
-    V4<double>::load(x + off + i, xv);
+    double rv[4], qv[4];
     V4<double>::load(r + off + i, rv);
-    V4<PT>::load(p + off + i, pv);
     V4<double>::load(q + off + i, qv);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      xv[k] = fma(al, pv[k], xv[k]);
       rv[k] = fma(-al, qv[k], rv[k]);
       acc[0] += rv[k] * rv[k];
     }
-    V4<double>::store(x + off + i, xv);
     V4<double>::store(r + off + i, rv);
     if constexpr (LO) V4<LoT>::store(rlo + off + i, rv);
     if (flexible) {
@@ -347,6 +462,30 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(double* __restrict__ x, do
   if (threadIdx.x == 0) {
     part_rr[(long long)s * gridDim.x + blockIdx.x] = acc[0];
     part_rzo[(long long)s * gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// x += alpha p with each system's last step: the direction of its last
+// iteration sits in buffer (iters - 1) mod 2. Systems that never iterated
+// have alpha = 0.
+template <class PT>
+__global__ void __launch_bounds__(kBlock) k_finalize_x(double* __restrict__ x, const PT* __restrict__ p0,
+                                                        const PT* __restrict__ p1, const SysState* sys,
+                                                        long long N2) {
+  const int s = blockIdx.y;
+  const int it = sys[s].iters;
+  const double al = sys[s].alpha;
+  if (it <= 0 || al == 0.0) return;
+  const PT* P = ((it - 1) & 1) ? p1 : p0;
+  const long long off = (long long)s * N2;
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double xv[4], pv[4];
+    V4<double>::load(x + off + i, xv);
+    V4<PT>::load(P + off + i, pv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xv[k] = fma(al, pv[k], xv[k]);
+    V4<double>::store(x + off + i, xv);
   }
 }
 
@@ -418,31 +557,6 @@ __global__ void __launch_bounds__(kBlock) k_widen(const float* __restrict__ in, 
     double v[4];
     V4<float>::load(in + i, v);
     V4<double>::store(out + i, v);
-  }
-}
-
-// p = z + beta p (p = z on the first direction), computed in FP64 and stored
-// in the direction's storage type.
-template <class PT, class ZT>
-__global__ void __launch_bounds__(kBlock) k_update_p(PT* __restrict__ p, const ZT* __restrict__ z,
-                                                      const SysState* sys, long long N2, int first) {
-  const int s = blockIdx.y;
-  if (!sys[s].active) return;
-  const double be = sys[s].beta;
-  const long long off = (long long)s * N2;
-  const long long stride = (long long)gridDim.x * kBlock * 4;
-  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
-    double zv[4], pv[4];
-    V4<ZT>::load(z + off + i, zv);
-    if (first) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pv[k] = zv[k];
-    } else {
-      V4<PT>::load(p + off + i, pv);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pv[k] = fma(be, pv[k], zv[k]);
-    }
-    V4<PT>::store(p + off + i, pv);
   }
 }
 
@@ -722,39 +836,70 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_fnorm, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec);
 }
 
-void launch_stencil_dot(const Work& w, hipStream_t st) {
-  dim3 g(w.n / kTile, w.n / kTile, w.B);
-  if (w.mixed == 0)
-    hipLaunchKernelGGL((k_stencil<true, double>), g, dim3(kBlock), 0, st, w.a, (const double*)w.p, w.q, w.n,
-                       w.sys, w.part_pq);
+
+// Columns per lane of the operator apply: the widest that divides the grid.
+int stencil_vec_default(int n) { return n % 256 == 0 ? 4 : n % 128 == 0 ? 2 : 1; }
+bool stencil_vec_valid(int n, int V) { return (V == 1 || V == 2 || V == 4) && n % (kWave * V) == 0; }
+
+template <bool FUSED, class PT, class ZT>
+void launch_stencil_t(int B, int n, int V, const double* a, const PT* pin, PT* pout, const ZT* z, double* x,
+                      double* q, const SysState* sys, double* part, int first, hipStream_t st) {
+  const dim3 g(n / (kWave * V), n / kTile, B), blk(kBlock);
+  if (V == 4)
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
   else
-    hipLaunchKernelGGL((k_stencil<true, float>), g, dim3(kBlock), 0, st, w.a, (const float*)w.p, w.q, w.n,
-                       w.sys, w.part_pq);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
+}
+
+void launch_stencil_fused(const Work& w, int k, hipStream_t st) {
+  // iteration k writes p_k into buffer k mod 2 and reads p_{k-1} from the other
+  void* pout = (k & 1) ? w.p2 : w.p;
+  const void* pin = (k & 1) ? w.p : w.p2;
+  if (w.mixed == 0)
+    launch_stencil_t<true, double, double>(w.B, w.n, w.V, w.a, (const double*)pin, (double*)pout,
+                                           (const double*)w.z, w.x, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+  else
+    launch_stencil_t<true, float, float>(w.B, w.n, w.V, w.a, (const float*)pin, (float*)pout, (const float*)w.z,
+                                         w.x, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+}
+
+int stencil_tiles_per_realization(int n, int V) { return (n / (kWave * V)) * (n / kTile); }
+
+void launch_update_r(const Work& w, int flexible, hipStream_t st) {
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_update_r<double, double, false>), g, blk, 0, st, w.r, w.q, (const double*)w.z,
+                       (double*)nullptr, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+  else if (w.mixed == 1)
+    hipLaunchKernelGGL((k_update_r<float, float, true>), g, blk, 0, st, w.r, w.q, (const float*)w.z,
+                       (float*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+  else
+    hipLaunchKernelGGL((k_update_r<float, __bf16, true>), g, blk, 0, st, w.r, w.q, (const float*)w.z,
+                       (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+}
+
+void launch_finalize_x(const Work& w, hipStream_t st) {
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_finalize_x<double>), g, blk, 0, st, w.x, (const double*)w.p, (const double*)w.p2,
+                       w.sys, w.N2);
+  else
+    hipLaunchKernelGGL((k_finalize_x<float>), g, blk, 0, st, w.x, (const float*)w.p, (const float*)w.p2,
+                       w.sys, w.N2);
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  dim3 g(n / kTile, n / kTile, B);
-  hipLaunchKernelGGL((k_stencil<false, double>), g, dim3(kBlock), 0, st, a, u, out, n,
-                     (const SysState*)nullptr, (double*)nullptr);
+  launch_stencil_t<false, double, double>(B, n, stencil_vec_default(n), a, u, (double*)nullptr,
+                                          (const double*)nullptr, (double*)nullptr, out, (const SysState*)nullptr,
+                                          (double*)nullptr, 0, st);
 }
 
 void launch_scalar_alpha(const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_tile);
+  hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_st);
 }
 
-void launch_update_xr(const Work& w, int flexible, hipStream_t st) {
-  const dim3 g(w.P_vec, w.S), blk(kBlock);
-  if (w.mixed == 0)
-    hipLaunchKernelGGL((k_update_xr<double, double, double, false>), g, blk, 0, st, w.x, w.r,
-                       (const double*)w.p, w.q, (const double*)w.z, (double*)nullptr, w.sys, w.N2, w.part_rr,
-                       w.part_rzo, flexible);
-  else if (w.mixed == 1)
-    hipLaunchKernelGGL((k_update_xr<float, float, float, true>), g, blk, 0, st, w.x, w.r, (const float*)w.p,
-                       w.q, (const float*)w.z, (float*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
-  else
-    hipLaunchKernelGGL((k_update_xr<float, float, __bf16, true>), g, blk, 0, st, w.x, w.r, (const float*)w.p,
-                       w.q, (const float*)w.z, (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
-}
 
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec, tol, maxit,
@@ -783,15 +928,6 @@ void launch_widen(const float* in, double* out, long long total, hipStream_t st)
   hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, total);
 }
 
-void launch_update_p(const Work& w, int first, hipStream_t st) {
-  const dim3 g(w.P_vec, w.S), blk(kBlock);
-  if (w.mixed == 0)
-    hipLaunchKernelGGL((k_update_p<double, double>), g, blk, 0, st, (double*)w.p, (const double*)w.z, w.sys,
-                       w.N2, first);
-  else
-    hipLaunchKernelGGL((k_update_p<float, float>), g, blk, 0, st, (float*)w.p, (const float*)w.z, w.sys, w.N2,
-                       first);
-}
 
 void launch_ahom(const Work& w, hipStream_t st) {
   dim3 g(w.n / kTile, w.n / kTile, w.B);

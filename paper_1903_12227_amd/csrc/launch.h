@@ -21,13 +21,16 @@ struct Work {
   // transform GEMMs are FP64 and FP32 otherwise (mixed modes); they only
   // steer the iteration, while x, r and q = A p stay FP64, so r = f - A x
   // holds to FP64 rounding in every mode.
-  void* p = nullptr;
+  void* p = nullptr;         // directions of even iterations
+  void* p2 = nullptr;        // directions of odd iterations
   double* q = nullptr;       // A p
   void* z = nullptr;
   void* rlo = nullptr;       // mixed modes: r rounded to the GEMM type, the first GEMM's input
   void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
   void* u2 = nullptr;
   int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
+  int V = 1;                 // columns per lane of the operator apply
+  int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0)
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
   double* part_pq = nullptr;   // [S][P] partial sums of p.Ap
@@ -36,7 +39,8 @@ struct Work {
   double* part_rz = nullptr;   // [S][P] partial sums of r.z
   double* part_misc = nullptr; // [B][P][kMiscNV] per-realization partials
   int* count = nullptr;        // [maxit+1] active-system counts per iteration
-  int P_tile = 0;   // workgroups per realization of the stencil-shaped kernels
+  int P_tile = 0;   // workgroups per realization of the RHS / A_hom / gradient kernels
+  int P_st = 0;     // workgroups per realization of the operator apply
   int P_vec = 0;    // workgroups per system of the vector kernels
   int P_gemm = 0;   // output tiles per system of the transform GEMMs
 };
@@ -49,13 +53,18 @@ void launch_rhs(const Work& w, hipStream_t st);
 void launch_scalar_init(const Work& w, hipStream_t st);
 void launch_meansub(const Work& w, hipStream_t st);
 void launch_scalar_fnorm(const Work& w, hipStream_t st);
-void launch_stencil_dot(const Work& w, hipStream_t st);
 void launch_scalar_alpha(const Work& w, hipStream_t st);
-void launch_update_xr(const Work& w, int flexible, hipStream_t st);
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
-void launch_update_p(const Work& w, int first, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
+// Fused direction step + operator apply of PCG iteration k, with w.V columns
+// per lane (w.P_st must equal stencil_tiles_per_realization(n, w.V)).
+void launch_stencil_fused(const Work& w, int k, hipStream_t st);
+int stencil_vec_default(int n);
+bool stencil_vec_valid(int n, int V);
+int stencil_tiles_per_realization(int n, int V);
+void launch_update_r(const Work& w, int flexible, hipStream_t st);
+void launch_finalize_x(const Work& w, hipStream_t st);
 void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
@@ -79,9 +88,11 @@ struct GemmTables {
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.
 // In the mixed modes the first transform reads w.rlo, which must hold r in
-// the GEMM precision; w.P_gemm must equal gemm_tiles_per_system(n, prec).
+// the GEMM precision; w.P_gemm must equal
+// gemm_tiles_per_system(n, prec, w.gemm_variant).
 void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st);
-int gemm_tiles_per_system(int n, int prec);
+bool gemm_variant_valid(int n, int prec, int variant);
+int gemm_tiles_per_system(int n, int prec, int variant);
 int gemm_tiles_per_system_max(int n);
 
 }  // namespace rve

@@ -11,9 +11,12 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <new>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rve.h"
@@ -55,9 +58,16 @@ struct EventTimer {
 
 }  // namespace
 
+// Autotuner key: (kind, n, precision, floor(log2 B)); kind 0 = columns per
+// lane of the operator apply, kind 1 = transform-GEMM tile variant.
+using TuneKey = std::tuple<int, int, int, int>;
+
 struct rve_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  int autotune = 1;
+  std::map<TuneKey, int> tune;
+  std::string tune_path;     // JSON-lines cache of tuned choices, or empty
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::map<int, Tables> tables;
@@ -141,20 +151,21 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
 
 // Carve the workspace of one equal-n batch; grows the arena if needed.
 struct Layout {
-  size_t off_x, off_r, off_p, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
+  size_t off_x, off_r, off_p, off_p2, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_count, off_status, total;
 };
 
 Layout plan(int B, int n, int prec, int maxit, Work* w) {
   Layout L{};
   const long long S = 2LL * B, N2 = (long long)n * n;
-  const int P_tile = (n / kTile) * (n / kTile);
+  const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
+  const int P_st = stencil_tiles_per_realization(n, stencil_vec_default(n));   // operator-apply tiles
   long long vb = N2 / 1024;
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
   const int P_vec = (int)vb;
   const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
-  const int P_gemm = gemm_tiles_per_system(n, gp);
+  const int P_gemm = gemm_tiles_per_system(n, gp, gemm_variant_valid(n, gp, 1) ? 1 : 0);
   const size_t vec = align_up((size_t)(S * N2) * 8);
   const size_t pzvec = align_up((size_t)(S * N2) * (prec == RVE_FP64 ? 8 : 4));
   const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(gp));
@@ -162,6 +173,7 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
   L.off_p = o; o += pzvec;
+  L.off_p2 = o; o += pzvec;
   L.off_q = o; o += vec;
   L.off_z = o; o += pzvec;
   L.off_rlo = o; o += prec == RVE_FP64 ? 0 : uvec;
@@ -182,9 +194,12 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   w->S = (int)S;
   w->N2 = N2;
   w->P_tile = P_tile;
+  w->P_st = P_st;
   w->P_vec = P_vec;
   w->P_gemm = P_gemm;
   w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
+  w->V = stencil_vec_default(n);
+  w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
 }
 
@@ -209,6 +224,7 @@ void bind(rve_ctx* ctx, const Layout& L, Work* w) {
   w->x = reinterpret_cast<double*>(base + L.off_x);
   w->r = reinterpret_cast<double*>(base + L.off_r);
   w->p = base + L.off_p;
+  w->p2 = base + L.off_p2;
   w->q = reinterpret_cast<double*>(base + L.off_q);
   w->z = base + L.off_z;
   w->rlo = w->mixed ? base + L.off_rlo : nullptr;
@@ -268,6 +284,88 @@ int harvest_timing(rve_ctx* ctx) {
   return RVE_OK;
 }
 
+int batch_bucket(int B) {
+  int b = 0;
+  while ((2 << b) <= B) ++b;
+  return b;
+}
+
+void load_tune_cache(rve_ctx* ctx) {
+  if (ctx->tune_path.empty()) return;
+  FILE* f = fopen(ctx->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    int kind, n, prec, bb, choice;
+    if (sscanf(line, " {\"kind\": %d, \"n\": %d, \"prec\": %d, \"batch_log2\": %d, \"choice\": %d",
+               &kind, &n, &prec, &bb, &choice) == 5)
+      ctx->tune[TuneKey(kind, n, prec, bb)] = choice;
+  }
+  fclose(f);
+}
+
+void save_tune_entry(rve_ctx* ctx, const TuneKey& k, int choice, const std::vector<std::pair<int, float>>& ms) {
+  if (ctx->tune_path.empty()) return;
+  FILE* f = fopen(ctx->tune_path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "{\"kind\": %d, \"n\": %d, \"prec\": %d, \"batch_log2\": %d, \"choice\": %d, \"ms\": {",
+          std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), choice);
+  for (size_t i = 0; i < ms.size(); ++i) fprintf(f, "%s\"%d\": %.4f", i ? ", " : "", ms[i].first, ms[i].second);
+  fprintf(f, "}}\n");
+  fclose(f);
+}
+
+// Best of three event-timed runs of `launch` for each candidate; the
+// launches must be idempotent (they are: the first PCG direction step and a
+// preconditioner apply to a fixed residual).
+template <class F>
+int tune_pick(rve_ctx* ctx, const TuneKey& key, const std::vector<int>& cands, F launch) {
+  auto it = ctx->tune.find(key);
+  if (it != ctx->tune.end()) return it->second;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return cands[0];
+  if (hipEventCreate(&e1) != hipSuccess) {
+    ignore(hipEventDestroy(e0));
+    return cands[0];
+  }
+  std::vector<std::pair<int, float>> times;
+  int best = cands[0];
+  float best_ms = 1e30f;
+  for (int c : cands) {
+    launch(c);   // warm-up (code load, caches)
+    float cbest = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      ignore(hipEventRecord(e0, ctx->stream));
+      launch(c);
+      ignore(hipEventRecord(e1, ctx->stream));
+      ignore(hipEventSynchronize(e1));
+      float ms = 1e30f;
+      if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < cbest) cbest = ms;
+    }
+    times.push_back({c, cbest});
+    if (cbest < best_ms) {
+      best_ms = cbest;
+      best = c;
+    }
+  }
+  ignore(hipEventDestroy(e0));
+  ignore(hipEventDestroy(e1));
+  ctx->tune[key] = best;
+  save_tune_entry(ctx, key, best, times);
+  return best;
+}
+
+// Number of systems that start iterating (read back once, for the tuner).
+int count_active(rve_ctx* ctx, const Work& w) {
+  std::vector<SysState> h(w.S);
+  if (hipMemcpyAsync(h.data(), w.sys, w.S * sizeof(SysState), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return 0;
+  int c = 0;
+  for (const auto& s : h) c += s.active;
+  return c;
+}
+
 // Solve B equal-size realizations whose coefficients sit at a_dev.
 // `status_host` (optional) receives the per-item statuses.
 int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const rve_opts* o,
@@ -288,7 +386,9 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
   gt.einv64 = tb->einv64;
   gt.einv32 = tb->einv32;
   const int prec = o->prec == RVE_FP64 ? kGemmF64 : o->prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
-  const int flexible = o->flexible < 0 ? (o->prec != RVE_FP64) : (o->flexible != 0);
+  // automatic: standard beta (the flexible form gave the same iteration counts
+  // with the BF16/FP32 transforms at contrast 10 and 100)
+  const int flexible = o->flexible < 0 ? 0 : (o->flexible != 0);
   int chunk = o->check_every > 0 ? o->check_every : 8;
   hipStream_t st = ctx->stream;
 
@@ -297,28 +397,60 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
   launch_scalar_init(w, st);
   launch_meansub(w, st);
   launch_scalar_fnorm(w, st);
+
+  // kernel variants: defaults, or the autotuner's choice for this shape
+  w.V = stencil_vec_default(n);
+  w.gemm_variant = gemm_variant_valid(n, prec, 1) ? 1 : 0;
+  const int bb = batch_bucket(B);
+  const TuneKey kst(0, n, o->prec, bb), kgm(1, n, o->prec, bb);
+  const bool tune_now = ctx->autotune &&
+                        (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) && count_active(ctx, w) > 0;
+  if (ctx->autotune) {
+    std::vector<int> gc;
+    for (int v : {0, 1})
+      if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
+    if (ctx->tune.count(kgm) || tune_now)
+      w.gemm_variant = tune_pick(ctx, kgm, gc, [&](int v) {
+        Work t2 = w;
+        t2.gemm_variant = v;
+        t2.P_gemm = gemm_tiles_per_system(n, prec, v);
+        launch_precond(t2, prec, gt, st);
+      });
+  }
+  w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
   {
     Timed t(ctx, 1);
     launch_precond(w, prec, gt, st);
   }
   launch_scalar_beta(w, flexible, 1, st);
-  {
-    Timed t(ctx, 3);
-    launch_update_p(w, 1, st);
+  if (ctx->autotune) {
+    std::vector<int> vc;
+    for (int v : {1, 2, 4})
+      if (stencil_vec_valid(n, v)) vc.push_back(v);
+    if (ctx->tune.count(kst) || tune_now)
+      w.V = tune_pick(ctx, kst, vc, [&](int v) {
+        Work t2 = w;
+        t2.V = v;
+        t2.P_st = stencil_tiles_per_realization(n, v);
+        launch_stencil_fused(t2, 0, st);
+      });
   }
+  w.P_st = stencil_tiles_per_realization(n, w.V);
 
+  // iteration k: p_k = z_k + beta p_{k-1} and x += alpha_{k-1} p_{k-1} inside
+  // the operator apply, alpha_k, r update, convergence, then z_{k+1}, beta_k
   int enq = 0, chunk_idx = 0;
   for (;;) {
     const int end = std::min(enq + chunk, o->maxit);
     for (; enq < end; ++enq) {
       {
         Timed t(ctx, 0);
-        launch_stencil_dot(w, st);
+        launch_stencil_fused(w, enq, st);
       }
       launch_scalar_alpha(w, st);
       {
         Timed t(ctx, 2);
-        launch_update_xr(w, flexible, st);
+        launch_update_r(w, flexible, st);
       }
       launch_scalar_conv(w, o->tol, o->maxit, enq, st);
       if (enq + 1 < o->maxit) {
@@ -327,10 +459,6 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
           launch_precond(w, prec, gt, st);
         }
         launch_scalar_beta(w, flexible, 0, st);
-        {
-          Timed t(ctx, 3);
-          launch_update_p(w, 0, st);
-        }
       }
     }
     const int slot = chunk_idx & 1;
@@ -346,6 +474,10 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
       if (ctx->h_count[prev] == 0) break;
     }
     ++chunk_idx;
+  }
+  {
+    Timed t(ctx, 3);
+    launch_finalize_x(w, st);
   }
 
   launch_ahom(w, st);
@@ -402,6 +534,8 @@ int rve_create(rve_ctx** out, int device, void* hip_stream) {
   if (!c) return RVE_ENOMEM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (const char* tp = std::getenv("RVE_TUNE_CACHE")) c->tune_path = tp;
+  load_tune_cache(c);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_count), 2 * sizeof(int), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
@@ -598,6 +732,23 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
   if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_set_autotune(rve_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 1) return RVE_EINVAL;
+  c->autotune = mode;
+  return RVE_OK;
+}
+
+int rve_get_tuned(rve_ctx* c, int kind, int n, int prec, int B, int* choice) {
+  if (!c || !choice || (kind != 0 && kind != 1) || B < 1) return RVE_EINVAL;
+  auto it = c->tune.find(TuneKey(kind, n, prec, batch_bucket(B)));
+  if (it == c->tune.end()) {
+    *choice = -1;
+    return RVE_NOT_CONVERGED;
+  }
+  *choice = it->second;
   return RVE_OK;
 }
 

@@ -238,3 +238,25 @@ def test_bench_workload_sampled(dev, prec):
     for b in range(B):
         ev = np.linalg.eigvalsh(A[b])
         assert 1.0 / np.mean(1.0 / a[b]) - 1e-9 <= ev[0] and ev[1] <= np.mean(a[b]) + 1e-9
+
+
+def test_autotuner_choices_and_cache(dev, tmp_path, monkeypatch):
+    rve = _rve()
+    n, B = 256, 4
+    a = _to(_fields(n, B, 12), dev)
+    opts = rve.Options(tol=1e-10, prec=2)
+    fixed = rve.Context(0)
+    fixed.set_autotune(False)
+    ref = rve.solve_batch(a, 0.125, opts, ctx=fixed).ahom.cpu().numpy()
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("RVE_TUNE_CACHE", str(cache))
+    tuned_ctx = rve.Context(0)
+    got = rve.solve_batch(a, 0.125, opts, ctx=tuned_ctx).ahom.cpu().numpy()
+    for b in range(B):
+        assert rel2(got[b], ref[b]) <= 1e-12
+    ch = tuned_ctx.tuned(n, 2, B)
+    assert ch["stencil_columns_per_lane"] in (1, 2, 4) and ch["gemm_variant"] in (0, 1)
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 2 and all(line.startswith('{"kind"') for line in lines)
+    reload_ctx = rve.Context(0)          # reads the cache at creation
+    assert reload_ctx.tuned(n, 2, B) == ch
