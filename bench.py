@@ -72,18 +72,20 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
 
 
 def bytes_per_node(prec_name, flexible):
-    """Algorithmic HBM bytes per node of each kernel class.
+    """Algorithmic HBM bytes per node of each kernel, per corrector system
+    (the operator apply: per realization, both systems).
 
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
     precision (s_g bytes) that the first transform reads; x, r, q stay FP64.
-      stencil   fused direction step + operator apply, per realization (both
-                systems): read z, p_old, x; write p_new, x, q; read a
-      update_r  per system: read r, q [+ z for flexible beta]; write r [+ r copy]
-      precond   per system, four transforms: read the r copy (FP64 r on the
-                FP64 path), write/read three intermediates, write z, re-read r
-                (FP64) for r.z
-      finalize  per system, once per solve: x += alpha p
+      stencil   fused direction step + operator apply: read z, p_old, x;
+                write p_new, x, q (per system), read a (once)
+      gemm1     read the r copy (FP64 r on the FP64 path), write T1
+      gemm2     read T1, write W = (Q R Q)./(a0 E)   (1/E is one shared n x n table)
+      gemm3     read W, write T3
+      gemm4     read T3, write z, re-read r (FP64) for r.z
+      update_r  read r, q [+ z for flexible beta]; write r [+ r copy]
+      finalize  once per solve: x += alpha p
     """
     sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
@@ -91,36 +93,98 @@ def bytes_per_node(prec_name, flexible):
     first_in = 8 if prec_name == "fp64" else sg
     return {
         "stencil": 2 * (sp + sp + 16 + sp + 8) + 8,
+        "gemm1": first_in + sg,
+        "gemm2": 2 * sg,
+        "gemm3": 2 * sg,
+        "gemm4": sg + sp + 8,
         "update_r": 8 + 8 + 8 + lo + (sp if flexible else 0),
-        "precond": first_in + 6 * sg + sp + 8,
         "finalize": 8 + sp + 8,
     }
 
 
-def roofline_entries(tim, it_all, n, B, prec_name, flexible):
-    """Achieved rates of the timed kernel classes from algorithmic bytes/flops.
+def kernel_entries(tim, it_all, n, prec_name, flexible):
+    """Per-kernel algorithmic bytes (and flops) summed over the timed launches.
 
-    it_all: (steps, B, 2) iteration counts. Per realization-step, stencil
-    applies = max over its two systems; per system, x/r and p updates = iters,
-    preconditioner applies = iters (one before the loop, one per continuing
-    iteration)."""
-    N2 = n * n
-    stencil_applies = float(it_all.max(dim=2).values.sum())       # realization-launch units
+    it_all: (steps, B, 2) iteration counts. A realization takes part in the
+    operator apply while either of its systems iterates (max over the two);
+    a system takes part in each residual update and each preconditioner
+    apply (one before the loop and one per continuing iteration) = iters;
+    the final update runs once per solve."""
+    N2 = float(n * n)
+    real_iters = float(it_all.max(dim=2).values.sum())
     sys_iters = float(it_all.sum())
+    n_sys = float(it_all.numel())
     bpn = bytes_per_node(prec_name, flexible)
+    units = {"stencil": real_iters, "gemm1": sys_iters, "gemm2": sys_iters, "gemm3": sys_iters,
+             "gemm4": sys_iters, "update_r": sys_iters, "finalize": n_sys}
     out = {}
-    ms, cnt = tim["stencil"]
-    out["stencil"] = {"bound": "hbm", "bytes": stencil_applies * bpn["stencil"] * N2, "ms": ms,
-                      "launches": cnt, "bytes_per_node": bpn["stencil"]}
-    ms, cnt = tim["update_r"]
-    out["update_r"] = {"bound": "hbm", "bytes": sys_iters * bpn["update_r"] * N2, "ms": ms,
-                       "launches": cnt, "bytes_per_node": bpn["update_r"]}
-    ms, cnt = tim["precond"]
-    # four transforms of 2 n^3 flops each per system-apply
-    out["precond"] = {"bound": "mfma", "flops": sys_iters * 8.0 * n * N2,
-                      "bytes": sys_iters * bpn["precond"] * N2, "ms": ms, "launches": 4 * cnt,
-                      "bytes_per_node": bpn["precond"]}
+    for k, u in units.items():
+        ms, cnt = tim[k]
+        e = {"ms": ms, "launches": cnt, "bytes_per_node": bpn[k], "bytes": u * bpn[k] * N2}
+        if k.startswith("gemm"):
+            e["flops"] = u * 2.0 * n * N2            # one n x n x n product per system
+        out[k] = e
     return out
+
+
+def roofline_for(name, e, prec_name, n):
+    """Roofline of one kernel: HBM-bound unless its arithmetic intensity
+    (flops per algorithmic byte) times the HBM peak exceeds the MFMA peak."""
+    sec = e["ms"] * 1e-3
+    avg = e["ms"] / max(e["launches"], 1)
+    if "flops" in e:
+        ai = e["flops"] / e["bytes"]
+        peak_f = MFMA_PEAK_TFS[prec_name]
+        if ai * HBM_PEAK_GBS / 1e3 > peak_f:
+            ach = e["flops"] / sec / 1e12
+            return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak_f, "unit": "TFLOP/s",
+                    "frac": ach / peak_f, "traffic": None, "avg_launch_ms": avg,
+                    "intensity_flop_per_byte": ai}
+    ach = e["bytes"] / sec / 1e9
+    out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg,
+           "algorithmic_bytes_per_launch": e["bytes"] / max(e["launches"], 1)}
+    if "flops" in e:
+        out["intensity_flop_per_byte"] = e["flops"] / e["bytes"]
+    return out
+
+
+KERNEL_SOURCES = ("paper_1903_12227_amd/csrc/common.h", "paper_1903_12227_amd/csrc/launch.h",
+                  "paper_1903_12227_amd/csrc/kernels_vec.hip", "paper_1903_12227_amd/csrc/kernels_gemm.hip",
+                  "paper_1903_12227_amd/csrc/rve_api.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_L64_n512_b256.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if it is absent or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(torch, dev):
+    """One plain device copy of a known size (2^28 bytes read, 2^28 written),
+    whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures."""
+    src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def main():
@@ -137,7 +201,12 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="realizations for the per-realization FP64 leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines file of autotuned kernel choices to read and extend "
+                         "(lets profiling runs replay the choices of a normal run)")
     args = ap.parse_args()
+    if args.tune_cache:
+        os.environ["RVE_TUNE_CACHE"] = args.tune_cache
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -164,6 +233,7 @@ def main():
     G[:, 0, 0] = 1.0      # d A_11 + d A_12
     G[:, 0, 1] = 1.0
     ctx = rve.context(0)
+    copy_calibration(torch, dev)
 
     # headline: mixed precision (BF16 transform GEMMs), batched
     mixed = rve.Options(tol=args.tol, prec=rve.MIX_BF16)
@@ -193,30 +263,19 @@ def main():
     torch.cuda.synchronize()
     v_plain = args.plain / (time.perf_counter() - t0)
 
-    # roofline of the dominant kernel class of the headline leg
-    ent = roofline_entries(tim_mix, it_mix_t, n, B, "bf16", flexible=False)
+    # roofline of the dominant kernel (largest total event time) of the headline leg
+    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False)
     dom = max(ent, key=lambda k: ent[k]["ms"])
-    e = ent[dom]
-    if e["bound"] == "hbm" or dom != "precond":
-        achieved = e["bytes"] / (e["ms"] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_ms": e["ms"] / max(e["launches"], 1)}
-    else:
-        achieved = e["flops"] / (e["ms"] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFS["bf16"],
-                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFS["bf16"], "traffic": None,
-                "avg_launch_ms": e["ms"] / max(e["launches"], 1)}
+    roof = roofline_for(dom, ent[dom], "bf16", n)
+    roof["traffic"] = measured_traffic(dom)
     kernels = {}
     for k, v in ent.items():
-        rec = {"ms_total": v["ms"], "launches": v["launches"], "bytes_per_node": v["bytes_per_node"],
-               "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
-        if "flops" in v:
-            rec["TFLOPs"] = v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else None
-        kernels[k] = rec
-    ent64 = roofline_entries(tim64, it64, n, B, "fp64", flexible=False)
-    p64 = ent64["precond"]
-    fp64_gemm_tfs = p64["flops"] / (p64["ms"] * 1e-3) / 1e12 if p64["ms"] > 0 else None
+        r = roofline_for(k, v, "bf16", n)
+        kernels[k] = {"ms_total": v["ms"], "launches": v["launches"], "bytes_per_node": v["bytes_per_node"],
+                      "bound": r["bound"], "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
+    ent64 = kernel_entries(tim64, it64, n, "fp64", flexible=False)
+    g64 = [ent64[k] for k in ("gemm1", "gemm2", "gemm3", "gemm4")]
+    fp64_gemm_tfs = sum(e["flops"] for e in g64) / (sum(e["ms"] for e in g64) * 1e-3) / 1e12
 
     cpu = None
     if not args.no_cpu:

@@ -202,11 +202,10 @@ int rve_get_tuned(rve_ctx* ctx, int kind, int n, int prec, int B, int* choice);
  * turns recording on (1) or off (0) and clears the accumulators; while it is
  * on, every launch of a class is bracketed by HIP events.
  * rve_last_timing returns the totals since the last rve_set_timing in
- * out_ms[4] and out_counts[4]: [0] operator applies fused with the
- * search-direction and iterate updates (one kernel launch each),
- * [1] preconditioner applies (four transform GEMM launches each),
- * [2] residual updates, [3] final iterate updates (one per solve); counts
- * are bracketed applies. */
+ * out_ms[7] and out_counts[7], one entry per kernel: [0] the operator apply
+ * fused with the search-direction and iterate updates, [1]..[4] the four
+ * transform GEMMs of the preconditioner in order, [5] the residual update,
+ * [6] the final iterate update (once per solve). */
 int rve_set_timing(rve_ctx* ctx, int enable);
 int rve_last_timing(rve_ctx* ctx, double* out_ms, long long* out_counts);
 

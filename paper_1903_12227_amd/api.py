@@ -65,14 +65,15 @@ class Context:
         N.check(self._lib.rve_set_timing(self.handle, int(bool(enable))), "rve_set_timing")
 
     def timing(self):
-        """Accumulated event timing since set_timing(True): dict of class ->
-        (total ms, applies) for 'stencil' (fused direction step and operator
-        apply), 'precond' (four GEMM launches per apply), 'update_r',
-        'finalize' (last x update, once per solve)."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_longlong * 4)()
+        """Accumulated event timing since set_timing(True): kernel ->
+        (total ms, launches) for 'stencil' (fused direction step and operator
+        apply), 'gemm1'..'gemm4' (the preconditioner's transforms),
+        'update_r', 'finalize' (last x update, once per solve)."""
+        ms = (ctypes.c_double * 7)()
+        cnt = (ctypes.c_longlong * 7)()
         N.check(self._lib.rve_last_timing(self.handle, ms, cnt), "rve_last_timing")
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(("stencil", "precond", "update_r", "finalize"))}
+        names = ("stencil", "gemm1", "gemm2", "gemm3", "gemm4", "update_r", "finalize")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
 
     def set_autotune(self, enable: bool):
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")

@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 bool big_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % TM == 0; }
 
 template <class Tr, class ZT>
-void run_precond(const Work& w, const GemmTables& t, hipStream_t st) {
+void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   using op_t = typename Tr::op_t;
   const int n = w.n;
   const long long T = (long long)w.S * (n / BM) * (n / BN);
@@ -405,39 +405,47 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st) {
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
   // T1 = (R Q)^T, from the FP64 residual or from its GEMM-precision copy
-  if (w.rlo)
+  if (phase >= 0 && phase != 0) {
+  } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, (const op_t*)w.rlo, Q, (void*)u1,
                        n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S,
                        w.sys, w.real, nullptr, nullptr, nullptr);
   // W = (Q R Q) ./ (a0 E)
-  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+  if (phase < 0 || phase == 1)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
                      w.real, einv, nullptr, nullptr);
   // T3 = (W Q)^T
-  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+  if (phase < 0 || phase == 2)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
                      w.real, nullptr, nullptr, nullptr);
   // z = Q W Q, partial sums of r.z
-  hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+  if (phase < 0 || phase == 3)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
                      nullptr, w.r, w.part_rz);
 }
 
 template <class ZT>
-void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st) {
+void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
   const long long T = (long long)w.S * (n / TM) * (n / TN);
   const dim3 grid((unsigned)T), block(kBlock);
   const __bf16* Q = reinterpret_cast<const __bf16*>(t.q);
   __bf16* u1 = reinterpret_cast<__bf16*>(w.u1);
   __bf16* u2 = reinterpret_cast<__bf16*>(w.u2);
-  hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, Q,
-                     (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
-  hipLaunchKernelGGL((k_hartley_bf16<kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                     w.real, t.einv32, nullptr, nullptr);
-  hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                     w.real, nullptr, nullptr, nullptr);
-  hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
-                     nullptr, w.r, w.part_rz);
+  if (phase < 0 || phase == 0)
+    hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, Q,
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
+  if (phase < 0 || phase == 1)
+    hipLaunchKernelGGL((k_hartley_bf16<kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+                       w.real, t.einv32, nullptr, nullptr);
+  if (phase < 0 || phase == 2)
+    hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+                       w.real, nullptr, nullptr, nullptr);
+  if (phase < 0 || phase == 3)
+    hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+                       nullptr, w.r, w.part_rz);
 }
 
 }  // namespace
@@ -456,16 +464,16 @@ int gemm_tiles_per_system(int n, int prec, int variant) {
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
 
-void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st) {
+void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st, int phase) {
   // z is FP64 with FP64 transforms and FP32 in the mixed modes
   if (prec == kGemmF64) {
-    run_precond<TrF64, double>(w, t, st);
+    run_precond<TrF64, double>(w, t, st, phase);
   } else if (prec == kGemmF32) {
-    run_precond<TrF32, float>(w, t, st);
+    run_precond<TrF32, float>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
-    run_precond_bf16_big<float>(w, t, st);
+    run_precond_bf16_big<float>(w, t, st, phase);
   } else {
-    run_precond<TrBF16, float>(w, t, st);
+    run_precond<TrBF16, float>(w, t, st, phase);
   }
 }
 

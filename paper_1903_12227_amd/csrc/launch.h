@@ -90,7 +90,8 @@ size_t gemm_elem_size(int prec);
 // In the mixed modes the first transform reads w.rlo, which must hold r in
 // the GEMM precision; w.P_gemm must equal
 // gemm_tiles_per_system(n, prec, w.gemm_variant).
-void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st);
+// phase < 0 launches all four transforms; 0..3 only that one (in order).
+void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st, int phase = -1);
 bool gemm_variant_valid(int n, int prec, int variant);
 int gemm_tiles_per_system(int n, int prec, int variant);
 int gemm_tiles_per_system_max(int n);

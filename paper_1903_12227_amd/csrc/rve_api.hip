@@ -36,16 +36,17 @@ struct Tables {
   float* einv32 = nullptr;
 };
 
-// Timed kernel classes: 0 stencil apply, 1 preconditioner apply (four
-// transform GEMMs), 2 x/r update, 3 search-direction update.
-constexpr int kTimedClasses = 4;
+// Timed kernels: 0 fused direction step + operator apply, 1..4 the four
+// transform GEMMs of the preconditioner, 5 residual update, 6 final iterate
+// update.
+constexpr int kTimedClasses = 7;
 
 struct EventTimer {
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, int>> pairs;   // (class, first event index)
   size_t used = 0;
-  double ms[kTimedClasses] = {0, 0, 0, 0};
-  long long count[kTimedClasses] = {0, 0, 0, 0};
+  double ms[kTimedClasses] = {0, 0, 0, 0, 0, 0, 0};
+  long long count[kTimedClasses] = {0, 0, 0, 0, 0, 0, 0};
   hipEvent_t next() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -366,6 +367,18 @@ int count_active(rve_ctx* ctx, const Work& w) {
   return c;
 }
 
+// The four transform GEMMs, each bracketed by the timer when it is on.
+void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt) {
+  if (!ctx->timing) {
+    launch_precond(w, prec, gt, ctx->stream);
+    return;
+  }
+  for (int ph = 0; ph < 4; ++ph) {
+    Timed t(ctx, 1 + ph);
+    launch_precond(w, prec, gt, ctx->stream, ph);
+  }
+}
+
 // Solve B equal-size realizations whose coefficients sit at a_dev.
 // `status_host` (optional) receives the per-item statuses.
 int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const rve_opts* o,
@@ -418,10 +431,7 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
       });
   }
   w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
-  {
-    Timed t(ctx, 1);
-    launch_precond(w, prec, gt, st);
-  }
+  precond_timed(ctx, w, prec, gt);
   launch_scalar_beta(w, flexible, 1, st);
   if (ctx->autotune) {
     std::vector<int> vc;
@@ -449,15 +459,12 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
       }
       launch_scalar_alpha(w, st);
       {
-        Timed t(ctx, 2);
+        Timed t(ctx, 5);
         launch_update_r(w, flexible, st);
       }
       launch_scalar_conv(w, o->tol, o->maxit, enq, st);
       if (enq + 1 < o->maxit) {
-        {
-          Timed t(ctx, 1);
-          launch_precond(w, prec, gt, st);
-        }
+        precond_timed(ctx, w, prec, gt);
         launch_scalar_beta(w, flexible, 0, st);
       }
     }
@@ -476,7 +483,7 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
     ++chunk_idx;
   }
   {
-    Timed t(ctx, 3);
+    Timed t(ctx, 6);
     launch_finalize_x(w, st);
   }
 
