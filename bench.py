@@ -78,27 +78,30 @@ def bytes_per_node(prec_name, flexible):
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
     precision (s_g bytes) that the first transform reads; x, r, q stay FP64.
-      stencil   fused direction step + operator apply: read z, p_old, x;
-                write p_new, x, q (per system), read a (once)
+      stencil   fused direction step + operator apply: read z, p_old;
+                write p_new, q (per system), read a (once)
       gemm1     read the r copy (FP64 r on the FP64 path), write T1
       gemm2     read T1, write W = (Q R Q)./(a0 E)   (1/E is one shared n x n table)
       gemm3     read W, write T3
-      gemm4     read T3, write z, re-read r (FP64) for r.z
+      gemm4     read T3, write z, re-read the residual the transforms started
+                from (the r copy; FP64 r on the FP64 path) for r.z
       update_r  read r, q [+ z for flexible beta]; write r [+ r copy]
-      finalize  once per solve: x += alpha p
+      fold_x    x += sum alpha_j p_j over the direction ring: per fold,
+                read and write x; per direction, read p once (handled in
+                kernel_entries: 16 ceil(iters / ring) + s_p iters per system)
     """
     sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": 2 * (sp + sp + 16 + sp + 8) + 8,
+        "stencil": 2 * (sp + sp + sp + 8) + 8,
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
-        "gemm4": sg + sp + 8,
+        "gemm4": sg + sp + first_in,
         "update_r": 8 + 8 + 8 + lo + (sp if flexible else 0),
-        "finalize": 8 + sp + 8,
+        "fold_x": sp,
     }
 
 
@@ -109,18 +112,23 @@ def kernel_entries(tim, it_all, n, prec_name, flexible):
     operator apply while either of its systems iterates (max over the two);
     a system takes part in each residual update and each preconditioner
     apply (one before the loop and one per continuing iteration) = iters;
-    the final update runs once per solve."""
+    the iterate update folds each direction into x once and reads and writes
+    x once per ring of directions, ceil(iters / DIRECTION_RING) times."""
+    import math
+    from paper_1903_12227_amd import DIRECTION_RING
     N2 = float(n * n)
     real_iters = float(it_all.max(dim=2).values.sum())
     sys_iters = float(it_all.sum())
-    n_sys = float(it_all.numel())
+    folds = float(sum(math.ceil(v / DIRECTION_RING) for v in it_all.flatten().tolist()))
     bpn = bytes_per_node(prec_name, flexible)
     units = {"stencil": real_iters, "gemm1": sys_iters, "gemm2": sys_iters, "gemm3": sys_iters,
-             "gemm4": sys_iters, "update_r": sys_iters, "finalize": n_sys}
+             "gemm4": sys_iters, "update_r": sys_iters, "fold_x": sys_iters}
     out = {}
     for k, u in units.items():
         ms, cnt = tim[k]
         e = {"ms": ms, "launches": cnt, "bytes_per_node": bpn[k], "bytes": u * bpn[k] * N2}
+        if k == "fold_x":
+            e["bytes"] += 16.0 * folds * N2
         if k.startswith("gemm"):
             e["flops"] = u * 2.0 * n * N2            # one n x n x n product per system
         out[k] = e

@@ -61,13 +61,23 @@ enum rve_status {
 };
 
 /* Arithmetic of the preconditioner's transform GEMMs (Q X Q on MFMA). The
- * residual update, the search directions, the CG dot products, the stencil
- * apply and the A_hom reductions are FP64 in every mode. */
+ * residual r, the iterate x, q = A p, the stencil arithmetic, the CG dot
+ * products and the A_hom reductions are FP64 in every mode; in the mixed
+ * modes the search directions p and the preconditioned residual z are
+ * stored in FP32 (they only steer the iteration: r = f - A x still holds to
+ * FP64 rounding, so the stopping test is unaffected). */
 enum rve_precision {
   RVE_FP64 = 0,      /* FP64 MFMA, FP64 intermediates */
   RVE_MIX_FP32 = 1,  /* FP32 MFMA, FP32 intermediates */
   RVE_MIX_BF16 = 2   /* BF16 MFMA operands, FP32 accumulation, BF16 intermediates */
 };
+
+/* The PCG iterate is not updated every iteration: the search directions of
+ * RVE_DIRECTION_RING consecutive iterations are kept, and x += sum_j
+ * alpha_j p_j is applied once per that many iterations and at the end, in
+ * the order of the plain recurrence (Sec. 3.5 PCG; the result is the same
+ * to the last bit). Device memory: that many direction vectors per system. */
+#define RVE_DIRECTION_RING 8
 
 typedef struct rve_opts {
   double tol;        /* relative residual target ||r||_2/||f||_2, > 0 */
@@ -185,15 +195,17 @@ const char* rve_status_string(int status);
 /*
  * Autotuner. With mode 1 (the default), the first solve of each
  * (n, precision, floor(log2 B)) times the candidate kernel variants on the
- * live data and keeps the fastest: the number of grid columns per lane of
- * the operator apply (1, 2 or 4) and the transform-GEMM tile (64 x 64, or
- * 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
+ * live data and keeps the fastest: the shape of the operator apply (V = 1, 2
+ * or 4 grid columns per lane, H = 16 or 64 rows per wave strip) and the
+ * transform-GEMM tile (64 x 64, or 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
  * and, if the environment variable RVE_TUNE_CACHE names a file, appended
  * there as JSON lines and read back by rve_create. Mode 0 uses fixed
  * defaults. Results do not depend on the choice beyond rounding order.
  *
- * rve_get_tuned: *choice for kind 0 (columns per lane) or 1 (GEMM variant)
- * of a shape, or -1 with return value RVE_NOT_CONVERGED if not tuned yet.
+ * rve_get_tuned: *choice for kind 0 (operator-apply shape, encoded as
+ * V + 8 (H / 16)) or 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128) of a shape,
+ * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
+ * that are not valid for a shape are ignored and tuned again.
  */
 int rve_set_autotune(rve_ctx* ctx, int mode);
 int rve_get_tuned(rve_ctx* ctx, int kind, int n, int prec, int B, int* choice);
@@ -203,9 +215,10 @@ int rve_get_tuned(rve_ctx* ctx, int kind, int n, int prec, int B, int* choice);
  * on, every launch of a class is bracketed by HIP events.
  * rve_last_timing returns the totals since the last rve_set_timing in
  * out_ms[7] and out_counts[7], one entry per kernel: [0] the operator apply
- * fused with the search-direction and iterate updates, [1]..[4] the four
- * transform GEMMs of the preconditioner in order, [5] the residual update,
- * [6] the final iterate update (once per solve). */
+ * fused with the search-direction update, [1]..[4] the four transform GEMMs
+ * of the preconditioner in order, [5] the residual update, [6] the iterate
+ * update x += sum alpha_j p_j, applied once per RVE_DIRECTION_RING iterations
+ * and once at the end of a solve. */
 int rve_set_timing(rve_ctx* ctx, int enable);
 int rve_last_timing(rve_ctx* ctx, double* out_ms, long long* out_counts);
 

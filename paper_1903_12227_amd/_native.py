@@ -7,6 +7,10 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librve.so")
 
+# Iterations per update of the PCG iterate from the ring of search directions
+# (RVE_DIRECTION_RING in the header).
+DIRECTION_RING = 8
+
 # enum rve_status
 OK, NOT_CONVERGED, BREAKDOWN, EINVAL, EHIP, ENOMEM = 0, 1, 2, -1, -2, -3
 # enum rve_precision

@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _native as N
-from ._native import FP64, MIX_BF16, MIX_FP32  # noqa: F401
+from ._native import DIRECTION_RING, FP64, MIX_BF16, MIX_FP32  # noqa: F401
 
 
 @dataclass
@@ -68,25 +68,30 @@ class Context:
         """Accumulated event timing since set_timing(True): kernel ->
         (total ms, launches) for 'stencil' (fused direction step and operator
         apply), 'gemm1'..'gemm4' (the preconditioner's transforms),
-        'update_r', 'finalize' (last x update, once per solve)."""
+        'update_r', 'fold_x' (x += sum alpha_j p_j, once per
+        DIRECTION_RING iterations and once at the end of a solve)."""
         ms = (ctypes.c_double * 7)()
         cnt = (ctypes.c_longlong * 7)()
         N.check(self._lib.rve_last_timing(self.handle, ms, cnt), "rve_last_timing")
-        names = ("stencil", "gemm1", "gemm2", "gemm3", "gemm4", "update_r", "finalize")
+        names = ("stencil", "gemm1", "gemm2", "gemm3", "gemm4", "update_r", "fold_x")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
 
     def set_autotune(self, enable: bool):
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
 
     def tuned(self, n: int, prec: int, B: int) -> dict:
-        """The autotuner's choices for a shape: columns per lane of the
-        operator apply and the transform-GEMM tile variant (-1: not tuned)."""
-        out = {}
-        for kind, name in ((0, "stencil_columns_per_lane"), (1, "gemm_variant")):
+        """The autotuner's choices for a shape: columns per lane and rows per
+        wave strip of the operator apply, and the transform-GEMM tile variant
+        (-1: not tuned)."""
+        got = []
+        for kind in (0, 1):
             c = ctypes.c_int(-1)
             self._lib.rve_get_tuned(self.handle, kind, int(n), int(prec), int(B), ctypes.byref(c))
-            out[name] = c.value
-        return out
+            got.append(c.value)
+        st = got[0]
+        return {"stencil_columns_per_lane": st & 7 if st >= 0 else -1,
+                "stencil_rows_per_strip": 16 * (st >> 3) if st >= 0 else -1,
+                "gemm_variant": got[1]}
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

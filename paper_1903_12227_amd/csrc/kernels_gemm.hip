@@ -86,17 +86,24 @@ template <> __device__ inline __bf16 cvtf<__bf16>(float v) { return (__bf16)v; }
 
 enum Epi { kEpiStore = 0, kEpiEinv = 1, kEpiZ = 2 };
 
+// The r.z partials of the last transform read the residual the transforms
+// started from: FP64 r with FP64 transforms, else its GEMM-precision copy
+// (the values the preconditioner was actually applied to).
+__device__ inline double widen(double v) { return v; }
+__device__ inline double widen(float v) { return (double)v; }
+__device__ inline double widen(__bf16 v) { return (double)(float)v; }
+
 // Elements of one K-slice per thread: (BM x BK) / 256.
 template <class Tr> struct Stage {
   static constexpr int PER = (BM * Tr::BK) / kBlock;   // 4 (FP64/FP32) or 16 (BF16)
   static constexpr int TPR = Tr::BK / PER;              // threads per row: 4
 };
 
-template <class Tr, class InT, int EPI, class ZT = double>
+template <class Tr, class InT, int EPI, class ZT = double, class RT = double>
 __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, const typename Tr::op_t* __restrict__ Qm,
                                                      void* __restrict__ out_v, int n, int S, const SysState* sys,
                                                      const RealState* real, const void* __restrict__ einv_v,
-                                                     const double* __restrict__ rres, double* __restrict__ part) {
+                                                     const RT* __restrict__ rres, double* __restrict__ part) {
   using op_t = typename Tr::op_t;
   using acc_t = typename Tr::acc_t;
   using accv_t = typename Tr::accv_t;
@@ -212,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
       ZT* out = reinterpret_cast<ZT*>(out_v);
       const ZT zs = (ZT)v;
       out[obase + e] = zs;
-      dot += (double)zs * rres[obase + e];
+      dot += (double)zs * widen(rres[obase + e]);
     } else {
       op_t* out = reinterpret_cast<op_t*>(out_v);
       if constexpr (sizeof(acc_t) == sizeof(op_t)) out[obase + e] = (op_t)v;
@@ -234,12 +241,12 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
 // The transposed output goes through LDS in two halves of 64 rows.
 constexpr int TM = 128, TN = 128, TK = 64, TLDA = TK + 8, TLDC = TM + 4;
 
-template <int EPI, class ZT>
+template <int EPI, class ZT, class RT = double>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_hartley_bf16(const __bf16* __restrict__ X, const __bf16* __restrict__ Qm,
                                                           void* __restrict__ out_v, int n, int S,
                                                           const SysState* sys, const RealState* real,
                                                           const float* __restrict__ einv,
-                                                          const double* __restrict__ rres,
+                                                          const RT* __restrict__ rres,
                                                           double* __restrict__ part) {
   constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(__bf16);
   constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
@@ -371,7 +378,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
       for (int e = 0; e < 32; ++e) {
         const ZT zs = (ZT)v[e];
         out[e] = zs;
-        dot += (double)zs * rres[obase + e];
+        dot += (double)zs * widen(rres[obase + e]);
       }
     } else {
       __bf16* out = reinterpret_cast<__bf16*>(out_v) + obase;
@@ -408,22 +415,26 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) 
   if (phase >= 0 && phase != 0) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, (const op_t*)w.rlo, Q, (void*)u1,
-                       n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S,
-                       w.sys, w.real, nullptr, nullptr, nullptr);
+                       w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
   // W = (Q R Q) ./ (a0 E)
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                     w.real, einv, nullptr, nullptr);
+                     w.real, einv, (const double*)nullptr, nullptr);
   // T3 = (W Q)^T
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                     w.real, nullptr, nullptr, nullptr);
+                     w.real, nullptr, (const double*)nullptr, nullptr);
   // z = Q W Q, partial sums of r.z
-  if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
-                     nullptr, w.r, w.part_rz);
+  if (phase >= 0 && phase != 3) {
+  } else if (w.rlo)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz);
+  else
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, w.r, w.part_rz);
 }
 
 template <class ZT>
@@ -436,16 +447,16 @@ void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st, in
   __bf16* u2 = reinterpret_cast<__bf16*>(w.u2);
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, Q,
-                       (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, nullptr);
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley_bf16<kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                       w.real, t.einv32, nullptr, nullptr);
+                       w.real, t.einv32, (const double*)nullptr, nullptr);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                       w.real, nullptr, nullptr, nullptr);
+                       w.real, nullptr, (const double*)nullptr, nullptr);
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
-                       nullptr, w.r, w.part_rz);
+    hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT, __bf16>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, (const __bf16*)w.rlo, w.part_rz);
 }
 
 }  // namespace

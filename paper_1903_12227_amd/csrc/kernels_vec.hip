@@ -272,71 +272,78 @@ template <int V> struct VecIO<float, V> {
   }
 };
 
-// Operator apply over V consecutive columns per lane (a 64V x 64 tile per
-// workgroup, each wave sliding down a 16-row strip), for both systems of a
-// realization. FUSED: the operand is the new search direction
-// p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on the fly for the V
-// nodes and their neighbours; p_k goes to a buffer different from p_{k-1}
-// (neighbouring workgroups still read p_{k-1} at tile edges), the deferred
-// update x += alpha_{k-1} p_{k-1} is applied, and q = A p_k is written with
-// partial sums of p_k.q (active systems only). Not FUSED: q = A u for a
-// caller's u (the plain operator apply).
+// Operator apply over V consecutive columns per lane for both systems of a
+// realization. A workgroup covers 64V columns x 4H rows; each of its four
+// waves slides a three-row register window down an H-row strip, so every
+// value is loaded about once (plus two halo rows per strip) and the +-1
+// columns come from the cache lines just loaded. FUSED: the operand is the
+// new search direction p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on
+// the fly for the V nodes and their neighbours; p_k goes to a ring slot other
+// than p_{k-1}'s (neighbouring workgroups still read p_{k-1} at tile edges),
+// and q = A p_k is written with partial sums of p_k.q (active systems only).
+// Not FUSED: q = A u for a caller's u (the plain operator apply).
+//
+// One-dimensional grid of gx * gy * B workgroups. The hardware hands
+// consecutive workgroup ids to the eight XCDs in turn; the id is remapped so
+// that each XCD receives a contiguous run of tiles (all tiles of a few
+// realizations, neighbours next to each other in time), and halo lines
+// fetched by one tile are found in that XCD's L2 by its neighbours.
 template <bool FUSED, class PT, class ZT, int V>
 __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a,
                                                        const PT* __restrict__ p_old, PT* __restrict__ p_new,
-                                                       const ZT* __restrict__ z, double* __restrict__ x,
-                                                       double* __restrict__ q, int n, const SysState* sys,
-                                                       double* __restrict__ part, int first) {
+                                                       const ZT* __restrict__ z, double* __restrict__ q, int n,
+                                                       int H, const SysState* sys, double* __restrict__ part,
+                                                       int first) {
   __shared__ double sh[4 * 2];
-  const int b = blockIdx.z;
+  const int gx = n / (kWave * V), gy = n / (4 * H);
+  const unsigned T = gridDim.x, L = blockIdx.x;
+  const unsigned t = (T & 7u) ? L : (L & 7u) * (T >> 3) + (L >> 3);
+  const int bx = (int)(t % (unsigned)gx);
+  const int by = (int)((t / (unsigned)gx) % (unsigned)gy);
+  const int b = (int)(t / (unsigned)(gx * gy));
   const int s0 = 2 * b, s1 = s0 + 1;
   const int act0 = FUSED ? sys[s0].active : 1, act1 = FUSED ? sys[s1].active : 1;
   if (!act0 && !act1) return;   // uniform over the workgroup
   const double be[2] = {FUSED && !first ? sys[s0].beta : 0.0, FUSED && !first ? sys[s1].beta : 0.0};
-  const double al[2] = {FUSED && !first ? sys[s0].alpha : 0.0, FUSED && !first ? sys[s1].alpha : 0.0};
   const int act[2] = {act0, act1};
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long N2 = (long long)n * n;
-  const int c0 = (blockIdx.x * kWave + lane) * V;
+  const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
-  const int row0 = blockIdx.y * kTile + w * kStrip;
+  const int row0 = by * 4 * H + w * H;
   const double* A = a + (long long)b * N2;
   const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
   const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
 
-  // operand row (V + 2 values: column c0-1, c0..c0+V-1, c0+V) of system i at row offset o;
-  // the previous direction at the V centre columns is kept in pc (for the x update)
-  auto load_row = [&](int i, long long o, double* u, double* pc) {
+  // operand row (V + 2 values: column c0-1, c0..c0+V-1, c0+V) of system i at row offset o
+  auto load_row = [&](int i, long long o, double* u) {
     double pv[V + 2];
-    VecIO<PT, V>::load(Pold[i] + o + c0, pv + 1);
-    if (!FUSED || !first) {
-      pv[0] = (double)Pold[i][o + cl];
-      pv[V + 1] = (double)Pold[i][o + cr];
-    }
     if constexpr (FUSED) {
-      double zv[V + 2];
-      VecIO<ZT, V>::load(Zs[i] + o + c0, zv + 1);
-      zv[0] = (double)Zs[i][o + cl];
-      zv[V + 1] = (double)Zs[i][o + cr];
+      VecIO<ZT, V>::load(Zs[i] + o + c0, u + 1);
+      u[0] = (double)Zs[i][o + cl];
+      u[V + 1] = (double)Zs[i][o + cr];
+      if (!first) {
+        VecIO<PT, V>::load(Pold[i] + o + c0, pv + 1);
+        pv[0] = (double)Pold[i][o + cl];
+        pv[V + 1] = (double)Pold[i][o + cr];
 #pragma unroll
-      for (int k = 0; k < V; ++k) pc[k] = first ? 0.0 : pv[k + 1];
-#pragma unroll
-      for (int k = 0; k < V + 2; ++k) u[k] = first ? zv[k] : fma(be[i], pv[k], zv[k]);
+        for (int k = 0; k < V + 2; ++k) u[k] = fma(be[i], pv[k], u[k]);
+      }
     } else {
-#pragma unroll
-      for (int k = 0; k < V + 2; ++k) u[k] = pv[k];
+      VecIO<PT, V>::load(Pold[i] + o + c0, u + 1);
+      u[0] = (double)Pold[i][o + cl];
+      u[V + 1] = (double)Pold[i][o + cr];
     }
   };
 
   const int rm = wrap_dec(row0, n);
   double um[2][V + 2], uc[2][V + 2], up[2][V + 2];
-  double pcur[2][V], pnxt[2][V], pdummy[V];
   {
     const long long om = (long long)rm * n, oc = (long long)row0 * n;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      load_row(i, om, um[i], pdummy);
-      load_row(i, oc, uc[i], pcur[i]);
+      load_row(i, om, um[i]);
+      load_row(i, oc, uc[i]);
     }
   }
   double am[V + 1];   // a[row-1][c0-1 .. c0+V-1]
@@ -346,11 +353,11 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
     VecIO<double, V>::load(A + om + c0, am + 1);
   }
   double d[2] = {0.0, 0.0};
-  for (int j = 0; j < kStrip; ++j) {
+  for (int j = 0; j < H; ++j) {
     const int row = row0 + j;
     const long long op = (long long)wrap_inc(row, n) * n, oc = (long long)row * n;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) load_row(i, op, up[i], pnxt[i]);
+    for (int i = 0; i < 2; ++i) load_row(i, op, up[i]);
     double ac[V + 1];
     ac[0] = A[oc + cl];
     VecIO<double, V>::load(A + oc + c0, ac + 1);
@@ -365,21 +372,12 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
         qv[k] = q1_apply(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
       }
       if (act[i]) {
-        double* Q = q + (long long)(s0 + i) * N2 + oc + c0;
-        VecIO<double, V>::store(Q, qv);
+        VecIO<double, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
         if constexpr (FUSED) {
           double pn[V];
 #pragma unroll
           for (int k = 0; k < V; ++k) pn[k] = uc[i][k + 1];
           VecIO<PT, V>::store(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
-          if (!first) {
-            double* X = x + (long long)(s0 + i) * N2 + oc + c0;
-            double xv[V];
-            VecIO<double, V>::load(X, xv);
-#pragma unroll
-            for (int k = 0; k < V; ++k) xv[k] = fma(al[i], pcur[i][k], xv[k]);
-            VecIO<double, V>::store(X, xv);
-          }
         }
       }
 #pragma unroll
@@ -389,8 +387,6 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
         um[i][k] = uc[i][k];
         uc[i][k] = up[i][k];
       }
-#pragma unroll
-      for (int k = 0; k < V; ++k) pcur[i][k] = pnxt[i][k];
     }
 #pragma unroll
     for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
@@ -398,15 +394,16 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
   if constexpr (FUSED) {
     block_sum<2>(d, sh);
     if (threadIdx.x == 0) {
-      const int P = gridDim.x * gridDim.y;
-      const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+      const int P = gx * gy;
+      const int tile = by * gx + bx;
       part[(long long)s0 * P + tile] = d[0];
       part[(long long)s1 * P + tile] = d[1];
     }
   }
 }
 
-__global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, int P) {
+__global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, int P, double* alpha_hist,
+                               int m, int slot) {
   const int s = blockIdx.x, lane = threadIdx.x;
   if (!sys[s].active) return;
   double v = 0;
@@ -421,6 +418,7 @@ __global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, i
     } else {
       S.alpha = S.rz / v;
     }
+    alpha_hist[(long long)s * m + slot] = S.alpha;
   }
 }
 
@@ -465,26 +463,42 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
   }
 }
 
-// x += alpha p with each system's last step: the direction of its last
-// iteration sits in buffer (iters - 1) mod 2. Systems that never iterated
-// have alpha = 0.
+// x += alpha_j p_j for j = j0 .. min(j1, iters) - 1 in increasing j, each
+// direction read from its ring slot j mod m (m <= kRing, hi - j0 <= m). A system's iters counts the
+// iterations that produced a direction with a valid step length, so the
+// direction of a breakdown (alpha = 0) is never folded in.
 template <class PT>
-__global__ void __launch_bounds__(kBlock) k_finalize_x(double* __restrict__ x, const PT* __restrict__ p0,
-                                                        const PT* __restrict__ p1, const SysState* sys,
-                                                        long long N2) {
+__global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const PT* __restrict__ ring,
+                                                    long long slot_stride, int m,
+                                                    const double* __restrict__ alpha_hist, const SysState* sys,
+                                                    long long N2, int j0, int j1) {
   const int s = blockIdx.y;
-  const int it = sys[s].iters;
-  const double al = sys[s].alpha;
-  if (it <= 0 || al == 0.0) return;
-  const PT* P = ((it - 1) & 1) ? p1 : p0;
+  const int hi = min(min(j1, sys[s].iters), j0 + m);
+  if (hi <= j0) return;
   const long long off = (long long)s * N2;
   const long long stride = (long long)gridDim.x * kBlock * 4;
-  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
-    double xv[4], pv[4];
-    V4<double>::load(x + off + i, xv);
-    V4<PT>::load(P + off + i, pv);
+  // all (at most kRing) directions are loaded before the first fma, so each
+  // lane has them in flight together; indices past the range repeat the last
+  // direction (a cache hit) and are not used
+  double al[kRing];
+  long long so[kRing];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xv[k] = fma(al, pv[k], xv[k]);
+  for (int t = 0; t < kRing; ++t) {
+    const int slot = min(j0 + t, hi - 1) % m;
+    al[t] = alpha_hist[(long long)s * m + slot];
+    so[t] = slot * slot_stride + off;
+  }
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double xv[4], pv[kRing][4];
+    V4<double>::load(x + off + i, xv);
+#pragma unroll
+    for (int t = 0; t < kRing; ++t) V4<PT>::load(ring + so[t] + i, pv[t]);
+#pragma unroll
+    for (int t = 0; t < kRing; ++t)
+      if (j0 + t < hi) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xv[k] = fma(al[t], pv[t][k], xv[k]);
+      }
     V4<double>::store(x + off + i, xv);
   }
 }
@@ -837,35 +851,43 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st) {
 }
 
 
-// Columns per lane of the operator apply: the widest that divides the grid.
-int stencil_vec_default(int n) { return n % 256 == 0 ? 4 : n % 128 == 0 ? 2 : 1; }
-bool stencil_vec_valid(int n, int V) { return (V == 1 || V == 2 || V == 4) && n % (kWave * V) == 0; }
+// Default operator-apply shape: the widest column count that divides the
+// grid, 16-row strips.
+int stencil_choice_default(int n) { return (n % 256 == 0 ? 4 : n % 128 == 0 ? 2 : 1) + 8 * (kStrip / 16); }
+bool stencil_choice_valid(int n, int c) {
+  const int V = stencil_choice_V(c), H = stencil_choice_H(c);
+  if (c < 0 || !(V == 1 || V == 2 || V == 4) || !(H == 16 || H == 32 || H == 64)) return false;
+  return n % (kWave * V) == 0 && n % (4 * H) == 0;
+}
 
 template <bool FUSED, class PT, class ZT>
-void launch_stencil_t(int B, int n, int V, const double* a, const PT* pin, PT* pout, const ZT* z, double* x,
+void launch_stencil_t(int B, int n, int V, int H, const double* a, const PT* pin, PT* pout, const ZT* z,
                       double* q, const SysState* sys, double* part, int first, hipStream_t st) {
-  const dim3 g(n / (kWave * V), n / kTile, B), blk(kBlock);
+  const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1>), g, blk, 0, st, a, pin, pout, z, x, q, n, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
 }
 
 void launch_stencil_fused(const Work& w, int k, hipStream_t st) {
-  // iteration k writes p_k into buffer k mod 2 and reads p_{k-1} from the other
-  void* pout = (k & 1) ? w.p2 : w.p;
-  const void* pin = (k & 1) ? w.p : w.p2;
+  // iteration k writes p_k into ring slot k mod m and reads p_{k-1} from the previous slot
+  const size_t esz = w.mixed == 0 ? 8 : 4;
+  const size_t slot_bytes = (size_t)w.S * (size_t)w.N2 * esz;
+  char* ring = static_cast<char*>(w.pring);
+  void* pout = ring + (size_t)(k % w.m_ring) * slot_bytes;
+  const void* pin = ring + (size_t)((k + w.m_ring - 1) % w.m_ring) * slot_bytes;
   if (w.mixed == 0)
-    launch_stencil_t<true, double, double>(w.B, w.n, w.V, w.a, (const double*)pin, (double*)pout,
-                                           (const double*)w.z, w.x, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+    launch_stencil_t<true, double, double>(w.B, w.n, w.V, w.H, w.a, (const double*)pin, (double*)pout,
+                                           (const double*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
   else
-    launch_stencil_t<true, float, float>(w.B, w.n, w.V, w.a, (const float*)pin, (float*)pout, (const float*)w.z,
-                                         w.x, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+    launch_stencil_t<true, float, float>(w.B, w.n, w.V, w.H, w.a, (const float*)pin, (float*)pout,
+                                         (const float*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
 }
 
-int stencil_tiles_per_realization(int n, int V) { return (n / (kWave * V)) * (n / kTile); }
+int stencil_tiles_per_realization(int n, int V, int H) { return (n / (kWave * V)) * (n / (4 * H)); }
 
 void launch_update_r(const Work& w, int flexible, hipStream_t st) {
   const dim3 g(w.P_vec, w.S), blk(kBlock);
@@ -880,24 +902,27 @@ void launch_update_r(const Work& w, int flexible, hipStream_t st) {
                        (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
 }
 
-void launch_finalize_x(const Work& w, hipStream_t st) {
+void launch_fold_x(const Work& w, int j0, int j1, hipStream_t st) {
   const dim3 g(w.P_vec, w.S), blk(kBlock);
+  const long long slot = (long long)w.S * w.N2;
   if (w.mixed == 0)
-    hipLaunchKernelGGL((k_finalize_x<double>), g, blk, 0, st, w.x, (const double*)w.p, (const double*)w.p2,
-                       w.sys, w.N2);
+    hipLaunchKernelGGL((k_fold_x<double>), g, blk, 0, st, w.x, (const double*)w.pring, slot, w.m_ring,
+                       w.alpha_hist, w.sys, w.N2, j0, j1);
   else
-    hipLaunchKernelGGL((k_finalize_x<float>), g, blk, 0, st, w.x, (const float*)w.p, (const float*)w.p2,
-                       w.sys, w.N2);
+    hipLaunchKernelGGL((k_fold_x<float>), g, blk, 0, st, w.x, (const float*)w.pring, slot, w.m_ring,
+                       w.alpha_hist, w.sys, w.N2, j0, j1);
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  launch_stencil_t<false, double, double>(B, n, stencil_vec_default(n), a, u, (double*)nullptr,
-                                          (const double*)nullptr, (double*)nullptr, out, (const SysState*)nullptr,
-                                          (double*)nullptr, 0, st);
+  const int c = stencil_choice_default(n);
+  launch_stencil_t<false, double, double>(B, n, stencil_choice_V(c), stencil_choice_H(c), a, u, (double*)nullptr,
+                                          (const double*)nullptr, out, (const SysState*)nullptr, (double*)nullptr,
+                                          0, st);
 }
 
-void launch_scalar_alpha(const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_st);
+void launch_scalar_alpha(const Work& w, int k, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_st, w.alpha_hist,
+                     w.m_ring, k % w.m_ring);
 }
 
 

@@ -17,12 +17,17 @@ struct Work {
   const double* a = nullptr; // [B][n][n] cells
   double* x = nullptr;       // [S][n][n] iterate (grid units)
   double* r = nullptr;       // residual
-  // Search direction p and preconditioned residual z are FP64 when the
+  // Search directions p and preconditioned residual z are FP64 when the
   // transform GEMMs are FP64 and FP32 otherwise (mixed modes); they only
   // steer the iteration, while x, r and q = A p stay FP64, so r = f - A x
   // holds to FP64 rounding in every mode.
-  void* p = nullptr;         // directions of even iterations
-  void* p2 = nullptr;        // directions of odd iterations
+  // The directions live in a ring of m_ring slots, [m_ring][S][n][n]: p_k is
+  // written to slot k mod m_ring, and x is brought up to date only every
+  // m_ring iterations, from the directions in the ring and their step
+  // lengths alpha_hist[S][m_ring].
+  void* pring = nullptr;
+  int m_ring = 2;
+  double* alpha_hist = nullptr;
   double* q = nullptr;       // A p
   void* z = nullptr;
   void* rlo = nullptr;       // mixed modes: r rounded to the GEMM type, the first GEMM's input
@@ -30,6 +35,7 @@ struct Work {
   void* u2 = nullptr;
   int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
   int V = 1;                 // columns per lane of the operator apply
+  int H = 16;                // rows per wave strip of the operator apply
   int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0)
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
@@ -53,18 +59,30 @@ void launch_rhs(const Work& w, hipStream_t st);
 void launch_scalar_init(const Work& w, hipStream_t st);
 void launch_meansub(const Work& w, hipStream_t st);
 void launch_scalar_fnorm(const Work& w, hipStream_t st);
-void launch_scalar_alpha(const Work& w, hipStream_t st);
+// alpha_k = r.z / p.Ap from the operator-apply partials; also kept in
+// alpha_hist for the deferred x update.
+void launch_scalar_alpha(const Work& w, int k, hipStream_t st);
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
 // Fused direction step + operator apply of PCG iteration k, with w.V columns
-// per lane (w.P_st must equal stencil_tiles_per_realization(n, w.V)).
+// per lane and w.H rows per wave strip (w.P_st must equal
+// stencil_tiles_per_realization(n, w.V, w.H)).
 void launch_stencil_fused(const Work& w, int k, hipStream_t st);
-int stencil_vec_default(int n);
-bool stencil_vec_valid(int n, int V);
-int stencil_tiles_per_realization(int n, int V);
+// Operator-apply shapes, encoded as c = V + 8 (H / 16): V in {1, 2, 4}
+// columns per lane, H in {16, 32, 64} rows per strip; valid when the
+// 64V x 4H workgroup tile divides the n x n grid.
+int stencil_choice_default(int n);
+bool stencil_choice_valid(int n, int c);
+inline int stencil_choice_V(int c) { return c & 7; }
+inline int stencil_choice_H(int c) { return 16 * (c >> 3); }
+int stencil_tiles_per_realization(int n, int V, int H);
 void launch_update_r(const Work& w, int flexible, hipStream_t st);
-void launch_finalize_x(const Work& w, hipStream_t st);
+// x += alpha_j p_j for j = j0, j0+1, ... up to min(j1, iters) - 1 of each
+// system, in increasing j (the order of the plain recurrence). The range
+// must hold at most m_ring directions that are all still in the ring.
+void launch_fold_x(const Work& w, int j0, int j1, hipStream_t st);
+constexpr int kRing = 8;   // direction ring length (iterations per x update)
 void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);

@@ -24,6 +24,8 @@
 
 using namespace rve;
 
+static_assert(kRing == RVE_DIRECTION_RING, "direction ring length must match the header");
+
 namespace {
 
 constexpr int kMinN = 64, kMaxN = 4096;
@@ -37,8 +39,8 @@ struct Tables {
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
-// transform GEMMs of the preconditioner, 5 residual update, 6 final iterate
-// update.
+// transform GEMMs of the preconditioner, 5 residual update, 6 iterate update
+// from the direction ring.
 constexpr int kTimedClasses = 7;
 
 struct EventTimer {
@@ -152,7 +154,7 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
 
 // Carve the workspace of one equal-n batch; grows the arena if needed.
 struct Layout {
-  size_t off_x, off_r, off_p, off_p2, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
+  size_t off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_count, off_status, total;
 };
 
@@ -160,7 +162,8 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   Layout L{};
   const long long S = 2LL * B, N2 = (long long)n * n;
   const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
-  const int P_st = stencil_tiles_per_realization(n, stencil_vec_default(n));   // operator-apply tiles
+  const int sc = stencil_choice_default(n);
+  const int P_st = stencil_tiles_per_realization(n, stencil_choice_V(sc), stencil_choice_H(sc));
   long long vb = N2 / 1024;
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
@@ -173,8 +176,10 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   size_t o = 0;
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
-  L.off_p = o; o += pzvec;
-  L.off_p2 = o; o += pzvec;
+  // direction ring: kRing slots, fewer when maxit cannot use them
+  const int m_ring = maxit + 1 < kRing ? (maxit + 1 < 2 ? 2 : maxit + 1) : kRing;
+  L.off_ring = o; o += (size_t)m_ring * pzvec;
+  L.off_ahist = o; o += align_up((size_t)S * m_ring * 8);
   L.off_q = o; o += vec;
   L.off_z = o; o += pzvec;
   L.off_rlo = o; o += prec == RVE_FP64 ? 0 : uvec;
@@ -199,7 +204,9 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   w->P_vec = P_vec;
   w->P_gemm = P_gemm;
   w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
-  w->V = stencil_vec_default(n);
+  w->V = stencil_choice_V(sc);
+  w->H = stencil_choice_H(sc);
+  w->m_ring = m_ring;
   w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
 }
@@ -224,8 +231,8 @@ void bind(rve_ctx* ctx, const Layout& L, Work* w) {
   char* base = static_cast<char*>(ctx->ws);
   w->x = reinterpret_cast<double*>(base + L.off_x);
   w->r = reinterpret_cast<double*>(base + L.off_r);
-  w->p = base + L.off_p;
-  w->p2 = base + L.off_p2;
+  w->pring = base + L.off_ring;
+  w->alpha_hist = reinterpret_cast<double*>(base + L.off_ahist);
   w->q = reinterpret_cast<double*>(base + L.off_q);
   w->z = base + L.off_z;
   w->rlo = w->mixed ? base + L.off_rlo : nullptr;
@@ -322,7 +329,9 @@ void save_tune_entry(rve_ctx* ctx, const TuneKey& k, int choice, const std::vect
 template <class F>
 int tune_pick(rve_ctx* ctx, const TuneKey& key, const std::vector<int>& cands, F launch) {
   auto it = ctx->tune.find(key);
-  if (it != ctx->tune.end()) return it->second;
+  // a cached choice is used only if it is a candidate for this shape
+  if (it != ctx->tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+    return it->second;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return cands[0];
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -412,7 +421,7 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
   launch_scalar_fnorm(w, st);
 
   // kernel variants: defaults, or the autotuner's choice for this shape
-  w.V = stencil_vec_default(n);
+  int sc = stencil_choice_default(n);
   w.gemm_variant = gemm_variant_valid(n, prec, 1) ? 1 : 0;
   const int bb = batch_bucket(B);
   const TuneKey kst(0, n, o->prec, bb), kgm(1, n, o->prec, bb);
@@ -436,28 +445,37 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
   if (ctx->autotune) {
     std::vector<int> vc;
     for (int v : {1, 2, 4})
-      if (stencil_vec_valid(n, v)) vc.push_back(v);
+      for (int hs : {16, 64})
+        if (stencil_choice_valid(n, v + 8 * (hs / 16))) vc.push_back(v + 8 * (hs / 16));
     if (ctx->tune.count(kst) || tune_now)
-      w.V = tune_pick(ctx, kst, vc, [&](int v) {
+      sc = tune_pick(ctx, kst, vc, [&](int c) {
         Work t2 = w;
-        t2.V = v;
-        t2.P_st = stencil_tiles_per_realization(n, v);
+        t2.V = stencil_choice_V(c);
+        t2.H = stencil_choice_H(c);
+        t2.P_st = stencil_tiles_per_realization(n, t2.V, t2.H);
         launch_stencil_fused(t2, 0, st);
       });
   }
-  w.P_st = stencil_tiles_per_realization(n, w.V);
+  w.V = stencil_choice_V(sc);
+  w.H = stencil_choice_H(sc);
+  w.P_st = stencil_tiles_per_realization(n, w.V, w.H);
 
-  // iteration k: p_k = z_k + beta p_{k-1} and x += alpha_{k-1} p_{k-1} inside
-  // the operator apply, alpha_k, r update, convergence, then z_{k+1}, beta_k
+  // iteration k: p_k = z_k + beta p_{k-1} inside the operator apply, alpha_k,
+  // r update, convergence, then z_{k+1}, beta_k. Every m_ring iterations the
+  // directions in the ring are folded into x before their slots are reused.
   int enq = 0, chunk_idx = 0;
   for (;;) {
     const int end = std::min(enq + chunk, o->maxit);
     for (; enq < end; ++enq) {
+      if (enq > 0 && enq % w.m_ring == 0) {
+        Timed t(ctx, 6);
+        launch_fold_x(w, enq - w.m_ring, enq, st);
+      }
       {
         Timed t(ctx, 0);
         launch_stencil_fused(w, enq, st);
       }
-      launch_scalar_alpha(w, st);
+      launch_scalar_alpha(w, enq, st);
       {
         Timed t(ctx, 5);
         launch_update_r(w, flexible, st);
@@ -483,8 +501,9 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
     ++chunk_idx;
   }
   {
+    // the directions since the last fold (iterations enq-1 and before)
     Timed t(ctx, 6);
-    launch_finalize_x(w, st);
+    launch_fold_x(w, ((enq - 1) / w.m_ring) * w.m_ring, o->maxit, st);
   }
 
   launch_ahom(w, st);

@@ -76,3 +76,15 @@ def test_host_argument_validation(lib):
     assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, 10.0, None) == N.EINVAL
     assert lib.rve_apply_operator(fake, 1, 64, fake, fake, fake) == N.EINVAL   # u aliases out
     assert lib.rve_apply_precond(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL
+
+
+def test_header_constants_match_binding():
+    from paper_1903_12227_amd import _native as N
+    src = open(HEADER).read()
+    m = re.search(r"#define\s+RVE_DIRECTION_RING\s+(\d+)", src)
+    assert m and int(m.group(1)) == N.DIRECTION_RING
+    for name, val in (("RVE_OK", N.OK), ("RVE_NOT_CONVERGED", N.NOT_CONVERGED), ("RVE_BREAKDOWN", N.BREAKDOWN),
+                      ("RVE_EINVAL", N.EINVAL), ("RVE_EHIP", N.EHIP), ("RVE_ENOMEM", N.ENOMEM),
+                      ("RVE_FP64", N.FP64), ("RVE_MIX_FP32", N.MIX_FP32), ("RVE_MIX_BF16", N.MIX_BF16)):
+        m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
+        assert m and int(m.group(1)) == val, name
