@@ -326,8 +326,11 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
         VecIO<PT, V>::load(Pold[i] + o + c0, pv + 1);
         pv[0] = (double)Pold[i][o + cl];
         pv[V + 1] = (double)Pold[i][o + cr];
+        // p_k is rounded to its storage type before it is used, so q = A p_k,
+        // p_k.q and the later x += alpha p_k all see the same direction and
+        // the recursive residual stays f - A x to FP64 rounding
 #pragma unroll
-        for (int k = 0; k < V + 2; ++k) u[k] = fma(be[i], pv[k], u[k]);
+        for (int k = 0; k < V + 2; ++k) u[k] = (double)(PT)fma(be[i], pv[k], u[k]);
       }
     } else {
       VecIO<PT, V>::load(Pold[i] + o + c0, u + 1);
@@ -381,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
         }
       }
 #pragma unroll
-      for (int k = 0; k < V; ++k) d[i] += (double)(PT)uc[i][k + 1] * qv[k];
+      for (int k = 0; k < V; ++k) d[i] += uc[i][k + 1] * qv[k];
 #pragma unroll
       for (int k = 0; k < V + 2; ++k) {
         um[i][k] = uc[i][k];

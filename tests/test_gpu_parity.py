@@ -120,6 +120,26 @@ def test_mixed_precision_matches_oracle(dev, prec, n):
         assert rel2(A[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_true_residual_meets_tolerance(dev, prec):
+    # The stopping test reads the recursively updated residual; it must stay
+    # the true residual f - A x (to FP64 rounding) in every precision, since
+    # x, r and q = A p are all updated with the same stored direction p.
+    rve = _rve()
+    n, B, tol = 128, 2, 1e-10
+    a = _fields(n, B, 14)
+    h = 1.0 / 8
+    res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=tol, prec=prec))
+    assert res.code == 0
+    x = res.phi.cpu().numpy() / h
+    for b in range(B):
+        A = q1.assemble(a[b])
+        for i, f in enumerate(q1.rhs(a[b])):
+            f = f - f.mean()
+            true = np.linalg.norm(f.ravel() - A @ x[b, i].ravel()) / np.linalg.norm(f)
+            assert true <= 2.0 * tol, (b, i, true)
+
+
 def test_uneven_batch_matches_oracle(dev):
     rve = _rve()
     items = []
