@@ -196,14 +196,15 @@ const char* rve_status_string(int status);
  * Autotuner. With mode 1 (the default), the first solve of each
  * (n, precision, floor(log2 B)) times the candidate kernel variants on the
  * live data and keeps the fastest: the shape of the operator apply (V = 1, 2
- * or 4 grid columns per lane, H = 16 or 64 rows per wave strip) and the
- * transform-GEMM tile (64 x 64, or 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
+ * or 4 grid columns per lane, H = 16 or 64 rows per wave strip, D = 1 or 2
+ * rows of loads in flight per wave) and the transform-GEMM tile (64 x 64,
+ * or 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
  * and, if the environment variable RVE_TUNE_CACHE names a file, appended
  * there as JSON lines and read back by rve_create. Mode 0 uses fixed
  * defaults. Results do not depend on the choice beyond rounding order.
  *
  * rve_get_tuned: *choice for kind 0 (operator-apply shape, encoded as
- * V + 8 (H / 16)) or 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128) of a shape,
+ * V + 8 (H / 16) + 64 (D - 1)) or 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128) of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
  * that are not valid for a shape are ignored and tuned again.
  */

@@ -80,9 +80,9 @@ class Context:
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
 
     def tuned(self, n: int, prec: int, B: int) -> dict:
-        """The autotuner's choices for a shape: columns per lane and rows per
-        wave strip of the operator apply, and the transform-GEMM tile variant
-        (-1: not tuned)."""
+        """The autotuner's choices for a shape: columns per lane, rows per
+        wave strip and rows of loads in flight per wave of the operator
+        apply, and the transform-GEMM tile variant (-1: not tuned)."""
         got = []
         for kind in (0, 1):
             c = ctypes.c_int(-1)
@@ -90,7 +90,8 @@ class Context:
             got.append(c.value)
         st = got[0]
         return {"stencil_columns_per_lane": st & 7 if st >= 0 else -1,
-                "stencil_rows_per_strip": 16 * (st >> 3) if st >= 0 else -1,
+                "stencil_rows_per_strip": 16 * ((st >> 3) & 7) if st >= 0 else -1,
+                "stencil_prefetch_rows": 1 + ((st >> 6) & 1) if st >= 0 else -1,
                 "gemm_variant": got[1]}
 
     def close(self):

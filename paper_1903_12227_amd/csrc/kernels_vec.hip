@@ -272,28 +272,46 @@ template <int V> struct VecIO<float, V> {
   }
 };
 
+// Loads of V consecutive values into registers of their own type (no
+// conversion, so the values may stay in flight while other work proceeds).
+template <class T, int V> struct alignas(sizeof(T) * V) Pack { T e[V]; };
+template <class T, int V>
+__device__ inline void raw_load(const T* p, T* v) {
+  constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;   // elements per load
+#pragma unroll
+  for (int k = 0; k < V; k += C) {
+    const Pack<T, C> t = *reinterpret_cast<const Pack<T, C>*>(p + k);
+#pragma unroll
+    for (int e = 0; e < C; ++e) v[k + e] = t.e[e];
+  }
+}
+
 // Operator apply over V consecutive columns per lane for both systems of a
 // realization. A workgroup covers 64V columns x 4H rows; each of its four
 // waves slides a three-row register window down an H-row strip, so every
 // value is loaded about once (plus two halo rows per strip) and the +-1
-// columns come from the cache lines just loaded. FUSED: the operand is the
-// new search direction p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on
-// the fly for the V nodes and their neighbours; p_k goes to a ring slot other
-// than p_{k-1}'s (neighbouring workgroups still read p_{k-1} at tile edges),
-// and q = A p_k is written with partial sums of p_k.q (active systems only).
-// Not FUSED: q = A u for a caller's u (the plain operator apply).
+// columns come from the cache lines just loaded. With D = 2 the loads of the
+// next row are issued one row ahead of their use (two row buffers that swap
+// roles), so each wave keeps two rows of loads in flight.
+// FUSED: the operand is the new search direction
+// p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on the fly for the V
+// nodes and their neighbours; p_k goes to a ring slot other than p_{k-1}'s
+// (neighbouring workgroups still read p_{k-1} at tile edges), and q = A p_k
+// is written with partial sums of p_k.q (active systems only). Not FUSED:
+// q = A u for a caller's u (the plain operator apply).
 //
 // One-dimensional grid of gx * gy * B workgroups. The hardware hands
 // consecutive workgroup ids to the eight XCDs in turn; the id is remapped so
 // that each XCD receives a contiguous run of tiles (all tiles of a few
 // realizations, neighbours next to each other in time), and halo lines
 // fetched by one tile are found in that XCD's L2 by its neighbours.
-template <bool FUSED, class PT, class ZT, int V>
+template <bool FUSED, class PT, class ZT, int V, int D>
 __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a,
                                                        const PT* __restrict__ p_old, PT* __restrict__ p_new,
                                                        const ZT* __restrict__ z, double* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part,
                                                        int first) {
+  static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
   const int gx = n / (kWave * V), gy = n / (4 * H);
   const unsigned T = gridDim.x, L = blockIdx.x;
@@ -314,56 +332,87 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
   const double* A = a + (long long)b * N2;
   const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
   const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
+  const bool need_p = !FUSED || !first;
 
-  // operand row (V + 2 values: column c0-1, c0..c0+V-1, c0+V) of system i at row offset o
-  auto load_row = [&](int i, long long o, double* u) {
-    double pv[V + 2];
+  // raw operand row o (V + 2 values per system: column c0-1, c0..c0+V-1,
+  // c0+V) and coefficient row oa (V + 1 values: c0-1 .. c0+V-1)
+  struct Raw {
+    ZT z[2][V + 2];
+    PT p[2][V + 2];
+    double a[V + 1];
+  };
+  auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if constexpr (FUSED) {
+        raw_load<ZT, V>(Zs[i] + o + c0, &R.z[i][1]);
+        R.z[i][0] = Zs[i][o + cl];
+        R.z[i][V + 1] = Zs[i][o + cr];
+      }
+      if (need_p) {
+        raw_load<PT, V>(Pold[i] + o + c0, &R.p[i][1]);
+        R.p[i][0] = Pold[i][o + cl];
+        R.p[i][V + 1] = Pold[i][o + cr];
+      }
+    }
+    if (with_a) {
+      R.a[0] = A[oa + cl];
+      raw_load<double, V>(A + oa + c0, &R.a[1]);
+    }
+  };
+  // operand values of system i from a raw row
+  auto cook = [&](const Raw& R, int i, double* u) {
     if constexpr (FUSED) {
-      VecIO<ZT, V>::load(Zs[i] + o + c0, u + 1);
-      u[0] = (double)Zs[i][o + cl];
-      u[V + 1] = (double)Zs[i][o + cr];
-      if (!first) {
-        VecIO<PT, V>::load(Pold[i] + o + c0, pv + 1);
-        pv[0] = (double)Pold[i][o + cl];
-        pv[V + 1] = (double)Pold[i][o + cr];
+      if (first) {
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) u[k] = (double)R.z[i][k];
+      } else {
         // p_k is rounded to its storage type before it is used, so q = A p_k,
         // p_k.q and the later x += alpha p_k all see the same direction and
         // the recursive residual stays f - A x to FP64 rounding
 #pragma unroll
-        for (int k = 0; k < V + 2; ++k) u[k] = (double)(PT)fma(be[i], pv[k], u[k]);
+        for (int k = 0; k < V + 2; ++k) u[k] = (double)(PT)fma(be[i], (double)R.p[i][k], (double)R.z[i][k]);
       }
     } else {
-      VecIO<PT, V>::load(Pold[i] + o + c0, u + 1);
-      u[0] = (double)Pold[i][o + cl];
-      u[V + 1] = (double)Pold[i][o + cr];
+#pragma unroll
+      for (int k = 0; k < V + 2; ++k) u[k] = (double)R.p[i][k];
     }
   };
 
   const int rm = wrap_dec(row0, n);
-  double um[2][V + 2], uc[2][V + 2], up[2][V + 2];
+  double um[2][V + 2], uc[2][V + 2], am[V + 1];
+  Raw R0, R1;
   {
-    const long long om = (long long)rm * n, oc = (long long)row0 * n;
+    load_raw(R0, (long long)rm * n, (long long)rm * n, true);
+    load_raw(R1, (long long)row0 * n, 0, false);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      load_row(i, om, um[i]);
-      load_row(i, oc, uc[i]);
+      cook(R0, i, um[i]);
+      cook(R1, i, uc[i]);
     }
-  }
-  double am[V + 1];   // a[row-1][c0-1 .. c0+V-1]
-  {
-    const long long om = (long long)rm * n;
-    am[0] = A[om + cl];
-    VecIO<double, V>::load(A + om + c0, am + 1);
-  }
-  double d[2] = {0.0, 0.0};
-  for (int j = 0; j < H; ++j) {
-    const int row = row0 + j;
-    const long long op = (long long)wrap_inc(row, n) * n, oc = (long long)row * n;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) load_row(i, op, up[i]);
-    double ac[V + 1];
-    ac[0] = A[oc + cl];
-    VecIO<double, V>::load(A + oc + c0, ac + 1);
+    for (int k = 0; k < V + 1; ++k) am[k] = R0.a[k];   // a[row-1][c0-1 .. c0+V-1]
+  }
+  if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true);
+
+  double d[2] = {0.0, 0.0};
+  // node row `row`: `use` holds (or receives, D = 1) operand row row+1 and
+  // coefficient row `row`; with D = 2 `fill` receives the next ones
+  auto step = [&](int j, Raw& use, Raw& fill) {
+    const int row = row0 + j;
+    const long long oc = (long long)row * n;
+    if constexpr (D == 1) {
+      load_raw(use, (long long)wrap_inc(row, n) * n, oc, true);
+    } else {
+      if (j + 1 < H) {
+        const int r1 = wrap_inc(row, n);
+        load_raw(fill, (long long)wrap_inc(r1, n) * n, (long long)r1 * n, true);
+      }
+    }
+    double up[2][V + 2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) cook(use, i, up[i]);
+    const double* ac = use.a;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       double qv[V];
@@ -393,6 +442,14 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
     }
 #pragma unroll
     for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
+  };
+  if constexpr (D == 1) {
+    for (int j = 0; j < H; ++j) step(j, R0, R0);
+  } else {
+    for (int j = 0; j < H; j += 2) {   // H is even; the two buffers swap roles
+      step(j, R0, R1);
+      step(j + 1, R1, R0);
+    }
   }
   if constexpr (FUSED) {
     block_sum<2>(d, sh);
@@ -858,21 +915,34 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st) {
 // grid, 16-row strips.
 int stencil_choice_default(int n) { return (n % 256 == 0 ? 4 : n % 128 == 0 ? 2 : 1) + 8 * (kStrip / 16); }
 bool stencil_choice_valid(int n, int c) {
-  const int V = stencil_choice_V(c), H = stencil_choice_H(c);
-  if (c < 0 || !(V == 1 || V == 2 || V == 4) || !(H == 16 || H == 32 || H == 64)) return false;
-  return n % (kWave * V) == 0 && n % (4 * H) == 0;
+  const int V = stencil_choice_V(c), H = stencil_choice_H(c), D = stencil_choice_D(c);
+  if (c < 0 || c >= 128 || !(V == 1 || V == 2 || V == 4) || !(H == 16 || H == 32 || H == 64)) return false;
+  return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
-template <bool FUSED, class PT, class ZT>
-void launch_stencil_t(int B, int n, int V, int H, const double* a, const PT* pin, PT* pout, const ZT* z,
+template <bool FUSED, class PT, class ZT, int D>
+void launch_stencil_d(int B, int n, int V, int H, const double* a, const PT* pin, PT* pout, const ZT* z,
                       double* q, const SysState* sys, double* part, int first, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
+                       first);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
+                       first);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part, first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
+                       first);
+}
+
+template <bool FUSED, class PT, class ZT>
+void launch_stencil_t(int B, int n, int c, const double* a, const PT* pin, PT* pout, const ZT* z, double* q,
+                      const SysState* sys, double* part, int first, hipStream_t st) {
+  const int V = stencil_choice_V(c), H = stencil_choice_H(c);
+  if (stencil_choice_D(c) == 2)
+    launch_stencil_d<FUSED, PT, ZT, 2>(B, n, V, H, a, pin, pout, z, q, sys, part, first, st);
+  else
+    launch_stencil_d<FUSED, PT, ZT, 1>(B, n, V, H, a, pin, pout, z, q, sys, part, first, st);
 }
 
 void launch_stencil_fused(const Work& w, int k, hipStream_t st) {
@@ -883,14 +953,16 @@ void launch_stencil_fused(const Work& w, int k, hipStream_t st) {
   void* pout = ring + (size_t)(k % w.m_ring) * slot_bytes;
   const void* pin = ring + (size_t)((k + w.m_ring - 1) % w.m_ring) * slot_bytes;
   if (w.mixed == 0)
-    launch_stencil_t<true, double, double>(w.B, w.n, w.V, w.H, w.a, (const double*)pin, (double*)pout,
+    launch_stencil_t<true, double, double>(w.B, w.n, w.stencil, w.a, (const double*)pin, (double*)pout,
                                            (const double*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
   else
-    launch_stencil_t<true, float, float>(w.B, w.n, w.V, w.H, w.a, (const float*)pin, (float*)pout,
+    launch_stencil_t<true, float, float>(w.B, w.n, w.stencil, w.a, (const float*)pin, (float*)pout,
                                          (const float*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
 }
 
-int stencil_tiles_per_realization(int n, int V, int H) { return (n / (kWave * V)) * (n / (4 * H)); }
+int stencil_tiles_per_realization(int n, int c) {
+  return (n / (kWave * stencil_choice_V(c))) * (n / (4 * stencil_choice_H(c)));
+}
 
 void launch_update_r(const Work& w, int flexible, hipStream_t st) {
   const dim3 g(w.P_vec, w.S), blk(kBlock);
@@ -917,8 +989,7 @@ void launch_fold_x(const Work& w, int j0, int j1, hipStream_t st) {
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  const int c = stencil_choice_default(n);
-  launch_stencil_t<false, double, double>(B, n, stencil_choice_V(c), stencil_choice_H(c), a, u, (double*)nullptr,
+  launch_stencil_t<false, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr,
                                           (const double*)nullptr, out, (const SysState*)nullptr, (double*)nullptr,
                                           0, st);
 }

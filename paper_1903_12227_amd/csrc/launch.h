@@ -34,8 +34,7 @@ struct Work {
   void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
   void* u2 = nullptr;
   int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
-  int V = 1;                 // columns per lane of the operator apply
-  int H = 16;                // rows per wave strip of the operator apply
+  int stencil = 0;           // operator-apply shape (stencil_choice_*)
   int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0)
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
@@ -65,18 +64,19 @@ void launch_scalar_alpha(const Work& w, int k, hipStream_t st);
 void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
-// Fused direction step + operator apply of PCG iteration k, with w.V columns
-// per lane and w.H rows per wave strip (w.P_st must equal
-// stencil_tiles_per_realization(n, w.V, w.H)).
+// Fused direction step + operator apply of PCG iteration k in the shape
+// w.stencil (w.P_st must equal stencil_tiles_per_realization(n, w.stencil)).
 void launch_stencil_fused(const Work& w, int k, hipStream_t st);
-// Operator-apply shapes, encoded as c = V + 8 (H / 16): V in {1, 2, 4}
-// columns per lane, H in {16, 32, 64} rows per strip; valid when the
-// 64V x 4H workgroup tile divides the n x n grid.
+// Operator-apply shapes, encoded as c = V + 8 (H / 16) + 64 (D - 1): V in
+// {1, 2, 4} columns per lane, H in {16, 32, 64} rows per wave strip, D in
+// {1, 2} rows of loads in flight per wave; valid when the 64V x 4H
+// workgroup tile divides the n x n grid.
 int stencil_choice_default(int n);
 bool stencil_choice_valid(int n, int c);
 inline int stencil_choice_V(int c) { return c & 7; }
-inline int stencil_choice_H(int c) { return 16 * (c >> 3); }
-int stencil_tiles_per_realization(int n, int V, int H);
+inline int stencil_choice_H(int c) { return 16 * ((c >> 3) & 7); }
+inline int stencil_choice_D(int c) { return 1 + ((c >> 6) & 1); }
+int stencil_tiles_per_realization(int n, int c);
 void launch_update_r(const Work& w, int flexible, hipStream_t st);
 // x += alpha_j p_j for j = j0, j0+1, ... up to min(j1, iters) - 1 of each
 // system, in increasing j (the order of the plain recurrence). The range

@@ -163,7 +163,7 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   const long long S = 2LL * B, N2 = (long long)n * n;
   const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
   const int sc = stencil_choice_default(n);
-  const int P_st = stencil_tiles_per_realization(n, stencil_choice_V(sc), stencil_choice_H(sc));
+  const int P_st = stencil_tiles_per_realization(n, sc);
   long long vb = N2 / 1024;
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
@@ -204,8 +204,7 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   w->P_vec = P_vec;
   w->P_gemm = P_gemm;
   w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
-  w->V = stencil_choice_V(sc);
-  w->H = stencil_choice_H(sc);
+  w->stencil = sc;
   w->m_ring = m_ring;
   w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
@@ -446,19 +445,20 @@ int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const
     std::vector<int> vc;
     for (int v : {1, 2, 4})
       for (int hs : {16, 64})
-        if (stencil_choice_valid(n, v + 8 * (hs / 16))) vc.push_back(v + 8 * (hs / 16));
+        for (int d : {1, 2}) {
+          const int c = v + 8 * (hs / 16) + 64 * (d - 1);
+          if (stencil_choice_valid(n, c)) vc.push_back(c);
+        }
     if (ctx->tune.count(kst) || tune_now)
       sc = tune_pick(ctx, kst, vc, [&](int c) {
         Work t2 = w;
-        t2.V = stencil_choice_V(c);
-        t2.H = stencil_choice_H(c);
-        t2.P_st = stencil_tiles_per_realization(n, t2.V, t2.H);
+        t2.stencil = c;
+        t2.P_st = stencil_tiles_per_realization(n, c);
         launch_stencil_fused(t2, 0, st);
       });
   }
-  w.V = stencil_choice_V(sc);
-  w.H = stencil_choice_H(sc);
-  w.P_st = stencil_tiles_per_realization(n, w.V, w.H);
+  w.stencil = sc;
+  w.P_st = stencil_tiles_per_realization(n, sc);
 
   // iteration k: p_k = z_k + beta p_{k-1} inside the operator apply, alpha_k,
   // r update, convergence, then z_{k+1}, beta_k. Every m_ring iterations the
