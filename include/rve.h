@@ -86,7 +86,8 @@ typedef struct rve_opts {
   int flexible;      /* 1: flexible (Polak-Ribiere) beta; 0: standard beta.
                         Negative: automatic (standard). */
   int check_every;   /* host polls the all-converged flag every this many
-                        iterations; <= 0 selects a default */
+                        iterations, rounded up to a multiple of
+                        RVE_DIRECTION_RING; <= 0: every RVE_DIRECTION_RING */
 } rve_opts;
 
 typedef struct rve_ctx rve_ctx;
@@ -117,6 +118,10 @@ int rve_set_stream(rve_ctx* ctx, void* hip_stream);
  * Returns the worst status over items (EINVAL/EHIP/ENOMEM before warnings).
  * Blocks the host on polls of the convergence flag (every check_every
  * iterations) and at the end, when it reads the per-item statuses.
+ * The iterations run in chunks of RVE_DIRECTION_RING, each replayed from a
+ * HIP graph captured on first use (see rve_set_graphs); a solve may run up
+ * to one chunk past the iteration where its last system stopped (those
+ * launches find no active system and return at once).
  */
 int rve_solve_batch(rve_ctx* ctx, int B, int n, double h, const double* a_dev,
                     const rve_opts* opts, double* phi_dev, double* ahom_dev,
@@ -132,7 +137,10 @@ int rve_solve_batch(rve_ctx* ctx, int B, int n, double h, const double* a_dev,
  *   phi_dev            packed like a_dev but with 2 n_b^2 nodes per item at
  *                      offset 2*cell_off[b], or NULL
  *   other outputs      as rve_solve_batch, indexed by item
- * Items of equal n are solved together; offsets must be non-overlapping.
+ * Items are grouped by n (each group one batch as in rve_solve_batch) and
+ * all groups iterate together: one captured chunk of iterations covers
+ * every size, and one convergence poll serves the whole call. Offsets must
+ * be non-overlapping.
  */
 int rve_solve_uneven(rve_ctx* ctx, int B, const int* n_host,
                      const int64_t* cell_off_host, double h, const double* a_dev,
@@ -209,6 +217,14 @@ const char* rve_status_string(int status);
  * that are not valid for a shape are ignored and tuned again.
  */
 int rve_set_autotune(rve_ctx* ctx, int mode);
+
+/* Chunks of PCG iterations: mode 1 (the default) captures each distinct
+ * chunk (same batches, pointers, kernel choices and options) once as a HIP
+ * graph, cached in the context, and replays it; mode 0 launches every
+ * kernel one by one. Both run the same kernels in the same order, so the
+ * results are identical to the last bit. While kernel timing is on
+ * (rve_set_timing) chunks are always launched one by one. */
+int rve_set_graphs(rve_ctx* ctx, int mode);
 int rve_get_tuned(rve_ctx* ctx, int kind, int n, int prec, int B, int* choice);
 
 /* Event timing of kernel classes on the context's stream. rve_set_timing

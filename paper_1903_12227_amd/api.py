@@ -79,6 +79,11 @@ class Context:
     def set_autotune(self, enable: bool):
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
 
+    def set_graphs(self, enable: bool):
+        """Replay each chunk of PCG iterations from a captured HIP graph (the
+        default) or launch its kernels one by one; results are identical."""
+        N.check(self._lib.rve_set_graphs(self.handle, int(bool(enable))), "rve_set_graphs")
+
     def tuned(self, n: int, prec: int, B: int) -> dict:
         """The autotuner's choices for a shape: columns per lane, rows per
         wave strip and rows of loads in flight per wave of the operator

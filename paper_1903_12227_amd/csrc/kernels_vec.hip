@@ -52,13 +52,24 @@ template <> struct V4<__bf16> {
   }
 };
 
-__global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B,
-                                                        int* count, int count_len) {
+__global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int stride = gridDim.x * kBlock;
   for (int i = t; i < S; i += stride) sys[i] = SysState{};
   for (int i = t; i < B; i += stride) real[i] = RealState{};
+}
+
+// Iteration counter and per-iteration counts of the systems still iterating,
+// shared by every batch of one solve.
+__global__ void __launch_bounds__(kBlock) k_ctl_reset(int* kiter, int* count, int count_len) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int stride = gridDim.x * kBlock;
+  if (t == 0) kiter[0] = 0;
   for (int i = t; i < count_len; i += stride) count[i] = 0;
+}
+
+__global__ void k_advance(int* kiter) {
+  if (threadIdx.x == 0) kiter[0] += 1;
 }
 
 // Galerkin right-hand sides f_i = -int a d(psi)/dx_i, integrated exactly per
@@ -305,14 +316,26 @@ __device__ inline void raw_load(const T* p, T* v) {
 // that each XCD receives a contiguous run of tiles (all tiles of a few
 // realizations, neighbours next to each other in time), and halo lines
 // fetched by one tile are found in that XCD's L2 by its neighbours.
+//
+// FUSED: iteration k is read from *kiter; p_k goes to ring slot k mod m and
+// p_{k-1} comes from slot (k - 1) mod m (slots slot_stride elements apart).
+// Not FUSED: the operand is p_in.
 template <bool FUSED, class PT, class ZT, int V, int D>
-__global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a,
-                                                       const PT* __restrict__ p_old, PT* __restrict__ p_new,
+__global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a, const PT* p_in, PT* ring,
+                                                       long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, double* __restrict__ q, int n,
-                                                       int H, const SysState* sys, double* __restrict__ part,
-                                                       int first) {
+                                                       int H, const SysState* sys, double* __restrict__ part) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
+  int first = 0;
+  const PT* __restrict__ p_old = p_in;
+  PT* __restrict__ p_new = nullptr;
+  if constexpr (FUSED) {
+    const int k = kiter[0];
+    first = k == 0;
+    p_new = ring + (long long)(k % m) * slot_stride;
+    p_old = ring + (long long)((k + m - 1) % m) * slot_stride;
+  }
   const int gx = n / (kWave * V), gy = n / (4 * H);
   const unsigned T = gridDim.x, L = blockIdx.x;
   const unsigned t = (T & 7u) ? L : (L & 7u) * (T >> 3) + (L >> 3);
@@ -463,9 +486,10 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
 }
 
 __global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, int P, double* alpha_hist,
-                               int m, int slot) {
+                               int m, const int* kiter) {
   const int s = blockIdx.x, lane = threadIdx.x;
   if (!sys[s].active) return;
+  const int slot = kiter[0] % m;
   double v = 0;
   for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
   v = wave_sum(v);
@@ -527,12 +551,19 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
 // direction read from its ring slot j mod m (m <= kRing, hi - j0 <= m). A system's iters counts the
 // iterations that produced a direction with a valid step length, so the
 // direction of a breakdown (alpha = 0) is never folded in.
+//
+// final = 0: the fold at the start of iteration k (a multiple of m), over the
+// m directions before it; final = 1: the fold after the last iteration K,
+// over the directions since the last multiple of m.
 template <class PT>
 __global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const PT* __restrict__ ring,
                                                     long long slot_stride, int m,
                                                     const double* __restrict__ alpha_hist, const SysState* sys,
-                                                    long long N2, int j0, int j1) {
+                                                    long long N2, const int* kiter, int final) {
   const int s = blockIdx.y;
+  const int k = kiter[0];
+  const int j0 = final ? (k > 0 ? ((k - 1) / m) * m : 0) : (k > m ? k - m : 0);
+  const int j1 = k;
   const int hi = min(min(j1, sys[s].iters), j0 + m);
   if (hi <= j0) return;
   const long long off = (long long)s * N2;
@@ -564,10 +595,11 @@ __global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const
 }
 
 __global__ void k_scalar_conv(SysState* sys, const double* __restrict__ part, int P, double tol, int maxit,
-                              int* count_slot, int S) {
+                              int* count, const int* kiter) {
   // one wave per system; blockDim = 64
   const int s = blockIdx.x, lane = threadIdx.x;
   if (!sys[s].active) return;
+  int* count_slot = count + kiter[0];
   double v = 0;
   for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
   v = wave_sum(v);
@@ -876,13 +908,20 @@ inline int vec_blocks(long long N2) {
 
 // ---------------------------------------------------------------- launchers
 
-void launch_init_state(const Work& w, int count_len, hipStream_t st) {
-  int m = w.S > count_len ? w.S : count_len;
-  int blocks = (m + kBlock - 1) / kBlock;
+void launch_init_state(const Work& w, hipStream_t st) {
+  int blocks = (w.S + kBlock - 1) / kBlock;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(kBlock), 0, st, w.sys, w.real, w.S, w.B, w.count,
-                     count_len);
+  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(kBlock), 0, st, w.sys, w.real, w.S, w.B);
 }
+
+void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st) {
+  int blocks = (count_len + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_ctl_reset, dim3(blocks), dim3(kBlock), 0, st, kiter, count, count_len);
+}
+
+void launch_advance(int* kiter, hipStream_t st) { hipLaunchKernelGGL(k_advance, dim3(1), dim3(kWave), 0, st, kiter); }
 
 void launch_rhs(const Work& w, hipStream_t st) {
   dim3 g(w.n / kTile, w.n / kTile, w.B);
@@ -921,43 +960,41 @@ bool stencil_choice_valid(int n, int c) {
 }
 
 template <bool FUSED, class PT, class ZT, int D>
-void launch_stencil_d(int B, int n, int V, int H, const double* a, const PT* pin, PT* pout, const ZT* z,
-                      double* q, const SysState* sys, double* part, int first, hipStream_t st) {
+void launch_stencil_d(int B, int n, int V, int H, const double* a, const PT* pin, PT* ring, long long slot_stride,
+                      int m, const int* kiter, const ZT* z, double* q, const SysState* sys, double* part,
+                      hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
-                       first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
+                       q, n, H, sys, part);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
-                       first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
+                       q, n, H, sys, part);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D>), g, blk, 0, st, a, pin, pout, z, q, n, H, sys, part,
-                       first);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
+                       q, n, H, sys, part);
 }
 
 template <bool FUSED, class PT, class ZT>
-void launch_stencil_t(int B, int n, int c, const double* a, const PT* pin, PT* pout, const ZT* z, double* q,
-                      const SysState* sys, double* part, int first, hipStream_t st) {
+void launch_stencil_t(int B, int n, int c, const double* a, const PT* pin, PT* ring, long long slot_stride, int m,
+                      const int* kiter, const ZT* z, double* q, const SysState* sys, double* part, hipStream_t st) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2>(B, n, V, H, a, pin, pout, z, q, sys, part, first, st);
+    launch_stencil_d<FUSED, PT, ZT, 2>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1>(B, n, V, H, a, pin, pout, z, q, sys, part, first, st);
+    launch_stencil_d<FUSED, PT, ZT, 1>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
 }
 
-void launch_stencil_fused(const Work& w, int k, hipStream_t st) {
-  // iteration k writes p_k into ring slot k mod m and reads p_{k-1} from the previous slot
-  const size_t esz = w.mixed == 0 ? 8 : 4;
-  const size_t slot_bytes = (size_t)w.S * (size_t)w.N2 * esz;
-  char* ring = static_cast<char*>(w.pring);
-  void* pout = ring + (size_t)(k % w.m_ring) * slot_bytes;
-  const void* pin = ring + (size_t)((k + w.m_ring - 1) % w.m_ring) * slot_bytes;
+void launch_stencil_fused(const Work& w, hipStream_t st) {
+  // iteration k (read on the device) writes p_k into ring slot k mod m and
+  // reads p_{k-1} from the previous slot
+  const long long slot = (long long)w.S * w.N2;
   if (w.mixed == 0)
-    launch_stencil_t<true, double, double>(w.B, w.n, w.stencil, w.a, (const double*)pin, (double*)pout,
-                                           (const double*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+    launch_stencil_t<true, double, double>(w.B, w.n, w.stencil, w.a, (const double*)nullptr, (double*)w.pring,
+                                           slot, w.m_ring, w.kiter, (const double*)w.z, w.q, w.sys, w.part_pq, st);
   else
-    launch_stencil_t<true, float, float>(w.B, w.n, w.stencil, w.a, (const float*)pin, (float*)pout,
-                                         (const float*)w.z, w.q, w.sys, w.part_pq, (int)(k == 0), st);
+    launch_stencil_t<true, float, float>(w.B, w.n, w.stencil, w.a, (const float*)nullptr, (float*)w.pring, slot,
+                                         w.m_ring, w.kiter, (const float*)w.z, w.q, w.sys, w.part_pq, st);
 }
 
 int stencil_tiles_per_realization(int n, int c) {
@@ -977,32 +1014,32 @@ void launch_update_r(const Work& w, int flexible, hipStream_t st) {
                        (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
 }
 
-void launch_fold_x(const Work& w, int j0, int j1, hipStream_t st) {
+void launch_fold_x(const Work& w, int final, hipStream_t st) {
   const dim3 g(w.P_vec, w.S), blk(kBlock);
   const long long slot = (long long)w.S * w.N2;
   if (w.mixed == 0)
     hipLaunchKernelGGL((k_fold_x<double>), g, blk, 0, st, w.x, (const double*)w.pring, slot, w.m_ring,
-                       w.alpha_hist, w.sys, w.N2, j0, j1);
+                       w.alpha_hist, w.sys, w.N2, (const int*)w.kiter, final);
   else
     hipLaunchKernelGGL((k_fold_x<float>), g, blk, 0, st, w.x, (const float*)w.pring, slot, w.m_ring,
-                       w.alpha_hist, w.sys, w.N2, j0, j1);
+                       w.alpha_hist, w.sys, w.N2, (const int*)w.kiter, final);
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  launch_stencil_t<false, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr,
-                                          (const double*)nullptr, out, (const SysState*)nullptr, (double*)nullptr,
-                                          0, st);
+  launch_stencil_t<false, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0, 1,
+                                          (const int*)nullptr, (const double*)nullptr, out, (const SysState*)nullptr,
+                                          (double*)nullptr, st);
 }
 
-void launch_scalar_alpha(const Work& w, int k, hipStream_t st) {
+void launch_scalar_alpha(const Work& w, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_alpha, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_pq, w.P_st, w.alpha_hist,
-                     w.m_ring, k % w.m_ring);
+                     w.m_ring, (const int*)w.kiter);
 }
 
 
-void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st) {
+void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec, tol, maxit,
-                     w.count + slot, w.S);
+                     w.count, (const int*)w.kiter);
 }
 
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) {

@@ -43,7 +43,12 @@ struct Work {
   double* part_rzo = nullptr;  // [S][P] partial sums of r_new.z_old (flexible beta)
   double* part_rz = nullptr;   // [S][P] partial sums of r.z
   double* part_misc = nullptr; // [B][P][kMiscNV] per-realization partials
-  int* count = nullptr;        // [maxit+1] active-system counts per iteration
+  // Shared by all batches of one solve: the iteration counter k (advanced on
+  // the device after each iteration, so a captured chunk of iterations can be
+  // replayed unchanged) and the per-iteration counts of systems still
+  // iterating (count[k]).
+  int* kiter = nullptr;
+  int* count = nullptr;
   int P_tile = 0;   // workgroups per realization of the RHS / A_hom / gradient kernels
   int P_st = 0;     // workgroups per realization of the operator apply
   int P_vec = 0;    // workgroups per system of the vector kernels
@@ -53,20 +58,24 @@ struct Work {
 constexpr int kMiscNV = 9;
 
 // Elementwise and stencil kernels (kernels_vec.hip).
-void launch_init_state(const Work& w, int count_len, hipStream_t st);
+void launch_init_state(const Work& w, hipStream_t st);
+void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st);
+void launch_advance(int* kiter, hipStream_t st);
 void launch_rhs(const Work& w, hipStream_t st);
 void launch_scalar_init(const Work& w, hipStream_t st);
 void launch_meansub(const Work& w, hipStream_t st);
 void launch_scalar_fnorm(const Work& w, hipStream_t st);
 // alpha_k = r.z / p.Ap from the operator-apply partials; also kept in
 // alpha_hist for the deferred x update.
-void launch_scalar_alpha(const Work& w, int k, hipStream_t st);
-void launch_scalar_conv(const Work& w, double tol, int maxit, int slot, hipStream_t st);
+void launch_scalar_alpha(const Work& w, hipStream_t st);
+// stopping test of iteration k; counts the systems that go on in count[k]
+void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
-// Fused direction step + operator apply of PCG iteration k in the shape
-// w.stencil (w.P_st must equal stencil_tiles_per_realization(n, w.stencil)).
-void launch_stencil_fused(const Work& w, int k, hipStream_t st);
+// Fused direction step + operator apply of the current PCG iteration in the
+// shape w.stencil (w.P_st must equal stencil_tiles_per_realization(n,
+// w.stencil)).
+void launch_stencil_fused(const Work& w, hipStream_t st);
 // Operator-apply shapes, encoded as c = V + 8 (H / 16) + 64 (D - 1): V in
 // {1, 2, 4} columns per lane, H in {16, 32, 64} rows per wave strip, D in
 // {1, 2} rows of loads in flight per wave; valid when the 64V x 4H
@@ -78,10 +87,11 @@ inline int stencil_choice_H(int c) { return 16 * ((c >> 3) & 7); }
 inline int stencil_choice_D(int c) { return 1 + ((c >> 6) & 1); }
 int stencil_tiles_per_realization(int n, int c);
 void launch_update_r(const Work& w, int flexible, hipStream_t st);
-// x += alpha_j p_j for j = j0, j0+1, ... up to min(j1, iters) - 1 of each
-// system, in increasing j (the order of the plain recurrence). The range
-// must hold at most m_ring directions that are all still in the ring.
-void launch_fold_x(const Work& w, int j0, int j1, hipStream_t st);
+// x += alpha_j p_j in increasing j (the order of the plain recurrence) over
+// the directions of each system still in the ring: final = 0 at the start of
+// iteration k = c m (directions k-m .. k-1), final = 1 after the last
+// iteration (directions since the last multiple of m).
+void launch_fold_x(const Work& w, int final, hipStream_t st);
 constexpr int kRing = 8;   // direction ring length (iterations per x update)
 void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);

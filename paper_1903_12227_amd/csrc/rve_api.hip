@@ -1,9 +1,12 @@
 // librve C ABI: context, workspace, transform tables and the PCG driver.
 //
 // The driver enqueues every step of the corrector path as HIP kernels on the
-// context's stream; the host only sequences launches and polls a pinned
-// all-converged counter once per chunk of iterations, keeping one chunk of
-// launches queued ahead so the GPU does not drain while the host waits.
+// context's stream. The PCG iterations run in chunks of RVE_DIRECTION_RING
+// iterations whose launches do not depend on the chunk's position (the
+// iteration counter lives on the device), so a chunk is captured once as a
+// HIP graph and replayed; the host only polls a pinned all-converged counter
+// once per chunk, keeping one chunk queued ahead so the GPU does not drain
+// while it waits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,6 +71,9 @@ using TuneKey = std::tuple<int, int, int, int>;
 struct rve_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;   // private stream the iteration chunks are captured on
+  int graphs = 1;                     // replay captured chunks (1) or launch them one by one (0)
+  std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
   std::string tune_path;     // JSON-lines cache of tuned choices, or empty
@@ -152,13 +158,15 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   return RVE_OK;
 }
 
-// Carve the workspace of one equal-n batch; grows the arena if needed.
+// Workspace: a control block shared by every batch of a solve (iteration
+// counter, per-iteration counts of systems still iterating), then one region
+// per equal-n batch, carved by plan() with offsets from the region start.
 struct Layout {
-  size_t off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
-  size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_count, off_status, total;
+  size_t off_a, off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
+  size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_status, total;
 };
 
-Layout plan(int B, int n, int prec, int maxit, Work* w) {
+Layout plan(int B, int n, int prec, Work* w) {
   Layout L{};
   const long long S = 2LL * B, N2 = (long long)n * n;
   const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
@@ -174,12 +182,13 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   const size_t pzvec = align_up((size_t)(S * N2) * (prec == RVE_FP64 ? 8 : 4));
   const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(gp));
   size_t o = 0;
+  // the batch's coefficients, copied in at the start of a solve: the
+  // captured chunks then reference workspace memory only
+  L.off_a = o; o += align_up((size_t)(B * N2) * 8);
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
-  // direction ring: kRing slots, fewer when maxit cannot use them
-  const int m_ring = maxit + 1 < kRing ? (maxit + 1 < 2 ? 2 : maxit + 1) : kRing;
-  L.off_ring = o; o += (size_t)m_ring * pzvec;
-  L.off_ahist = o; o += align_up((size_t)S * m_ring * 8);
+  L.off_ring = o; o += (size_t)kRing * pzvec;   // direction ring
+  L.off_ahist = o; o += align_up((size_t)S * kRing * 8);
   L.off_q = o; o += vec;
   L.off_z = o; o += pzvec;
   L.off_rlo = o; o += prec == RVE_FP64 ? 0 : uvec;
@@ -192,7 +201,6 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   L.off_rzo = o; o += align_up(S * P_vec * 8);
   L.off_rz = o; o += align_up(S * gemm_tiles_per_system_max(n) * 8);
   L.off_misc = o; o += align_up((size_t)B * P_tile * kMiscNV * 8);
-  L.off_count = o; o += align_up((size_t)(maxit + 2) * sizeof(int));
   L.off_status = o; o += align_up((size_t)B * sizeof(int));
   L.total = o;
   w->B = B;
@@ -205,15 +213,24 @@ Layout plan(int B, int n, int prec, int maxit, Work* w) {
   w->P_gemm = P_gemm;
   w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
   w->stencil = sc;
-  w->m_ring = m_ring;
+  w->m_ring = kRing;
   w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
+}
+
+// Control block: kiter at the start, count[count_len] after it.
+size_t ctl_bytes(int count_len) { return align_up(256) + align_up((size_t)count_len * sizeof(int)); }
+
+void clear_graphs(rve_ctx* ctx) {
+  for (auto& kv : ctx->graph_cache) ignore(hipGraphExecDestroy(kv.second));
+  ctx->graph_cache.clear();
 }
 
 int ensure_ws(rve_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return RVE_OK;
   if (ctx->ws) {
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    clear_graphs(ctx);   // captured chunks point into the old arena
     ignore(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
@@ -226,8 +243,7 @@ int ensure_ws(rve_ctx* ctx, size_t bytes) {
   return RVE_OK;
 }
 
-void bind(rve_ctx* ctx, const Layout& L, Work* w) {
-  char* base = static_cast<char*>(ctx->ws);
+void bind(char* base, const Layout& L, Work* w) {
   w->x = reinterpret_cast<double*>(base + L.off_x);
   w->r = reinterpret_cast<double*>(base + L.off_r);
   w->pring = base + L.off_ring;
@@ -244,7 +260,6 @@ void bind(rve_ctx* ctx, const Layout& L, Work* w) {
   w->part_rzo = reinterpret_cast<double*>(base + L.off_rzo);
   w->part_rz = reinterpret_cast<double*>(base + L.off_rz);
   w->part_misc = reinterpret_cast<double*>(base + L.off_misc);
-  w->count = reinterpret_cast<int*>(base + L.off_count);
 }
 
 int check_opts(const rve_opts* o) {
@@ -255,7 +270,8 @@ int check_opts(const rve_opts* o) {
   return RVE_OK;
 }
 
-// Kernel-class timing with event pairs on the context stream.
+// Kernel-class timing with event pairs on the context stream (never used
+// while a chunk is being captured: timing runs launch eagerly).
 struct Timed {
   rve_ctx* ctx;
   int cls;
@@ -376,148 +392,254 @@ int count_active(rve_ctx* ctx, const Work& w) {
 }
 
 // The four transform GEMMs, each bracketed by the timer when it is on.
-void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt) {
+void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt, hipStream_t st) {
   if (!ctx->timing) {
-    launch_precond(w, prec, gt, ctx->stream);
+    launch_precond(w, prec, gt, st);
     return;
   }
   for (int ph = 0; ph < 4; ++ph) {
     Timed t(ctx, 1 + ph);
-    launch_precond(w, prec, gt, ctx->stream, ph);
+    launch_precond(w, prec, gt, st, ph);
   }
 }
 
-// Solve B equal-size realizations whose coefficients sit at a_dev.
-// `status_host` (optional) receives the per-item statuses.
-int solve_equal(rve_ctx* ctx, int B, int n, double h, const double* a_dev, const rve_opts* o,
-                double* phi, double* ahom, double* flux, int* iters, double* relres, int* status_dev,
-                std::vector<int>* status_host) {
+// One equal-n batch of a solve: its inputs and outputs (device) and its
+// workspace region.
+struct Batch {
+  int B = 0, n = 0;
+  const double* a = nullptr;                 // [B][n][n], or the items below
+  std::vector<const double*> a_items;        // item k's n x n cells (when not contiguous)
+  double *phi = nullptr, *ahom = nullptr, *flux = nullptr, *relres = nullptr;
+  int *iters = nullptr, *status = nullptr;
   Work w;
-  const Layout L = plan(B, n, o->prec, o->maxit, &w);
-  int rc = ensure_ws(ctx, L.total);
-  if (rc) return rc;
-  bind(ctx, L, &w);
-  w.a = a_dev;
-  Tables* tb = nullptr;
-  rc = build_tables(ctx, n, &tb);
-  if (rc) return rc;
+  Layout L;
+  size_t base = 0;
   GemmTables gt;
-  gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
-                                                                                : (const void*)tb->q16;
-  gt.einv64 = tb->einv64;
-  gt.einv32 = tb->einv32;
+  int prec = kGemmF64;
+};
+
+// One chunk of kRing PCG iterations for every batch: the fold of the previous
+// chunk's directions into x, then per iteration and batch: operator apply
+// with the direction step, alpha, residual update, stopping test, the four
+// transforms z = B^+ r, beta; then the shared iteration counter advances.
+// Nothing in it depends on the chunk's position, so it can be captured once
+// and replayed.
+void run_chunk(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int flexible, hipStream_t st) {
+  for (auto& b : bs) {
+    Timed t(ctx, 6);
+    launch_fold_x(b.w, 0, st);
+  }
+  for (int it = 0; it < kRing; ++it) {
+    for (auto& b : bs) {
+      {
+        Timed t(ctx, 0);
+        launch_stencil_fused(b.w, st);
+      }
+      launch_scalar_alpha(b.w, st);
+      {
+        Timed t(ctx, 5);
+        launch_update_r(b.w, flexible, st);
+      }
+      launch_scalar_conv(b.w, o->tol, o->maxit, st);
+      precond_timed(ctx, b.w, b.prec, b.gt, st);
+      launch_scalar_beta(b.w, flexible, 0, st);
+    }
+    launch_advance(bs[0].w.kiter, st);
+  }
+}
+
+// The captured chunk for this exact set of batches (pointers, shapes, kernel
+// choices, options), captured on first use.
+int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int flexible, hipGraphExec_t* out) {
+  std::vector<long long> key;
+  long long tolbits = 0;
+  std::memcpy(&tolbits, &o->tol, sizeof tolbits);
+  key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, (long long)bs.size()});
+  for (auto& b : bs)
+    key.insert(key.end(), {b.B, b.n, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
+  auto it = ctx->graph_cache.find(key);
+  if (it != ctx->graph_cache.end()) {
+    *out = it->second;
+    return RVE_OK;
+  }
+  if (ctx->graph_cache.size() >= 32) clear_graphs(ctx);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  run_chunk(ctx, bs, o, flexible, ctx->cap_stream);
+  const hipError_t launch_err = hipGetLastError();
+  const hipError_t end_err = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (launch_err != hipSuccess || end_err != hipSuccess) {
+    fprintf(stderr, "librve: capturing a PCG chunk failed: %s\n",
+            hipGetErrorString(launch_err != hipSuccess ? launch_err : end_err));
+    if (g) ignore(hipGraphDestroy(g));
+    return RVE_EHIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  ignore(hipGraphDestroy(g));
+  HIP_TRY(ie);
+  ctx->graph_cache[key] = ex;
+  *out = ex;
+  return RVE_OK;
+}
+
+// Solve every batch (each B equal-size realizations) together: all batches
+// step through the same PCG iterations, sharing one iteration counter and
+// one convergence poll. `status_host` (optional) receives the per-item
+// statuses, batch after batch.
+int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts* o,
+                  std::vector<int>* status_host) {
   const int prec = o->prec == RVE_FP64 ? kGemmF64 : o->prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
   // automatic: standard beta (the flexible form gave the same iteration counts
   // with the BF16/FP32 transforms at contrast 10 and 100)
   const int flexible = o->flexible < 0 ? 0 : (o->flexible != 0);
-  int chunk = o->check_every > 0 ? o->check_every : 8;
+  const int count_len = o->maxit + kRing;
+  size_t total = ctl_bytes(count_len);
+  for (auto& b : bs) {
+    b.L = plan(b.B, b.n, o->prec, &b.w);
+    b.base = total;
+    total += b.L.total;
+  }
+  int rc = ensure_ws(ctx, total);
+  if (rc) return rc;
+  char* ws = static_cast<char*>(ctx->ws);
+  int* kiter = reinterpret_cast<int*>(ws);
+  int* count = reinterpret_cast<int*>(ws + align_up(256));
   hipStream_t st = ctx->stream;
-
-  launch_init_state(w, o->maxit + 2, st);
-  launch_rhs(w, st);
-  launch_scalar_init(w, st);
-  launch_meansub(w, st);
-  launch_scalar_fnorm(w, st);
-
-  // kernel variants: defaults, or the autotuner's choice for this shape
-  int sc = stencil_choice_default(n);
-  w.gemm_variant = gemm_variant_valid(n, prec, 1) ? 1 : 0;
-  const int bb = batch_bucket(B);
-  const TuneKey kst(0, n, o->prec, bb), kgm(1, n, o->prec, bb);
-  const bool tune_now = ctx->autotune &&
-                        (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) && count_active(ctx, w) > 0;
-  if (ctx->autotune) {
-    std::vector<int> gc;
-    for (int v : {0, 1})
-      if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
-    if (ctx->tune.count(kgm) || tune_now)
-      w.gemm_variant = tune_pick(ctx, kgm, gc, [&](int v) {
-        Work t2 = w;
-        t2.gemm_variant = v;
-        t2.P_gemm = gemm_tiles_per_system(n, prec, v);
-        launch_precond(t2, prec, gt, st);
-      });
-  }
-  w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
-  precond_timed(ctx, w, prec, gt);
-  launch_scalar_beta(w, flexible, 1, st);
-  if (ctx->autotune) {
-    std::vector<int> vc;
-    for (int v : {1, 2, 4})
-      for (int hs : {16, 64})
-        for (int d : {1, 2}) {
-          const int c = v + 8 * (hs / 16) + 64 * (d - 1);
-          if (stencil_choice_valid(n, c)) vc.push_back(c);
-        }
-    if (ctx->tune.count(kst) || tune_now)
-      sc = tune_pick(ctx, kst, vc, [&](int c) {
-        Work t2 = w;
-        t2.stencil = c;
-        t2.P_st = stencil_tiles_per_realization(n, c);
-        launch_stencil_fused(t2, 0, st);
-      });
-  }
-  w.stencil = sc;
-  w.P_st = stencil_tiles_per_realization(n, sc);
-
-  // iteration k: p_k = z_k + beta p_{k-1} inside the operator apply, alpha_k,
-  // r update, convergence, then z_{k+1}, beta_k. Every m_ring iterations the
-  // directions in the ring are folded into x before their slots are reused.
-  int enq = 0, chunk_idx = 0;
-  for (;;) {
-    const int end = std::min(enq + chunk, o->maxit);
-    for (; enq < end; ++enq) {
-      if (enq > 0 && enq % w.m_ring == 0) {
-        Timed t(ctx, 6);
-        launch_fold_x(w, enq - w.m_ring, enq, st);
-      }
-      {
-        Timed t(ctx, 0);
-        launch_stencil_fused(w, enq, st);
-      }
-      launch_scalar_alpha(w, enq, st);
-      {
-        Timed t(ctx, 5);
-        launch_update_r(w, flexible, st);
-      }
-      launch_scalar_conv(w, o->tol, o->maxit, enq, st);
-      if (enq + 1 < o->maxit) {
-        precond_timed(ctx, w, prec, gt);
-        launch_scalar_beta(w, flexible, 0, st);
-      }
+  for (auto& b : bs) {
+    bind(ws + b.base, b.L, &b.w);
+    double* a_ws = reinterpret_cast<double*>(ws + b.base + b.L.off_a);
+    const size_t cells = (size_t)b.n * b.n;
+    if (b.a_items.empty()) {
+      HIP_TRY(hipMemcpyAsync(a_ws, b.a, (size_t)b.B * cells * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      for (int k = 0; k < b.B; ++k)
+        HIP_TRY(hipMemcpyAsync(a_ws + k * cells, b.a_items[k], cells * 8, hipMemcpyDeviceToDevice, st));
     }
-    const int slot = chunk_idx & 1;
-    HIP_TRY(hipMemcpyAsync(ctx->h_count + slot, w.count + (enq - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+    b.w.a = a_ws;
+    b.w.kiter = kiter;
+    b.w.count = count;
+    if (!b.status) b.status = reinterpret_cast<int*>(ws + b.base + b.L.off_status);
+    Tables* tb = nullptr;
+    rc = build_tables(ctx, b.n, &tb);
+    if (rc) return rc;
+    b.gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
+                                                                                  : (const void*)tb->q16;
+    b.gt.einv64 = tb->einv64;
+    b.gt.einv32 = tb->einv32;
+    b.prec = prec;
+  }
+
+  launch_ctl_reset(kiter, count, count_len, st);
+  for (auto& b : bs) {
+    launch_init_state(b.w, st);
+    launch_rhs(b.w, st);
+    launch_scalar_init(b.w, st);
+    launch_meansub(b.w, st);
+    launch_scalar_fnorm(b.w, st);
+  }
+
+  // kernel variants: defaults, or the autotuner's choice for each shape; then
+  // z_0 and beta's first call for each batch
+  for (auto& b : bs) {
+    Work& w = b.w;
+    const int n = b.n;
+    const int bb = batch_bucket(b.B);
+    const TuneKey kst(0, n, o->prec, bb), kgm(1, n, o->prec, bb);
+    const bool tune_now = ctx->autotune && (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) &&
+                          count_active(ctx, w) > 0;
+    if (ctx->autotune) {
+      std::vector<int> gc;
+      for (int v : {0, 1})
+        if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
+      if (ctx->tune.count(kgm) || tune_now)
+        w.gemm_variant = tune_pick(ctx, kgm, gc, [&](int v) {
+          Work t2 = w;
+          t2.gemm_variant = v;
+          t2.P_gemm = gemm_tiles_per_system(n, prec, v);
+          launch_precond(t2, prec, b.gt, st);
+        });
+    }
+    w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
+    precond_timed(ctx, w, prec, b.gt, st);
+    launch_scalar_beta(w, flexible, 1, st);
+    int sc = stencil_choice_default(n);
+    if (ctx->autotune) {
+      std::vector<int> vc;
+      for (int v : {1, 2, 4})
+        for (int hs : {16, 64})
+          for (int d : {1, 2}) {
+            const int c = v + 8 * (hs / 16) + 64 * (d - 1);
+            if (stencil_choice_valid(n, c)) vc.push_back(c);
+          }
+      // the first operator apply (iteration 0) is idempotent: it reads z_0
+      if (ctx->tune.count(kst) || tune_now)
+        sc = tune_pick(ctx, kst, vc, [&](int c) {
+          Work t2 = w;
+          t2.stencil = c;
+          t2.P_st = stencil_tiles_per_realization(n, c);
+          launch_stencil_fused(t2, st);
+        });
+    }
+    w.stencil = sc;
+    w.P_st = stencil_tiles_per_realization(n, sc);
+  }
+
+  // iterations in chunks of kRing, replayed from a captured graph unless
+  // kernel timing is on; the host polls the count of the chunk before the one
+  // just enqueued, so one chunk of work stays queued while it waits
+  hipGraphExec_t ex = nullptr;
+  if (ctx->graphs && !ctx->timing) {
+    rc = chunk_graph(ctx, bs, o, flexible, &ex);
+    if (rc) return rc;
+  }
+  const int max_chunks = (o->maxit + kRing - 1) / kRing;
+  const int per_poll = o->check_every > 0 ? std::max(1, (o->check_every + kRing - 1) / kRing) : 1;
+  for (int c = 0, polls = 0;; ++c) {
+    if (ex)
+      HIP_TRY(hipGraphLaunch(ex, st));
+    else
+      run_chunk(ctx, bs, o, flexible, st);
+    const bool last = c + 1 >= max_chunks;
+    if (!last && (c + 1) % per_poll != 0) continue;
+    const int slot = polls & 1;
+    HIP_TRY(hipMemcpyAsync(ctx->h_count + slot, count + (c * kRing + kRing - 1), sizeof(int),
+                           hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(ctx->chunk_ev[slot], st));
-    if (enq >= o->maxit) {
+    if (last) {
       HIP_TRY(hipEventSynchronize(ctx->chunk_ev[slot]));
       break;
     }
-    if (chunk_idx > 0) {
+    if (polls > 0) {
       const int prev = slot ^ 1;
       HIP_TRY(hipEventSynchronize(ctx->chunk_ev[prev]));
       if (ctx->h_count[prev] == 0) break;
     }
-    ++chunk_idx;
-  }
-  {
-    // the directions since the last fold (iterations enq-1 and before)
-    Timed t(ctx, 6);
-    launch_fold_x(w, ((enq - 1) / w.m_ring) * w.m_ring, o->maxit, st);
+    ++polls;
   }
 
-  launch_ahom(w, st);
-  launch_scalar_ahom(w, ahom, flux, st);
-  if (phi) launch_phi_out(w, phi, h, st);
-  int* stat = status_dev ? status_dev : reinterpret_cast<int*>(static_cast<char*>(ctx->ws) + L.off_status);
-  launch_finalize(w, iters, relres, stat, st);
+  for (auto& b : bs) {
+    {
+      // the directions since the last fold
+      Timed t(ctx, 6);
+      launch_fold_x(b.w, 1, st);
+    }
+    launch_ahom(b.w, st);
+    launch_scalar_ahom(b.w, b.ahom, b.flux, st);
+    if (b.phi) launch_phi_out(b.w, b.phi, h, st);
+    launch_finalize(b.w, b.iters, b.relres, b.status, st);
+  }
   HIP_TRY(hipGetLastError());
-  std::vector<int> hs(B);
-  HIP_TRY(hipMemcpyAsync(hs.data(), stat, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<int> hs;
+  for (auto& b : bs) {
+    const size_t o0 = hs.size();
+    hs.resize(o0 + b.B);
+    HIP_TRY(hipMemcpyAsync(hs.data() + o0, b.status, b.B * sizeof(int), hipMemcpyDeviceToHost, st));
+  }
   HIP_TRY(hipStreamSynchronize(st));
   harvest_timing(ctx);
   int worst = RVE_OK;
-  for (int b = 0; b < B; ++b) worst = worse(worst, hs[b]);
+  for (int v : hs) worst = worse(worst, v);
   if (status_host) *status_host = hs;
   return worst;
 }
@@ -568,7 +690,8 @@ int rve_create(rve_ctx** out, int device, void* hip_stream) {
     return RVE_ENOMEM;
   }
   if (hipEventCreateWithFlags(&c->chunk_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->chunk_ev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->chunk_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     ignore(hipHostFree(c->h_count));
     delete c;
     return RVE_EHIP;
@@ -588,7 +711,9 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.einv64));
     ignore(hipFree(kv.second.einv32));
   }
+  clear_graphs(c);
   if (c->ws) ignore(hipFree(c->ws));
+  ignore(hipStreamDestroy(c->cap_stream));
   for (auto e : c->timer.pool) ignore(hipEventDestroy(e));
   ignore(hipEventDestroy(c->chunk_ev[0]));
   ignore(hipEventDestroy(c->chunk_ev[1]));
@@ -610,8 +735,18 @@ int rve_solve_batch(rve_ctx* c, int B, int n, double h, const double* a_dev, con
     return RVE_EINVAL;
   if (check_opts(o)) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
-  return solve_equal(c, B, n, h, a_dev, o, phi_dev, ahom_dev, ahom_flux_dev, iters_dev, relres_dev,
-                     status_dev, nullptr);
+  std::vector<Batch> bs(1);
+  Batch& b = bs[0];
+  b.B = B;
+  b.n = n;
+  b.a = a_dev;
+  b.phi = phi_dev;
+  b.ahom = ahom_dev;
+  b.flux = ahom_flux_dev;
+  b.iters = iters_dev;
+  b.relres = relres_dev;
+  b.status = status_dev;
+  return solve_batches(c, bs, h, o, nullptr);
 }
 
 int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, double h,
@@ -636,63 +771,72 @@ int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, d
     if (k + 1 < B && end > off[order[k + 1]]) return RVE_EINVAL;
   }
   HIP_TRY(hipSetDevice(c->device));
-  // group items by size
+  // group items by size; each group's items are copied into its workspace,
+  // all groups are solved together (one chunk of iterations covers every
+  // size), and the outputs, staged per group, are scattered back
   std::map<int, std::vector<int>> groups;
   for (int b = 0; b < B; ++b) groups[n_host[b]].push_back(b);
-  int worst = RVE_OK;
+  size_t bytes = 0;
+  for (auto& g : groups) {
+    const size_t Bg = g.second.size(), N2 = (size_t)g.first * g.first;
+    bytes += (phi_dev ? align_up(2 * Bg * N2 * 8) : 0) + 3 * align_up(Bg * 4 * 8) +
+             2 * align_up(Bg * 2 * 4) + align_up(Bg * 4);
+  }
+  char* stage = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&stage), bytes, c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return RVE_ENOMEM;
+  }
+  size_t o2 = 0;
+  auto take = [&](size_t nb) { char* p = stage + o2; o2 += align_up(nb); return p; };
+  std::vector<Batch> bs;
+  std::vector<const std::vector<int>*> members;
   for (auto& g : groups) {
     const int n = g.first;
     const std::vector<int>& items = g.second;
     const int Bg = (int)items.size();
     const size_t N2 = (size_t)n * n;
-    // staging: a [Bg][N2], phi [Bg][2][N2], small outputs
-    double *a_g = nullptr, *phi_g = nullptr, *ah_g = nullptr, *fl_g = nullptr, *rr_g = nullptr;
-    int *it_g = nullptr, *st_g = nullptr;
-    const size_t bytes = Bg * N2 * 8 + (phi_dev ? 2 * Bg * N2 * 8 : 0) + Bg * (4 + 4 + 2) * 8 + Bg * 3 * 4 + 1024;
-    char* stage = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void**>(&stage), bytes, c->stream) != hipSuccess) {
-      (void)hipGetLastError();
-      return RVE_ENOMEM;
-    }
-    size_t o2 = 0;
-    auto take = [&](size_t b) { char* p = stage + o2; o2 += align_up(b); return p; };
-    o2 = 0;
-    a_g = reinterpret_cast<double*>(take(Bg * N2 * 8));
-    if (phi_dev) phi_g = reinterpret_cast<double*>(take(2 * Bg * N2 * 8));
-    ah_g = reinterpret_cast<double*>(take(Bg * 4 * 8));
-    fl_g = reinterpret_cast<double*>(take(Bg * 4 * 8));
-    rr_g = reinterpret_cast<double*>(take(Bg * 2 * 8));
-    it_g = reinterpret_cast<int*>(take(Bg * 2 * 4));
-    st_g = reinterpret_cast<int*>(take(Bg * 4));
-    (void)o2;
-    for (int k = 0; k < Bg; ++k)
-      HIP_TRY(hipMemcpyAsync(a_g + k * N2, a_dev + off[items[k]], N2 * 8, hipMemcpyDeviceToDevice, c->stream));
-    std::vector<int> hs;
-    const int rc = solve_equal(c, Bg, n, h, a_g, o, phi_g, ah_g, fl_g, it_g, rr_g, st_g, &hs);
-    if (rc == RVE_EHIP || rc == RVE_ENOMEM) {
-      ignore(hipFreeAsync(stage, c->stream));
-      return rc;
-    }
-    for (int k = 0; k < Bg; ++k) {
+    Batch bt;
+    bt.B = Bg;
+    bt.n = n;
+    for (int k = 0; k < Bg; ++k) bt.a_items.push_back(a_dev + off[items[k]]);
+    if (phi_dev) bt.phi = reinterpret_cast<double*>(take(2 * Bg * N2 * 8));
+    bt.ahom = reinterpret_cast<double*>(take(Bg * 4 * 8));
+    bt.flux = reinterpret_cast<double*>(take(Bg * 4 * 8));
+    bt.relres = reinterpret_cast<double*>(take(Bg * 4 * 8));
+    bt.iters = reinterpret_cast<int*>(take(Bg * 2 * 4));
+    bt.status = reinterpret_cast<int*>(take(Bg * 4));
+    bs.push_back(bt);
+    members.push_back(&items);
+  }
+  const int rc = solve_batches(c, bs, h, o, nullptr);
+  if (rc == RVE_EHIP || rc == RVE_ENOMEM) {
+    ignore(hipFreeAsync(stage, c->stream));
+    return rc;
+  }
+  for (size_t gi = 0; gi < bs.size(); ++gi) {
+    const Batch& bt = bs[gi];
+    const size_t N2 = (size_t)bt.n * bt.n;
+    const std::vector<int>& items = *members[gi];
+    for (int k = 0; k < bt.B; ++k) {
       const int b = items[k];
-      HIP_TRY(hipMemcpyAsync(ahom_dev + 4 * b, ah_g + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(ahom_dev + 4 * b, bt.ahom + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
       if (ahom_flux_dev)
-        HIP_TRY(hipMemcpyAsync(ahom_flux_dev + 4 * b, fl_g + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(ahom_flux_dev + 4 * b, bt.flux + 4 * k, 32, hipMemcpyDeviceToDevice, c->stream));
       if (relres_dev)
-        HIP_TRY(hipMemcpyAsync(relres_dev + 2 * b, rr_g + 2 * k, 16, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(relres_dev + 2 * b, bt.relres + 2 * k, 16, hipMemcpyDeviceToDevice, c->stream));
       if (iters_dev)
-        HIP_TRY(hipMemcpyAsync(iters_dev + 2 * b, it_g + 2 * k, 8, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(iters_dev + 2 * b, bt.iters + 2 * k, 8, hipMemcpyDeviceToDevice, c->stream));
       if (status_dev)
-        HIP_TRY(hipMemcpyAsync(status_dev + b, st_g + k, 4, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(status_dev + b, bt.status + k, 4, hipMemcpyDeviceToDevice, c->stream));
       if (phi_dev)
-        HIP_TRY(hipMemcpyAsync(phi_dev + 2 * off[b], phi_g + 2 * k * N2, 2 * N2 * 8, hipMemcpyDeviceToDevice,
+        HIP_TRY(hipMemcpyAsync(phi_dev + 2 * off[b], bt.phi + 2 * k * N2, 2 * N2 * 8, hipMemcpyDeviceToDevice,
                                c->stream));
     }
-    HIP_TRY(hipFreeAsync(stage, c->stream));
-    worst = worse(worst, rc);
   }
+  HIP_TRY(hipFreeAsync(stage, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  return worst;
+  return rc;
 }
 
 int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
@@ -732,16 +876,16 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
-  const Layout L = plan(B, n, prec, 1, &w);
+  const Layout L = plan(B, n, prec, &w);
   int rc = ensure_ws(c, L.total);
   if (rc) return rc;
-  bind(c, L, &w);
+  bind(static_cast<char*>(c->ws), L, &w);
   w.a = a_dev;
   Tables* tb = nullptr;
   rc = build_tables(c, n, &tb);
   if (rc) return rc;
   // a0 of each realization, exactly as the solver derives it
-  launch_init_state(w, 1, c->stream);
+  launch_init_state(w, c->stream);
   launch_rhs(w, c->stream);
   launch_scalar_init(w, c->stream);
   GemmTables gt;
@@ -758,6 +902,12 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
   if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_set_graphs(rve_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 1) return RVE_EINVAL;
+  c->graphs = mode;
   return RVE_OK;
 }
 

@@ -251,6 +251,48 @@ def test_iterate_after_k_iterations(dev, k):
             assert np.max(np.abs(phi[b, i] - ref.phi[i])) <= 1e-10 * np.max(np.abs(ref.phi[i]))
 
 
+def _fixed_ctx(rve, graphs):
+    ctx = rve.Context(0)
+    ctx.set_autotune(False)      # same kernel variants in every context
+    ctx.set_graphs(graphs)
+    return ctx
+
+
+def _same(r1, r2):
+    return all(torch.equal(getattr(r1, k), getattr(r2, k)) for k in ("ahom", "ahom_flux", "phi", "iters", "relres",
+                                                                     "status"))
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_graph_replay_matches_eager(dev, prec):
+    # the captured chunk is replayed several times per solve, and the cached
+    # graph again by later solves, with eager launches and host polls in
+    # between; every result must equal the eager launches' to the last bit
+    rve = _rve()
+    a = _to(_fields(128, 3, 15), dev)
+    opts = rve.Options(tol=1e-10, prec=prec)
+    ref = rve.solve_batch(a, 0.125, opts, ctx=_fixed_ctx(rve, False))
+    g = _fixed_ctx(rve, True)
+    for _ in range(3):
+        assert _same(rve.solve_batch(a, 0.125, opts, ctx=g), ref)
+    # a poll every 24 iterations runs the same kernels
+    opts24 = rve.Options(tol=1e-10, prec=prec, check_every=24)
+    assert _same(rve.solve_batch(a, 0.125, opts24, ctx=g), ref)
+
+
+def test_uneven_graph_matches_eager(dev):
+    rve = _rve()
+    fields = [_fields(n, 1, 16 + n)[0] for n in (64, 192, 64, 128, 192)]
+    opts = rve.Options(tol=1e-10, prec=1)
+    ref = rve.solve_uneven([torch.from_numpy(f).to(dev) for f in fields], 0.125, opts, want_phi=True,
+                           ctx=_fixed_ctx(rve, False))
+    g = _fixed_ctx(rve, True)
+    for _ in range(2):
+        got = rve.solve_uneven([torch.from_numpy(f).to(dev) for f in fields], 0.125, opts, want_phi=True, ctx=g)
+        assert torch.equal(got.ahom, ref.ahom) and torch.equal(got.iters, ref.iters)
+        assert all(torch.equal(x, y) for x, y in zip(got.phi, ref.phi))
+
+
 def test_bitwise_reproducible(dev):
     rve = _rve()
     a = _to(_fields(128, 3, 9), dev)
