@@ -72,6 +72,18 @@ enum rve_precision {
   RVE_MIX_BF16 = 2   /* BF16 MFMA operands, FP32 accumulation, BF16 intermediates */
 };
 
+/* Arithmetic of the operator apply inside PCG. With RVE_STENCIL_FP32 the
+ * coefficients, the direction p (rounded to FP32 before use) and q = A p are
+ * FP32 while the p.Ap partial sums stay FP64; since q is then only an FP32
+ * approximation of A p, the residual is recomputed as r = f - A x in FP64
+ * from the current iterate every RVE_DIRECTION_RING iterations, which keeps
+ * the stopping test on the true residual to within FP32 rounding of the last
+ * few steps. */
+enum rve_stencil_precision {
+  RVE_STENCIL_FP64 = 0,
+  RVE_STENCIL_FP32 = 1
+};
+
 /* The PCG iterate is not updated every iteration: the search directions of
  * RVE_DIRECTION_RING consecutive iterations are kept, and x += sum_j
  * alpha_j p_j is applied once per that many iterations and at the end, in
@@ -88,12 +100,13 @@ typedef struct rve_opts {
   int check_every;   /* host polls the all-converged flag every this many
                         iterations, rounded up to a multiple of
                         RVE_DIRECTION_RING; <= 0: every RVE_DIRECTION_RING */
+  int stencil_prec;  /* enum rve_stencil_precision */
 } rve_opts;
 
 typedef struct rve_ctx rve_ctx;
 
 /* Fill *opts with defaults: tol 1e-10, maxit 2000, FP64, automatic beta,
- * automatic polling. */
+ * automatic polling, FP64 operator apply. */
 void rve_default_opts(rve_opts* opts);
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -211,8 +224,9 @@ const char* rve_status_string(int status);
  * there as JSON lines and read back by rve_create. Mode 0 uses fixed
  * defaults. Results do not depend on the choice beyond rounding order.
  *
- * rve_get_tuned: *choice for kind 0 (operator-apply shape, encoded as
- * V + 8 (H / 16) + 64 (D - 1)) or 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128) of a shape,
+ * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
+ * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128)
+ * or 2 (FP32 operator-apply shape, encoded as kind 0) of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
  * that are not valid for a shape are ignored and tuned again.
  */

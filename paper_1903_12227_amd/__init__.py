@@ -10,7 +10,9 @@ Q1 discretisation by preconditioned CG and reduce them to the homogenized
 All arithmetic runs in librve (hand-written HIP kernels for gfx950, C ABI in
 include/rve.h); this package only marshals torch tensors into it.
 """
-from ._native import FP64, MIX_FP32, MIX_BF16, DIRECTION_RING, LIB_PATH, RveError  # noqa: F401
+from ._native import (  # noqa: F401
+    FP64, MIX_FP32, MIX_BF16, STENCIL_FP64, STENCIL_FP32, DIRECTION_RING, LIB_PATH, RveError,
+)
 from .api import (  # noqa: F401
     Context, Options, Result, context, solve_batch, solve_uneven, grad, stats,
     apply_operator, apply_precond,

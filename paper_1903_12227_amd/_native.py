@@ -15,6 +15,7 @@ DIRECTION_RING = 8
 OK, NOT_CONVERGED, BREAKDOWN, EINVAL, EHIP, ENOMEM = 0, 1, 2, -1, -2, -3
 # enum rve_precision
 FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
+STENCIL_FP64, STENCIL_FP32 = 0, 1
 
 EXPORTS = (
     "rve_default_opts", "rve_create", "rve_destroy", "rve_set_stream",
@@ -27,7 +28,7 @@ EXPORTS = (
 
 class RveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("prec", ctypes.c_int),
-                ("flexible", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("flexible", ctypes.c_int), ("check_every", ctypes.c_int), ("stencil_prec", ctypes.c_int)]
 
 
 _lib = None

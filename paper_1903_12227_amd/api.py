@@ -24,10 +24,11 @@ class Options:
     prec: int = FP64            # FP64, MIX_FP32 or MIX_BF16 (preconditioner GEMMs)
     flexible: int = -1          # -1 automatic, 0 standard beta, 1 flexible beta
     check_every: int = 0        # convergence poll period (0 = library default)
+    stencil_prec: int = 0       # 0 FP64 operator apply, 1 FP32 (with FP64 residual replacement)
 
     def to_c(self) -> N.RveOpts:
         return N.RveOpts(float(self.tol), int(self.maxit), int(self.prec), int(self.flexible),
-                         int(self.check_every))
+                         int(self.check_every), int(self.stencil_prec))
 
 
 @dataclass
@@ -84,12 +85,12 @@ class Context:
         default) or launch its kernels one by one; results are identical."""
         N.check(self._lib.rve_set_graphs(self.handle, int(bool(enable))), "rve_set_graphs")
 
-    def tuned(self, n: int, prec: int, B: int) -> dict:
+    def tuned(self, n: int, prec: int, B: int, stencil_prec: int = 0) -> dict:
         """The autotuner's choices for a shape: columns per lane, rows per
         wave strip and rows of loads in flight per wave of the operator
         apply, and the transform-GEMM tile variant (-1: not tuned)."""
         got = []
-        for kind in (0, 1):
+        for kind in (2 if stencil_prec else 0, 1):
             c = ctypes.c_int(-1)
             self._lib.rve_get_tuned(self.handle, kind, int(n), int(prec), int(B), ctypes.byref(c))
             got.append(c.value)

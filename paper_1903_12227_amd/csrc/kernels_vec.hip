@@ -229,50 +229,51 @@ __global__ void k_scalar_fnorm(SysState* sys, const double* __restrict__ part, i
 //   centre (2/3)(a00+a01+a10+a11); (p+-1, q): -(a10+a11)/6, -(a00+a01)/6;
 //   (p, q+-1): -(a01+a11)/6, -(a00+a10)/6; diagonals -a_e/3 of the one
 //   cell they share with the node.
-__device__ inline double q1_apply(double a00, double a01, double a10, double a11, const double (&um)[3],
-                                  const double (&uc)[3], const double (&up)[3]) {
-  double v = kTwoThirds * ((a00 + a01) + (a10 + a11)) * uc[1];
-  v -= kSixth * ((a10 + a11) * up[1] + (a00 + a01) * um[1] + (a01 + a11) * uc[2] + (a00 + a10) * uc[0]);
-  v -= kThird * (a11 * up[2] + a01 * um[2] + a10 * up[0] + a00 * um[0]);
+template <class T>
+__device__ inline T q1_apply(T a00, T a01, T a10, T a11, const T (&um)[3], const T (&uc)[3], const T (&up)[3]) {
+  T v = (T)kTwoThirds * ((a00 + a01) + (a10 + a11)) * uc[1];
+  v -= (T)kSixth * ((a10 + a11) * up[1] + (a00 + a01) * um[1] + (a01 + a11) * uc[2] + (a00 + a10) * uc[0]);
+  v -= (T)kThird * (a11 * up[2] + a01 * um[2] + a10 * up[0] + a00 * um[0]);
   return v;
 }
 
-// V consecutive elements of a row, widened to FP64 / rounded from FP64.
+// V consecutive elements of a row, converted to / from the register type S.
 template <class T, int V> struct VecIO;
 template <int V> struct VecIO<double, V> {
-  __device__ static void load(const double* p, double* v) {
+  template <class S> __device__ static void load(const double* p, S* v) {
     if constexpr (V == 1) {
-      v[0] = p[0];
+      v[0] = (S)p[0];
     } else {
 #pragma unroll
       for (int k = 0; k < V; k += 2) {
         const double2 t = *reinterpret_cast<const double2*>(p + k);
-        v[k] = t.x; v[k + 1] = t.y;
+        v[k] = (S)t.x; v[k + 1] = (S)t.y;
       }
     }
   }
-  __device__ static void store(double* p, const double* v) {
+  template <class S> __device__ static void store(double* p, const S* v) {
     if constexpr (V == 1) {
-      p[0] = v[0];
+      p[0] = (double)v[0];
     } else {
 #pragma unroll
-      for (int k = 0; k < V; k += 2) *reinterpret_cast<double2*>(p + k) = make_double2(v[k], v[k + 1]);
+      for (int k = 0; k < V; k += 2)
+        *reinterpret_cast<double2*>(p + k) = make_double2((double)v[k], (double)v[k + 1]);
     }
   }
 };
 template <int V> struct VecIO<float, V> {
-  __device__ static void load(const float* p, double* v) {
+  template <class S> __device__ static void load(const float* p, S* v) {
     if constexpr (V == 4) {
       const float4 t = *reinterpret_cast<const float4*>(p);
-      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+      v[0] = (S)t.x; v[1] = (S)t.y; v[2] = (S)t.z; v[3] = (S)t.w;
     } else if constexpr (V == 2) {
       const float2 t = *reinterpret_cast<const float2*>(p);
-      v[0] = t.x; v[1] = t.y;
+      v[0] = (S)t.x; v[1] = (S)t.y;
     } else {
-      v[0] = p[0];
+      v[0] = (S)p[0];
     }
   }
-  __device__ static void store(float* p, const double* v) {
+  template <class S> __device__ static void store(float* p, const S* v) {
     if constexpr (V == 4) {
       *reinterpret_cast<float4*>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
     } else if constexpr (V == 2) {
@@ -320,10 +321,13 @@ __device__ inline void raw_load(const T* p, T* v) {
 // FUSED: iteration k is read from *kiter; p_k goes to ring slot k mod m and
 // p_{k-1} comes from slot (k - 1) mod m (slots slot_stride elements apart).
 // Not FUSED: the operand is p_in.
-template <bool FUSED, class PT, class ZT, int V, int D>
-__global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__ a, const PT* p_in, PT* ring,
+// CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
+// FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
+// FP64 either way (the product of two FP32 values is exact in FP64).
+template <bool FUSED, class PT, class ZT, int V, int D, class CT>
+__global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, const PT* p_in, PT* ring,
                                                        long long slot_stride, int m, const int* kiter,
-                                                       const ZT* __restrict__ z, double* __restrict__ q, int n,
+                                                       const ZT* __restrict__ z, CT* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
@@ -352,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
   const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = by * 4 * H + w * H;
-  const double* A = a + (long long)b * N2;
+  const CT* A = a + (long long)b * N2;
   const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
   const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
   const bool need_p = !FUSED || !first;
@@ -362,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
   struct Raw {
     ZT z[2][V + 2];
     PT p[2][V + 2];
-    double a[V + 1];
+    CT a[V + 1];
   };
   auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a) {
 #pragma unroll
@@ -380,30 +384,30 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
     }
     if (with_a) {
       R.a[0] = A[oa + cl];
-      raw_load<double, V>(A + oa + c0, &R.a[1]);
+      raw_load<CT, V>(A + oa + c0, &R.a[1]);
     }
   };
   // operand values of system i from a raw row
-  auto cook = [&](const Raw& R, int i, double* u) {
+  auto cook = [&](const Raw& R, int i, CT* u) {
     if constexpr (FUSED) {
       if (first) {
 #pragma unroll
-        for (int k = 0; k < V + 2; ++k) u[k] = (double)R.z[i][k];
+        for (int k = 0; k < V + 2; ++k) u[k] = (CT)(PT)R.z[i][k];
       } else {
-        // p_k is rounded to its storage type before it is used, so q = A p_k,
-        // p_k.q and the later x += alpha p_k all see the same direction and
-        // the recursive residual stays f - A x to FP64 rounding
+        // p_k is rounded to its storage type (and to CT) before it is used,
+        // so q = A p_k, p_k.q and the later x += alpha p_k all see the same
+        // direction and the recursive residual follows f - A x
 #pragma unroll
-        for (int k = 0; k < V + 2; ++k) u[k] = (double)(PT)fma(be[i], (double)R.p[i][k], (double)R.z[i][k]);
+        for (int k = 0; k < V + 2; ++k) u[k] = (CT)(PT)fma(be[i], (double)R.p[i][k], (double)R.z[i][k]);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < V + 2; ++k) u[k] = (double)R.p[i][k];
+      for (int k = 0; k < V + 2; ++k) u[k] = (CT)R.p[i][k];
     }
   };
 
   const int rm = wrap_dec(row0, n);
-  double um[2][V + 2], uc[2][V + 2], am[V + 1];
+  CT um[2][V + 2], uc[2][V + 2], am[V + 1];
   Raw R0, R1;
   {
     load_raw(R0, (long long)rm * n, (long long)rm * n, true);
@@ -432,31 +436,31 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const double* __restrict__
         load_raw(fill, (long long)wrap_inc(r1, n) * n, (long long)r1 * n, true);
       }
     }
-    double up[2][V + 2];
+    CT up[2][V + 2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) cook(use, i, up[i]);
-    const double* ac = use.a;
+    const CT* ac = use.a;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      double qv[V];
+      CT qv[V];
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        const double sm[3] = {um[i][k], um[i][k + 1], um[i][k + 2]};
-        const double sc[3] = {uc[i][k], uc[i][k + 1], uc[i][k + 2]};
-        const double sp[3] = {up[i][k], up[i][k + 1], up[i][k + 2]};
-        qv[k] = q1_apply(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
+        const CT sm[3] = {um[i][k], um[i][k + 1], um[i][k + 2]};
+        const CT sc[3] = {uc[i][k], uc[i][k + 1], uc[i][k + 2]};
+        const CT sp[3] = {up[i][k], up[i][k + 1], up[i][k + 2]};
+        qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
       }
       if (act[i]) {
-        VecIO<double, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
+        VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
         if constexpr (FUSED) {
-          double pn[V];
+          CT pn[V];
 #pragma unroll
           for (int k = 0; k < V; ++k) pn[k] = uc[i][k + 1];
           VecIO<PT, V>::store(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
         }
       }
 #pragma unroll
-      for (int k = 0; k < V; ++k) d[i] += uc[i][k + 1] * qv[k];
+      for (int k = 0; k < V; ++k) d[i] += (double)uc[i][k + 1] * (double)qv[k];
 #pragma unroll
       for (int k = 0; k < V + 2; ++k) {
         um[i][k] = uc[i][k];
@@ -509,8 +513,8 @@ __global__ void k_scalar_alpha(SysState* sys, const double* __restrict__ part, i
 // r -= alpha q, partial sums of r.r (and of r.z for the flexible beta); in
 // mixed modes also the GEMM-precision copy of the new r. (Used with the fused
 // stencil, which applies the x update.)
-template <class ZT, class LoT, bool LO>
-__global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, const double* __restrict__ q,
+template <class ZT, class LoT, bool LO, class QT>
+__global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, const QT* __restrict__ q,
                                                       const ZT* __restrict__ z, LoT* __restrict__ rlo,
                                                       const SysState* sys, long long N2,
                                                       double* __restrict__ part_rr,
@@ -525,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
   for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
     double rv[4], qv[4];
     V4<double>::load(r + off + i, rv);
-    V4<double>::load(q + off + i, qv);
+    V4<QT>::load(q + off + i, qv);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       rv[k] = fma(-al, qv[k], rv[k]);
@@ -959,59 +963,129 @@ bool stencil_choice_valid(int n, int c) {
   return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
-template <bool FUSED, class PT, class ZT, int D>
-void launch_stencil_d(int B, int n, int V, int H, const double* a, const PT* pin, PT* ring, long long slot_stride,
-                      int m, const int* kiter, const ZT* z, double* q, const SysState* sys, double* part,
+template <bool FUSED, class PT, class ZT, int D, class CT>
+void launch_stencil_d(int B, int n, int V, int H, const CT* a, const PT* pin, PT* ring, long long slot_stride,
+                      int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
                       hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
-                       q, n, H, sys, part);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
+                       z, q, n, H, sys, part);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
-                       q, n, H, sys, part);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
+                       z, q, n, H, sys, part);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter, z,
-                       q, n, H, sys, part);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
+                       z, q, n, H, sys, part);
 }
 
-template <bool FUSED, class PT, class ZT>
-void launch_stencil_t(int B, int n, int c, const double* a, const PT* pin, PT* ring, long long slot_stride, int m,
-                      const int* kiter, const ZT* z, double* q, const SysState* sys, double* part, hipStream_t st) {
+template <bool FUSED, class PT, class ZT, class CT>
+void launch_stencil_t(int B, int n, int c, const CT* a, const PT* pin, PT* ring, long long slot_stride, int m,
+                      const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, hipStream_t st) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
+    launch_stencil_d<FUSED, PT, ZT, 2, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
+    launch_stencil_d<FUSED, PT, ZT, 1, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
+}
+
+template <class PT>
+void launch_stencil_fused_p(const Work& w, hipStream_t st) {
+  const long long slot = (long long)w.S * w.N2;
+  if (w.sprec)
+    launch_stencil_t<true, PT, PT, float>(w.B, w.n, w.stencil, w.a32, (const PT*)nullptr, (PT*)w.pring, slot,
+                                          w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq, st);
+  else
+    launch_stencil_t<true, PT, PT, double>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
+                                           w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, st);
 }
 
 void launch_stencil_fused(const Work& w, hipStream_t st) {
   // iteration k (read on the device) writes p_k into ring slot k mod m and
   // reads p_{k-1} from the previous slot
-  const long long slot = (long long)w.S * w.N2;
   if (w.mixed == 0)
-    launch_stencil_t<true, double, double>(w.B, w.n, w.stencil, w.a, (const double*)nullptr, (double*)w.pring,
-                                           slot, w.m_ring, w.kiter, (const double*)w.z, w.q, w.sys, w.part_pq, st);
+    launch_stencil_fused_p<double>(w, st);
   else
-    launch_stencil_t<true, float, float>(w.B, w.n, w.stencil, w.a, (const float*)nullptr, (float*)w.pring, slot,
-                                         w.m_ring, w.kiter, (const float*)w.z, w.q, w.sys, w.part_pq, st);
+    launch_stencil_fused_p<float>(w, st);
 }
 
 int stencil_tiles_per_realization(int n, int c) {
   return (n / (kWave * stencil_choice_V(c))) * (n / (4 * stencil_choice_H(c)));
 }
 
-void launch_update_r(const Work& w, int flexible, hipStream_t st) {
+template <class QT>
+void launch_update_r_q(const Work& w, int flexible, hipStream_t st) {
   const dim3 g(w.P_vec, w.S), blk(kBlock);
+  const QT* q = reinterpret_cast<const QT*>(w.q);
   if (w.mixed == 0)
-    hipLaunchKernelGGL((k_update_r<double, double, false>), g, blk, 0, st, w.r, w.q, (const double*)w.z,
+    hipLaunchKernelGGL((k_update_r<double, double, false, QT>), g, blk, 0, st, w.r, q, (const double*)w.z,
                        (double*)nullptr, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
   else if (w.mixed == 1)
-    hipLaunchKernelGGL((k_update_r<float, float, true>), g, blk, 0, st, w.r, w.q, (const float*)w.z,
+    hipLaunchKernelGGL((k_update_r<float, float, true, QT>), g, blk, 0, st, w.r, q, (const float*)w.z,
                        (float*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
   else
-    hipLaunchKernelGGL((k_update_r<float, __bf16, true>), g, blk, 0, st, w.r, w.q, (const float*)w.z,
+    hipLaunchKernelGGL((k_update_r<float, __bf16, true, QT>), g, blk, 0, st, w.r, q, (const float*)w.z,
                        (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+}
+
+void launch_update_r(const Work& w, int flexible, hipStream_t st) {
+  // q = A p is FP32 with the FP32 operator apply
+  if (w.sprec)
+    launch_update_r_q<float>(w, flexible, st);
+  else
+    launch_update_r_q<double>(w, flexible, st);
+}
+
+// r = f - A x for every active system, and its GEMM-precision copy: the
+// residual replacement of the FP32 operator apply (A x in FP64 in q).
+template <class LoT, bool LO>
+__global__ void __launch_bounds__(kBlock) k_replace_r(double* __restrict__ r, const double* __restrict__ f,
+                                                       const double* __restrict__ ax, LoT* __restrict__ rlo,
+                                                       const SysState* sys, long long N2) {
+  const int s = blockIdx.y;
+  if (!sys[s].active) return;
+  const long long off = (long long)s * N2;
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double fv[4], qv[4];
+    V4<double>::load(f + off + i, fv);
+    V4<double>::load(ax + off + i, qv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fv[k] -= qv[k];
+    V4<double>::store(r + off + i, fv);
+    if constexpr (LO) V4<LoT>::store(rlo + off + i, fv);
+  }
+}
+
+void launch_replace_r(const Work& w, hipStream_t st) {
+  // A x (FP64) into q, then r = f - A x
+  launch_apply_stencil(w.B, w.n, w.a, w.x, w.q, st);
+  const dim3 g(w.P_vec, w.S), blk(kBlock);
+  if (w.mixed == 0)
+    hipLaunchKernelGGL((k_replace_r<double, false>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
+                       (double*)nullptr, w.sys, w.N2);
+  else if (w.mixed == 1)
+    hipLaunchKernelGGL((k_replace_r<float, true>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
+                       (float*)w.rlo, w.sys, w.N2);
+  else
+    hipLaunchKernelGGL((k_replace_r<__bf16, true>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
+                       (__bf16*)w.rlo, w.sys, w.N2);
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_f32(const double* __restrict__ in, float* __restrict__ out,
+                                                    long long total) {
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < total; i += stride) {
+    double v[4];
+    V4<double>::load(in + i, v);
+    V4<float>::store(out + i, v);
+  }
+}
+
+void launch_to_f32(const double* in, float* out, long long total, hipStream_t st) {
+  long long nb = (total + 4LL * kBlock - 1) / (4LL * kBlock);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, total);
 }
 
 void launch_fold_x(const Work& w, int final, hipStream_t st) {
@@ -1026,9 +1100,9 @@ void launch_fold_x(const Work& w, int final, hipStream_t st) {
 }
 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  launch_stencil_t<false, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0, 1,
-                                          (const int*)nullptr, (const double*)nullptr, out, (const SysState*)nullptr,
-                                          (double*)nullptr, st);
+  launch_stencil_t<false, double, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0, 1,
+                                                  (const int*)nullptr, (const double*)nullptr, out,
+                                                  (const SysState*)nullptr, (double*)nullptr, st);
 }
 
 void launch_scalar_alpha(const Work& w, hipStream_t st) {

@@ -34,6 +34,11 @@ struct Work {
   void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
   void* u2 = nullptr;
   int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
+  // FP32 operator apply: a32 holds the coefficients in FP32, q is FP32, and
+  // f (the mean-free right-hand sides) serves the periodic r = f - A x
+  int sprec = 0;
+  const float* a32 = nullptr;
+  double* f = nullptr;
   int stencil = 0;           // operator-apply shape (stencil_choice_*)
   int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0)
   SysState* sys = nullptr;   // [S]
@@ -87,6 +92,9 @@ inline int stencil_choice_H(int c) { return 16 * ((c >> 3) & 7); }
 inline int stencil_choice_D(int c) { return 1 + ((c >> 6) & 1); }
 int stencil_tiles_per_realization(int n, int c);
 void launch_update_r(const Work& w, int flexible, hipStream_t st);
+// residual replacement r = f - A x (FP64) of the FP32 operator apply
+void launch_replace_r(const Work& w, hipStream_t st);
+void launch_to_f32(const double* in, float* out, long long total, hipStream_t st);
 // x += alpha_j p_j in increasing j (the order of the plain recurrence) over
 // the directions of each system still in the ring: final = 0 at the start of
 // iteration k = c m (directions k-m .. k-1), final = 1 after the last

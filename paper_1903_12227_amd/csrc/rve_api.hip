@@ -64,8 +64,9 @@ struct EventTimer {
 
 }  // namespace
 
-// Autotuner key: (kind, n, precision, floor(log2 B)); kind 0 = columns per
-// lane of the operator apply, kind 1 = transform-GEMM tile variant.
+// Autotuner key: (kind, n, precision, floor(log2 B)); kind 0 = shape of the
+// FP64 operator apply, 1 = transform-GEMM tile variant, 2 = shape of the FP32
+// operator apply.
 using TuneKey = std::tuple<int, int, int, int>;
 
 struct rve_ctx {
@@ -162,11 +163,11 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
 // counter, per-iteration counts of systems still iterating), then one region
 // per equal-n batch, carved by plan() with offsets from the region start.
 struct Layout {
-  size_t off_a, off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
+  size_t off_a, off_a32, off_f, off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_status, total;
 };
 
-Layout plan(int B, int n, int prec, Work* w) {
+Layout plan(int B, int n, int prec, int sprec, Work* w) {
   Layout L{};
   const long long S = 2LL * B, N2 = (long long)n * n;
   const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
@@ -185,6 +186,9 @@ Layout plan(int B, int n, int prec, Work* w) {
   // the batch's coefficients, copied in at the start of a solve: the
   // captured chunks then reference workspace memory only
   L.off_a = o; o += align_up((size_t)(B * N2) * 8);
+  // FP32 operator apply: FP32 coefficients and the right-hand sides
+  L.off_a32 = o; o += sprec ? align_up((size_t)(B * N2) * 4) : 0;
+  L.off_f = o; o += sprec ? vec : 0;
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
   L.off_ring = o; o += (size_t)kRing * pzvec;   // direction ring
@@ -214,6 +218,7 @@ Layout plan(int B, int n, int prec, Work* w) {
   w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
   w->stencil = sc;
   w->m_ring = kRing;
+  w->sprec = sprec;
   w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
 }
@@ -260,6 +265,8 @@ void bind(char* base, const Layout& L, Work* w) {
   w->part_rzo = reinterpret_cast<double*>(base + L.off_rzo);
   w->part_rz = reinterpret_cast<double*>(base + L.off_rz);
   w->part_misc = reinterpret_cast<double*>(base + L.off_misc);
+  w->a32 = w->sprec ? reinterpret_cast<const float*>(base + L.off_a32) : nullptr;
+  w->f = w->sprec ? reinterpret_cast<double*>(base + L.off_f) : nullptr;
 }
 
 int check_opts(const rve_opts* o) {
@@ -267,6 +274,7 @@ int check_opts(const rve_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RVE_EINVAL;
   if (o->maxit < 1 || o->maxit > 1000000) return RVE_EINVAL;
   if (o->prec < RVE_FP64 || o->prec > RVE_MIX_BF16) return RVE_EINVAL;
+  if (o->stencil_prec != RVE_STENCIL_FP64 && o->stencil_prec != RVE_STENCIL_FP32) return RVE_EINVAL;
   return RVE_OK;
 }
 
@@ -426,8 +434,12 @@ struct Batch {
 // and replayed.
 void run_chunk(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int flexible, hipStream_t st) {
   for (auto& b : bs) {
-    Timed t(ctx, 6);
-    launch_fold_x(b.w, 0, st);
+    {
+      Timed t(ctx, 6);
+      launch_fold_x(b.w, 0, st);
+    }
+    // FP32 operator apply: the residual restarts from r = f - A x (FP64)
+    if (b.w.sprec) launch_replace_r(b.w, st);
   }
   for (int it = 0; it < kRing; ++it) {
     for (auto& b : bs) {
@@ -454,7 +466,8 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
   std::vector<long long> key;
   long long tolbits = 0;
   std::memcpy(&tolbits, &o->tol, sizeof tolbits);
-  key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, (long long)bs.size()});
+  key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec,
+                         (long long)bs.size()});
   for (auto& b : bs)
     key.insert(key.end(), {b.B, b.n, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
   auto it = ctx->graph_cache.find(key);
@@ -496,7 +509,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
   const int count_len = o->maxit + kRing;
   size_t total = ctl_bytes(count_len);
   for (auto& b : bs) {
-    b.L = plan(b.B, b.n, o->prec, &b.w);
+    b.L = plan(b.B, b.n, o->prec, o->stencil_prec, &b.w);
     b.base = total;
     total += b.L.total;
   }
@@ -537,6 +550,10 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     launch_scalar_init(b.w, st);
     launch_meansub(b.w, st);
     launch_scalar_fnorm(b.w, st);
+    if (b.w.sprec) {
+      HIP_TRY(hipMemcpyAsync(b.w.f, b.w.r, (size_t)b.w.S * b.w.N2 * 8, hipMemcpyDeviceToDevice, st));
+      launch_to_f32(b.w.a, const_cast<float*>(b.w.a32), (long long)b.B * b.w.N2, st);
+    }
   }
 
   // kernel variants: defaults, or the autotuner's choice for each shape; then
@@ -545,7 +562,8 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     Work& w = b.w;
     const int n = b.n;
     const int bb = batch_bucket(b.B);
-    const TuneKey kst(0, n, o->prec, bb), kgm(1, n, o->prec, bb);
+    // kind 0: FP64 operator-apply shape, kind 2: FP32 operator-apply shape
+    const TuneKey kst(w.sprec ? 2 : 0, n, o->prec, bb), kgm(1, n, o->prec, bb);
     const bool tune_now = ctx->autotune && (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) &&
                           count_active(ctx, w) > 0;
     if (ctx->autotune) {
@@ -657,6 +675,7 @@ void rve_default_opts(rve_opts* o) {
   o->prec = RVE_FP64;
   o->flexible = -1;
   o->check_every = 0;
+  o->stencil_prec = RVE_STENCIL_FP64;
 }
 
 const char* rve_status_string(int s) {
@@ -876,7 +895,7 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
-  const Layout L = plan(B, n, prec, &w);
+  const Layout L = plan(B, n, prec, 0, &w);
   int rc = ensure_ws(c, L.total);
   if (rc) return rc;
   bind(static_cast<char*>(c->ws), L, &w);
@@ -918,7 +937,7 @@ int rve_set_autotune(rve_ctx* c, int mode) {
 }
 
 int rve_get_tuned(rve_ctx* c, int kind, int n, int prec, int B, int* choice) {
-  if (!c || !choice || (kind != 0 && kind != 1) || B < 1) return RVE_EINVAL;
+  if (!c || !choice || kind < 0 || kind > 2 || B < 1) return RVE_EINVAL;
   auto it = c->tune.find(TuneKey(kind, n, prec, batch_bucket(B)));
   if (it == c->tune.end()) {
     *choice = -1;

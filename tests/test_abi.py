@@ -40,6 +40,7 @@ def test_status_strings_and_defaults(lib):
     o = N.RveOpts()
     lib.rve_default_opts(ctypes.byref(o))
     assert o.tol == 1e-10 and o.maxit == 2000 and o.prec == N.FP64 and o.flexible == -1
+    assert o.stencil_prec == N.STENCIL_FP64
 
 
 def test_host_argument_validation(lib):
@@ -59,6 +60,9 @@ def test_host_argument_validation(lib):
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
     bad = N.RveOpts(1e-10, 0, 0, -1, 0)
+    assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                               None, None) == N.EINVAL
+    bad = N.RveOpts(1e-10, 10, 0, -1, 0, 2)
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
     bad = N.RveOpts(1e-10, 10, 7, -1, 0)
@@ -85,6 +89,7 @@ def test_header_constants_match_binding():
     assert m and int(m.group(1)) == N.DIRECTION_RING
     for name, val in (("RVE_OK", N.OK), ("RVE_NOT_CONVERGED", N.NOT_CONVERGED), ("RVE_BREAKDOWN", N.BREAKDOWN),
                       ("RVE_EINVAL", N.EINVAL), ("RVE_EHIP", N.EHIP), ("RVE_ENOMEM", N.ENOMEM),
-                      ("RVE_FP64", N.FP64), ("RVE_MIX_FP32", N.MIX_FP32), ("RVE_MIX_BF16", N.MIX_BF16)):
+                      ("RVE_FP64", N.FP64), ("RVE_MIX_FP32", N.MIX_FP32), ("RVE_MIX_BF16", N.MIX_BF16),
+                      ("RVE_STENCIL_FP64", N.STENCIL_FP64), ("RVE_STENCIL_FP32", N.STENCIL_FP32)):
         m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
         assert m and int(m.group(1)) == val, name

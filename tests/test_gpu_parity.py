@@ -140,6 +140,41 @@ def test_true_residual_meets_tolerance(dev, prec):
             assert true <= 2.0 * tol, (b, i, true)
 
 
+@pytest.mark.parametrize("prec", [0, 2])
+def test_fp32_stencil_matches_oracle(dev, prec):
+    # FP32 operator apply with FP64 partial sums and the residual recomputed
+    # as f - A x every 8 iterations: A_hom to the mixed-precision bound and
+    # the true residual at the tolerance
+    rve = _rve()
+    n, B, tol = 128, 2, 1e-10
+    a = _fields(n, B, 17)
+    h = 1.0 / 8
+    res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=tol, prec=prec, stencil_prec=1))
+    assert res.code == 0
+    A = res.ahom.cpu().numpy()
+    x = res.phi.cpu().numpy() / h
+    for b in range(B):
+        assert rel2(A[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-8
+        K = q1.assemble(a[b])
+        for i, f in enumerate(q1.rhs(a[b])):
+            f = f - f.mean()
+            true = np.linalg.norm(f.ravel() - K @ x[b, i].ravel()) / np.linalg.norm(f)
+            assert true <= 2.0 * tol, (b, i, true)
+
+
+def test_fp32_stencil_uneven_contrast_100(dev):
+    rve = _rve()
+    items = []
+    for k, L in enumerate((8, 16, 8, 24)):
+        items.append(realization(BooleanModel(L=L, m0=8, a_in=100.0), 5, k))
+    opts = rve.Options(tol=1e-10, prec=2, stencil_prec=1)
+    res = rve.solve_uneven([torch.from_numpy(f).to(dev) for f in items], 0.125, opts)
+    assert res.code == 0
+    A = res.ahom.cpu().numpy()
+    for b, f in enumerate(items):
+        assert rel2(A[b], oa.solve(f, tol=1e-13).ahom) <= 1e-8
+
+
 def test_uneven_batch_matches_oracle(dev):
     rve = _rve()
     items = []
