@@ -14,6 +14,14 @@ per-realization FP64 PCG are timed beside it.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 Prints one JSON line.
+
+    python bench.py --survey
+Times the other workloads of the study instead (one JSON line each): one
+realization at L = 8; 256 at L = 32 with their mean and variance; 1024 of
+mixed L in {8, 16, 32, 64} at contrast 100 with FP64 and FP32 operator
+applies; 16 at L = 128, h = 1/16 with BF16 and FP32 transforms against FP64;
+the gradient at L = 64 for 64 realizations and the quartic tensor of 4096
+realizations at L = 16.
 """
 from __future__ import annotations
 
@@ -212,6 +220,7 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines file of autotuned kernel choices to read and extend "
                          "(lets profiling runs replay the choices of a normal run)")
+    ap.add_argument("--survey", action="store_true", help="time the other workloads instead")
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["RVE_TUNE_CACHE"] = args.tune_cache
@@ -230,6 +239,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.survey:
+        survey(rve, torch, dev)
+        return
     L, m0, B = args.L, args.m0, args.batch
     n, h = L * m0, 1.0 / m0
     model = BooleanModel(L=L, m0=m0, a_in=args.contrast, a_bg=1.0)
@@ -311,6 +323,99 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def survey(rve, torch, dev):
+    """One JSON line per workload: wall time per call (after one warm-up call
+    of the same shape, so tuning and graph capture are excluded), mean PCG
+    iterations, and where a reference run exists the largest relative A_hom
+    deviation from it (max |dA_ij| / max(|A_11|, |A_22|))."""
+    import numpy as np
+
+    from sampler import BooleanModel, batch, uneven_batch
+
+    def timed(fn, reps=1):
+        out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    def dev_rel(A, R):
+        A, R = A.cpu().numpy(), R.cpu().numpy()
+        scale = np.maximum(np.abs(R[:, 0, 0]), np.abs(R[:, 1, 1]))
+        return float(np.max(np.abs(A - R).reshape(len(A), -1).max(axis=1) / scale))
+
+    def emit(name, **kw):
+        print(json.dumps({"survey": name, **kw}), flush=True)
+
+    def fields(L, m0, contrast, count, config):
+        return torch.from_numpy(batch(BooleanModel(L=L, m0=m0, a_in=contrast), config, count)).to(dev)
+
+    # one realization, L = 8 (n = 64), FP64: latency
+    a = fields(8, 8, 10.0, 1, 11)
+    for graphs in (True, False):
+        ctx = rve.Context(0)
+        ctx.set_graphs(graphs)
+        dt, r = timed(lambda: rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.FP64), ctx=ctx), reps=20)
+        emit("L=8 n=64, 1 realization, FP64", graphs=graphs, ms=1e3 * dt, iters_mean=float(r.iters.double().mean()))
+
+    # 256 realizations at L = 32 (n = 256) with mean and variance
+    a = fields(32, 8, 10.0, 256, 12)
+    for prec, name in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16")):
+        def step():
+            r = rve.solve_batch(a, 1 / 8, rve.Options(prec=prec), want_phi=False)
+            return r, rve.stats(r.ahom, 32.0)
+        dt, (r, st) = timed(step, reps=3)
+        emit("L=32 n=256, 256 realizations + mean/variance", gemm=name, ms=1e3 * dt,
+             realizations_s=256 / dt, iters_mean=float(r.iters.double().mean()))
+        if prec == rve.FP64:
+            ref = r.ahom
+
+    # 1024 realizations of L in {8, 16, 32, 64}, contrast 100, FP64 vs FP32 operator apply
+    mix = uneven_batch([8, 16, 32, 64], m0=8, a_in=100.0, a_bg=1.0, config=3, per_size=256)
+    ft = [torch.from_numpy(f).to(dev) for _, f in mix]
+    ref = None
+    for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16")):
+        for sprec, sname in ((0, "fp64"), (1, "fp32")):
+            o = rve.Options(prec=prec, stencil_prec=sprec)
+            dt, r = timed(lambda: rve.solve_uneven(ft, 1 / 8, o))
+            if ref is None:
+                ref = r.ahom
+            emit("1024 realizations, L in {8,16,32,64} (n 64..512), contrast 100", gemm=pname, stencil=sname,
+                 ms=1e3 * dt, realizations_s=len(ft) / dt, iters_mean=float(r.iters.double().mean()),
+                 ahom_rel_dev_vs_fp64=dev_rel(r.ahom, ref), code=r.code)
+
+    # 16 realizations at L = 128, h = 1/16 (n = 2048)
+    a = fields(128, 16, 10.0, 16, 14)
+    r64 = rve.solve_batch(a, 1 / 16, rve.Options(prec=rve.FP64), want_phi=False)
+    for prec, pname in ((rve.MIX_BF16, "bf16"), (rve.MIX_FP32, "fp32"), (rve.FP64, "fp64")):
+        dt, r = timed(lambda: rve.solve_batch(a, 1 / 16, rve.Options(prec=prec), want_phi=False))
+        emit("L=128 h=1/16 n=2048, 16 realizations", gemm=pname, ms=1e3 * dt, realizations_s=16 / dt,
+             iters_mean=float(r.iters.double().mean()), ahom_rel_dev_vs_fp64=dev_rel(r.ahom, r64.ahom))
+    del a, r64
+
+    # gradient at L = 64 for 64 realizations; quartic tensor over 4096 at L = 16
+    a = fields(64, 8, 10.0, 64, 15)
+    G = torch.zeros((64, 2, 2), dtype=torch.float64, device=dev)
+    G[:, 0, 0] = 1.0
+    G[:, 0, 1] = 1.0
+
+    def grad_step():
+        r = rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.MIX_BF16))
+        return rve.grad(a, r.phi, 1 / 8, G, a_in=10.0)
+    dt, _ = timed(grad_step, reps=2)
+    emit("L=64 n=512, 64 realizations: solve + dA/da per cell + dA/dcontrast", gemm="bf16", ms=1e3 * dt)
+    a = fields(16, 8, 10.0, 4096, 16)
+
+    def quartic():
+        r = rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.MIX_BF16), want_phi=False)
+        return rve.stats(r.ahom, 16.0)
+    dt, st = timed(quartic)
+    emit("L=16 n=128, 4096 realizations: A_hom and the quartic tensor", gemm="bf16", ms=1e3 * dt,
+         realizations_s=4096 / dt)
 
 
 def cpu_baseline(fields, seconds):
