@@ -218,19 +218,30 @@ const char* rve_status_string(int status);
  * (n, precision, floor(log2 B)) times the candidate kernel variants on the
  * live data and keeps the fastest: the shape of the operator apply (V = 1, 2
  * or 4 grid columns per lane, H = 16 or 64 rows per wave strip, D = 1 or 2
- * rows of loads in flight per wave) and the transform-GEMM tile (64 x 64,
- * or 128 x 128 for BF16 when n % 128 == 0). Choices are cached in the context
+ * rows of loads in flight per wave) and the transform-GEMM variant (64 x 64
+ * tiles, or for BF16 128 x 128 tiles when n % 128 == 0; the even/odd-folded
+ * variant is used only through rve_force_variants, since its saving per
+ * apply is outweighed by extra iterations). Choices are cached in the context
  * and, if the environment variable RVE_TUNE_CACHE names a file, appended
  * there as JSON lines and read back by rve_create. Mode 0 uses fixed
  * defaults. Results do not depend on the choice beyond rounding order.
  *
  * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
- * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128)
- * or 2 (FP32 operator-apply shape, encoded as kind 0) of a shape,
+ * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128,
+ * 2 = folded 128 x 128) or 2 (FP32 operator-apply shape, encoded as kind 0)
+ * of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
  * that are not valid for a shape are ignored and tuned again.
  */
 int rve_set_autotune(rve_ctx* ctx, int mode);
+
+/* Use these kernel variants instead of the autotuner's or default choice
+ * (-1: no override): an operator-apply shape as encoded for rve_get_tuned
+ * kind 0 / 2, and a transform-GEMM variant (0: 64 x 64 tiles; 1: 128 x 128
+ * BF16 tiles, n % 128 == 0; 2: even/odd-folded 128 x 128 BF16 tiles, half the
+ * MFMA work, n % 256 == 0). An override that is not valid for a shape is
+ * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
+int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
 
 /* Chunks of PCG iterations: mode 1 (the default) captures each distinct
  * chunk (same batches, pointers, kernel choices and options) once as a HIP

@@ -22,7 +22,7 @@ EXPORTS = (
     "rve_solve_batch", "rve_solve_uneven", "rve_grad", "rve_stats",
     "rve_status_string", "rve_set_timing", "rve_last_timing",
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
-    "rve_set_graphs",
+    "rve_set_graphs", "rve_force_variants",
 )
 
 

@@ -80,6 +80,13 @@ class Context:
     def set_autotune(self, enable: bool):
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
 
+    def force_variants(self, stencil: int = -1, gemm: int = -1):
+        """Use these kernel variants instead of the autotuner's (-1: no
+        override): an operator-apply shape code (see tuned()) and a
+        transform-GEMM variant (0: 64 x 64, 1: 128 x 128 BF16, 2: even/odd
+        folded 128 x 128 BF16)."""
+        N.check(self._lib.rve_force_variants(self.handle, int(stencil), int(gemm)), "rve_force_variants")
+
     def set_graphs(self, enable: bool):
         """Replay each chunk of PCG iterations from a captured HIP graph (the
         default) or launch its kernels one by one; results are identical."""

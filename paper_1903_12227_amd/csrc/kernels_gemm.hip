@@ -399,7 +399,278 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   }
 }
 
+// Even/odd-folded BF16 transform (n % 256 == 0), half the MFMA work of
+// k_hartley_bf16 for the same output. Q = c + s with
+// c[t][k] = cos(2 pi t k / n)/sqrt(n) even and s[t][k] = sin(2 pi t k / n)/sqrt(n)
+// odd under t -> n - t and under k -> n - k. For 0 <= k < n/2 and h = n/2:
+//   C[r][k] = sum_{t<h} Xe[r][t] c[t][k] + (-1)^k X[r][h]/sqrt(n),
+//   S[r][k] = sum_{t<h} Xo[r][t] s[t][k],
+// with Xe[t] = X[t] + X[n-t], Xo[t] = X[t] - X[n-t] for t >= 1, Xe[0] = X[0],
+// Xo[0] = 0; then (X Q)[r][k] = C + S and (X Q)[r][n-k] = C - S. The one
+// output row these miss, (X Q)[r][h] = sum_j (-1)^j X[r][j]/sqrt(n), is the
+// alternating sum of the folded operand plus (-1)^h X[r][h], accumulated by
+// the tiles of the first column block while they fold. The folded operand
+// is rounded to BF16 once more than the plain transform's input.
+// Tile: 128 rows r x 128 columns k < h, two accumulator sets (C and S) per
+// wave, operand tiles Xe, Xo, c, s of 128 x 32 BF16 in LDS; the epilogue
+// writes output rows k and n - k through LDS, transposed as in
+// k_hartley_bf16.
+constexpr int SK = 32, SLDA = SK + 8;   // K slice and operand row stride of the folded kernel
+
+template <int EPI, class ZT, class RT = double>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_hartley_bf16_sym(const __bf16* __restrict__ X, const __bf16* __restrict__ Ch, const __bf16* __restrict__ Sh,
+                   void* __restrict__ out_v, int n, int S, const SysState* sys, const RealState* real,
+                   const float* __restrict__ einv, const RT* __restrict__ rres, double* __restrict__ part) {
+  constexpr int kOp = TM * SLDA;   // elements of one operand tile
+  constexpr size_t kOpBytes = 4 * (size_t)kOp * sizeof(__bf16);
+  constexpr size_t kCBytes = 2 * (size_t)64 * TLDC * sizeof(float);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kCBytes ? kOpBytes : kCBytes];
+  __shared__ float hrow[TM];
+  __shared__ double red[4];
+  __bf16* Ae = reinterpret_cast<__bf16*>(smem);
+  __bf16* Ao = Ae + kOp;
+  __bf16* Bc = Ao + kOp;
+  __bf16* Bsn = Bc + kOp;
+  float* Cp = reinterpret_cast<float*>(smem);
+  float* Cm = Cp + 64 * TLDC;
+
+  const int h = n / 2;
+  const int NB = h / TN, MB = n / TM;
+  const long long T = (long long)S * MB * NB;
+  long long tt = blockIdx.x;
+  if ((T & 7) == 0) tt = (tt & 7) * (T >> 3) + (tt >> 3);   // XCD-contiguous tile ranges
+  const int nb = (int)(tt % NB);
+  const long long rest = tt / NB;
+  const int mb = (int)(rest % MB);
+  const int s = (int)(rest / MB);
+  if (sys && !sys[s].active) return;
+
+  const long long N2 = (long long)n * n;
+  const __bf16* Xs = X + (long long)s * N2 + (long long)mb * TM * n;
+  const __bf16* Cq = Ch + (long long)nb * TN * h;
+  const __bf16* Sq = Sh + (long long)nb * TN * h;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int lr = tid >> 2, lc = (tid & 3) * 8;   // rows lr and lr + 64, 8 values each
+  const float isq = (float)(1.0 / sqrt((double)n));
+  if (tid < TM) hrow[tid] = (float)Xs[(long long)tid * n + h] * isq;   // read after the first barrier
+
+  // register staging of the next K slice: forward and mirrored row chunks of
+  // X (the mirrored chunk [n-t0-8, n-t0) plus the single value X[n-t0]) and
+  // the c / s table rows
+  uint4 fa0, fa1, ma0, ma1, rc0, rc1, rs0, rs1;
+  __bf16 ea0, ea1;
+  float alt0 = 0.f, alt1 = 0.f;   // alternating row sums (first column block)
+  const long long r64 = 64LL * n;
+  const __bf16* xr = Xs + (long long)lr * n;
+  const __bf16* cr = Cq + (long long)lr * h + lc;
+  const __bf16* sr = Sq + (long long)lr * h + lc;
+  const long long h64 = 64LL * h;
+#define RVE_SYM_GLOAD(t0)                                                                     \
+  do {                                                                                       \
+    const int tf = (t0) + lc, tm = n - (t0) - lc;                                            \
+    const int te = tf == 0 ? 0 : tm;                                                         \
+    fa0 = *reinterpret_cast<const uint4*>(xr + tf);                                          \
+    fa1 = *reinterpret_cast<const uint4*>(xr + r64 + tf);                                    \
+    ma0 = *reinterpret_cast<const uint4*>(xr + tm - 8);                                      \
+    ma1 = *reinterpret_cast<const uint4*>(xr + r64 + tm - 8);                                \
+    ea0 = xr[te];                                                                            \
+    ea1 = xr[r64 + te];                                                                      \
+    rc0 = *reinterpret_cast<const uint4*>(cr + (t0));                                        \
+    rc1 = *reinterpret_cast<const uint4*>(cr + h64 + (t0));                                  \
+    rs0 = *reinterpret_cast<const uint4*>(sr + (t0));                                        \
+    rs1 = *reinterpret_cast<const uint4*>(sr + h64 + (t0));                                  \
+  } while (0)
+  // fold one staged row chunk (row lr + 64 i) into Xe / Xo and store it
+  auto fold = [&](int t0, int i, const uint4& f4, const uint4& m4, __bf16 ev, float& alt) {
+    const v8bf f = __builtin_bit_cast(v8bf, f4), m = __builtin_bit_cast(v8bf, m4);
+    v8bf ve, vo;
+    float sum = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = t0 + lc + e;
+      const float xf = (float)f[e];
+      const float xm = e == 0 ? (float)ev : (float)m[8 - e];
+      ve[e] = (__bf16)(t == 0 ? xf : xf + xm);
+      vo[e] = (__bf16)(t == 0 ? 0.f : xf - xm);
+      sum += (t & 1) ? -(float)ve[e] : (float)ve[e];
+    }
+    if (nb == 0) alt += sum;
+    *reinterpret_cast<v8bf*>(Ae + (lr + 64 * i) * SLDA + lc) = ve;
+    *reinterpret_cast<v8bf*>(Ao + (lr + 64 * i) * SLDA + lc) = vo;
+  };
+#define RVE_SYM_SSTORE(t0)                                                                    \
+  do {                                                                                       \
+    fold((t0), 0, fa0, ma0, ea0, alt0);                                                      \
+    fold((t0), 1, fa1, ma1, ea1, alt1);                                                      \
+    *reinterpret_cast<uint4*>(Bc + lr * SLDA + lc) = rc0;                                    \
+    *reinterpret_cast<uint4*>(Bc + (lr + 64) * SLDA + lc) = rc1;                             \
+    *reinterpret_cast<uint4*>(Bsn + lr * SLDA + lc) = rs0;                                   \
+    *reinterpret_cast<uint4*>(Bsn + (lr + 64) * SLDA + lc) = rs1;                            \
+  } while (0)
+
+  v4f accc[4][4], accs[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        accc[i][j][e] = 0.f;
+        accs[i][j][e] = 0.f;
+      }
+
+  const int frow = lane & 15, fk = (lane >> 4) * 8;
+  RVE_SYM_GLOAD(0);
+  RVE_SYM_SSTORE(0);
+  __syncthreads();
+  for (int t0 = 0; t0 < h; t0 += SK) {
+    const bool more = t0 + SK < h;
+    if (more) RVE_SYM_GLOAD(t0 + SK);
+    {
+      v8bf bq[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bq[j] = *reinterpret_cast<const v8bf*>(Bc + (wn * 64 + j * 16 + frow) * SLDA + fk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const v8bf ae = *reinterpret_cast<const v8bf*>(Ae + (wm * 64 + i * 16 + frow) * SLDA + fk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          accc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ae, bq[j], accc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bq[j] = *reinterpret_cast<const v8bf*>(Bsn + (wn * 64 + j * 16 + frow) * SLDA + fk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const v8bf ao = *reinterpret_cast<const v8bf*>(Ao + (wm * 64 + i * 16 + frow) * SLDA + fk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          accs[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao, bq[j], accs[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      RVE_SYM_SSTORE(t0 + SK);
+      __syncthreads();
+    }
+  }
+#undef RVE_SYM_GLOAD
+#undef RVE_SYM_SSTORE
+
+  float scale = 1.f;
+  if constexpr (EPI == kEpiEinv) scale = (float)real[s >> 1].inv_a0;
+  double dot = 0.0;
+  // one output value at (output row krow, column col) through the epilogue
+  auto emit1 = [&](long long krow, long long col, float v) {
+    const long long idx = (long long)s * N2 + krow * n + col;
+    if constexpr (EPI == kEpiEinv) v *= einv[krow * n + col] * scale;
+    if constexpr (EPI == kEpiZ) {
+      const ZT zs = (ZT)v;
+      reinterpret_cast<ZT*>(out_v)[idx] = zs;
+      dot += (double)zs * widen(rres[idx]);
+    } else {
+      reinterpret_cast<__bf16*>(out_v)[idx] = (__bf16)v;
+    }
+  };
+  // 32 consecutive values of output row krow from column m0
+  auto emit32 = [&](long long krow, long long m0, float* v) {
+    const long long obase = (long long)s * N2 + krow * n + m0;
+    if constexpr (EPI == kEpiEinv) {
+#pragma unroll
+      for (int e = 0; e < 32; e += 4) {
+        const float4 g = *reinterpret_cast<const float4*>(einv + krow * n + m0 + e);
+        v[e] *= g.x * scale; v[e + 1] *= g.y * scale; v[e + 2] *= g.z * scale; v[e + 3] *= g.w * scale;
+      }
+    }
+    if constexpr (EPI == kEpiZ) {
+      ZT* out = reinterpret_cast<ZT*>(out_v) + obase;
+#pragma unroll
+      for (int e = 0; e < 32; ++e) {
+        const ZT zs = (ZT)v[e];
+        out[e] = zs;
+        dot += (double)zs * widen(rres[obase + e]);
+      }
+    } else {
+      __bf16* out = reinterpret_cast<__bf16*>(out_v) + obase;
+#pragma unroll
+      for (int e = 0; e < 32; e += 8) {
+        v8bf pk;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pk[k] = (__bf16)v[e + k];
+        *reinterpret_cast<v8bf*>(out + e) = pk;
+      }
+    }
+  };
+
+  // output row h: alternating row sums (first column block), summed over the
+  // 8 lanes that folded the row's chunks
+  if (nb == 0) {
+    float al[2] = {alt0, alt1};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      al[i] += __shfl_xor(al[i], 1, 4);
+      al[i] += __shfl_xor(al[i], 2, 4);
+    }
+    if ((tid & 3) == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = lr + 64 * i;
+        const float xh = (float)Xs[(long long)row * n + h];
+        emit1(h, (long long)mb * TM + row, (al[i] + ((h & 1) ? -xh : xh)) * isq);
+      }
+    }
+  }
+
+  // rows k (C + S) and n - k (C - S) of the 128 columns of this tile, in two
+  // halves of 64 columns, transposed through LDS; k = 0 has no mirror row
+  const int orow = tid >> 2, oc0 = (tid & 3) * 32;
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+    if (wn == hh) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int rl = wm * 64 + i * 16 + 4 * (lane >> 4) + e;
+            const int kl = j * 16 + (lane & 15);
+            // (-1)^k X[r][h]/sqrt(n): k has the parity of the lane
+            const float c = accc[i][j][e] + ((lane & 1) ? -hrow[rl] : hrow[rl]);
+            Cp[kl * TLDC + rl] = c + accs[i][j][e];
+            Cm[kl * TLDC + rl] = c - accs[i][j][e];
+          }
+    }
+    __syncthreads();
+    const long long k = (long long)nb * TN + hh * 64 + orow;
+    const long long m0 = (long long)mb * TM + oc0;
+    float v[32];
+#pragma unroll
+    for (int e = 0; e < 32; e += 4) {
+      const float4 c = *reinterpret_cast<const float4*>(Cp + orow * TLDC + oc0 + e);
+      v[e] = c.x; v[e + 1] = c.y; v[e + 2] = c.z; v[e + 3] = c.w;
+    }
+    emit32(k, m0, v);
+    if (k != 0) {
+#pragma unroll
+      for (int e = 0; e < 32; e += 4) {
+        const float4 c = *reinterpret_cast<const float4*>(Cm + orow * TLDC + oc0 + e);
+        v[e] = c.x; v[e + 1] = c.y; v[e + 2] = c.z; v[e + 3] = c.w;
+      }
+      emit32(n - k, m0, v);
+    }
+    __syncthreads();
+  }
+  if constexpr (EPI == kEpiZ) {
+    double d[1] = {dot};
+    block_sum<1>(d, red);
+    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = d[0];
+  }
+}
+
 bool big_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % TM == 0; }
+bool folded_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % (2 * TN) == 0; }
 
 template <class Tr, class ZT>
 void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
@@ -459,6 +730,27 @@ void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st, in
                        w.real, nullptr, (const __bf16*)w.rlo, w.part_rz);
 }
 
+template <class ZT>
+void run_precond_bf16_sym(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
+  const int n = w.n;
+  const long long T = (long long)w.S * (n / TM) * (n / (2 * TN));
+  const dim3 grid((unsigned)T), block(kBlock);
+  __bf16* u1 = reinterpret_cast<__bf16*>(w.u1);
+  __bf16* u2 = reinterpret_cast<__bf16*>(w.u2);
+  if (phase < 0 || phase == 0)
+    hipLaunchKernelGGL((k_hartley_bf16_sym<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, t.ch16,
+                       t.sh16, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (phase < 0 || phase == 1)
+    hipLaunchKernelGGL((k_hartley_bf16_sym<kEpiEinv, float>), grid, block, 0, st, (const __bf16*)u1, t.ch16,
+                       t.sh16, (void*)u2, n, w.S, w.sys, w.real, t.einv32, (const double*)nullptr, nullptr);
+  if (phase < 0 || phase == 2)
+    hipLaunchKernelGGL((k_hartley_bf16_sym<kEpiStore, float>), grid, block, 0, st, (const __bf16*)u2, t.ch16,
+                       t.sh16, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (phase < 0 || phase == 3)
+    hipLaunchKernelGGL((k_hartley_bf16_sym<kEpiZ, ZT, __bf16>), grid, block, 0, st, (const __bf16*)u1, t.ch16,
+                       t.sh16, w.z, n, w.S, w.sys, w.real, nullptr, (const __bf16*)w.rlo, w.part_rz);
+}
+
 }  // namespace
 
 size_t gemm_elem_size(int prec) {
@@ -466,11 +758,11 @@ size_t gemm_elem_size(int prec) {
 }
 
 bool gemm_variant_valid(int n, int prec, int variant) {
-  return variant == 0 || (variant == 1 && big_bf16_tiles(n, prec));
+  return variant == 0 || (variant == 1 && big_bf16_tiles(n, prec)) || (variant == 2 && folded_bf16_tiles(n, prec));
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
-  return variant == 1 ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
+  return variant == 2 ? (n / TM) * (n / (2 * TN)) : variant == 1 ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
 }
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
@@ -481,6 +773,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond<TrF64, double>(w, t, st, phase);
   } else if (prec == kGemmF32) {
     run_precond<TrF32, float>(w, t, st, phase);
+  } else if (w.gemm_variant == 2) {
+    run_precond_bf16_sym<float>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
     run_precond_bf16_big<float>(w, t, st, phase);
   } else {

@@ -320,6 +320,8 @@ __device__ inline void raw_load(const T* p, T* v) {
 //
 // FUSED: iteration k is read from *kiter; p_k goes to ring slot k mod m and
 // p_{k-1} comes from slot (k - 1) mod m (slots slot_stride elements apart).
+// probe = 1 (autotuner timing at k = 0 only) reads p_{k-1} as a later
+// iteration would; its outputs are rewritten by the real iteration 0.
 // Not FUSED: the operand is p_in.
 // CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
 // FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
@@ -328,7 +330,8 @@ template <bool FUSED, class PT, class ZT, int V, int D, class CT>
 __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, const PT* p_in, PT* ring,
                                                        long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
-                                                       int H, const SysState* sys, double* __restrict__ part) {
+                                                       int H, const SysState* sys, double* __restrict__ part,
+                                                       int probe) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
   int first = 0;
@@ -336,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
   PT* __restrict__ p_new = nullptr;
   if constexpr (FUSED) {
     const int k = kiter[0];
-    first = k == 0;
+    first = k == 0 && !probe;   // a probe does the work of a later iteration
     p_new = ring + (long long)(k % m) * slot_stride;
     p_old = ring + (long long)((k + m - 1) % m) * slot_stride;
   }
@@ -966,47 +969,51 @@ bool stencil_choice_valid(int n, int c) {
 template <bool FUSED, class PT, class ZT, int D, class CT>
 void launch_stencil_d(int B, int n, int V, int H, const CT* a, const PT* pin, PT* ring, long long slot_stride,
                       int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
-                      hipStream_t st) {
+                      int probe, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part);
+                       z, q, n, H, sys, part, probe);
   else if (V == 2)
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part);
+                       z, q, n, H, sys, part, probe);
   else
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part);
+                       z, q, n, H, sys, part, probe);
 }
 
 template <bool FUSED, class PT, class ZT, class CT>
 void launch_stencil_t(int B, int n, int c, const CT* a, const PT* pin, PT* ring, long long slot_stride, int m,
-                      const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, hipStream_t st) {
+                      const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
+                      hipStream_t st) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
+    launch_stencil_d<FUSED, PT, ZT, 2, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, probe,
+                                           st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, st);
+    launch_stencil_d<FUSED, PT, ZT, 1, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, probe,
+                                           st);
 }
 
 template <class PT>
-void launch_stencil_fused_p(const Work& w, hipStream_t st) {
+void launch_stencil_fused_p(const Work& w, int probe, hipStream_t st) {
   const long long slot = (long long)w.S * w.N2;
   if (w.sprec)
     launch_stencil_t<true, PT, PT, float>(w.B, w.n, w.stencil, w.a32, (const PT*)nullptr, (PT*)w.pring, slot,
-                                          w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq, st);
+                                          w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq, probe,
+                                          st);
   else
     launch_stencil_t<true, PT, PT, double>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                           w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, st);
+                                           w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
 }
 
-void launch_stencil_fused(const Work& w, hipStream_t st) {
+void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
   // iteration k (read on the device) writes p_k into ring slot k mod m and
   // reads p_{k-1} from the previous slot
   if (w.mixed == 0)
-    launch_stencil_fused_p<double>(w, st);
+    launch_stencil_fused_p<double>(w, probe, st);
   else
-    launch_stencil_fused_p<float>(w, st);
+    launch_stencil_fused_p<float>(w, probe, st);
 }
 
 int stencil_tiles_per_realization(int n, int c) {
@@ -1102,7 +1109,7 @@ void launch_fold_x(const Work& w, int final, hipStream_t st) {
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
   launch_stencil_t<false, double, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0, 1,
                                                   (const int*)nullptr, (const double*)nullptr, out,
-                                                  (const SysState*)nullptr, (double*)nullptr, st);
+                                                  (const SysState*)nullptr, (double*)nullptr, 0, st);
 }
 
 void launch_scalar_alpha(const Work& w, hipStream_t st) {

@@ -40,7 +40,8 @@ struct Work {
   const float* a32 = nullptr;
   double* f = nullptr;
   int stencil = 0;           // operator-apply shape (stencil_choice_*)
-  int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0)
+  int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0);
+                             // 2: even/odd-folded 128 x 128 (BF16, n % 256 == 0)
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
   double* part_pq = nullptr;   // [S][P] partial sums of p.Ap
@@ -79,8 +80,10 @@ void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
 // Fused direction step + operator apply of the current PCG iteration in the
 // shape w.stencil (w.P_st must equal stencil_tiles_per_realization(n,
-// w.stencil)).
-void launch_stencil_fused(const Work& w, hipStream_t st);
+// w.stencil)). probe = 1, only at iteration 0 and only for timing, reads the
+// previous direction's ring slot like a later iteration (outputs are then
+// rewritten by the real iteration 0).
+void launch_stencil_fused(const Work& w, hipStream_t st, int probe = 0);
 // Operator-apply shapes, encoded as c = V + 8 (H / 16) + 64 (D - 1): V in
 // {1, 2, 4} columns per lane, H in {16, 32, 64} rows per wave strip, D in
 // {1, 2} rows of loads in flight per wave; valid when the 64V x 4H
@@ -120,6 +123,8 @@ struct GemmTables {
   const void* q = nullptr;        // [n][n] Hartley matrix in the GEMM operand type
   const double* einv64 = nullptr; // [n][n] 1/E, (0,0) entry 0
   const float* einv32 = nullptr;
+  const __bf16* ch16 = nullptr;   // [n/2][n/2] cos(2 pi k t/n)/sqrt(n), BF16 (folded transform)
+  const __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t/n)/sqrt(n), BF16
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.

@@ -39,6 +39,8 @@ struct Tables {
   __bf16* q16 = nullptr;
   double* einv64 = nullptr;
   float* einv32 = nullptr;
+  __bf16* ch16 = nullptr;   // [n/2][n/2] cos(2 pi k t / n)/sqrt(n), row k (n % 256 == 0 only)
+  __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t / n)/sqrt(n)
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
@@ -74,6 +76,8 @@ struct rve_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;   // private stream the iteration chunks are captured on
   int graphs = 1;                     // replay captured chunks (1) or launch them one by one (0)
+  int force_stencil = -1;             // operator-apply shape to use instead of the tuner's (-1: none)
+  int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
   std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
@@ -141,12 +145,23 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
       einv[(size_t)k * n + l] = inv;
       einv32[(size_t)k * n + l] = (float)inv;
     }
+  // half-size cosine and sine parts of Q for the even/odd-folded transform
+  const int h = n / 2;
+  const size_t H2 = (size_t)h * h;
+  std::vector<__bf16> ch(H2), sh(H2);
+  for (int k = 0; k < h; ++k)
+    for (int j = 0; j < h; ++j) {
+      const double ang = two_pi * (double)((long long)k * j % n) / (double)n;
+      ch[(size_t)k * h + j] = (__bf16)(float)(std::cos(ang) * inv_sqrt);
+      sh[(size_t)k * h + j] = (__bf16)(float)(std::sin(ang) * inv_sqrt);
+    }
   Tables t;
   if (hipMalloc(&t.q64, N2 * 8) != hipSuccess || hipMalloc(&t.q32, N2 * 4) != hipSuccess ||
       hipMalloc(&t.q16, N2 * 2) != hipSuccess || hipMalloc(&t.einv64, N2 * 8) != hipSuccess ||
-      hipMalloc(&t.einv32, N2 * 4) != hipSuccess) {
+      hipMalloc(&t.einv32, N2 * 4) != hipSuccess || hipMalloc(&t.ch16, H2 * 2) != hipSuccess ||
+      hipMalloc(&t.sh16, H2 * 2) != hipSuccess) {
     ignore(hipFree(t.q64)); ignore(hipFree(t.q32)); ignore(hipFree(t.q16));
-    ignore(hipFree(t.einv64)); ignore(hipFree(t.einv32));
+    ignore(hipFree(t.einv64)); ignore(hipFree(t.einv32)); ignore(hipFree(t.ch16)); ignore(hipFree(t.sh16));
     return RVE_ENOMEM;
   }
   HIP_TRY(hipMemcpy(t.q64, q.data(), N2 * 8, hipMemcpyHostToDevice));
@@ -154,6 +169,8 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   HIP_TRY(hipMemcpy(t.q16, q16.data(), N2 * 2, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(t.einv64, einv.data(), N2 * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(t.einv32, einv32.data(), N2 * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.ch16, ch.data(), H2 * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.sh16, sh.data(), H2 * 2, hipMemcpyHostToDevice));
   ctx->tables[n] = t;
   *out = &ctx->tables[n];
   return RVE_OK;
@@ -540,6 +557,8 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
                                                                                   : (const void*)tb->q16;
     b.gt.einv64 = tb->einv64;
     b.gt.einv32 = tb->einv32;
+    b.gt.ch16 = tb->ch16;
+    b.gt.sh16 = tb->sh16;
     b.prec = prec;
   }
 
@@ -565,9 +584,12 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     // kind 0: FP64 operator-apply shape, kind 2: FP32 operator-apply shape
     const TuneKey kst(w.sprec ? 2 : 0, n, o->prec, bb), kgm(1, n, o->prec, bb);
     const bool tune_now = ctx->autotune && (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) &&
-                          count_active(ctx, w) > 0;
+                          (ctx->force_stencil < 0 || ctx->force_gemm < 0) && count_active(ctx, w) > 0;
     if (ctx->autotune) {
       std::vector<int> gc;
+      // the even/odd-folded variant (2) is faster per apply but its extra BF16
+      // rounding costs iterations (n = 512: 39.3 vs 38.0; n = 2048: 149 vs
+      // 100), which a per-apply timing cannot see: it is used only on request
       for (int v : {0, 1})
         if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
       if (ctx->tune.count(kgm) || tune_now)
@@ -578,6 +600,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
           launch_precond(t2, prec, b.gt, st);
         });
     }
+    if (ctx->force_gemm >= 0 && gemm_variant_valid(n, prec, ctx->force_gemm)) w.gemm_variant = ctx->force_gemm;
     w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
     precond_timed(ctx, w, prec, b.gt, st);
     launch_scalar_beta(w, flexible, 1, st);
@@ -590,15 +613,22 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
             const int c = v + 8 * (hs / 16) + 64 * (d - 1);
             if (stencil_choice_valid(n, c)) vc.push_back(c);
           }
-      // the first operator apply (iteration 0) is idempotent: it reads z_0
+      // candidates are timed on probes of iteration 0 that also read the
+      // previous direction's slot (zeroed here), i.e. do a later iteration's
+      // work; iteration 0 then rewrites everything they wrote
+      if (tune_now && !ctx->tune.count(kst)) {
+        const size_t slot = (size_t)w.S * w.N2 * (w.mixed ? 4 : 8);
+        HIP_TRY(hipMemsetAsync(static_cast<char*>(w.pring) + (kRing - 1) * slot, 0, slot, st));
+      }
       if (ctx->tune.count(kst) || tune_now)
         sc = tune_pick(ctx, kst, vc, [&](int c) {
           Work t2 = w;
           t2.stencil = c;
           t2.P_st = stencil_tiles_per_realization(n, c);
-          launch_stencil_fused(t2, st);
+          launch_stencil_fused(t2, st, 1);
         });
     }
+    if (ctx->force_stencil >= 0 && stencil_choice_valid(n, ctx->force_stencil)) sc = ctx->force_stencil;
     w.stencil = sc;
     w.P_st = stencil_tiles_per_realization(n, sc);
   }
@@ -729,6 +759,8 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.q16));
     ignore(hipFree(kv.second.einv64));
     ignore(hipFree(kv.second.einv32));
+    ignore(hipFree(kv.second.ch16));
+    ignore(hipFree(kv.second.sh16));
   }
   clear_graphs(c);
   if (c->ws) ignore(hipFree(c->ws));
@@ -912,15 +944,31 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
                                                                          : (const void*)tb->q16;
   gt.einv64 = tb->einv64;
   gt.einv32 = tb->einv32;
+  gt.ch16 = tb->ch16;
+  gt.sh16 = tb->sh16;
   w.r = const_cast<double*>(r_dev);
   w.sys = nullptr;
   if (w.mixed) launch_round_lo(w, c->stream);
+  const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  if (c->force_gemm >= 0 && gemm_variant_valid(n, gp, c->force_gemm)) {
+    w.gemm_variant = c->force_gemm;
+    w.P_gemm = gemm_tiles_per_system(n, gp, w.gemm_variant);
+  }
   // the solver keeps z in FP32 in the mixed modes; the caller wants FP64
   void* z_solver = w.z;
   w.z = w.mixed ? z_solver : (void*)z_dev;
   launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
   if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
+  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 2) return RVE_EINVAL;
+  // a well-formed shape code (every shape tiles the largest supported grid)
+  if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
+  c->force_stencil = stencil_choice;
+  c->force_gemm = gemm_variant;
   return RVE_OK;
 }
 

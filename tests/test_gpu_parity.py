@@ -67,6 +67,46 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
             assert np.linalg.norm(zc - ref) <= tol * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("n", [256, 512])
+def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
+    # 128-row tiles (1) and the even/odd-folded tiles (2, half the MFMA work,
+    # one more BF16 rounding of the folded input) against the FFT apply
+    rve = _rve()
+    rng = np.random.default_rng(n + variant)
+    a = _fields(n, 2, 52)
+    r = rng.standard_normal((2, 2, n, n))
+    r -= r.mean(axis=(2, 3), keepdims=True)
+    ctx = rve.Context(0)
+    ctx.force_variants(gemm=variant)
+    z = rve.apply_precond(_to(a, dev), _to(r, dev), 2, ctx=ctx).cpu().numpy()
+    E = q1.symbol(n)
+    for b in range(2):
+        a0 = oa.preconditioner_scale(a[b])
+        for i in range(2):
+            ref = precond_apply(r[b, i], a0, E)
+            zc = z[b, i] - z[b, i].mean()
+            assert np.linalg.norm(zc - ref) <= 3e-2 * np.linalg.norm(ref)
+
+
+def test_folded_transform_solve_matches_oracle(dev):
+    rve = _rve()
+    n, B, tol, h = 256, 2, 1e-10, 1.0 / 8
+    a = _fields(n, B, 53)
+    ctx = rve.Context(0)
+    ctx.force_variants(gemm=2)
+    res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=tol, prec=2), ctx=ctx)
+    assert res.code == 0
+    A = res.ahom.cpu().numpy()
+    x = res.phi.cpu().numpy() / h
+    for b in range(B):
+        assert rel2(A[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-8
+        K = q1.assemble(a[b])
+        for i, f in enumerate(q1.rhs(a[b])):
+            f = f - f.mean()
+            assert np.linalg.norm(f.ravel() - K @ x[b, i].ravel()) / np.linalg.norm(f) <= 2.0 * tol
+
+
 @pytest.mark.parametrize("n,B", [(64, 4), (128, 3)])
 def test_solve_fp64_matches_oracle(dev, n, B):
     rve = _rve()
