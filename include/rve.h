@@ -235,6 +235,29 @@ const char* rve_status_string(int status);
  */
 int rve_set_autotune(rve_ctx* ctx, int mode);
 
+/*
+ * Sample B coefficient fields of the random inclusion model (Sec. 2, covered
+ * domain eqn. Stoch-decomp, coefficient eqn. ahm_coef) on the device, for
+ * realizations first .. first + B - 1, into a_dev [B][n][n] (FP64, device).
+ *
+ * Lattice law: each of the n^2 sites (i, j) is independently the centre of
+ * a side x side square with probability occ_threshold / 2^32 (for Poisson
+ * centres with mean mu per site, occ_threshold = round(2^32 (1 - exp(-mu)));
+ * with mu = ln 2 / side^2 half the cells are covered on average). Site
+ * s = i n + j of realization r is a centre iff word (s mod 4) of
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (s div 4, r mod 2^32,
+ * r div 2^32, 0) and key (seed mod 2^32, seed div 2^32) is below
+ * occ_threshold. A square centred at s covers cells s - side/2 + u,
+ * u = 0 .. side-1, in each direction (mod n); covered cells take a_in, the
+ * others a_bg. Integer arithmetic only: a realization's field does not
+ * depend on the batch it is drawn in or on the device.
+ *
+ * Requires n as for rve_solve_batch, 1 <= side <= min(32, n),
+ * 1 <= B <= 65535, first >= 0, a_in and a_bg > 0 and finite.
+ */
+int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int64_t first,
+                       uint32_t occ_threshold, double a_in, double a_bg, double* a_dev);
+
 /* Use these kernel variants instead of the autotuner's or default choice
  * (-1: no override): an operator-apply shape as encoded for rve_get_tuned
  * kind 0 / 2, and a transform-GEMM variant (0: 64 x 64 tiles; 1: 128 x 128

@@ -15,6 +15,6 @@ from ._native import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Context, Options, Result, context, solve_batch, solve_uneven, grad, stats,
-    apply_operator, apply_precond,
+    apply_operator, apply_precond, occupancy_threshold, sample_lattice,
 )
 from .autograd import RveAhom, RveAhomContrast, ahom  # noqa: F401

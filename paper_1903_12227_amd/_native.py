@@ -22,7 +22,7 @@ EXPORTS = (
     "rve_solve_batch", "rve_solve_uneven", "rve_grad", "rve_stats",
     "rve_status_string", "rve_set_timing", "rve_last_timing",
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
-    "rve_set_graphs", "rve_force_variants",
+    "rve_set_graphs", "rve_force_variants", "rve_sample_lattice",
 )
 
 
@@ -58,6 +58,10 @@ def _declare(lib):
     lib.rve_apply_precond.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
     lib.rve_set_autotune.argtypes = [_vp, _i]
     lib.rve_get_tuned.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(_i)]
+    lib.rve_set_graphs.argtypes = [_vp, _i]
+    lib.rve_force_variants.argtypes = [_vp, _i, _i]
+    lib.rve_sample_lattice.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
+                                       _d, _d, _vp]
     for name in EXPORTS:
         if name not in ("rve_default_opts", "rve_status_string"):
             getattr(lib, name).restype = _i

@@ -267,6 +267,26 @@ def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = No
     return out
 
 
+def occupancy_threshold(mu: float) -> int:
+    """Integer site-occupancy threshold of rve_sample_lattice for Poisson
+    centres with mean mu per lattice site: round(2^32 (1 - exp(-mu)))."""
+    import math
+    return int(min(max(round(4294967296.0 * -math.expm1(-float(mu))), 0), 0xFFFFFFFF))
+
+
+def sample_lattice(B: int, n: int, side: int, *, seed: int, first: int = 0, occ_threshold: int,
+                   a_in: float, a_bg: float = 1.0, device=None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """B fields (B, n, n) FP64 of the inclusion model sampled on the device
+    for realizations first .. first + B - 1 (see rve_sample_lattice)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ctx = ctx or context(dev.index)
+    a = torch.empty((int(B), int(n), int(n)), dtype=torch.float64, device=dev)
+    N.check(ctx._lib.rve_sample_lattice(ctx.bind_stream(), int(B), int(n), int(side), int(seed) & (2**64 - 1),
+                                        int(first), int(occ_threshold), float(a_in), float(a_bg), _p(a)),
+            "rve_sample_lattice")
+    return a
+
+
 def apply_precond(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
                   ctx: Optional[Context] = None) -> torch.Tensor:
     """(a0 A_Delta)^+ r with a0 from each field a: a (B, n, n), r (B, 2, n, n)."""

@@ -117,6 +117,12 @@ void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t 
 void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out,
                           hipStream_t st);
 
+// On-device sampling of the inclusion model (kernels_sample.hip): B fields
+// [B][n][n] for realizations first .. first + B - 1.
+bool sample_side_valid(int n, int side);
+void launch_sample_lattice(int B, int n, int side, unsigned long long seed, long long first, unsigned occ_threshold,
+                           double a_in, double a_bg, double* a, hipStream_t st);
+
 // Transform GEMMs of the preconditioner (kernels_gemm.hip).
 enum GemmPrec { kGemmF64 = 0, kGemmF32 = 1, kGemmBF16 = 2 };
 struct GemmTables {

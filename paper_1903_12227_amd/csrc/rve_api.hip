@@ -963,6 +963,18 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   return RVE_OK;
 }
 
+int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_t first, uint32_t occ_threshold,
+                       double a_in, double a_bg, double* a_dev) {
+  if (!c || B < 1 || B > 65535 || !n_supported(n) || !sample_side_valid(n, side) || first < 0 || !a_dev)
+    return RVE_EINVAL;
+  if (!(a_in > 0.0) || !(a_bg > 0.0) || !std::isfinite(a_in) || !std::isfinite(a_bg)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_sample_lattice(B, n, side, (unsigned long long)seed, (long long)first, occ_threshold, a_in, a_bg, a_dev,
+                        c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
 int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
   if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 2) return RVE_EINVAL;
   // a well-formed shape code (every shape tiles the largest supported grid)
