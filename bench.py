@@ -416,6 +416,27 @@ def survey(rve, torch, dev):
     dt, st = timed(quartic)
     emit("L=16 n=128, 4096 realizations: A_hom and the quartic tensor", gemm="bf16", ms=1e3 * dt,
          realizations_s=4096 / dt)
+    del a
+
+    # on-device sampling: fields per second, and whole ensembles sampled and
+    # solved on the device (the spread of A_hom should fall like 1/L)
+    import math
+
+    from paper_1903_12227_amd import ensemble
+    for L, B in ((64, 256), (16, 4096)):
+        thr = rve.occupancy_threshold(math.log(2.0) / 64)
+        dt, _ = timed(lambda: rve.sample_lattice(B, 8 * L, 8, seed=1, occ_threshold=thr, a_in=10.0, device=dev),
+                      reps=5)
+        emit(f"on-device sampling, L={L} n={8 * L}", fields=B, ms=1e3 * dt, fields_s=B / dt)
+    for L, Nn in ((8, 16384), (16, 16384), (32, 4096), (64, 1024)):
+        t0 = time.perf_counter()
+        out = ensemble.run_ensemble(L, 8, 10.0, Nn, batch=4096 if L <= 16 else 1024, seed=2, device=dev)
+        dt = time.perf_counter() - t0
+        st = out["stats"]
+        emit(f"ensemble sampled and solved on the device, L={L} n={8 * L}", N=Nn, s=dt, realizations_s=Nn / dt,
+             mean_a11=float(st["mean"][0, 0]), std_a12=float(st["std_a12"]),
+             std_a11_minus_a22=float(st["std_a11_minus_a22"]), L_times_std_a12=L * float(st["std_a12"]),
+             L_times_std_a11_minus_a22=L * float(st["std_a11_minus_a22"]))
 
 
 def cpu_baseline(fields, seconds):

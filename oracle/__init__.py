@@ -21,9 +21,15 @@ ahom   One realization end to end: correctors, the homogenized 2x2 matrix in
 stats  Ensemble statistics: empirical mean (A_hom_Empir), centred variances,
        the uncentred standard deviations Var1/Var2, and the quartic tensor
        (eqn. quartic).
+fd5    The lumped five-point discretisation of Sec. 3.2 (eqns. Lapl_Kron_D,
+       As_Kron) with the finite-difference Laplacian preconditioner (eqn.
+       Lap_Kron): operator, right-hand sides, homogenized matrix, gradient.
+lattice_sample
+       The on-device sampler's law: lattice Poisson square centres decided by
+       Philox4x32-10 words (Salmon et al., SC'11), squares painted into cells.
 
 Pinning status: every function here is pinned by a ``-m "not gpu"`` test
 against closed forms, brute force or invariants (see tests/test_oracle_*.py).
 No function is "parity unpinned".
 """
-from . import q1, pcg, ahom, stats  # noqa: F401
+from . import q1, pcg, ahom, stats, fd5, lattice_sample  # noqa: F401

@@ -27,16 +27,18 @@ def precond_apply(r: np.ndarray, a0: float, E: np.ndarray) -> np.ndarray:
     return np.fft.ifft2(R * inv).real
 
 
-def pcg(A, f: np.ndarray, a0: float, tol: float, maxit: int):
+def pcg(A, f: np.ndarray, a0: float, tol: float, maxit: int, E: np.ndarray = None):
     """Standard PCG (x0 = 0) on A u = f with z = B^+ r.
 
     Stops when ||r||_2 / ||f||_2 <= tol (r is the recursively updated
     residual). An iteration is one product with A. Returns (u, iterations,
     true relative residual ||f - A u|| / ||f||). A zero right-hand side
-    returns u = 0 after 0 iterations.
+    returns u = 0 after 0 iterations. E is the symbol of the constant
+    coefficient operator B / a0 (default: the Q1 one).
     """
     n = f.shape[0]
-    E = q1.symbol(n)
+    if E is None:
+        E = q1.symbol(n)
     fv = f.ravel()
     fnorm = np.linalg.norm(fv)
     x = np.zeros_like(fv)
