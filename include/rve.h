@@ -84,6 +84,20 @@ enum rve_stencil_precision {
   RVE_STENCIL_FP32 = 1
 };
 
+/* Discretisation. RVE_SCHEME_Q1: the consistent Q1 Galerkin operator
+ * (Sec. 3.1 eqn. FEM_discr; nine-point stencil) with the Q1 constant
+ * coefficient preconditioner a0 (K (x) M + M (x) K). RVE_SCHEME_FD5: the
+ * lumped form of Sec. 3.2 (eqns. Lapl_Kron_D, As_Kron: each cell contributes
+ * a_e (k (x) d + d (x) k) with the lumped mass d = diag(1/2, 1/2); a
+ * five-point stencil whose edges carry the mean of their two cells), with the
+ * finite-difference Laplacian a0 (Delta_1 (x) I + I (x) Delta_2) of eqn.
+ * Lap_Kron as preconditioner. Both have the same right-hand sides; A_hom and
+ * its gradient use the scheme's own quadrature (edges for RVE_SCHEME_FD5). */
+enum rve_scheme {
+  RVE_SCHEME_Q1 = 0,
+  RVE_SCHEME_FD5 = 1
+};
+
 /* The PCG iterate is not updated every iteration: the search directions of
  * RVE_DIRECTION_RING consecutive iterations are kept, and x += sum_j
  * alpha_j p_j is applied once per that many iterations and at the end, in
@@ -101,12 +115,13 @@ typedef struct rve_opts {
                         iterations, rounded up to a multiple of
                         RVE_DIRECTION_RING; <= 0: every RVE_DIRECTION_RING */
   int stencil_prec;  /* enum rve_stencil_precision */
+  int scheme;        /* enum rve_scheme (RVE_SCHEME_FD5 needs RVE_STENCIL_FP64) */
 } rve_opts;
 
 typedef struct rve_ctx rve_ctx;
 
 /* Fill *opts with defaults: tol 1e-10, maxit 2000, FP64, automatic beta,
- * automatic polling, FP64 operator apply. */
+ * automatic polling, FP64 operator apply, Q1 scheme. */
 void rve_default_opts(rve_opts* opts);
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -175,10 +190,11 @@ int rve_solve_uneven(rve_ctx* ctx, int B, const int* n_host,
  *   a_in         coefficient value of the inclusion cells
  *   grad_in_dev  [B] output: sum_ij G_ij d A_ij / d a_in, where every cell
  *                with a_e == a_in moves with a_in; or NULL
+ *   scheme       enum rve_scheme the correctors were computed with
  */
 int rve_grad(rve_ctx* ctx, int B, int n, const double* a_dev,
              const double* phi_dev, double h, const double* G_dev,
-             double* grad_a_dev, double a_in, double* grad_in_dev);
+             double* grad_a_dev, double a_in, double* grad_in_dev, int scheme);
 
 /*
  * Ensemble statistics of N homogenized matrices at RVE size L (Sec. 4.2
@@ -195,20 +211,21 @@ int rve_stats(rve_ctx* ctx, int N, double L, const double* ahom_dev, double* out
 /*
  * The two linear maps of the PCG, one call each, for checking them alone.
  *
- * rve_apply_operator: out = A u for the Q1 stiffness of each field (grid
- * units; Sec. 3.1 eqn. FEM_discr, assembled there by the Kronecker sums of
- * Sec. 3.2, applied here matrix-free as a 9-point stencil).
+ * rve_apply_operator: out = A u for the stiffness of each field in scheme
+ * `scheme` (grid units; Q1: Sec. 3.1 eqn. FEM_discr, assembled there by the
+ * Kronecker sums of Sec. 3.2, applied here matrix-free as a 9-point stencil;
+ * FD5: the lumped five-point form).
  *   a_dev [B][n][n] cells; u_dev, out_dev [B][2][n][n] nodes (distinct).
  *
  * rve_apply_precond: z = (a0 A_Delta)^+ r (Sec. 3.5) with a0 = (max a +
- * min a)/2 of each field and the transform GEMMs in precision `prec`
- * (enum rve_precision).
+ * min a)/2 of each field, A_Delta the scheme's constant-coefficient operator
+ * and the transform GEMMs in precision `prec` (enum rve_precision).
  *   a_dev [B][n][n]; r_dev, z_dev [B][2][n][n] (distinct).
  */
 int rve_apply_operator(rve_ctx* ctx, int B, int n, const double* a_dev, const double* u_dev,
-                       double* out_dev);
+                       double* out_dev, int scheme);
 int rve_apply_precond(rve_ctx* ctx, int B, int n, const double* a_dev, const double* r_dev,
-                      double* z_dev, int prec);
+                      double* z_dev, int prec, int scheme);
 
 /* Static string for a status code. */
 const char* rve_status_string(int status);
@@ -228,8 +245,8 @@ const char* rve_status_string(int status);
  *
  * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
  * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128,
- * 2 = folded 128 x 128) or 2 (FP32 operator-apply shape, encoded as kind 0)
- * of a shape,
+ * 2 = folded 128 x 128), 2 (FP32 operator-apply shape) or 3 (five-point
+ * operator-apply shape), the last two encoded as kind 0, of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
  * that are not valid for a shape are ignored and tuned again.
  */

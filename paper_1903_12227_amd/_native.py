@@ -16,6 +16,8 @@ OK, NOT_CONVERGED, BREAKDOWN, EINVAL, EHIP, ENOMEM = 0, 1, 2, -1, -2, -3
 # enum rve_precision
 FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
 STENCIL_FP64, STENCIL_FP32 = 0, 1
+# enum rve_scheme
+SCHEME_Q1, SCHEME_FD5 = 0, 1
 
 EXPORTS = (
     "rve_default_opts", "rve_create", "rve_destroy", "rve_set_stream",
@@ -28,7 +30,8 @@ EXPORTS = (
 
 class RveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("prec", ctypes.c_int),
-                ("flexible", ctypes.c_int), ("check_every", ctypes.c_int), ("stencil_prec", ctypes.c_int)]
+                ("flexible", ctypes.c_int), ("check_every", ctypes.c_int), ("stencil_prec", ctypes.c_int),
+                ("scheme", ctypes.c_int)]
 
 
 _lib = None
@@ -48,14 +51,14 @@ def _declare(lib):
                                     _vp, _vp, _vp, _vp, _vp, _vp]
     lib.rve_solve_uneven.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_int64),
                                      _d, _vp, ctypes.POINTER(RveOpts), _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _d, _vp]
+    lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _d, _vp, _i]
     lib.rve_stats.argtypes = [_vp, _i, _d, _vp, _vp]
     lib.rve_status_string.argtypes = [_i]
     lib.rve_status_string.restype = ctypes.c_char_p
     lib.rve_set_timing.argtypes = [_vp, _i]
     lib.rve_last_timing.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong)]
-    lib.rve_apply_operator.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
-    lib.rve_apply_precond.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
+    lib.rve_apply_operator.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
+    lib.rve_apply_precond.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i, _i]
     lib.rve_set_autotune.argtypes = [_vp, _i]
     lib.rve_get_tuned.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(_i)]
     lib.rve_set_graphs.argtypes = [_vp, _i]

@@ -25,10 +25,11 @@ class Options:
     flexible: int = -1          # -1 automatic, 0 standard beta, 1 flexible beta
     check_every: int = 0        # convergence poll period (0 = library default)
     stencil_prec: int = 0       # 0 FP64 operator apply, 1 FP32 (with FP64 residual replacement)
+    scheme: int = 0             # 0 consistent Q1 (nine-point), 1 lumped five-point
 
     def to_c(self) -> N.RveOpts:
         return N.RveOpts(float(self.tol), int(self.maxit), int(self.prec), int(self.flexible),
-                         int(self.check_every), int(self.stencil_prec))
+                         int(self.check_every), int(self.stencil_prec), int(self.scheme))
 
 
 @dataclass
@@ -224,7 +225,7 @@ def solve_uneven(fields: Sequence[torch.Tensor], h: float = 1.0, opts: Optional[
 
 
 def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
-         a_in: Optional[float] = None, ctx: Optional[Context] = None):
+         a_in: Optional[float] = None, ctx: Optional[Context] = None, scheme: int = 0):
     """sum_ij G_ij dA_ij/da per cell, (B, n, n); and, if a_in is given, the
     derivative with respect to the common value of the cells equal to a_in."""
     _need(a, "a")
@@ -237,7 +238,7 @@ def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
     out = torch.empty_like(a)
     gin = torch.empty((B,), dtype=torch.float64, device=a.device) if a_in is not None else None
     N.check(ctx._lib.rve_grad(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out),
-                              float(a_in if a_in is not None else 0.0), _p(gin)), "rve_grad")
+                              float(a_in if a_in is not None else 0.0), _p(gin), int(scheme)), "rve_grad")
     return out, gin
 
 
@@ -253,7 +254,8 @@ def stats(ahom: torch.Tensor, L: float, ctx: Optional[Context] = None) -> dict:
             "std_a11_minus_a22": out[9], "quartic": out[10:26].view(4, 4)}
 
 
-def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = None,
+                   scheme: int = 0) -> torch.Tensor:
     """A u for the Q1 operator of each field: a (B, n, n), u (B, 2, n, n)."""
     _need(a, "a")
     _need(u, "u")
@@ -262,7 +264,7 @@ def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = No
         raise ValueError("u must be (B, 2, n, n)")
     ctx = ctx or context(a.device.index)
     out = torch.empty_like(u)
-    N.check(ctx._lib.rve_apply_operator(ctx.bind_stream(), B, n, _p(a), _p(u), _p(out)),
+    N.check(ctx._lib.rve_apply_operator(ctx.bind_stream(), B, n, _p(a), _p(u), _p(out), int(scheme)),
             "rve_apply_operator")
     return out
 
@@ -288,7 +290,7 @@ def sample_lattice(B: int, n: int, side: int, *, seed: int, first: int = 0, occ_
 
 
 def apply_precond(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
-                  ctx: Optional[Context] = None) -> torch.Tensor:
+                  ctx: Optional[Context] = None, scheme: int = 0) -> torch.Tensor:
     """(a0 A_Delta)^+ r with a0 from each field a: a (B, n, n), r (B, 2, n, n)."""
     _need(a, "a")
     _need(r, "r")
@@ -297,6 +299,6 @@ def apply_precond(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
         raise ValueError("r must be (B, 2, n, n)")
     ctx = ctx or context(a.device.index)
     z = torch.empty_like(r)
-    N.check(ctx._lib.rve_apply_precond(ctx.bind_stream(), B, n, _p(a), _p(r), _p(z), int(prec)),
+    N.check(ctx._lib.rve_apply_precond(ctx.bind_stream(), B, n, _p(a), _p(r), _p(z), int(prec), int(scheme)),
             "rve_apply_precond")
     return z

@@ -23,12 +23,13 @@ class RveAhom(torch.autograd.Function):
         res = api.solve_batch(a.detach().contiguous(), h, opts, want_phi=True, want_flux=False)
         ctx.save_for_backward(a, res.phi)
         ctx.h = h
+        ctx.scheme = opts.scheme if opts is not None else 0
         return res.ahom
 
     @staticmethod
     def backward(ctx, G: torch.Tensor):
         a, phi = ctx.saved_tensors
-        g, _ = api.grad(a.detach().contiguous(), phi, ctx.h, G.contiguous())
+        g, _ = api.grad(a.detach().contiguous(), phi, ctx.h, G.contiguous(), scheme=ctx.scheme)
         return g, None, None
 
 
@@ -42,6 +43,7 @@ class RveAhomContrast(torch.autograd.Function):
         res = api.solve_batch(a.detach().contiguous(), h, opts, want_phi=True, want_flux=False)
         ctx.save_for_backward(a, res.phi, contrast)
         ctx.h = h
+        ctx.scheme = opts.scheme if opts is not None else 0
         return res.ahom
 
     @staticmethod
@@ -50,7 +52,8 @@ class RveAhomContrast(torch.autograd.Function):
         vals = contrast.detach().reshape(-1).cpu()
         if vals.numel() != 1 and not bool(torch.all(vals == vals[0])):
             raise ValueError("RveAhomContrast needs one contrast value for the batch")
-        _, gin = api.grad(a.detach().contiguous(), phi, ctx.h, G.contiguous(), a_in=float(vals[0]))
+        _, gin = api.grad(a.detach().contiguous(), phi, ctx.h, G.contiguous(), a_in=float(vals[0]),
+                          scheme=ctx.scheme)
         if contrast.dim() == 0:
             return gin.sum().reshape(()), None, None, None
         return gin.reshape(contrast.shape), None, None, None

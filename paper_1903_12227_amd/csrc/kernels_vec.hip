@@ -237,6 +237,18 @@ __device__ inline T q1_apply(T a00, T a01, T a10, T a11, const T (&um)[3], const
   return v;
 }
 
+// Lumped five-point operator (Sec. 3.2, eqns. Lapl_Kron_D and As_Kron with
+// cell blocks): each edge carries the mean of the two cells beside it, so at
+// node (p, q), with the same cells and rows as q1_apply,
+//   (A u) = [(a10+a11)(u - u(p+1,q)) + (a00+a01)(u - u(p-1,q))
+//            + (a01+a11)(u - u(p,q+1)) + (a00+a10)(u - u(p,q-1))] / 2.
+template <class T>
+__device__ inline T fd5_apply(T a00, T a01, T a10, T a11, const T (&um)[3], const T (&uc)[3], const T (&up)[3]) {
+  const T c = uc[1];
+  return (T)0.5 * ((a10 + a11) * (c - up[1]) + (a00 + a01) * (c - um[1]) + (a01 + a11) * (c - uc[2]) +
+                   (a00 + a10) * (c - uc[0]));
+}
+
 // V consecutive elements of a row, converted to / from the register type S.
 template <class T, int V> struct VecIO;
 template <int V> struct VecIO<double, V> {
@@ -323,10 +335,12 @@ __device__ inline void raw_load(const T* p, T* v) {
 // probe = 1 (autotuner timing at k = 0 only) reads p_{k-1} as a later
 // iteration would; its outputs are rewritten by the real iteration 0.
 // Not FUSED: the operand is p_in.
+// SCH selects the operator: 0 the consistent Q1 nine-point stencil, 1 the
+// lumped five-point one.
 // CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
 // FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
 // FP64 either way (the product of two FP32 values is exact in FP64).
-template <bool FUSED, class PT, class ZT, int V, int D, class CT>
+template <bool FUSED, class PT, class ZT, int V, int D, class CT, int SCH>
 __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, const PT* p_in, PT* ring,
                                                        long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
@@ -451,7 +465,10 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
         const CT sm[3] = {um[i][k], um[i][k + 1], um[i][k + 2]};
         const CT sc[3] = {uc[i][k], uc[i][k + 1], uc[i][k + 2]};
         const CT sp[3] = {up[i][k], up[i][k + 1], up[i][k + 2]};
-        qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
+        if constexpr (SCH == 1)
+          qv[k] = fd5_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
+        else
+          qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
       }
       if (act[i]) {
         VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
@@ -685,22 +702,30 @@ struct CellGrad {
   __device__ double D1() const { return 0.5 * (b1 + t1); }
   __device__ double D2() const { return 0.5 * (b2 + t2); }
 };
+// Lumped five-point scheme: the cell's share of the edge quadrature is half
+// of each of its four edges, so int d1u d1v -> (b1u b1v + t1u t1v)/2 and
+// likewise along x2; the averages D1, D2 are unchanged.
+template <int SCH>
 __device__ inline double grad_dot(const CellGrad& u, const CellGrad& v) {
+  if constexpr (SCH == 1)
+    return 0.5 * ((u.b1 * v.b1 + u.t1 * v.t1) + (u.b2 * v.b2 + u.t2 * v.t2));
   return kThird * ((u.b1 * v.b1 + u.t1 * v.t1) + (u.b2 * v.b2 + u.t2 * v.t2)) +
          kSixth * ((u.b1 * v.t1 + u.t1 * v.b1) + (u.b2 * v.t2 + u.t2 * v.b2));
 }
-// E_ij(e) = int_e (e_i + grad phi_i).(e_j + grad phi_j).
+// E_ij(e) = int_e (e_i + grad phi_i).(e_j + grad phi_j) in the scheme's quadrature.
+template <int SCH>
 struct CellEnergy {
   double e11, e12, e22;
   __device__ CellEnergy(const CellGrad& u, const CellGrad& v) {
-    e11 = 1.0 + 2.0 * u.D1() + grad_dot(u, u);
-    e12 = u.D2() + v.D1() + grad_dot(u, v);
-    e22 = 1.0 + 2.0 * v.D2() + grad_dot(v, v);
+    e11 = 1.0 + 2.0 * u.D1() + grad_dot<SCH>(u, u);
+    e12 = u.D2() + v.D1() + grad_dot<SCH>(u, v);
+    e22 = 1.0 + 2.0 * v.D2() + grad_dot<SCH>(v, v);
   }
 };
 
 // Per-tile partials of sum_e a_e E_ij(e) (energy form), of the flux-form
 // integrands a(delta_ij + d_j phi_i), and of sum phi_i.
+template <int SCH>
 __global__ void __launch_bounds__(kBlock) k_ahom(const double* __restrict__ a, const double* __restrict__ x,
                                                   int n, double* __restrict__ part) {
   __shared__ double sh[4 * 9];
@@ -721,7 +746,7 @@ __global__ void __launch_bounds__(kBlock) k_ahom(const double* __restrict__ a, c
     const double u10 = X0[on + col], u11 = X0[on + cp], v10 = X1[on + col], v11 = X1[on + cp];
     const double ae = A[(long long)row * n + col];
     const CellGrad gu(u00, u01, u10, u11), gv(v00, v01, v10, v11);
-    const CellEnergy E(gu, gv);
+    const CellEnergy<SCH> E(gu, gv);
     acc[0] += ae * E.e11;
     acc[1] += ae * E.e12;
     acc[2] += ae * E.e22;
@@ -810,6 +835,7 @@ __global__ void k_finalize(const SysState* sys, int B, int* iters, double* relre
 
 // grad[e] = sum_ij G_ij dA_ij/da_e = (G11 E11 + (G12 + G21) E12 + G22 E22)/n^2,
 // plus per-tile partial sums over the cells with a_e == a_in.
+template <int SCH>
 __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ a, const double* __restrict__ phi,
                                                   double inv_h, const double* __restrict__ G,
                                                   double* __restrict__ grad, double a_in, int n,
@@ -835,7 +861,7 @@ __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ a, c
     const long long on = (long long)wrap_inc(row, n) * n;
     const double u10 = X0[on + col] * inv_h, u11 = X0[on + cp] * inv_h;
     const double v10 = X1[on + col] * inv_h, v11 = X1[on + cp] * inv_h;
-    const CellEnergy E(CellGrad(u00, u01, u10, u11), CellGrad(v00, v01, v10, v11));
+    const CellEnergy<SCH> E(CellGrad(u00, u01, u10, u11), CellGrad(v00, v01, v10, v11));
     const double g = g11 * E.e11 + g12 * E.e12 + g22 * E.e22;
     const long long oc = (long long)row * n + col;
     Gr[oc] = g;
@@ -966,45 +992,48 @@ bool stencil_choice_valid(int n, int c) {
   return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
-template <bool FUSED, class PT, class ZT, int D, class CT>
+template <bool FUSED, class PT, class ZT, int D, class CT, int SCH>
 void launch_stencil_d(int B, int n, int V, int H, const CT* a, const PT* pin, PT* ring, long long slot_stride,
                       int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
                       int probe, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part, probe);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part, probe);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT>), g, blk, 0, st, a, pin, ring, slot_stride, m, kiter,
-                       z, q, n, H, sys, part, probe);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe);
 }
 
-template <bool FUSED, class PT, class ZT, class CT>
+template <bool FUSED, class PT, class ZT, class CT, int SCH>
 void launch_stencil_t(int B, int n, int c, const CT* a, const PT* pin, PT* ring, long long slot_stride, int m,
                       const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
                       hipStream_t st) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, probe,
-                                           st);
+    launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
+                                                probe, st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1, CT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part, probe,
-                                           st);
+    launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
+                                                probe, st);
 }
 
 template <class PT>
 void launch_stencil_fused_p(const Work& w, int probe, hipStream_t st) {
   const long long slot = (long long)w.S * w.N2;
-  if (w.sprec)
-    launch_stencil_t<true, PT, PT, float>(w.B, w.n, w.stencil, w.a32, (const PT*)nullptr, (PT*)w.pring, slot,
-                                          w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq, probe,
-                                          st);
+  if (w.sprec)   // FP32 apply: the Q1 operator only
+    launch_stencil_t<true, PT, PT, float, 0>(w.B, w.n, w.stencil, w.a32, (const PT*)nullptr, (PT*)w.pring, slot,
+                                             w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq,
+                                             probe, st);
+  else if (w.scheme == 1)
+    launch_stencil_t<true, PT, PT, double, 1>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
+                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
   else
-    launch_stencil_t<true, PT, PT, double>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                           w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
+    launch_stencil_t<true, PT, PT, double, 0>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
+                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
 }
 
 void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
@@ -1066,7 +1095,7 @@ __global__ void __launch_bounds__(kBlock) k_replace_r(double* __restrict__ r, co
 
 void launch_replace_r(const Work& w, hipStream_t st) {
   // A x (FP64) into q, then r = f - A x
-  launch_apply_stencil(w.B, w.n, w.a, w.x, w.q, st);
+  launch_apply_stencil(w.B, w.n, 0, w.a, w.x, w.q, st);
   const dim3 g(w.P_vec, w.S), blk(kBlock);
   if (w.mixed == 0)
     hipLaunchKernelGGL((k_replace_r<double, false>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
@@ -1106,10 +1135,15 @@ void launch_fold_x(const Work& w, int final, hipStream_t st) {
                        w.alpha_hist, w.sys, w.N2, (const int*)w.kiter, final);
 }
 
-void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out, hipStream_t st) {
-  launch_stencil_t<false, double, double, double>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0, 1,
-                                                  (const int*)nullptr, (const double*)nullptr, out,
-                                                  (const SysState*)nullptr, (double*)nullptr, 0, st);
+void launch_apply_stencil(int B, int n, int scheme, const double* a, const double* u, double* out, hipStream_t st) {
+  if (scheme == 1)
+    launch_stencil_t<false, double, double, double, 1>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0,
+                                                       1, (const int*)nullptr, (const double*)nullptr, out,
+                                                       (const SysState*)nullptr, (double*)nullptr, 0, st);
+  else
+    launch_stencil_t<false, double, double, double, 0>(B, n, stencil_choice_default(n), a, u, (double*)nullptr, 0,
+                                                       1, (const int*)nullptr, (const double*)nullptr, out,
+                                                       (const SysState*)nullptr, (double*)nullptr, 0, st);
 }
 
 void launch_scalar_alpha(const Work& w, hipStream_t st) {
@@ -1148,7 +1182,10 @@ void launch_widen(const float* in, double* out, long long total, hipStream_t st)
 
 void launch_ahom(const Work& w, hipStream_t st) {
   dim3 g(w.n / kTile, w.n / kTile, w.B);
-  hipLaunchKernelGGL(k_ahom, g, dim3(kBlock), 0, st, w.a, w.x, w.n, w.part_misc);
+  if (w.scheme == 1)
+    hipLaunchKernelGGL(k_ahom<1>, g, dim3(kBlock), 0, st, w.a, w.x, w.n, w.part_misc);
+  else
+    hipLaunchKernelGGL(k_ahom<0>, g, dim3(kBlock), 0, st, w.a, w.x, w.n, w.part_misc);
 }
 
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st) {
@@ -1165,10 +1202,13 @@ void launch_finalize(const Work& w, int* iters, double* relres, int* status, hip
                      relres, status);
 }
 
-void launch_grad(int B, int n, const double* a, const double* phi, double inv_h, const double* G,
+void launch_grad(int B, int n, int scheme, const double* a, const double* phi, double inv_h, const double* G,
                  double* grad, double a_in, double* part, int want_in, hipStream_t st) {
   dim3 g(n / kTile, n / kTile, B);
-  hipLaunchKernelGGL(k_grad, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
+  if (scheme == 1)
+    hipLaunchKernelGGL(k_grad<1>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
+  else
+    hipLaunchKernelGGL(k_grad<0>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
 }
 
 void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st) {

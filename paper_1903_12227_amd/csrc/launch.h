@@ -37,6 +37,7 @@ struct Work {
   // FP32 operator apply: a32 holds the coefficients in FP32, q is FP32, and
   // f (the mean-free right-hand sides) serves the periodic r = f - A x
   int sprec = 0;
+  int scheme = 0;            // 0: consistent Q1 nine-point operator; 1: lumped five-point
   const float* a32 = nullptr;
   double* f = nullptr;
   int stencil = 0;           // operator-apply shape (stencil_choice_*)
@@ -109,12 +110,12 @@ void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
 void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st);
 void launch_finalize(const Work& w, int* iters, double* relres, int* status, hipStream_t st);
-void launch_grad(int B, int n, const double* a, const double* phi, double inv_h,
+void launch_grad(int B, int n, int scheme, const double* a, const double* phi, double inv_h,
                  const double* G, double* grad, double a_in, double* part, int want_in,
                  hipStream_t st);
 void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st);
 void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t st);
-void launch_apply_stencil(int B, int n, const double* a, const double* u, double* out,
+void launch_apply_stencil(int B, int n, int scheme, const double* a, const double* u, double* out,
                           hipStream_t st);
 
 // On-device sampling of the inclusion model (kernels_sample.hip): B fields

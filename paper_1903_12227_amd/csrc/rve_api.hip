@@ -39,6 +39,8 @@ struct Tables {
   __bf16* q16 = nullptr;
   double* einv64 = nullptr;
   float* einv32 = nullptr;
+  double* einv64_fd = nullptr;   // 1/E of the finite-difference Laplacian (five-point scheme)
+  float* einv32_fd = nullptr;
   __bf16* ch16 = nullptr;   // [n/2][n/2] cos(2 pi k t / n)/sqrt(n), row k (n % 256 == 0 only)
   __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t / n)/sqrt(n)
 };
@@ -120,8 +122,8 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
     return RVE_OK;
   }
   const size_t N2 = (size_t)n * n;
-  std::vector<double> q(N2), einv(N2);
-  std::vector<float> q32(N2), einv32(N2);
+  std::vector<double> q(N2), einv(N2), einvf(N2);
+  std::vector<float> q32(N2), einv32(N2), einvf32(N2);
   std::vector<__bf16> q16(N2);
   const double two_pi = 6.283185307179586476925286766559;
   const double inv_sqrt = 1.0 / std::sqrt((double)n);
@@ -144,6 +146,11 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
       const double inv = (k == 0 && l == 0) ? 0.0 : 1.0 / E;
       einv[(size_t)k * n + l] = inv;
       einv32[(size_t)k * n + l] = (float)inv;
+      // five-point: (2 - 2 c_k) + (2 - 2 c_l)
+      const double Ef = 4.0 - 2.0 * c[k] - 2.0 * c[l];
+      const double invf = (k == 0 && l == 0) ? 0.0 : 1.0 / Ef;
+      einvf[(size_t)k * n + l] = invf;
+      einvf32[(size_t)k * n + l] = (float)invf;
     }
   // half-size cosine and sine parts of Q for the even/odd-folded transform
   const int h = n / 2;
@@ -159,9 +166,11 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   if (hipMalloc(&t.q64, N2 * 8) != hipSuccess || hipMalloc(&t.q32, N2 * 4) != hipSuccess ||
       hipMalloc(&t.q16, N2 * 2) != hipSuccess || hipMalloc(&t.einv64, N2 * 8) != hipSuccess ||
       hipMalloc(&t.einv32, N2 * 4) != hipSuccess || hipMalloc(&t.ch16, H2 * 2) != hipSuccess ||
-      hipMalloc(&t.sh16, H2 * 2) != hipSuccess) {
+      hipMalloc(&t.sh16, H2 * 2) != hipSuccess || hipMalloc(&t.einv64_fd, N2 * 8) != hipSuccess ||
+      hipMalloc(&t.einv32_fd, N2 * 4) != hipSuccess) {
     ignore(hipFree(t.q64)); ignore(hipFree(t.q32)); ignore(hipFree(t.q16));
     ignore(hipFree(t.einv64)); ignore(hipFree(t.einv32)); ignore(hipFree(t.ch16)); ignore(hipFree(t.sh16));
+    ignore(hipFree(t.einv64_fd)); ignore(hipFree(t.einv32_fd));
     return RVE_ENOMEM;
   }
   HIP_TRY(hipMemcpy(t.q64, q.data(), N2 * 8, hipMemcpyHostToDevice));
@@ -170,6 +179,8 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   HIP_TRY(hipMemcpy(t.einv64, einv.data(), N2 * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(t.einv32, einv32.data(), N2 * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(t.ch16, ch.data(), H2 * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einv64_fd, einvf.data(), N2 * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einv32_fd, einvf32.data(), N2 * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(t.sh16, sh.data(), H2 * 2, hipMemcpyHostToDevice));
   ctx->tables[n] = t;
   *out = &ctx->tables[n];
@@ -184,7 +195,7 @@ struct Layout {
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_status, total;
 };
 
-Layout plan(int B, int n, int prec, int sprec, Work* w) {
+Layout plan(int B, int n, int prec, int sprec, int scheme, Work* w) {
   Layout L{};
   const long long S = 2LL * B, N2 = (long long)n * n;
   const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
@@ -236,6 +247,7 @@ Layout plan(int B, int n, int prec, int sprec, Work* w) {
   w->stencil = sc;
   w->m_ring = kRing;
   w->sprec = sprec;
+  w->scheme = scheme;
   w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
   return L;
 }
@@ -292,6 +304,8 @@ int check_opts(const rve_opts* o) {
   if (o->maxit < 1 || o->maxit > 1000000) return RVE_EINVAL;
   if (o->prec < RVE_FP64 || o->prec > RVE_MIX_BF16) return RVE_EINVAL;
   if (o->stencil_prec != RVE_STENCIL_FP64 && o->stencil_prec != RVE_STENCIL_FP32) return RVE_EINVAL;
+  if (o->scheme != RVE_SCHEME_Q1 && o->scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
+  if (o->scheme == RVE_SCHEME_FD5 && o->stencil_prec != RVE_STENCIL_FP64) return RVE_EINVAL;
   return RVE_OK;
 }
 
@@ -483,7 +497,7 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
   std::vector<long long> key;
   long long tolbits = 0;
   std::memcpy(&tolbits, &o->tol, sizeof tolbits);
-  key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec,
+  key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec, o->scheme,
                          (long long)bs.size()});
   for (auto& b : bs)
     key.insert(key.end(), {b.B, b.n, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
@@ -526,7 +540,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
   const int count_len = o->maxit + kRing;
   size_t total = ctl_bytes(count_len);
   for (auto& b : bs) {
-    b.L = plan(b.B, b.n, o->prec, o->stencil_prec, &b.w);
+    b.L = plan(b.B, b.n, o->prec, o->stencil_prec, o->scheme, &b.w);
     b.base = total;
     total += b.L.total;
   }
@@ -555,8 +569,8 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     if (rc) return rc;
     b.gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
                                                                                   : (const void*)tb->q16;
-    b.gt.einv64 = tb->einv64;
-    b.gt.einv32 = tb->einv32;
+    b.gt.einv64 = o->scheme == RVE_SCHEME_FD5 ? tb->einv64_fd : tb->einv64;
+    b.gt.einv32 = o->scheme == RVE_SCHEME_FD5 ? tb->einv32_fd : tb->einv32;
     b.gt.ch16 = tb->ch16;
     b.gt.sh16 = tb->sh16;
     b.prec = prec;
@@ -581,8 +595,8 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     Work& w = b.w;
     const int n = b.n;
     const int bb = batch_bucket(b.B);
-    // kind 0: FP64 operator-apply shape, kind 2: FP32 operator-apply shape
-    const TuneKey kst(w.sprec ? 2 : 0, n, o->prec, bb), kgm(1, n, o->prec, bb);
+    // kind 0: FP64 operator-apply shape, 2: FP32 apply, 3: five-point apply
+    const TuneKey kst(w.sprec ? 2 : w.scheme ? 3 : 0, n, o->prec, bb), kgm(1, n, o->prec, bb);
     const bool tune_now = ctx->autotune && (!ctx->tune.count(kst) || !ctx->tune.count(kgm)) &&
                           (ctx->force_stencil < 0 || ctx->force_gemm < 0) && count_active(ctx, w) > 0;
     if (ctx->autotune) {
@@ -706,6 +720,7 @@ void rve_default_opts(rve_opts* o) {
   o->flexible = -1;
   o->check_every = 0;
   o->stencil_prec = RVE_STENCIL_FP64;
+  o->scheme = RVE_SCHEME_Q1;
 }
 
 const char* rve_status_string(int s) {
@@ -760,6 +775,8 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.einv64));
     ignore(hipFree(kv.second.einv32));
     ignore(hipFree(kv.second.ch16));
+    ignore(hipFree(kv.second.einv64_fd));
+    ignore(hipFree(kv.second.einv32_fd));
     ignore(hipFree(kv.second.sh16));
   }
   clear_graphs(c);
@@ -891,15 +908,17 @@ int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, d
 }
 
 int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
-             const double* G_dev, double* grad_a_dev, double a_in, double* grad_in_dev) {
+             const double* G_dev, double* grad_a_dev, double a_in, double* grad_in_dev, int scheme) {
   if (!c || B < 1 || !n_supported(n) || !(h > 0.0) || !a_dev || !phi_dev || !G_dev || !grad_a_dev)
     return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   const int P = (n / kTile) * (n / kTile);
   const int rc = ensure_ws(c, align_up((size_t)B * P * 8));
   if (rc) return rc;
   double* part = static_cast<double*>(c->ws);
-  launch_grad(B, n, a_dev, phi_dev, 1.0 / h, G_dev, grad_a_dev, a_in, part, grad_in_dev != nullptr, c->stream);
+  launch_grad(B, n, scheme, a_dev, phi_dev, 1.0 / h, G_dev, grad_a_dev, a_in, part, grad_in_dev != nullptr,
+              c->stream);
   if (grad_in_dev) launch_scalar_grad(B, n, part, grad_in_dev, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
@@ -913,21 +932,24 @@ int rve_stats(rve_ctx* c, int N, double L, const double* ahom_dev, double* out_d
   return RVE_OK;
 }
 
-int rve_apply_operator(rve_ctx* c, int B, int n, const double* a_dev, const double* u_dev, double* out_dev) {
+int rve_apply_operator(rve_ctx* c, int B, int n, const double* a_dev, const double* u_dev, double* out_dev,
+                       int scheme) {
   if (!c || B < 1 || !n_supported(n) || !a_dev || !u_dev || !out_dev || u_dev == out_dev) return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
-  launch_apply_stencil(B, n, a_dev, u_dev, out_dev, c->stream);
+  launch_apply_stencil(B, n, scheme, a_dev, u_dev, out_dev, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
 }
 
 int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const double* r_dev, double* z_dev,
-                      int prec) {
+                      int prec, int scheme) {
   if (!c || B < 1 || !n_supported(n) || !a_dev || !r_dev || !z_dev || r_dev == z_dev) return RVE_EINVAL;
   if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
-  const Layout L = plan(B, n, prec, 0, &w);
+  const Layout L = plan(B, n, prec, 0, scheme, &w);
   int rc = ensure_ws(c, L.total);
   if (rc) return rc;
   bind(static_cast<char*>(c->ws), L, &w);
@@ -942,8 +964,8 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   GemmTables gt;
   gt.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
                                                                          : (const void*)tb->q16;
-  gt.einv64 = tb->einv64;
-  gt.einv32 = tb->einv32;
+  gt.einv64 = scheme == RVE_SCHEME_FD5 ? tb->einv64_fd : tb->einv64;
+  gt.einv32 = scheme == RVE_SCHEME_FD5 ? tb->einv32_fd : tb->einv32;
   gt.ch16 = tb->ch16;
   gt.sh16 = tb->sh16;
   w.r = const_cast<double*>(r_dev);
@@ -997,7 +1019,7 @@ int rve_set_autotune(rve_ctx* c, int mode) {
 }
 
 int rve_get_tuned(rve_ctx* c, int kind, int n, int prec, int B, int* choice) {
-  if (!c || !choice || kind < 0 || kind > 2 || B < 1) return RVE_EINVAL;
+  if (!c || !choice || kind < 0 || kind > 3 || B < 1) return RVE_EINVAL;
   auto it = c->tune.find(TuneKey(kind, n, prec, batch_bucket(B)));
   if (it == c->tune.end()) {
     *choice = -1;

@@ -40,7 +40,7 @@ def test_status_strings_and_defaults(lib):
     o = N.RveOpts()
     lib.rve_default_opts(ctypes.byref(o))
     assert o.tol == 1e-10 and o.maxit == 2000 and o.prec == N.FP64 and o.flexible == -1
-    assert o.stencil_prec == N.STENCIL_FP64
+    assert o.stencil_prec == N.STENCIL_FP64 and o.scheme == N.SCHEME_Q1
 
 
 def test_host_argument_validation(lib):
@@ -66,6 +66,10 @@ def test_host_argument_validation(lib):
     assert lib.rve_force_variants(fake, -1, 3) == N.EINVAL
     assert lib.rve_force_variants(fake, 5, -1) == N.EINVAL
     assert lib.rve_force_variants(None, -1, -1) == N.EINVAL
+    for bad in (N.RveOpts(1e-10, 10, 0, -1, 0, 0, 2), N.RveOpts(1e-10, 10, 0, -1, 0, 1, 1)):
+        # unknown scheme; five-point with the FP32 apply
+        assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                                   None, None) == N.EINVAL
     bad = N.RveOpts(1e-10, 10, 0, -1, 0, 2)
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
@@ -81,9 +85,14 @@ def test_host_argument_validation(lib):
     assert lib.rve_solve_uneven(fake, 2, ns, offs, 0.125, fake, ctypes.byref(o), None, fake, None, None,
                                 None, None) == N.EINVAL
     assert lib.rve_stats(fake, 1, 16.0, fake, fake) == N.EINVAL
-    assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, 10.0, None) == N.EINVAL
-    assert lib.rve_apply_operator(fake, 1, 64, fake, fake, fake) == N.EINVAL   # u aliases out
-    assert lib.rve_apply_precond(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL
+    assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, 10.0, None, 0) == N.EINVAL
+    assert lib.rve_apply_operator(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL   # u aliases out
+    assert lib.rve_apply_precond(fake, 1, 64, fake, fake, fake, 0, 0) == N.EINVAL
+    # unknown scheme
+    other = ctypes.c_void_p(2)
+    assert lib.rve_grad(fake, 1, 64, fake, fake, 0.125, fake, other, 10.0, None, 2) == N.EINVAL
+    assert lib.rve_apply_operator(fake, 1, 64, fake, fake, other, 2) == N.EINVAL
+    assert lib.rve_apply_precond(fake, 1, 64, fake, fake, other, 0, 2) == N.EINVAL
 
 
 def test_header_constants_match_binding():
@@ -94,6 +103,7 @@ def test_header_constants_match_binding():
     for name, val in (("RVE_OK", N.OK), ("RVE_NOT_CONVERGED", N.NOT_CONVERGED), ("RVE_BREAKDOWN", N.BREAKDOWN),
                       ("RVE_EINVAL", N.EINVAL), ("RVE_EHIP", N.EHIP), ("RVE_ENOMEM", N.ENOMEM),
                       ("RVE_FP64", N.FP64), ("RVE_MIX_FP32", N.MIX_FP32), ("RVE_MIX_BF16", N.MIX_BF16),
-                      ("RVE_STENCIL_FP64", N.STENCIL_FP64), ("RVE_STENCIL_FP32", N.STENCIL_FP32)):
+                      ("RVE_STENCIL_FP64", N.STENCIL_FP64), ("RVE_STENCIL_FP32", N.STENCIL_FP32),
+                      ("RVE_SCHEME_Q1", N.SCHEME_Q1), ("RVE_SCHEME_FD5", N.SCHEME_FD5)):
         m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
         assert m and int(m.group(1)) == val, name
