@@ -438,6 +438,31 @@ def survey(rve, torch, dev):
              std_a11_minus_a22=float(st["std_a11_minus_a22"]), L_times_std_a12=L * float(st["std_a12"]),
              L_times_std_a11_minus_a22=L * float(st["std_a11_minus_a22"]))
 
+    # the paper's ensemble (exactly L^2 squares of side 2 alpha = 1/2, a = 1 on
+    # the covered set and 0.4 elsewhere, m0 = 4) with the lumped five-point
+    # scheme: spread of A_hom against Sec. 5, Table a_stan_dev_L1 (N = 10^4)
+    paper = {16: (0.000656, 0.001527), 32: (0.000337, 0.000778), 64: (0.000167, 0.000386)}
+    from sampler import BooleanModel as BM
+    for L in (16, 32, 64):
+        model = BM(L=L, m0=4, a_in=1.0, a_bg=0.4, law="paper", alpha=0.25)
+        Nn = 10000
+        fields_host = [batch(model, 77, 2500, start=s0) for s0 in range(0, Nn, 2500)]
+        for scheme, sname in ((rve.SCHEME_FD5, "fd5"), (rve.SCHEME_Q1, "q1")):
+            A = []
+            t0 = time.perf_counter()
+            for fh in fields_host:
+                r = rve.solve_batch(torch.from_numpy(fh).to(dev), 0.25,
+                                    rve.Options(prec=rve.MIX_BF16, scheme=scheme), want_phi=False, want_flux=False)
+                A.append(r.ahom.cpu().numpy())
+            dt = time.perf_counter() - t0
+            A = np.concatenate(A)
+            s12 = float(np.sqrt(np.mean(A[:, 0, 1] ** 2)))
+            sdd = float(np.sqrt(np.mean((A[:, 0, 0] - A[:, 1, 1]) ** 2)))
+            emit(f"paper ensemble, L={L} n={4 * L} (m0=4, alpha=1/4, lambda=0.4)", scheme=sname, N=Nn, s=dt,
+                 std_a12=s12, paper_std_a12=paper[L][0], ratio_a12=s12 / paper[L][0],
+                 std_a11_minus_a22=sdd, paper_std_a11_minus_a22=paper[L][1], ratio_a11_minus_a22=sdd / paper[L][1],
+                 mean_a11=float(A[:, 0, 0].mean()))
+
 
 def cpu_baseline(fields, seconds):
     """The oracle, as it is, on the host: sequential realizations of the same
