@@ -27,9 +27,12 @@ fd5    The lumped five-point discretisation of Sec. 3.2 (eqns. Lapl_Kron_D,
 lattice_sample
        The on-device sampler's law: lattice Poisson square centres decided by
        Philox4x32-10 words (Salmon et al., SC'11), squares painted into cells.
+dos    Spectral density of the stiffness matrix (Appendix, eqns. DOS,
+       DOS_gauss): exact from eigenvalues, and the Chebyshev-moment estimate
+       with probe vectors.
 
 Pinning status: every function here is pinned by a ``-m "not gpu"`` test
 against closed forms, brute force or invariants (see tests/test_oracle_*.py).
 No function is "parity unpinned".
 """
-from . import q1, pcg, ahom, stats, fd5, lattice_sample  # noqa: F401
+from . import q1, pcg, ahom, stats, fd5, lattice_sample, dos  # noqa: F401
