@@ -253,6 +253,30 @@ const char* rve_status_string(int status);
 int rve_set_autotune(rve_ctx* ctx, int mode);
 
 /*
+ * Spectral density of the stiffness matrix (Appendix, eqns. DOS and
+ * DOS_gauss): phi_eta(t) = (1/m) sum_j g_eta(t - lambda_j), m = n^2, g_eta the
+ * Gaussian of width eta, estimated with probe vectors v (for example with
+ * entries +-1): (1/m) tr g(t - A) ~ mean_v v^T g(t - A) v / m, expanded in
+ * Chebyshev polynomials of Ahat = A / c - I, c = lmax / 2.
+ *
+ * rve_dos_moments: mu_dev [B][nv][K] (device) receives
+ * mu_k = v^T T_k(Ahat) v / m for the operator of field b (scheme: enum
+ * rve_scheme) and its probes v_dev [B][nv][n][n] (device, nv even). lmax
+ * must bound the largest eigenvalue (e.g. 16/3 max a for RVE_SCHEME_Q1 and
+ * 8 max a for RVE_SCHEME_FD5, by Gershgorin). About K/2 operator applies
+ * per probe.
+ *
+ * rve_dos_eval: phi_dev [B][nt] (device) receives
+ * sum_k a_k(t) mubar_k at the points t_dev [nt] (device), mubar the mean of
+ * the nv probes' moments and a_k(t) the Chebyshev coefficients of
+ * x -> g_eta(t - c (1 + x)) by a Chebyshev-Gauss rule with Q >= K nodes.
+ */
+int rve_dos_moments(rve_ctx* ctx, int B, int n, int scheme, const double* a_dev, int nv,
+                    const double* v_dev, double lmax, int K, double* mu_dev);
+int rve_dos_eval(rve_ctx* ctx, int B, int nv, int K, const double* mu_dev, double lmax,
+                 double eta, int Q, int nt, const double* t_dev, double* phi_dev);
+
+/*
  * Sample B coefficient fields of the random inclusion model (Sec. 2, covered
  * domain eqn. Stoch-decomp, coefficient eqn. ahm_coef) on the device, for
  * realizations first .. first + B - 1, into a_dev [B][n][n] (FP64, device).

@@ -16,6 +16,7 @@ from ._native import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Context, Options, Result, context, solve_batch, solve_uneven, grad, stats,
-    apply_operator, apply_precond, occupancy_threshold, sample_lattice,
+    apply_operator, apply_precond, occupancy_threshold, sample_lattice, dos_moments, dos_eval,
+    spectral_density,
 )
 from .autograd import RveAhom, RveAhomContrast, ahom  # noqa: F401

@@ -24,7 +24,7 @@ EXPORTS = (
     "rve_solve_batch", "rve_solve_uneven", "rve_grad", "rve_stats",
     "rve_status_string", "rve_set_timing", "rve_last_timing",
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
-    "rve_set_graphs", "rve_force_variants", "rve_sample_lattice",
+    "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
 )
 
 
@@ -63,6 +63,8 @@ def _declare(lib):
     lib.rve_get_tuned.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(_i)]
     lib.rve_set_graphs.argtypes = [_vp, _i]
     lib.rve_force_variants.argtypes = [_vp, _i, _i]
+    lib.rve_dos_moments.argtypes = [_vp, _i, _i, _i, _vp, _i, _vp, _d, _i, _vp]
+    lib.rve_dos_eval.argtypes = [_vp, _i, _i, _i, _vp, _d, _d, _i, _i, _vp, _vp]
     lib.rve_sample_lattice.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
                                        _d, _d, _vp]
     for name in EXPORTS:

@@ -269,6 +269,54 @@ def apply_operator(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = No
     return out
 
 
+def dos_moments(a: torch.Tensor, v: torch.Tensor, lmax: float, K: int, scheme: int = 0,
+                ctx: Optional[Context] = None) -> torch.Tensor:
+    """Chebyshev moments (B, nv, K) of the stiffness matrix of each field a
+    (B, n, n) with probes v (B, nv, n, n), nv even (see rve_dos_moments)."""
+    _need(a, "a")
+    _need(v, "v")
+    B, n = a.shape[0], a.shape[1]
+    if v.dim() != 4 or v.shape[0] != B or v.shape[2:] != (n, n):
+        raise ValueError("v must be (B, nv, n, n)")
+    nv = v.shape[1]
+    ctx = ctx or context(a.device.index)
+    mu = torch.empty((B, nv, int(K)), dtype=torch.float64, device=a.device)
+    N.check(ctx._lib.rve_dos_moments(ctx.bind_stream(), B, n, int(scheme), _p(a), nv, _p(v), float(lmax), int(K),
+                                     _p(mu)), "rve_dos_moments")
+    return mu
+
+
+def dos_eval(mu: torch.Tensor, t: torch.Tensor, lmax: float, eta: float, Q: Optional[int] = None,
+             ctx: Optional[Context] = None) -> torch.Tensor:
+    """Gaussian-broadened spectral density (B, nt) at the points t (nt,)
+    from moments mu (B, nv, K), averaged over the probes."""
+    _need(mu, "mu")
+    _need(t, "t")
+    B, nv, K = mu.shape
+    Q = int(Q) if Q is not None else 4 * K
+    ctx = ctx or context(mu.device.index)
+    phi = torch.empty((B, t.numel()), dtype=torch.float64, device=mu.device)
+    N.check(ctx._lib.rve_dos_eval(ctx.bind_stream(), B, nv, K, _p(mu), float(lmax), float(eta), Q, t.numel(),
+                                  _p(t), _p(phi)), "rve_dos_eval")
+    return phi
+
+
+def spectral_density(a: torch.Tensor, t: torch.Tensor, eta: float, *, probes: int = 8, K: Optional[int] = None,
+                     scheme: int = 0, seed: int = 0, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Spectral density (B, nt) of the stiffness matrix of each field, with
+    `probes` random +-1 probe vectors (seeded, drawn on the host) and enough
+    moments to resolve the width eta."""
+    B, n = a.shape[0], a.shape[1]
+    amax = float(a.max().item())
+    lmax = (8.0 if scheme == 1 else 16.0 / 3.0) * amax
+    if K is None:
+        K = int(min(20000, max(64, 6.0 * lmax / eta)))
+    import numpy as np
+    g = np.random.default_rng(seed)
+    v = torch.from_numpy(g.choice([-1.0, 1.0], size=(B, probes, n, n))).to(a.device)
+    return dos_eval(dos_moments(a, v, lmax, K, scheme, ctx), t, lmax, eta, ctx=ctx)
+
+
 def occupancy_threshold(mu: float) -> int:
     """Integer site-occupancy threshold of rve_sample_lattice for Poisson
     centres with mean mu per lattice site: round(2^32 (1 - exp(-mu)))."""

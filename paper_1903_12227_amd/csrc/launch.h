@@ -124,6 +124,13 @@ bool sample_side_valid(int n, int side);
 void launch_sample_lattice(int B, int n, int side, unsigned long long seed, long long first, unsigned occ_threshold,
                            double a_in, double a_bg, double* a, hipStream_t st);
 
+// Spectral density by Chebyshev moments (kernels_dos.hip).
+int dos_vec_tiles(long long N2);
+void launch_dos_moments(int B, int n, int scheme, const double* a, int nv, double* W, double* Wp, double* AW,
+                        double lmax, int K, double* part, double* mu, hipStream_t st);
+void launch_dos_eval(int B, int nv, int K, const double* mu, double lmax, double eta, int Q, int nt,
+                     const double* t, double* S, double* phi, hipStream_t st);
+
 // Transform GEMMs of the preconditioner (kernels_gemm.hip).
 enum GemmPrec { kGemmF64 = 0, kGemmF32 = 1, kGemmBF16 = 2 };
 struct GemmTables {

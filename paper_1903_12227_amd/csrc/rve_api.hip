@@ -985,6 +985,50 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   return RVE_OK;
 }
 
+int rve_dos_moments(rve_ctx* c, int B, int n, int scheme, const double* a_dev, int nv, const double* v_dev,
+                    double lmax, int K, double* mu_dev) {
+  if (!c || B < 1 || !n_supported(n) || !a_dev || !v_dev || !mu_dev || nv < 2 || nv % 2 || K < 1 || K > 1000000)
+    return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
+  if (!(lmax > 0.0) || !std::isfinite(lmax)) return RVE_EINVAL;
+  if ((long long)B * nv > 65535) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  const long long N2 = (long long)n * n, S = (long long)B * nv;
+  const size_t vec = align_up((size_t)(S * N2) * 8);
+  const size_t part = align_up((size_t)S * dos_vec_tiles(N2) * 2 * 8);
+  int rc = ensure_ws(c, 3 * vec + part);
+  if (rc) return rc;
+  char* ws = static_cast<char*>(c->ws);
+  double* W = reinterpret_cast<double*>(ws);
+  double* Wp = reinterpret_cast<double*>(ws + vec);
+  double* AW = reinterpret_cast<double*>(ws + 2 * vec);
+  double* P = reinterpret_cast<double*>(ws + 3 * vec);
+  // probes [B][nv][n][n] -> pair-major [nv/2][B][2][n][n]
+  for (int b = 0; b < B; ++b)
+    for (int v = 0; v < nv; ++v)
+      HIP_TRY(hipMemcpyAsync(W + (((long long)(v / 2) * B + b) * 2 + (v % 2)) * N2,
+                             v_dev + ((long long)b * nv + v) * N2, N2 * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(Wp, 0, (size_t)(S * N2) * 8, c->stream));
+  launch_dos_moments(B, n, scheme, a_dev, nv, W, Wp, AW, lmax, K, P, mu_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_dos_eval(rve_ctx* c, int B, int nv, int K, const double* mu_dev, double lmax, double eta, int Q, int nt,
+                 const double* t_dev, double* phi_dev) {
+  if (!c || B < 1 || B > 65535 || nv < 1 || K < 1 || Q < K || Q > 10000000 || nt < 1 || !mu_dev || !t_dev ||
+      !phi_dev)
+    return RVE_EINVAL;
+  if (!(lmax > 0.0) || !std::isfinite(lmax) || !(eta > 0.0) || !std::isfinite(eta)) return RVE_EINVAL;
+  if ((nt + kBlock - 1) / kBlock > 2147483647 || (Q + kBlock - 1) / kBlock > 2147483647) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  int rc = ensure_ws(c, align_up((size_t)B * Q * 8));
+  if (rc) return rc;
+  launch_dos_eval(B, nv, K, mu_dev, lmax, eta, Q, nt, t_dev, static_cast<double*>(c->ws), phi_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
 int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_t first, uint32_t occ_threshold,
                        double a_in, double a_bg, double* a_dev) {
   if (!c || B < 1 || B > 65535 || !n_supported(n) || !sample_side_valid(n, side) || first < 0 || !a_dev)
