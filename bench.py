@@ -463,6 +463,24 @@ def survey(rve, torch, dev):
                  std_a11_minus_a22=sdd, paper_std_a11_minus_a22=paper[L][1], ratio_a11_minus_a22=sdd / paper[L][1],
                  mean_a11=float(A[:, 0, 0].mean()))
 
+    # spectral density (Appendix): sample-average DOS of 20 realizations at
+    # L = 8 and L = 16 (lambda = 0.5, alpha = 1/4, m0 = 8), the shapes the
+    # appendix finds nearly independent of L (Remark DOS_Per_L)
+    t = torch.linspace(0.0, 16.0 / 3.0, 200, dtype=torch.float64, device=dev)
+    curves = {}
+    for L in (8, 16):
+        model = BM(L=L, m0=8, a_in=1.0, a_bg=0.5, law="paper", alpha=0.25)
+        a = torch.from_numpy(batch(model, 78, 20)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi = rve.spectral_density(a, t, 0.02 * 16.0 / 3.0, probes=8, seed=L)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        curves[L] = phi.mean(dim=0).cpu().numpy()
+        emit(f"spectral density, L={L} n={8 * L}, 20 realizations", probes=8, s=dt)
+    d = float(np.abs(curves[8] - curves[16]).sum() / np.abs(curves[16]).sum())
+    emit("spectral density: relative L1 distance of the mean curves at L=8 and L=16", distance=d)
+
 
 def cpu_baseline(fields, seconds):
     """The oracle, as it is, on the host: sequential realizations of the same
