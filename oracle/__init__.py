@@ -27,6 +27,10 @@ fd5    The lumped five-point discretisation of Sec. 3.2 (eqns. Lapl_Kron_D,
 lattice_sample
        The on-device sampler's law: lattice Poisson square centres decided by
        Philox4x32-10 words (Salmon et al., SC'11), squares painted into cells.
+q1_3d  The three-dimensional corrector problems (d = 3; Sec. 2 and eqn.
+       As_Kron_d): trilinear Q1 stiffness and right-hand sides, the rank-3
+       constant-coefficient symbol and its FFT pseudo-inverse, PCG, and the
+       3 x 3 homogenized matrix in energy and flux form.
 dos    Spectral density of the stiffness matrix (Appendix, eqns. DOS,
        DOS_gauss): exact from eigenvalues, and the Chebyshev-moment estimate
        with probe vectors.
@@ -35,4 +39,4 @@ Pinning status: every function here is pinned by a ``-m "not gpu"`` test
 against closed forms, brute force or invariants (see tests/test_oracle_*.py).
 No function is "parity unpinned".
 """
-from . import q1, pcg, ahom, stats, fd5, lattice_sample, dos  # noqa: F401
+from . import q1, pcg, ahom, stats, fd5, lattice_sample, dos, q1_3d  # noqa: F401
