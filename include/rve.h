@@ -157,6 +157,46 @@ int rve_solve_batch(rve_ctx* ctx, int B, int n, double h, const double* a_dev,
                     int* status_dev);
 
 /*
+ * Three-dimensional corrector problems (d = 3): the setting of Sec. 2 with
+ * a(x) times the 3 x 3 identity, the trilinear Q1 discretisation (eqn.
+ * As_Kron_d: the element stiffness k (x) m (x) m + m (x) k (x) m + m (x) m (x) k)
+ * and the constant-coefficient preconditioner a0 A_Delta of Sec. 3.5,
+ * diagonalised by Hartley transforms along the three axes (six transform
+ * GEMMs per apply). B realizations of equal size n, 3B systems.
+ *
+ *   n             64 <= n <= 256, n % 64 == 0 (grid n x n x n, x3 contiguous;
+ *                 cell (i,j,k) spans nodes i..i+1, j..j+1, k..k+1 mod n)
+ *   a_dev         [B][n][n][n] FP64 per-cell coefficients, each > 0
+ *   h             mesh width (> 0); phi is returned in physical units (x h)
+ *   phi_dev       [B][3][n][n][n] FP64 correctors (mean zero), or NULL
+ *   ahom_dev      [B][3][3] FP64 energy-form A_hom (required)
+ *   ahom_flux_dev [B][3][3] FP64 flux-form A_hom, or NULL
+ *   iters_dev     [B][3] int PCG iterations per direction, or NULL
+ *   relres_dev    [B][3] FP64 final recursive relative residual, or NULL
+ *   status_dev    [B] int per-item status, or NULL
+ *
+ * opts as for rve_solve_batch, with stencil_prec = RVE_STENCIL_FP64 and
+ * scheme = RVE_SCHEME_Q1 (anything else: RVE_EINVAL). Same iteration chunks,
+ * graph replay, polling and return convention as rve_solve_batch.
+ */
+int rve_solve_batch_3d(rve_ctx* ctx, int B, int n, double h, const double* a_dev,
+                       const rve_opts* opts, double* phi_dev, double* ahom_dev,
+                       double* ahom_flux_dev, int* iters_dev, double* relres_dev,
+                       int* status_dev);
+
+/* out = A u for B three-dimensional fields: a_dev [B][n][n][n] cells,
+ * u_dev and out_dev [B][n][n][n] nodes (one operand per realization;
+ * u_dev != out_dev); n as for rve_solve_batch_3d. Asynchronous. */
+int rve_apply_operator_3d(rve_ctx* ctx, int B, int n, const double* a_dev,
+                          const double* u_dev, double* out_dev);
+
+/* z = (a0 A_Delta)^+ r for the three systems of each realization:
+ * r_dev, z_dev [B][3][n][n][n] FP64, a0 from a_dev as in the solver,
+ * transforms in `prec` (enum rve_precision). Asynchronous. */
+int rve_apply_precond_3d(rve_ctx* ctx, int B, int n, const double* a_dev,
+                         const double* r_dev, double* z_dev, int prec);
+
+/*
  * Realizations of different sizes in one call (packed input).
  *
  *   n_host[B]          grid size of item b (host)

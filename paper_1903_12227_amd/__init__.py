@@ -17,6 +17,6 @@ from ._native import (  # noqa: F401
 from .api import (  # noqa: F401
     Context, Options, Result, context, solve_batch, solve_uneven, grad, stats,
     apply_operator, apply_precond, occupancy_threshold, sample_lattice, dos_moments, dos_eval,
-    spectral_density,
+    spectral_density, solve_batch_3d, apply_operator_3d, apply_precond_3d,
 )
 from .autograd import RveAhom, RveAhomContrast, ahom  # noqa: F401

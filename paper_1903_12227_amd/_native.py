@@ -25,6 +25,7 @@ EXPORTS = (
     "rve_status_string", "rve_set_timing", "rve_last_timing",
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
+    "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d",
 )
 
 
@@ -49,6 +50,10 @@ def _declare(lib):
     lib.rve_set_stream.argtypes = [_vp, _vp]
     lib.rve_solve_batch.argtypes = [_vp, _i, _i, _d, _vp, ctypes.POINTER(RveOpts),
                                     _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.rve_solve_batch_3d.argtypes = [_vp, _i, _i, _d, _vp, ctypes.POINTER(RveOpts),
+                                       _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.rve_apply_operator_3d.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
+    lib.rve_apply_precond_3d.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
     lib.rve_solve_uneven.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_int64),
                                      _d, _vp, ctypes.POINTER(RveOpts), _vp, _vp, _vp, _vp, _vp, _vp]
     lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _d, _vp, _i]

@@ -34,11 +34,11 @@ class Options:
 
 @dataclass
 class Result:
-    ahom: torch.Tensor                  # (B, 2, 2) energy form
-    ahom_flux: Optional[torch.Tensor]   # (B, 2, 2) flux form
-    phi: Optional[torch.Tensor]         # (B, 2, n, n) correctors x h, mean zero
-    iters: torch.Tensor                 # (B, 2) int32
-    relres: torch.Tensor                # (B, 2) float64
+    ahom: torch.Tensor                  # (B, d, d) energy form (d = 2, or 3 for the 3D solver)
+    ahom_flux: Optional[torch.Tensor]   # (B, d, d) flux form
+    phi: Optional[torch.Tensor]         # (B, d, n, n[, n]) correctors x h, mean zero
+    iters: torch.Tensor                 # (B, d) int32
+    relres: torch.Tensor                # (B, d) float64
     status: torch.Tensor                # (B,) int32
     code: int                           # worst status of the call
 
@@ -182,6 +182,63 @@ def solve_batch(a: torch.Tensor, h: float = 1.0, opts: Optional[Options] = None,
                                     _p(phi), _p(ahom), _p(flux), _p(iters), _p(relres), _p(status))
     _check_batch(code, status, "rve_solve_batch")
     return Result(ahom, flux, phi, iters, relres, status, code)
+
+
+def solve_batch_3d(a: torch.Tensor, h: float = 1.0, opts: Optional[Options] = None, *,
+                   want_phi: bool = True, want_flux: bool = True,
+                   ctx: Optional[Context] = None) -> Result:
+    """Correctors and the 3 x 3 A_hom of B equal-size three-dimensional
+    realizations a (B, n, n, n) FP64 (see rve_solve_batch_3d)."""
+    _need(a, "a")
+    if a.dim() == 3:
+        a = a.unsqueeze(0)
+    if a.dim() != 4 or not (a.shape[1] == a.shape[2] == a.shape[3]):
+        raise ValueError("a must have shape (B, n, n, n)")
+    B, n = a.shape[0], a.shape[1]
+    opts = opts or Options()
+    ctx = ctx or context(a.device.index)
+    dev = a.device
+    ahom = torch.empty((B, 3, 3), dtype=torch.float64, device=dev)
+    flux = torch.empty((B, 3, 3), dtype=torch.float64, device=dev) if want_flux else None
+    phi = torch.empty((B, 3, n, n, n), dtype=torch.float64, device=dev) if want_phi else None
+    iters = torch.empty((B, 3), dtype=torch.int32, device=dev)
+    relres = torch.empty((B, 3), dtype=torch.float64, device=dev)
+    status = torch.full((B,), _UNSET, dtype=torch.int32, device=dev)
+    c_opts = opts.to_c()
+    code = ctx._lib.rve_solve_batch_3d(ctx.bind_stream(), B, n, float(h), _p(a), ctypes.byref(c_opts),
+                                       _p(phi), _p(ahom), _p(flux), _p(iters), _p(relres), _p(status))
+    _check_batch(code, status, "rve_solve_batch_3d")
+    return Result(ahom, flux, phi, iters, relres, status, code)
+
+
+def apply_operator_3d(a: torch.Tensor, u: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+    """A u for the trilinear Q1 operator of each field: a and u (B, n, n, n)."""
+    _need(a, "a")
+    _need(u, "u")
+    if a.dim() != 4 or u.shape != a.shape:
+        raise ValueError("a and u must be (B, n, n, n)")
+    B, n = a.shape[0], a.shape[1]
+    ctx = ctx or context(a.device.index)
+    out = torch.empty_like(u)
+    N.check(ctx._lib.rve_apply_operator_3d(ctx.bind_stream(), B, n, _p(a), _p(u), _p(out)), "rve_apply_operator_3d")
+    return out
+
+
+def apply_precond_3d(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
+                     ctx: Optional[Context] = None) -> torch.Tensor:
+    """(a0 A_Delta)^+ r in three dimensions: a (B, n, n, n), r (B, 3, n, n, n)."""
+    _need(a, "a")
+    _need(r, "r")
+    if a.dim() != 4:
+        raise ValueError("a must be (B, n, n, n)")
+    B, n = a.shape[0], a.shape[1]
+    if r.shape != (B, 3, n, n, n):
+        raise ValueError("r must be (B, 3, n, n, n)")
+    ctx = ctx or context(a.device.index)
+    z = torch.empty_like(r)
+    N.check(ctx._lib.rve_apply_precond_3d(ctx.bind_stream(), B, n, _p(a), _p(r), _p(z), int(prec)),
+            "rve_apply_precond_3d")
+    return z
 
 
 def solve_uneven(fields: Sequence[torch.Tensor], h: float = 1.0, opts: Optional[Options] = None, *,

@@ -18,6 +18,15 @@
 // the second scales by 1/(a0 E), the fourth writes z in FP64 and emits
 // partial sums of r.z.
 //
+// Three dimensions (eqn. As_Kron_d): A_Delta = K (x) M (x) M + M (x) K (x) M
+// + M (x) M (x) K is diagonalised by Q (x) Q (x) Q with
+// E[k][l][m] = kappa_k mu_l mu_m + mu_k kappa_l mu_m + mu_k mu_l kappa_m,
+// kappa = 2 - 2c, mu = (4 + 2c)/6. Viewing an n x n x n array as an n^2 x n
+// matrix (x3 contiguous), out = (X Q)^T transforms the last axis and rotates
+// the axes ([i][j][k] -> [k][i][j]), so three such GEMMs transform every
+// axis and restore the layout: six launches of the same kernel (D = 3, row
+// count n^2), the third scaling by 1/(a0 E).
+//
 // Tiling: 256 threads (2 x 2 waves) per 64 x 64 output tile; each wave owns
 // a 32 x 32 block = 2 x 2 MFMA 16x16 tiles. Operand tiles are staged through
 // LDS with the next K slice prefetched into registers; the output tile is
@@ -99,11 +108,14 @@ template <class Tr> struct Stage {
   static constexpr int TPR = Tr::BK / PER;              // threads per row: 4
 };
 
-template <class Tr, class InT, int EPI, class ZT = double, class RT = double>
+// D = 2: each system is n x n; D = 3: each system is an n^2 x n matrix
+// (rows R = n^2) and its output (X Q)^T is n x n^2; D systems per realization.
+template <class Tr, class InT, int EPI, class ZT = double, class RT = double, int D = 2>
 __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, const typename Tr::op_t* __restrict__ Qm,
                                                      void* __restrict__ out_v, int n, int S, const SysState* sys,
                                                      const RealState* real, const void* __restrict__ einv_v,
                                                      const RT* __restrict__ rres, double* __restrict__ part) {
+  static_assert(D == 2 || D == 3, "dimension");
   using op_t = typename Tr::op_t;
   using acc_t = typename Tr::acc_t;
   using accv_t = typename Tr::accv_t;
@@ -118,7 +130,8 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   op_t* Bs = As + BM * LDA;
   acc_t* Cs = reinterpret_cast<acc_t*>(smem);
 
-  const int NB = n / BN, MB = n / BM;
+  const long long R = D == 3 ? (long long)n * n : (long long)n;   // rows of X per system
+  const int NB = n / BN, MB = (int)(R / BM);
   const long long T = (long long)S * MB * NB;
   long long t = blockIdx.x;
   if ((T & 7) == 0) t = (t & 7) * (T >> 3) + (t >> 3);   // XCD-contiguous tile ranges
@@ -128,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   const int s = (int)(rest / MB);
   if (sys && !sys[s].active) return;
 
-  const long long N2 = (long long)n * n;
+  const long long N2 = R * n;   // elements per system
   const InT* Xs = X + (long long)s * N2 + (long long)mb * BM * n;
   const op_t* Qs = Qm + (long long)nb * BN * n;
 
@@ -204,16 +217,16 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
 
   // output tile: BN rows (l) of BM contiguous values (m); 4 threads per row
   const int orow = tid >> 2, oc0 = (tid & 3) * 16;
-  const long long obase = (long long)s * N2 + (long long)(nb * BN + orow) * n + mb * BM + oc0;
+  const long long obase = (long long)s * N2 + (long long)(nb * BN + orow) * R + mb * BM + oc0;
   double dot = 0.0;
   acc_t scale = (acc_t)1;
-  if constexpr (EPI == kEpiEinv) scale = (acc_t)real[s >> 1].inv_a0;
+  if constexpr (EPI == kEpiEinv) scale = (acc_t)real[D == 2 ? (s >> 1) : s / 3].inv_a0;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     acc_t v = Cs[orow * LDC + oc0 + e];
     if constexpr (EPI == kEpiEinv) {
       const acc_t* einv = reinterpret_cast<const acc_t*>(einv_v);
-      v = v * einv[(long long)(nb * BN + orow) * n + mb * BM + oc0 + e] * scale;
+      v = v * einv[(long long)(nb * BN + orow) * R + mb * BM + oc0 + e] * scale;
     }
     if constexpr (EPI == kEpiZ) {
       ZT* out = reinterpret_cast<ZT*>(out_v);
@@ -229,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   if constexpr (EPI == kEpiZ) {
     double d[1] = {dot};
     block_sum<1>(d, red);
-    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = d[0];
+    if (tid == 0) part[(long long)s * ((long long)MB * NB) + (long long)mb * NB + nb] = d[0];
   }
 }
 
@@ -708,6 +721,48 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) 
                        w.real, nullptr, w.r, w.part_rz);
 }
 
+// Three dimensions: six transforms out = (X Q)^T of the n^2 x n views; the
+// third scales by 1/(a0 E), the sixth writes z with partial sums of r.z.
+template <class Tr, class ZT>
+void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
+  using op_t = typename Tr::op_t;
+  const int n = w.n;
+  const long long T = (long long)w.S * gemm_tiles_per_system3(n);
+  const dim3 grid((unsigned)T), block(kBlock);
+  const op_t* Q = reinterpret_cast<const op_t*>(t.q);
+  const void* einv =
+      std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv3_64 : (const void*)t.einv3_32;
+  op_t* u1 = reinterpret_cast<op_t*>(w.u1);
+  op_t* u2 = reinterpret_cast<op_t*>(w.u2);
+  auto on = [&](int ph) { return phase < 0 || phase == ph; };
+  if (!on(0)) {
+  } else if (w.rlo)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, (const op_t*)w.rlo,
+                       Q, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore, double, double, 3>), grid, block, 0, st, w.r, Q, (void*)u1,
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (on(1))
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (on(2))
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
+                       w.S, w.sys, w.real, einv, (const double*)nullptr, nullptr);
+  if (on(3))
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (on(4))
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+  if (!on(5)) {
+  } else if (w.rlo)
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz);
+  else
+    hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, w.r, w.part_rz);
+}
+
 template <class ZT>
 void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
@@ -767,9 +822,20 @@ int gemm_tiles_per_system(int n, int prec, int variant) {
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
 
+int gemm_tiles_per_system3(int n) { return (n / BM) * n * (n / BN); }
+
+int precond_phases(const Work& w) { return w.dim == 3 ? 6 : 4; }
+
 void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st, int phase) {
   // z is FP64 with FP64 transforms and FP32 in the mixed modes
-  if (prec == kGemmF64) {
+  if (w.dim == 3) {
+    if (prec == kGemmF64)
+      run_precond3<TrF64, double>(w, t, st, phase);
+    else if (prec == kGemmF32)
+      run_precond3<TrF32, float>(w, t, st, phase);
+    else
+      run_precond3<TrBF16, float>(w, t, st, phase);
+  } else if (prec == kGemmF64) {
     run_precond<TrF64, double>(w, t, st, phase);
   } else if (prec == kGemmF32) {
     run_precond<TrF32, float>(w, t, st, phase);

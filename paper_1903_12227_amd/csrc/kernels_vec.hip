@@ -957,11 +957,13 @@ void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st) {
 void launch_advance(int* kiter, hipStream_t st) { hipLaunchKernelGGL(k_advance, dim3(1), dim3(kWave), 0, st, kiter); }
 
 void launch_rhs(const Work& w, hipStream_t st) {
+  if (w.dim == 3) return launch_rhs3(w, st);
   dim3 g(w.n / kTile, w.n / kTile, w.B);
   hipLaunchKernelGGL(k_rhs, g, dim3(kBlock), 0, st, w.a, w.r, w.n, w.part_misc);
 }
 
 void launch_scalar_init(const Work& w, hipStream_t st) {
+  if (w.dim == 3) return launch_scalar_init3(w, st);
   hipLaunchKernelGGL(k_scalar_init, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, w.P_tile, w.n);
 }
 
@@ -1037,6 +1039,7 @@ void launch_stencil_fused_p(const Work& w, int probe, hipStream_t st) {
 }
 
 void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
+  if (w.dim == 3) return launch_stencil3_fused(w, st, probe);
   // iteration k (read on the device) writes p_k into ring slot k mod m and
   // reads p_{k-1} from the previous slot
   if (w.mixed == 0)
@@ -1181,6 +1184,7 @@ void launch_widen(const float* in, double* out, long long total, hipStream_t st)
 
 
 void launch_ahom(const Work& w, hipStream_t st) {
+  if (w.dim == 3) return launch_ahom3(w, st);
   dim3 g(w.n / kTile, w.n / kTile, w.B);
   if (w.scheme == 1)
     hipLaunchKernelGGL(k_ahom<1>, g, dim3(kBlock), 0, st, w.a, w.x, w.n, w.part_misc);
@@ -1189,6 +1193,7 @@ void launch_ahom(const Work& w, hipStream_t st) {
 }
 
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st) {
+  if (w.dim == 3) return launch_scalar_ahom3(w, ahom, ahom_flux, st);
   hipLaunchKernelGGL(k_scalar_ahom, dim3(w.B), dim3(kWave), 0, st, w.sys, w.part_misc, w.P_tile, w.n, ahom,
                      ahom_flux);
 }
@@ -1198,6 +1203,7 @@ void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st) {
 }
 
 void launch_finalize(const Work& w, int* iters, double* relres, int* status, hipStream_t st) {
+  if (w.dim == 3) return launch_finalize3(w, iters, relres, status, st);
   hipLaunchKernelGGL(k_finalize, dim3((w.B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, w.sys, w.B, iters,
                      relres, status);
 }

@@ -10,12 +10,13 @@
 namespace rve {
 
 // Device pointers and sizes of one equal-n batch of B realizations
-// (S = 2B corrector systems, system s = 2b + i for direction i).
+// (S = dim B corrector systems, system s = dim b + i for direction i).
 struct Work {
   int B = 0, n = 0, S = 0;
-  long long N2 = 0;          // n*n
-  const double* a = nullptr; // [B][n][n] cells
-  double* x = nullptr;       // [S][n][n] iterate (grid units)
+  int dim = 2;               // 2: n x n grids; 3: n x n x n grids (x3 contiguous)
+  long long N2 = 0;          // nodes per system: n^dim
+  const double* a = nullptr; // [B][n^dim] cells
+  double* x = nullptr;       // [S][n^dim] iterate (grid units)
   double* r = nullptr;       // residual
   // Search directions p and preconditioned residual z are FP64 when the
   // transform GEMMs are FP64 and FP32 otherwise (mixed modes); they only
@@ -63,6 +64,7 @@ struct Work {
 };
 
 constexpr int kMiscNV = 9;
+constexpr int kMiscNV3 = 18;   // per-realization partials of the three-dimensional kernels
 
 // Elementwise and stencil kernels (kernels_vec.hip).
 void launch_init_state(const Work& w, hipStream_t st);
@@ -118,6 +120,23 @@ void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t 
 void launch_apply_stencil(int B, int n, int scheme, const double* a, const double* u, double* out,
                           hipStream_t st);
 
+// Three-dimensional corrector problems (kernels_3d.hip). Cells and nodes
+// [n][n][n], x3 contiguous; cell (i, j, k) spans nodes i..i+1, j..j+1,
+// k..k+1 (mod n). The launchers of the dimension-specific steps above
+// (RHS, scalar_init, fused operator apply, A_hom, finalize) forward here
+// when w.dim == 3; the per-system vector kernels serve both dimensions.
+constexpr int kStrip3 = 16;   // planes per wave strip of the 3D tile kernels
+// workgroups per system (operator apply) or realization (RHS, A_hom) of the
+// 3D tile kernels: 64 x3-columns x 4 x2-rows x kStrip3 x1-planes each
+__host__ __device__ inline int tiles3(int n) { return (n / kWave) * (n / 4) * (n / kStrip3); }
+void launch_rhs3(const Work& w, hipStream_t st);
+void launch_scalar_init3(const Work& w, hipStream_t st);
+void launch_stencil3_fused(const Work& w, hipStream_t st, int probe);
+void launch_apply_stencil3(int B, int n, const double* a, const double* u, double* out, hipStream_t st);
+void launch_ahom3(const Work& w, hipStream_t st);
+void launch_scalar_ahom3(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
+void launch_finalize3(const Work& w, int* iters, double* relres, int* status, hipStream_t st);
+
 // On-device sampling of the inclusion model (kernels_sample.hip): B fields
 // [B][n][n] for realizations first .. first + B - 1.
 bool sample_side_valid(int n, int side);
@@ -139,6 +158,8 @@ struct GemmTables {
   const float* einv32 = nullptr;
   const __bf16* ch16 = nullptr;   // [n/2][n/2] cos(2 pi k t/n)/sqrt(n), BF16 (folded transform)
   const __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t/n)/sqrt(n), BF16
+  const double* einv3_64 = nullptr;  // [n][n][n] 1/E of the 3D operator (w.dim == 3), (0,0,0) entry 0
+  const float* einv3_32 = nullptr;
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.
@@ -146,7 +167,10 @@ size_t gemm_elem_size(int prec);
 // the GEMM precision; w.P_gemm must equal
 // gemm_tiles_per_system(n, prec, w.gemm_variant).
 // phase < 0 launches all four transforms; 0..3 only that one (in order).
+// With w.dim == 3 there are six transforms (phases 0..5), in 64 x 64 tiles.
 void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st, int phase = -1);
+int precond_phases(const Work& w);
+int gemm_tiles_per_system3(int n);
 bool gemm_variant_valid(int n, int prec, int variant);
 int gemm_tiles_per_system(int n, int prec, int variant);
 int gemm_tiles_per_system_max(int n);

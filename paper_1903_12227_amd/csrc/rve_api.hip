@@ -32,6 +32,7 @@ static_assert(kRing == RVE_DIRECTION_RING, "direction ring length must match the
 namespace {
 
 constexpr int kMinN = 64, kMaxN = 4096;
+constexpr int kMaxN3 = 256;   // three dimensions: n^3 nodes per system
 
 struct Tables {
   double* q64 = nullptr;
@@ -43,6 +44,8 @@ struct Tables {
   float* einv32_fd = nullptr;
   __bf16* ch16 = nullptr;   // [n/2][n/2] cos(2 pi k t / n)/sqrt(n), row k (n % 256 == 0 only)
   __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t / n)/sqrt(n)
+  double* einv3_64 = nullptr;   // [n][n][n] 1/E of the 3D operator, built on first use
+  float* einv3_32 = nullptr;
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
@@ -107,6 +110,7 @@ namespace {
 inline void ignore(hipError_t) {}
 
 bool n_supported(int n) { return n >= kMinN && n <= kMaxN && n % 64 == 0; }
+bool n_supported3(int n) { return n >= kMinN && n <= kMaxN3 && n % 64 == 0; }
 
 // Errors (negative codes) dominate warnings; among equals the larger magnitude.
 int worse(int x, int y) { return (x < 0 || y < 0) ? std::min(x, y) : std::max(x, y); }
@@ -187,6 +191,47 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   return RVE_OK;
 }
 
+// The 3D symbol's reciprocal (kappa = 2 - 2c, mu = (4 + 2c)/6, c = cos(2 pi k / n)):
+// E = kappa_k mu_l mu_m + mu_k kappa_l mu_m + mu_k mu_l kappa_m, (0,0,0) -> 0.
+int build_tables3(rve_ctx* ctx, int n, Tables** out) {
+  int rc = build_tables(ctx, n, out);
+  if (rc) return rc;
+  Tables* t = *out;
+  if (t->einv3_64) return RVE_OK;
+  const size_t N3 = (size_t)n * n * n;
+  std::vector<double> e64(N3);
+  std::vector<float> e32(N3);
+  std::vector<double> kap(n), mu(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k = 0; k < n; ++k) {
+    const double c = std::cos(two_pi * (double)k / (double)n);
+    kap[k] = 2.0 - 2.0 * c;
+    mu[k] = (4.0 + 2.0 * c) / 6.0;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double E = kap[i] * mu[j] * mu[k] + mu[i] * kap[j] * mu[k] + mu[i] * mu[j] * kap[k];
+        const double inv = (i == 0 && j == 0 && k == 0) ? 0.0 : 1.0 / E;
+        const size_t o = ((size_t)i * n + j) * n + k;
+        e64[o] = inv;
+        e32[o] = (float)inv;
+      }
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+  if (hipMalloc(&d64, N3 * 8) != hipSuccess || hipMalloc(&d32, N3 * 4) != hipSuccess) {
+    ignore(hipFree(d64));
+    ignore(hipFree(d32));
+    (void)hipGetLastError();
+    return RVE_ENOMEM;
+  }
+  HIP_TRY(hipMemcpy(d64, e64.data(), N3 * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d32, e32.data(), N3 * 4, hipMemcpyHostToDevice));
+  t->einv3_64 = d64;
+  t->einv3_32 = d32;
+  return RVE_OK;
+}
+
 // Workspace: a control block shared by every batch of a solve (iteration
 // counter, per-iteration counts of systems still iterating), then one region
 // per equal-n batch, carved by plan() with offsets from the region start.
@@ -195,18 +240,21 @@ struct Layout {
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_status, total;
 };
 
-Layout plan(int B, int n, int prec, int sprec, int scheme, Work* w) {
+Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   Layout L{};
-  const long long S = 2LL * B, N2 = (long long)n * n;
-  const int P_tile = (n / kTile) * (n / kTile);            // RHS / A_hom / gradient tiles
+  const long long S = (long long)dim * B, N2 = dim == 3 ? (long long)n * n * n : (long long)n * n;
+  // RHS / A_hom / gradient tiles per realization
+  const int P_tile = dim == 3 ? tiles3(n) : (n / kTile) * (n / kTile);
   const int sc = stencil_choice_default(n);
-  const int P_st = stencil_tiles_per_realization(n, sc);
+  const int P_st = dim == 3 ? tiles3(n) : stencil_tiles_per_realization(n, sc);
   long long vb = N2 / 1024;
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
   const int P_vec = (int)vb;
   const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
-  const int P_gemm = gemm_tiles_per_system(n, gp, gemm_variant_valid(n, gp, 1) ? 1 : 0);
+  const int gv = dim == 2 && gemm_variant_valid(n, gp, 1) ? 1 : 0;
+  const int P_gemm = dim == 3 ? gemm_tiles_per_system3(n) : gemm_tiles_per_system(n, gp, gv);
+  const int misc_nv = dim == 3 ? kMiscNV3 : kMiscNV;
   const size_t vec = align_up((size_t)(S * N2) * 8);
   const size_t pzvec = align_up((size_t)(S * N2) * (prec == RVE_FP64 ? 8 : 4));
   const size_t uvec = align_up((size_t)(S * N2) * gemm_elem_size(gp));
@@ -228,15 +276,16 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, Work* w) {
   L.off_u2 = o; o += uvec;
   L.off_sys = o; o += align_up(S * sizeof(SysState));
   L.off_real = o; o += align_up(B * sizeof(RealState));
-  L.off_pq = o; o += align_up(S * P_tile * 8);
+  L.off_pq = o; o += align_up(S * std::max(P_tile, P_st) * 8);
   L.off_rr = o; o += align_up(S * P_vec * 8);
   L.off_rzo = o; o += align_up(S * P_vec * 8);
-  L.off_rz = o; o += align_up(S * gemm_tiles_per_system_max(n) * 8);
-  L.off_misc = o; o += align_up((size_t)B * P_tile * kMiscNV * 8);
+  L.off_rz = o; o += align_up(S * (dim == 3 ? gemm_tiles_per_system3(n) : gemm_tiles_per_system_max(n)) * 8);
+  L.off_misc = o; o += align_up((size_t)B * P_tile * misc_nv * 8);
   L.off_status = o; o += align_up((size_t)B * sizeof(int));
   L.total = o;
   w->B = B;
   w->n = n;
+  w->dim = dim;
   w->S = (int)S;
   w->N2 = N2;
   w->P_tile = P_tile;
@@ -248,7 +297,7 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, Work* w) {
   w->m_ring = kRing;
   w->sprec = sprec;
   w->scheme = scheme;
-  w->gemm_variant = gemm_variant_valid(n, gp, 1) ? 1 : 0;
+  w->gemm_variant = gv;
   return L;
 }
 
@@ -436,8 +485,12 @@ void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt, 
     launch_precond(w, prec, gt, st);
     return;
   }
-  for (int ph = 0; ph < 4; ++ph) {
-    Timed t(ctx, 1 + ph);
+  // classes 1..4: the first transform, the scaling one, the plain ones, the
+  // last (2D: phases 0..3; 3D: 0, 2, {1, 3, 4}, 5)
+  const int np = precond_phases(w);
+  for (int ph = 0; ph < np; ++ph) {
+    const int cls = np == 4 ? 1 + ph : ph == 0 ? 1 : ph == 2 ? 2 : ph == 5 ? 4 : 3;
+    Timed t(ctx, cls);
     launch_precond(w, prec, gt, st, ph);
   }
 }
@@ -446,7 +499,8 @@ void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt, 
 // workspace region.
 struct Batch {
   int B = 0, n = 0;
-  const double* a = nullptr;                 // [B][n][n], or the items below
+  int dim = 2;
+  const double* a = nullptr;                 // [B][n^dim], or the items below
   std::vector<const double*> a_items;        // item k's n x n cells (when not contiguous)
   double *phi = nullptr, *ahom = nullptr, *flux = nullptr, *relres = nullptr;
   int *iters = nullptr, *status = nullptr;
@@ -500,7 +554,7 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
   key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec, o->scheme,
                          (long long)bs.size()});
   for (auto& b : bs)
-    key.insert(key.end(), {b.B, b.n, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
+    key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
   auto it = ctx->graph_cache.find(key);
   if (it != ctx->graph_cache.end()) {
     *out = it->second;
@@ -540,7 +594,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
   const int count_len = o->maxit + kRing;
   size_t total = ctl_bytes(count_len);
   for (auto& b : bs) {
-    b.L = plan(b.B, b.n, o->prec, o->stencil_prec, o->scheme, &b.w);
+    b.L = plan(b.B, b.n, o->prec, o->stencil_prec, o->scheme, b.dim, &b.w);
     b.base = total;
     total += b.L.total;
   }
@@ -553,7 +607,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
   for (auto& b : bs) {
     bind(ws + b.base, b.L, &b.w);
     double* a_ws = reinterpret_cast<double*>(ws + b.base + b.L.off_a);
-    const size_t cells = (size_t)b.n * b.n;
+    const size_t cells = (size_t)b.w.N2;
     if (b.a_items.empty()) {
       HIP_TRY(hipMemcpyAsync(a_ws, b.a, (size_t)b.B * cells * 8, hipMemcpyDeviceToDevice, st));
     } else {
@@ -565,8 +619,10 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     b.w.count = count;
     if (!b.status) b.status = reinterpret_cast<int*>(ws + b.base + b.L.off_status);
     Tables* tb = nullptr;
-    rc = build_tables(ctx, b.n, &tb);
+    rc = b.dim == 3 ? build_tables3(ctx, b.n, &tb) : build_tables(ctx, b.n, &tb);
     if (rc) return rc;
+    b.gt.einv3_64 = tb->einv3_64;
+    b.gt.einv3_32 = tb->einv3_32;
     b.gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
                                                                                   : (const void*)tb->q16;
     b.gt.einv64 = o->scheme == RVE_SCHEME_FD5 ? tb->einv64_fd : tb->einv64;
@@ -594,6 +650,11 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
   for (auto& b : bs) {
     Work& w = b.w;
     const int n = b.n;
+    if (b.dim == 3) {   // one operator-apply shape and one transform variant
+      precond_timed(ctx, w, prec, b.gt, st);
+      launch_scalar_beta(w, flexible, 1, st);
+      continue;
+    }
     const int bb = batch_bucket(b.B);
     // kind 0: FP64 operator-apply shape, 2: FP32 apply, 3: five-point apply
     const TuneKey kst(w.sprec ? 2 : w.scheme ? 3 : 0, n, o->prec, bb), kgm(1, n, o->prec, bb);
@@ -778,6 +839,8 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.einv64_fd));
     ignore(hipFree(kv.second.einv32_fd));
     ignore(hipFree(kv.second.sh16));
+    ignore(hipFree(kv.second.einv3_64));
+    ignore(hipFree(kv.second.einv3_32));
   }
   clear_graphs(c);
   if (c->ws) ignore(hipFree(c->ws));
@@ -815,6 +878,80 @@ int rve_solve_batch(rve_ctx* c, int B, int n, double h, const double* a_dev, con
   b.relres = relres_dev;
   b.status = status_dev;
   return solve_batches(c, bs, h, o, nullptr);
+}
+
+// Launch-size bound of the 3D kernels: every grid stays below 2^31 workgroups.
+static bool fits3(int B, int n) {
+  const long long per = std::max<long long>(tiles3(n), gemm_tiles_per_system3(n));
+  return (long long)B * 3 * per < (1LL << 31);
+}
+
+int rve_solve_batch_3d(rve_ctx* c, int B, int n, double h, const double* a_dev, const rve_opts* o,
+                       double* phi_dev, double* ahom_dev, double* ahom_flux_dev, int* iters_dev,
+                       double* relres_dev, int* status_dev) {
+  if (!c || B < 1 || !n_supported3(n) || !fits3(B, n) || !(h > 0.0) || !std::isfinite(h) || !a_dev ||
+      !ahom_dev)
+    return RVE_EINVAL;
+  if (check_opts(o)) return RVE_EINVAL;
+  if (o->stencil_prec != RVE_STENCIL_FP64 || o->scheme != RVE_SCHEME_Q1) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  std::vector<Batch> bs(1);
+  Batch& b = bs[0];
+  b.B = B;
+  b.n = n;
+  b.dim = 3;
+  b.a = a_dev;
+  b.phi = phi_dev;
+  b.ahom = ahom_dev;
+  b.flux = ahom_flux_dev;
+  b.iters = iters_dev;
+  b.relres = relres_dev;
+  b.status = status_dev;
+  return solve_batches(c, bs, h, o, nullptr);
+}
+
+int rve_apply_operator_3d(rve_ctx* c, int B, int n, const double* a_dev, const double* u_dev, double* out_dev) {
+  if (!c || B < 1 || !n_supported3(n) || !fits3(B, n) || !a_dev || !u_dev || !out_dev || u_dev == out_dev)
+    return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_apply_stencil3(B, n, a_dev, u_dev, out_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_apply_precond_3d(rve_ctx* c, int B, int n, const double* a_dev, const double* r_dev, double* z_dev,
+                         int prec) {
+  if (!c || B < 1 || !n_supported3(n) || !fits3(B, n) || !a_dev || !r_dev || !z_dev || r_dev == z_dev)
+    return RVE_EINVAL;
+  if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  Work w;
+  const Layout L = plan(B, n, prec, 0, RVE_SCHEME_Q1, 3, &w);
+  int rc = ensure_ws(c, L.total);
+  if (rc) return rc;
+  bind(static_cast<char*>(c->ws), L, &w);
+  w.a = a_dev;
+  Tables* tb = nullptr;
+  rc = build_tables3(c, n, &tb);
+  if (rc) return rc;
+  // a0 of each realization, exactly as the solver derives it
+  launch_init_state(w, c->stream);
+  launch_rhs(w, c->stream);
+  launch_scalar_init(w, c->stream);
+  GemmTables gt;
+  gt.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
+                                                                         : (const void*)tb->q16;
+  gt.einv3_64 = tb->einv3_64;
+  gt.einv3_32 = tb->einv3_32;
+  w.r = const_cast<double*>(r_dev);
+  w.sys = nullptr;
+  if (w.mixed) launch_round_lo(w, c->stream);
+  void* z_solver = w.z;
+  w.z = w.mixed ? z_solver : (void*)z_dev;
+  launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
+  if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
 }
 
 int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, double h,
@@ -949,7 +1086,7 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
-  const Layout L = plan(B, n, prec, 0, scheme, &w);
+  const Layout L = plan(B, n, prec, 0, scheme, 2, &w);
   int rc = ensure_ws(c, L.total);
   if (rc) return rc;
   bind(static_cast<char*>(c->ws), L, &w);

@@ -10,4 +10,7 @@ from .boolean_model import (  # noqa: F401
     realization,
     batch,
     uneven_batch,
+    BooleanModel3D,
+    realization_3d,
+    batch_3d,
 )

@@ -115,3 +115,56 @@ def uneven_batch(sizes, m0: int, a_in: float, a_bg: float, config: int,
         model = BooleanModel(L=int(L), m0=m0, a_in=a_in, a_bg=a_bg)
         out.append((int(L), realization(model, config, r)))
     return out
+
+
+@dataclass(frozen=True)
+class BooleanModel3D:
+    """The same model on the three-dimensional torus [0, L)^3 (the setting of
+    Sec. 2 carries over unchanged to d = 3): a Poisson(ln 2 * L^3) number of
+    cubes of side ``side`` cells (default m0: unit cubes) with centres uniform
+    on the node lattice, so each cell is covered by a Poisson(ln 2) number of
+    cubes and half the torus is covered on average. Cell (i, j, k) spans
+    nodes i..i+1, j..j+1, k..k+1; arrays are [i][j][k] with x3 contiguous."""
+    L: int
+    m0: int
+    a_in: float = 10.0
+    a_bg: float = 1.0
+    side: int | None = None
+
+    @property
+    def n(self) -> int:
+        return self.m0 * self.L
+
+
+_KEY_3D = 3
+
+
+def covered_mask_3d(model: BooleanModel3D, config: int, index: int) -> np.ndarray:
+    """Boolean (n, n, n) mask of cells covered by at least one cube."""
+    n = model.n
+    rng = _rng(config, index + (_KEY_3D << 40))
+    k = int(rng.poisson(np.log(2.0) * model.L ** 3))
+    side = model.m0 if model.side is None else int(model.side)
+    centres = rng.integers(0, n, size=(k, 3))
+    mask = np.zeros((n, n, n), dtype=bool)
+    off = np.arange(side) - side // 2
+    for c in centres:
+        ii = (c[0] + off) % n
+        jj = (c[1] + off) % n
+        kk = (c[2] + off) % n
+        mask[np.ix_(ii, jj, kk)] = True
+    return mask
+
+
+def realization_3d(model: BooleanModel3D, config: int, index: int) -> np.ndarray:
+    """Per-cell coefficient field, float64 (n, n, n), C-contiguous."""
+    return np.where(covered_mask_3d(model, config, index), float(model.a_in), float(model.a_bg)).astype(np.float64)
+
+
+def batch_3d(model: BooleanModel3D, config: int, count: int, start: int = 0) -> np.ndarray:
+    """``count`` realizations with indices start..start+count-1, shape (count, n, n, n)."""
+    n = model.n
+    out = np.empty((count, n, n, n), dtype=np.float64)
+    for b in range(count):
+        out[b] = realization_3d(model, config, start + b)
+    return out

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "rve.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rve_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(rve_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +31,37 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
     from paper_1903_12227_amd import _native
     assert set(_native.EXPORTS) == set(names)
+
+
+def test_host_argument_validation_3d(lib):
+    from paper_1903_12227_amd import _native as N
+    o = N.RveOpts()
+    lib.rve_default_opts(ctypes.byref(o))
+    fake = ctypes.c_void_p(1)
+    other = ctypes.c_void_p(2)
+    assert lib.rve_solve_batch_3d(None, 1, 64, 0.125, fake, ctypes.byref(o), None, fake, None, None, None,
+                                  None) == N.EINVAL
+    # n must be a multiple of 64 in [64, 256]
+    for n in (0, 32, 96, 320, 512):
+        assert lib.rve_solve_batch_3d(fake, 1, n, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                      None, None) == N.EINVAL
+        assert lib.rve_apply_operator_3d(fake, 1, n, fake, fake, other) == N.EINVAL
+        assert lib.rve_apply_precond_3d(fake, 1, n, fake, fake, other, 0) == N.EINVAL
+    # the FP32 apply and the five-point scheme are two-dimensional only
+    for bad in (N.RveOpts(1e-10, 10, 0, -1, 0, 1, 0), N.RveOpts(1e-10, 10, 0, -1, 0, 0, 1)):
+        assert lib.rve_solve_batch_3d(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                                      None, None) == N.EINVAL
+    assert lib.rve_solve_batch_3d(fake, 0, 64, 0.125, fake, ctypes.byref(o), None, fake, None, None, None,
+                                  None) == N.EINVAL
+    assert lib.rve_solve_batch_3d(fake, 1, 64, 0.125, fake, ctypes.byref(o), None, None, None, None, None,
+                                  None) == N.EINVAL
+    # in-place operands and unknown precisions
+    assert lib.rve_apply_operator_3d(fake, 1, 64, fake, fake, fake) == N.EINVAL
+    assert lib.rve_apply_precond_3d(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL
+    assert lib.rve_apply_precond_3d(fake, 1, 64, fake, fake, other, 5) == N.EINVAL
+    # launch-size bound: B so large that a grid would pass 2^31 workgroups
+    assert lib.rve_solve_batch_3d(fake, 1 << 22, 256, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                  None, None) == N.EINVAL
 
 
 def test_status_strings_and_defaults(lib):

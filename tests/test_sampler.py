@@ -40,3 +40,22 @@ def test_uneven_batch_shares():
     assert sorted(Ls) == [8, 8, 8, 16, 16, 16]
     for L, a in items:
         assert a.shape == (4 * L, 4 * L)
+
+
+def test_3d_model_deterministic_half_coverage_and_cube_size():
+    from sampler import BooleanModel3D, batch_3d, realization_3d
+    m = BooleanModel3D(L=4, m0=8, a_in=7.0)
+    a = batch_3d(m, 5, 3)
+    assert a.shape == (3, 32, 32, 32) and a.dtype == np.float64 and a.flags.c_contiguous
+    np.testing.assert_array_equal(a[1], realization_3d(m, 5, 1))
+    assert set(np.unique(a)) <= {1.0, 7.0}
+    # each cell covered by Poisson(ln 2) cubes: half the torus on average
+    cover = np.mean([(realization_3d(BooleanModel3D(L=4, m0=2), 6, r) == 10.0).mean() for r in range(40)])
+    assert abs(cover - 0.5) < 0.04
+    # a realization with a single cube of side 3 covers a 3 x 3 x 3 block
+    one = [realization_3d(BooleanModel3D(L=1, m0=8, side=3), 7, r) for r in range(20)]
+    counts = sorted({int((f == 10.0).sum()) for f in one} - {0})
+    assert counts[0] == 27
+    f = next(f for f in one if (f == 10.0).sum() == 27)
+    idx = np.argwhere(f == 10.0)
+    assert all(len(np.unique(idx[:, d])) == 3 for d in range(3))
