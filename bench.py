@@ -221,6 +221,7 @@ def main():
                     help="JSON-lines file of autotuned kernel choices to read and extend "
                          "(lets profiling runs replay the choices of a normal run)")
     ap.add_argument("--survey", action="store_true", help="time the other workloads instead")
+    ap.add_argument("--survey3d", action="store_true", help="time only the three-dimensional workloads")
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["RVE_TUNE_CACHE"] = args.tune_cache
@@ -241,6 +242,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.survey:
         survey(rve, torch, dev)
+        return
+    if args.survey3d:
+        survey_3d(rve, torch, dev, lambda name, **kw: print(json.dumps({"survey": name, **kw}), flush=True))
         return
     L, m0, B = args.L, args.m0, args.batch
     n, h = L * m0, 1.0 / m0
@@ -481,6 +485,78 @@ def survey(rve, torch, dev):
     d = float(np.abs(curves[8] - curves[16]).sum() / np.abs(curves[16]).sum())
     emit("spectral density: relative L1 distance of the mean curves at L=8 and L=16", distance=d)
 
+    survey_3d(rve, torch, dev, emit)
+
+
+def bytes_per_node_3d(prec_name):
+    """Algorithmic HBM bytes per node and corrector system of each kernel
+    class of the three-dimensional path. As bytes_per_node, except that the
+    operator apply runs one system per workgroup (it reads a for each
+    system) and the preconditioner has six transforms: gemm1 the first (reads
+    the residual copy), gemm2 the scaling one, gemm3 the four plain ones
+    together, gemm4 the last (writes z, re-reads the residual copy)."""
+    sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
+    sp = 8 if prec_name == "fp64" else 4
+    lo = 0 if prec_name == "fp64" else sg
+    first_in = 8 if prec_name == "fp64" else sg
+    return {"stencil": 3 * sp + 8 + 8, "gemm1": first_in + sg, "gemm2": 2 * sg, "gemm3": 4 * 2 * sg,
+            "gemm4": sg + sp + first_in, "update_r": 8 + 8 + 8 + lo, "fold_x": sp}
+
+
+def survey_3d(rve, torch, dev, emit):
+    """Three-dimensional corrector problems (unit cubes, contrast 10, tol
+    1e-10): wall time per batch, and per kernel class the event time, the
+    algorithmic bandwidth and its fraction of the HBM peak (and the GEMMs'
+    TFLOP/s)."""
+    import math
+
+    import numpy as np
+
+    from paper_1903_12227_amd import DIRECTION_RING
+    from sampler import BooleanModel3D, batch_3d
+
+    ctx = rve.Context(0)
+    for L, B in ((8, 64), (16, 8)):
+        n = 8 * L
+        N3 = float(n) ** 3
+        a = torch.from_numpy(batch_3d(BooleanModel3D(L=L, m0=8, a_in=10.0), 90 + L, B)).to(dev)
+        ref = None
+        for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16")):
+            opts = rve.Options(tol=1e-10, prec=prec)
+            rve.solve_batch_3d(a, 0.125, opts, want_phi=False, ctx=ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = rve.solve_batch_3d(a, 0.125, opts, want_phi=False, ctx=ctx)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            A = res.ahom.cpu().numpy()
+            if ref is None:
+                ref = A
+            dev_rel = float(np.max(np.abs(A - ref)) / np.max(np.abs(np.diagonal(ref, axis1=1, axis2=2))))
+            ctx.set_timing(True)
+            r2 = rve.solve_batch_3d(a, 0.125, opts, want_phi=False, ctx=ctx)
+            torch.cuda.synchronize()
+            tim = ctx.timing()
+            ctx.set_timing(False)
+            its = r2.iters.cpu().numpy()
+            sys_it = float(its.sum())
+            folds = float(sum(math.ceil(v / DIRECTION_RING) for v in its.ravel().tolist()))
+            bpn = bytes_per_node_3d(pname)
+            kern = {}
+            for k, (ms, cnt) in tim.items():
+                if cnt == 0:
+                    continue
+                byts = sys_it * bpn[k] * N3 + (16.0 * folds * N3 if k == "fold_x" else 0.0)
+                e = {"ms": round(ms, 3), "launches": cnt, "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+                if k.startswith("gemm"):
+                    per = 4 if k == "gemm3" else 1
+                    e["TFLOPs"] = round(sys_it * per * 2.0 * n * N3 / (ms * 1e-3) / 1e12, 1)
+                kern[k] = e
+            emit(f"3D L={L} n={n}, {B} realizations (3 correctors + 3x3 A_hom)", gemm=pname, ms=1e3 * dt,
+                 realizations_s=B / dt, iters_mean=float(its.mean()), ahom_rel_dev_vs_fp64=dev_rel,
+                 code=int(res.code), mean_a11=float(A[:, 0, 0].mean()), kernels=kern)
+    ctx.close()
 
 def cpu_baseline(fields, seconds):
     """The oracle, as it is, on the host: sequential realizations of the same

@@ -18,8 +18,9 @@
 // Tile kernels: 256 threads per workgroup; lane = x3 index within a 64-wide
 // column block, the four waves take four consecutive x2 rows, and each wave
 // slides a register window along x1 over a strip of kStrip3 planes, so a
-// value is loaded from HBM about once per strip (plus a halo plane) and its
-// x2 / x3 neighbours come from cache lines the workgroup has just fetched.
+// value is loaded from HBM about once per strip (plus a halo plane); the
+// operator apply stages each plane with its x2 / x3 halo in LDS, the RHS and
+// A_hom kernels take the neighbours from cache lines just fetched.
 // One-dimensional grid with the XCD-contiguous remap of the 2D kernels.
 // Reductions go through per-workgroup partials finished in a fixed order.
 #include "launch.h"
@@ -176,18 +177,29 @@ __global__ void k_scalar_init3(SysState* sys, RealState* real, const double* __r
 // q = A u over one system per workgroup (coefficients of realization
 // unit / spr).
 // FUSED: u is the new search direction p_k = z_k + beta_{k-1} p_{k-1}
-// (p_0 = z_0), formed on the fly at the node and its neighbours and rounded
-// to its storage type PT before use; p_k goes to ring slot k mod m (k read
-// from *kiter), p_{k-1} comes from slot (k - 1) mod m; q and partial sums of
-// p_k.q are written for active systems. probe = 1 (timing at k = 0 only)
-// reads p_{k-1} as a later iteration would.
+// (p_0 = z_0), rounded to its storage type PT before use; p_k goes to ring
+// slot k mod m (k read from *kiter), p_{k-1} comes from slot (k - 1) mod m;
+// q and partial sums of p_k.q are written for active systems. probe = 1
+// (timing at k = 0 only) reads p_{k-1} as a later iteration would.
 // Not FUSED: u = p_in, spr = 1 (one operand per realization).
+//
+// Each step of the strip stages the next operand plane of the workgroup's
+// region (its 4 x 64 nodes plus a one-node halo: 6 x 66, the direction
+// formed once per node) and the current cell plane (5 x 65) in LDS, double
+// buffered so one barrier per step suffices; each lane then reads its 3 x 3
+// neighbourhood and 2 x 2 cells from LDS and keeps the two previous planes
+// in registers.
 template <bool FUSED, class PT>
 __global__ void __launch_bounds__(kBlock) k_stencil3(const double* __restrict__ a, const PT* p_in, PT* ring,
                                                       long long slot_stride, int m, const int* kiter,
                                                       const PT* __restrict__ z, double* __restrict__ q, int n,
                                                       int spr, const SysState* sys, double* __restrict__ part,
                                                       int probe) {
+  constexpr int CW = kWave + 2, PE = 6 * CW;   // staged operand plane: rows j0-1 .. j0+4, cols k0-1 .. k0+64
+  constexpr int AC = kWave + 1, AE = 5 * AC;   // staged cell plane: rows j0-1 .. j0+3, cols k0-1 .. k0+63
+  static_assert(PE <= 2 * kBlock && AE <= 2 * kBlock, "two staged elements per thread");
+  __shared__ double su[2][PE];
+  __shared__ double sa[2][AE];
   __shared__ double sh[4];
   const Tile3 tl = tile3_of(n);
   const int s = tl.unit;
@@ -207,54 +219,110 @@ __global__ void __launch_bounds__(kBlock) k_stencil3(const double* __restrict__ 
   const double* A = a + (long long)(s / spr) * N3;
   const PT* Po = p_old + (long long)s * N3;
   const PT* Zs = FUSED ? z + (long long)s * N3 : nullptr;
-  const int k = tl.k, j = tl.j;
-  const int col[3] = {wrap_dec(k, n), k, wrap_inc(k, n)};
-  const long long row[3] = {(long long)wrap_dec(j, n) * n, (long long)j * n, (long long)wrap_inc(j, n) * n};
-  const bool need_p = !FUSED || !first;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k0 = tl.k - lane, j0 = tl.j - w;
 
-  auto load_plane = [&](int pi, double (&u)[3][3]) {
-    const long long pl = (long long)pi * NN;
-    PT pv[3][3], zv[3][3];
+  // in-plane offsets of this thread's staged elements: element tid (always
+  // inside both regions) and element tid + 256 (inside for the first
+  // PE - 256 / AE - 256 threads; elsewhere the offset is 0, so the load stays
+  // in bounds, and the LDS write is skipped)
+  int po[2], ao[2];
 #pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int x = 0; x < 3; ++x) {
-        const long long o = pl + row[y] + col[x];
-        if (need_p) pv[y][x] = Po[o];
-        if constexpr (FUSED) zv[y][x] = Zs[o];
-      }
-#pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int x = 0; x < 3; ++x) {
-        if constexpr (FUSED) {
-          // p_k is rounded to PT before use, so q = A p_k, p_k.q and the
-          // later x += alpha p_k all see the same direction
-          u[y][x] = first ? (double)zv[y][x] : (double)(PT)fma(beta, (double)pv[y][x], (double)zv[y][x]);
-        } else {
-          u[y][x] = (double)pv[y][x];
-        }
-      }
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * kBlock;
+    int gj = j0 - 1 + e / CW, gk = k0 - 1 + e % CW;
+    gj = gj < 0 ? gj + n : gj >= n ? gj - n : gj;
+    gk = gk < 0 ? gk + n : gk >= n ? gk - n : gk;
+    po[u] = e < PE ? gj * n + gk : 0;
+    int hj = j0 - 1 + e / AC, hk = k0 - 1 + e % AC;
+    hj = hj < 0 ? hj + n : hj;
+    hk = hk < 0 ? hk + n : hk;
+    ao[u] = e < AE ? hj * n + hk : 0;
+  }
+  const bool p1 = tid + kBlock < PE, a1 = tid + kBlock < AE;
+  // raw loads of one operand plane and one cell plane, kept in registers
+  // (issued a step ahead of their use, so they stay in flight across the
+  // barrier and the arithmetic of the current step). The previous direction
+  // is loaded at k = 0 too (its slot holds earlier data) and then not used.
+  struct Raw {
+    PT z[2], p[2];
+    double a[2];
   };
-  auto load_cells = [&](int ci, double (&c)[2][2]) {
-    const long long pl = (long long)ci * NN;
+  auto load_op = [&](int pi, Raw& R) {
+    const PT* pp = Po + (long long)pi * NN;
+    const PT* zp = FUSED ? Zs + (long long)pi * NN : nullptr;
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      c[y][0] = A[pl + row[y] + col[0]];
-      c[y][1] = A[pl + row[y] + col[1]];
+    for (int u = 0; u < 2; ++u) {
+      if constexpr (FUSED) R.z[u] = zp[po[u]];
+      R.p[u] = pp[po[u]];
     }
+  };
+  auto load_cells = [&](int ci, Raw& R) {
+    const double* ap = A + (long long)ci * NN;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) R.a[u] = ap[ao[u]];
+  };
+  auto cook = [&](const Raw& R, int u) -> double {
+    if constexpr (FUSED) {
+      // p_k is rounded to PT before use, so q = A p_k, p_k.q and the later
+      // x += alpha p_k all see the same direction
+      const double pk = (double)(PT)fma(beta, (double)R.p[u], (double)R.z[u]);
+      return first ? (double)R.z[u] : pk;
+    } else {
+      return (double)R.p[u];
+    }
+  };
+  auto stage_op = [&](const Raw& R, int buf) {
+    su[buf][tid] = cook(R, 0);
+    if (p1) su[buf][tid + kBlock] = cook(R, 1);
+  };
+  auto stage_cells = [&](const Raw& R, int buf) {
+    sa[buf][tid] = R.a[0];
+    if (a1) sa[buf][tid + kBlock] = R.a[1];
+  };
+  auto read_plane = [&](int buf, double (&u)[3][3]) {
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int x = 0; x < 3; ++x) u[y][x] = su[buf][(w + y) * CW + lane + x];
+  };
+  auto read_cells = [&](int buf, double (&c)[2][2]) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) c[y][x] = sa[buf][(w + y) * AC + lane + x];
   };
 
   double u[3][3][3];    // operand [plane i-1, i, i+1][row j-1, j, j+1][col k-1, k, k+1]
   double ac[2][2][2];   // cells [plane i-1, i][row j-1, j][col k-1, k]
-  load_plane(wrap_dec(tl.i0, n), u[0]);
-  load_plane(tl.i0, u[1]);
-  load_cells(wrap_dec(tl.i0, n), ac[0]);
+  // LDS buffer b is rewritten only after every thread has passed the barrier
+  // that follows its last read of b (the barrier of the next step)
+  Raw R;
+  load_op(wrap_dec(tl.i0, n), R);
+  load_cells(wrap_dec(tl.i0, n), R);
+  stage_op(R, 0);
+  stage_cells(R, 0);
+  load_op(tl.i0, R);
+  __syncthreads();
+  read_plane(0, u[0]);
+  read_cells(0, ac[0]);
+  stage_op(R, 1);
+  load_op(wrap_inc(tl.i0, n), R);
+  load_cells(tl.i0, R);
+  __syncthreads();
+  read_plane(1, u[1]);
   double d = 0.0;
   for (int t = 0; t < kStrip3; ++t) {
-    const int i = tl.i0 + t;
-    load_plane(wrap_inc(i, n), u[2]);
-    load_cells(i, ac[1]);
+    const int i = tl.i0 + t, buf = t & 1;
+    stage_op(R, buf);   // operand plane i + 1
+    stage_cells(R, buf);   // cell plane i
+    if (t + 1 < kStrip3) {
+      load_op(wrap_inc(i + 1, n), R);
+      load_cells(i + 1, R);
+    }
+    __syncthreads();
+    read_plane(buf, u[2]);
+    read_cells(buf, ac[1]);
     const double c = u[1][1][1];
     double qv = 0.0;
 #pragma unroll
@@ -267,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil3(const double* __restrict__ 
           qv += ac[x][y][zz] * (4.0 * c - ((u[ix][iy][1] + u[ix][1][iz]) + (u[1][iy][iz] + u[ix][iy][iz])));
         }
     qv *= kTwelfth;
-    const long long o = (long long)s * N3 + (long long)i * NN + row[1] + k;
+    const long long o = (long long)s * N3 + (long long)i * NN + (long long)tl.j * n + tl.k;
     q[o] = qv;
     if constexpr (FUSED) {
       p_new[o] = (PT)c;
