@@ -277,6 +277,26 @@ def main():
                                             args.fp64_steps, ctx, timing=True)
     v64 = args.fp64_steps * B / t64
 
+    log("B = 64 and host-resident legs")
+    b64 = [x[:64].contiguous() for x in batches]
+    t_b64, _, _, _ = timed_steps(rve, torch, b64, h, mixed, G[:64].contiguous(), args.contrast, L, 1,
+                                 args.steps, ctx)
+    v_b64 = args.steps * 64 / t_b64
+    # inputs resident in pinned host memory: each step first copies its batch
+    # to the device (PCIe-inclusive rate; `value` keeps inputs in HBM)
+    pinned = [torch.from_numpy(x).pin_memory() for x in host]
+    a_buf = torch.empty_like(batches[0])
+    a_buf.copy_(pinned[0], non_blocking=True)
+    run_step(rve, a_buf, h, mixed, G, args.contrast, L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a_buf.copy_(pinned[k % len(pinned)], non_blocking=True)
+        run_step(rve, a_buf, h, mixed, G, args.contrast, L)
+    torch.cuda.synchronize()
+    v_h2d = args.steps * B / (time.perf_counter() - t0)
+    del pinned, a_buf, b64
+
     log("plain per-realization FP64 leg")
     single = batches[0][: args.plain]
     rve.solve_batch(single[0:1].contiguous(), h, fp64, want_phi=True, want_flux=True)
@@ -320,6 +340,9 @@ def main():
         "fp64_batched": {"value": v64, "ms_per_step": 1e3 * t64 / args.fp64_steps,
                          "iters_mean": float(it64.mean()), "gemm_TFLOPs": fp64_gemm_tfs},
         "plain_fp64_per_realization": {"value": v_plain, "realizations": args.plain},
+        "batch_64": {"value": v_b64, "ms_per_step": 1e3 * t_b64 / args.steps},
+        "host_inputs_pcie_inclusive": {"value": v_h2d, "note": "each step copies its batch from pinned host "
+                                                               "memory to the device inside the timed region"},
         "speedup_vs_plain_fp64": value / v_plain,
         "speedup_vs_fp64_batched": value / v64,
         "roofline": roof,
@@ -395,11 +418,61 @@ def survey(rve, torch, dev):
     # 16 realizations at L = 128, h = 1/16 (n = 2048)
     a = fields(128, 16, 10.0, 16, 14)
     r64 = rve.solve_batch(a, 1 / 16, rve.Options(prec=rve.FP64), want_phi=False)
+    ctx4 = rve.Context(0)
     for prec, pname in ((rve.MIX_BF16, "bf16"), (rve.MIX_FP32, "fp32"), (rve.FP64, "fp64")):
-        dt, r = timed(lambda: rve.solve_batch(a, 1 / 16, rve.Options(prec=prec), want_phi=False))
+        dt, r = timed(lambda: rve.solve_batch(a, 1 / 16, rve.Options(prec=prec), want_phi=False, ctx=ctx4))
+        # transform-GEMM utilisation from an event-timed solve: 2 n^3 flops per
+        # system and transform, four transforms per apply, iters applies per system
+        ctx4.set_timing(True)
+        rt = rve.solve_batch(a, 1 / 16, rve.Options(prec=prec), want_phi=False, ctx=ctx4)
+        torch.cuda.synchronize()
+        tim = ctx4.timing()
+        ctx4.set_timing(False)
+        gms = sum(tim[k][0] for k in ("gemm1", "gemm2", "gemm3", "gemm4"))
+        gfl = float(rt.iters.double().sum()) * 4 * 2.0 * 2048.0 ** 3
+        tfs = gfl / (gms * 1e-3) / 1e12
         emit("L=128 h=1/16 n=2048, 16 realizations", gemm=pname, ms=1e3 * dt, realizations_s=16 / dt,
-             iters_mean=float(r.iters.double().mean()), ahom_rel_dev_vs_fp64=dev_rel(r.ahom, r64.ahom))
+             iters_mean=float(r.iters.double().mean()), ahom_rel_dev_vs_fp64=dev_rel(r.ahom, r64.ahom),
+             gemm_TFLOPs=tfs, gemm_peak_frac=tfs / MFMA_PEAK_TFS[pname])
+    ctx4.close()
     del a, r64
+
+    # comparison point: the same preconditioner apply by real FFTs (the
+    # vendor FFT through torch, not part of the path), 512 systems of 512^2
+    # (the headline batch), against the transform GEMMs' event time per apply
+    a = fields(64, 8, 10.0, 256, 17)
+    ctxp = rve.Context(0)
+    rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.MIX_BF16), want_phi=False, ctx=ctxp)
+    ctxp.set_timing(True)
+    rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.MIX_BF16), want_phi=False, ctx=ctxp)
+    torch.cuda.synchronize()
+    tim = ctxp.timing()
+    ctxp.set_timing(False)
+    ctxp.close()
+    per_apply = sum(tim[k][0] for k in ("gemm1", "gemm2", "gemm3", "gemm4")) / max(tim["gemm1"][1], 1)
+    c = torch.cos(2 * torch.pi * torch.arange(512, dtype=torch.float64, device=dev) / 512)
+    E = (8 - 2 * c[:, None] - 2 * c[None, :] - 4 * c[:, None] * c[None, :]) / 3
+    inv = 1.0 / E
+    inv[0, 0] = 0.0
+    inv = inv[:, :257]
+    for dt_, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+        r = torch.randn((512, 512, 512), dtype=dt_, device=dev)
+        iv = inv.to(dt_)
+
+        def fft_apply():
+            return torch.fft.irfft2(torch.fft.rfft2(r) * iv, s=(512, 512))
+        fft_apply()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fft_apply()
+        e1.record()
+        torch.cuda.synchronize()
+        emit("comparison: preconditioner apply for 512 systems of 512^2 by real FFTs (vendor, via torch)",
+             fft_dtype=name, fft_ms=e0.elapsed_time(e1) / 5, hartley_bf16_gemms_ms=per_apply)
+        del r
+    del a
 
     # gradient at L = 64 for 64 realizations; quartic tensor over 4096 at L = 16
     a = fields(64, 8, 10.0, 64, 15)

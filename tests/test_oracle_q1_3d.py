@@ -237,3 +237,28 @@ def test_pcg_true_residual():
     x, it, rel = q3.pcg(A, f, 5.5, 1e-10, 500)
     assert rel < 2e-10 and 5 < it < 100
     assert isinstance(A, sp.csr_matrix)
+
+
+def test_matches_dense_pseudoinverse_solve():
+    # n = 4 (64 unknowns): the correctors against the dense pseudo-inverse
+    n = 4
+    a = field(n, 12)
+    A = q3.assemble(a).toarray()
+    f = q3.rhs(a)
+    Ap = np.linalg.pinv(A)
+    x, its = q3.correctors(a, tol=1e-13)
+    for i in range(3):
+        xd = Ap @ (f[i] - f[i].mean()).ravel()
+        xd -= xd.mean()
+        np.testing.assert_allclose(x[i].ravel(), xd, atol=1e-11)
+    E, _F = q3.ahom(a, x)
+    Ed, _ = q3.ahom(a, np.array([(Ap @ (f[i] - f[i].mean()).ravel()).reshape(n, n, n) for i in range(3)]))
+    np.testing.assert_allclose(E, Ed, rtol=1e-11)
+
+
+def test_homogeneity():
+    n = 4
+    a = field(n, 13)
+    E1, _, _, _ = q3.homogenize(a)
+    E2, _, _, _ = q3.homogenize(2.5 * a)
+    np.testing.assert_allclose(E2, 2.5 * E1, rtol=1e-11)
