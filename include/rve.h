@@ -69,7 +69,13 @@ enum rve_status {
 enum rve_precision {
   RVE_FP64 = 0,      /* FP64 MFMA, FP64 intermediates */
   RVE_MIX_FP32 = 1,  /* FP32 MFMA, FP32 intermediates */
-  RVE_MIX_BF16 = 2   /* BF16 MFMA operands, FP32 accumulation, BF16 intermediates */
+  RVE_MIX_BF16 = 2,  /* BF16 MFMA operands, FP32 accumulation, BF16 intermediates */
+  RVE_MIX_FP16 = 3   /* FP16 MFMA operands, FP32 accumulation, FP16 intermediates; the
+                        residual copy is scaled per system to 0.25 sqrt(N)/||r|| and the
+                        symbol's reciprocal stored as E_min/E, so every intermediate stays
+                        below the 2-norm of the scaled residual (in rve_apply_precond*,
+                        where no residual norm is at hand, the caller's r is used unscaled
+                        and must keep its 2-norm below about 6e4) */
 };
 
 /* Arithmetic of the operator apply inside PCG. With RVE_STENCIL_FP32 the

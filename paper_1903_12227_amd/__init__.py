@@ -11,7 +11,7 @@ All arithmetic runs in librve (hand-written HIP kernels for gfx950, C ABI in
 include/rve.h); this package only marshals torch tensors into it.
 """
 from ._native import (  # noqa: F401
-    FP64, MIX_FP32, MIX_BF16, STENCIL_FP64, STENCIL_FP32, SCHEME_Q1, SCHEME_FD5, DIRECTION_RING, LIB_PATH,
+    FP64, MIX_FP32, MIX_BF16, MIX_FP16, STENCIL_FP64, STENCIL_FP32, SCHEME_Q1, SCHEME_FD5, DIRECTION_RING, LIB_PATH,
     RveError,
 )
 from .api import (  # noqa: F401

@@ -14,7 +14,7 @@ DIRECTION_RING = 8
 # enum rve_status
 OK, NOT_CONVERGED, BREAKDOWN, EINVAL, EHIP, ENOMEM = 0, 1, 2, -1, -2, -3
 # enum rve_precision
-FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
+FP64, MIX_FP32, MIX_BF16, MIX_FP16 = 0, 1, 2, 3
 STENCIL_FP64, STENCIL_FP32 = 0, 1
 # enum rve_scheme
 SCHEME_Q1, SCHEME_FD5 = 0, 1

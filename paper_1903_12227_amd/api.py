@@ -14,14 +14,14 @@ from typing import Optional, Sequence
 import torch
 
 from . import _native as N
-from ._native import DIRECTION_RING, FP64, MIX_BF16, MIX_FP32  # noqa: F401
+from ._native import DIRECTION_RING, FP64, MIX_BF16, MIX_FP16, MIX_FP32  # noqa: F401
 
 
 @dataclass
 class Options:
     tol: float = 1e-10          # relative residual target ||r||/||f||
     maxit: int = 2000
-    prec: int = FP64            # FP64, MIX_FP32 or MIX_BF16 (preconditioner GEMMs)
+    prec: int = FP64            # FP64, MIX_FP32, MIX_BF16 or MIX_FP16 (preconditioner GEMMs)
     flexible: int = -1          # -1 automatic, 0 standard beta, 1 flexible beta
     check_every: int = 0        # convergence poll period (0 = library default)
     stencil_prec: int = 0       # 0 FP64 operator apply, 1 FP32 (with FP64 residual replacement)

@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs3(const double* __restrict__ a, d
 
 // Per realization (one wave): the coefficient statistics, a0, and the means
 // of the three raw right-hand sides.
-__global__ void k_scalar_init3(SysState* sys, RealState* real, const double* __restrict__ part, int P, int n) {
+__global__ void k_scalar_init3(SysState* sys, RealState* real, const double* __restrict__ part, int P, int n,
+                               int scaled) {
   const int b = blockIdx.x, lane = threadIdx.x;
   double f[3] = {0.0, 0.0, 0.0}, sa = 0.0, bad = 0.0, mn = 1.0e308, mx = -1.0e308;
   for (int t = lane; t < P; t += kWave) {
@@ -170,6 +171,8 @@ __global__ void k_scalar_init3(SysState* sys, RealState* real, const double* __r
     for (int d = 0; d < 3; ++d) {
       sys[3 * b + d].mean_f = f[d] / N3;
       sys[3 * b + d].valid = valid;
+      // scaled copies: |f - mean f| <= 2 (a_max - a_min)
+      if (scaled && mx > mn) sys[3 * b + d].lo_next = 0.25 / (mx - mn);
     }
   }
 }
@@ -503,7 +506,8 @@ void launch_rhs3(const Work& w, hipStream_t st) {
 }
 
 void launch_scalar_init3(const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar_init3, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, tiles3(w.n), w.n);
+  hipLaunchKernelGGL(k_scalar_init3, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, tiles3(w.n), w.n,
+                     (int)(w.mixed == 3));
 }
 
 void launch_stencil3_fused(const Work& w, hipStream_t st, int probe) {

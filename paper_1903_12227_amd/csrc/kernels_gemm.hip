@@ -44,6 +44,7 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 64, BN = 64;
 
@@ -85,13 +86,35 @@ struct TrBF16 {
   __device__ static int acc_row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// FP16 operands (16x16x32, FP32 accumulation; same lane layouts as BF16).
+// The FP16 path keeps every operand in range by scaling: the residual copy
+// is stored times a per-system factor sigma (0.25 sqrt(N) / ||r||, so its
+// 2-norm is about sqrt(N)/4), the symbol's reciprocal is stored as
+// E_min / E <= 1, and since the transforms are orthogonal no entry of any
+// intermediate exceeds the 2-norm of the scaled input; the last transform
+// multiplies by 1 / (sigma E_min a0).
+struct TrF16 {
+  using op_t = _Float16;
+  using acc_t = float;
+  using accv_t = v4f;
+  static constexpr int BK = 64, KM = 32, PAD = 8;
+  __device__ static accv_t mma(const op_t* a, const op_t* b, accv_t c) {
+    const v8h av = *reinterpret_cast<const v8h*>(a);
+    const v8h bv = *reinterpret_cast<const v8h*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+  }
+  __device__ static int acc_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
 template <class T> __device__ inline T cvt(double v);
 template <> __device__ inline double cvt<double>(double v) { return v; }
 template <> __device__ inline float cvt<float>(double v) { return (float)v; }
 template <> __device__ inline __bf16 cvt<__bf16>(double v) { return (__bf16)(float)v; }
+template <> __device__ inline _Float16 cvt<_Float16>(double v) { return (_Float16)(float)v; }
 template <class T> __device__ inline T cvtf(float v);
 template <> __device__ inline float cvtf<float>(float v) { return v; }
 template <> __device__ inline __bf16 cvtf<__bf16>(float v) { return (__bf16)v; }
+template <> __device__ inline _Float16 cvtf<_Float16>(float v) { return (_Float16)v; }
 
 enum Epi { kEpiStore = 0, kEpiEinv = 1, kEpiZ = 2 };
 
@@ -101,6 +124,22 @@ enum Epi { kEpiStore = 0, kEpiEinv = 1, kEpiZ = 2 };
 __device__ inline double widen(double v) { return v; }
 __device__ inline double widen(float v) { return (double)v; }
 __device__ inline double widen(__bf16 v) { return (double)(float)v; }
+__device__ inline double widen(_Float16 v) { return (double)(float)v; }
+
+// Epilogue factors of the scaled (FP16) path: the scaling transform skips
+// 1/a0, the last one multiplies z by 1 / (sigma E_min a0) and the r.z partial
+// sum (taken against the scaled residual copy) by 1 / sigma. Unscaled paths:
+// sigma = E_min = 1 and 1/a0 in the scaling transform, exactly as before.
+struct EpiScale {
+  double z = 1.0, dot = 1.0;
+  __device__ EpiScale(int scaled, const SysState* sys, const RealState* real, int s, int r, double emin) {
+    if (scaled) {
+      const double sig = sys ? sys[s].lo_scale : 1.0;
+      z = real[r].inv_a0 / (sig * emin);
+      dot = 1.0 / sig;
+    }
+  }
+};
 
 // Elements of one K-slice per thread: (BM x BK) / 256.
 template <class Tr> struct Stage {
@@ -114,7 +153,8 @@ template <class Tr, class InT, int EPI, class ZT = double, class RT = double, in
 __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, const typename Tr::op_t* __restrict__ Qm,
                                                      void* __restrict__ out_v, int n, int S, const SysState* sys,
                                                      const RealState* real, const void* __restrict__ einv_v,
-                                                     const RT* __restrict__ rres, double* __restrict__ part) {
+                                                     const RT* __restrict__ rres, double* __restrict__ part,
+                                                     int scaled, double emin) {
   static_assert(D == 2 || D == 3, "dimension");
   using op_t = typename Tr::op_t;
   using acc_t = typename Tr::acc_t;
@@ -220,7 +260,9 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   const long long obase = (long long)s * N2 + (long long)(nb * BN + orow) * R + mb * BM + oc0;
   double dot = 0.0;
   acc_t scale = (acc_t)1;
-  if constexpr (EPI == kEpiEinv) scale = (acc_t)real[D == 2 ? (s >> 1) : s / 3].inv_a0;
+  const int rz = D == 2 ? (s >> 1) : s / 3;
+  if constexpr (EPI == kEpiEinv) scale = scaled ? (acc_t)1 : (acc_t)real[rz].inv_a0;
+  EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, rz, emin);
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     acc_t v = Cs[orow * LDC + oc0 + e];
@@ -230,7 +272,7 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
     }
     if constexpr (EPI == kEpiZ) {
       ZT* out = reinterpret_cast<ZT*>(out_v);
-      const ZT zs = (ZT)v;
+      const ZT zs = scaled ? (ZT)((double)v * es.z) : (ZT)v;
       out[obase + e] = zs;
       dot += (double)zs * widen(rres[obase + e]);
     } else {
@@ -242,38 +284,50 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   if constexpr (EPI == kEpiZ) {
     double d[1] = {dot};
     block_sum<1>(d, red);
-    if (tid == 0) part[(long long)s * ((long long)MB * NB) + (long long)mb * NB + nb] = d[0];
+    if (tid == 0) part[(long long)s * ((long long)MB * NB) + (long long)mb * NB + nb] = scaled ? d[0] * es.dot : d[0];
   }
 }
 
-// Pure-BF16 transform GEMM with a 128 x 128 output tile (n % 128 == 0):
-// 2 x 2 waves of 64 x 64, i.e. 4 x 4 MFMA 16x16x32 blocks per wave, so each
-// operand fragment read from LDS feeds four MFMAs. Operand tiles (128 x 64
-// BF16, row stride 144 B: conflict-free 16-byte fragment reads) are loaded
-// with 16-byte global loads, the next K slice prefetched into registers.
-// The transposed output goes through LDS in two halves of 64 rows.
+// 16-bit transform GEMM (BF16 or FP16 operands, FP32 accumulation) with a
+// 128 x 128 output tile (n % 128 == 0): 2 x 2 waves of 64 x 64, i.e. 4 x 4
+// MFMA 16x16x32 blocks per wave, so each operand fragment read from LDS
+// feeds four MFMAs. Operand tiles (128 x 64, row stride 144 B: conflict-free
+// 16-byte fragment reads) are loaded with 16-byte global loads, the next K
+// slice prefetched into registers. The transposed output goes through LDS
+// in two halves of 64 rows.
 constexpr int TM = 128, TN = 128, TK = 64, TLDA = TK + 8, TLDC = TM + 4;
 
-template <int EPI, class ZT, class RT = double>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_hartley_bf16(const __bf16* __restrict__ X, const __bf16* __restrict__ Qm,
+template <class T> struct H16;
+template <> struct H16<__bf16> {
+  typedef v8bf v8;
+  __device__ static v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct H16<_Float16> {
+  typedef v8h v8;
+  __device__ static v4f mma(v8h a, v8h b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+template <class T, int EPI, class ZT, class RT = double>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm,
                                                           void* __restrict__ out_v, int n, int S,
                                                           const SysState* sys, const RealState* real,
                                                           const float* __restrict__ einv,
                                                           const RT* __restrict__ rres,
-                                                          double* __restrict__ part) {
-  constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(__bf16);
+                                                          double* __restrict__ part, int scaled, double emin) {
+  typedef typename H16<T>::v8 v8t;
+  constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(T);
   constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
   static_assert(kCBytes <= kOpBytes, "staging must fit in the operand buffers");
   __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
   __shared__ double red[4];
-  __bf16* As = reinterpret_cast<__bf16*>(smem);
-  __bf16* Bs = As + TM * TLDA;
+  T* As = reinterpret_cast<T*>(smem);
+  T* Bs = As + TM * TLDA;
   float* Cs = reinterpret_cast<float*>(smem);
 
   const int NB = n / TN, MB = n / TM;
-  const long long T = (long long)S * MB * NB;
+  const long long NT = (long long)S * MB * NB;
   long long t = blockIdx.x;
-  if ((T & 7) == 0) t = (t & 7) * (T >> 3) + (t >> 3);   // XCD-contiguous tile ranges
+  if ((NT & 7) == 0) t = (t & 7) * (NT >> 3) + (t >> 3);   // XCD-contiguous tile ranges
   const int nb = (int)(t % NB);
   const long long rest = t / NB;
   const int mb = (int)(rest % MB);
@@ -281,8 +335,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   if (sys && !sys[s].active) return;
 
   const long long N2 = (long long)n * n;
-  const __bf16* Xs = X + (long long)s * N2 + (long long)mb * TM * n;
-  const __bf16* Qs = Qm + (long long)nb * TN * n;
+  const T* Xs = X + (long long)s * N2 + (long long)mb * TM * n;
+  const T* Qs = Qm + (long long)nb * TN * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int lr = tid >> 3, lc = (tid & 7) * 8;
@@ -290,8 +344,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   // register staging of the next K slice (kept out of lambdas so that it
   // stays in VGPRs)
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  const __bf16* xa = Xs + (long long)lr * n + lc;
-  const __bf16* qa = Qs + (long long)lr * n + lc;
+  const T* xa = Xs + (long long)lr * n + lc;
+  const T* qa = Qs + (long long)lr * n + lc;
   const long long r32 = 32LL * n;
 #define RVE_GLOAD(k0)                                                        \
   do {                                                                      \
@@ -333,15 +387,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
     if (more) RVE_GLOAD(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 32) {
-      v8bf bf[4];
+      v8t bf[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bf[j] = *reinterpret_cast<const v8bf*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
+        bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const v8bf af = *reinterpret_cast<const v8bf*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
+        const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
       }
     }
     __syncthreads();
@@ -354,7 +408,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 #undef RVE_SSTORE
 
   float scale = 1.f;
-  if constexpr (EPI == kEpiEinv) scale = (float)real[s >> 1].inv_a0;
+  if constexpr (EPI == kEpiEinv) scale = scaled ? 1.f : (float)real[s >> 1].inv_a0;
+  EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
   double dot = 0.0;
   const int orow = tid >> 2, oc0 = (tid & 3) * 32;
 #pragma unroll
@@ -389,18 +444,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
       ZT* out = reinterpret_cast<ZT*>(out_v) + obase;
 #pragma unroll
       for (int e = 0; e < 32; ++e) {
-        const ZT zs = (ZT)v[e];
+        const ZT zs = scaled ? (ZT)((double)v[e] * es.z) : (ZT)v[e];
         out[e] = zs;
         dot += (double)zs * widen(rres[obase + e]);
       }
     } else {
-      __bf16* out = reinterpret_cast<__bf16*>(out_v) + obase;
+      T* out = reinterpret_cast<T*>(out_v) + obase;
 #pragma unroll
       for (int e = 0; e < 32; e += 8) {
-        v8bf pk;
+        v8t pk;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pk[k] = (__bf16)v[e + k];
-        *reinterpret_cast<v8bf*>(out + e) = pk;
+        for (int k = 0; k < 8; ++k) pk[k] = (T)v[e + k];
+        *reinterpret_cast<v8t*>(out + e) = pk;
       }
     }
     __syncthreads();
@@ -408,7 +463,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   if constexpr (EPI == kEpiZ) {
     double d[1] = {dot};
     block_sum<1>(d, red);
-    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = d[0];
+    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = scaled ? d[0] * es.dot : d[0];
   }
 }
 
@@ -427,7 +482,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 // Tile: 128 rows r x 128 columns k < h, two accumulator sets (C and S) per
 // wave, operand tiles Xe, Xo, c, s of 128 x 32 BF16 in LDS; the epilogue
 // writes output rows k and n - k through LDS, transposed as in
-// k_hartley_bf16.
+// k_hartley_h16.
 constexpr int SK = 32, SLDA = SK + 8;   // K slice and operand row stride of the folded kernel
 
 template <int EPI, class ZT, class RT = double>
@@ -682,9 +737,10 @@ k_hartley_bf16_sym(const __bf16* __restrict__ X, const __bf16* __restrict__ Ch, 
   }
 }
 
-bool big_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % TM == 0; }
+bool big_bf16_tiles(int n, int prec) { return (prec == kGemmBF16 || prec == kGemmF16) && n % TM == 0; }
 bool folded_bf16_tiles(int n, int prec) { return prec == kGemmBF16 && n % (2 * TN) == 0; }
 
+// The four (2D) transforms with the 64 x 64 kernel.
 template <class Tr, class ZT>
 void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   using op_t = typename Tr::op_t;
@@ -695,30 +751,32 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) 
   const void* einv = std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv64 : (const void*)t.einv32;
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
+  const int sc = t.scaled;
+  const double em = t.emin;
   // T1 = (R Q)^T, from the FP64 residual or from its GEMM-precision copy
   if (phase >= 0 && phase != 0) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, (const op_t*)w.rlo, Q, (void*)u1,
-                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S,
-                       w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   // W = (Q R Q) ./ (a0 E)
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                     w.real, einv, (const double*)nullptr, nullptr);
+                       w.real, einv, (const double*)nullptr, nullptr, sc, em);
   // T3 = (W Q)^T
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                     w.real, nullptr, (const double*)nullptr, nullptr);
+                       w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   // z = Q W Q, partial sums of r.z
   if (phase >= 0 && phase != 3) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz);
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, sc, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, w.r, w.part_rz);
+                       w.real, nullptr, w.r, w.part_rz, sc, em);
 }
 
 // Three dimensions: six transforms out = (X Q)^T of the n^2 x n views; the
@@ -734,55 +792,60 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
       std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv3_64 : (const void*)t.einv3_32;
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
+  const int sc = t.scaled;
+  const double em = t.emin;
   auto on = [&](int ph) { return phase < 0 || phase == ph; };
   if (!on(0)) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, (const op_t*)w.rlo,
-                       Q, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       Q, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore, double, double, 3>), grid, block, 0, st, w.r, Q, (void*)u1,
-                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (on(1))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (on(2))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, einv, (const double*)nullptr, nullptr);
+                       w.S, w.sys, w.real, einv, (const double*)nullptr, nullptr, sc, em);
   if (on(3))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (on(4))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (!on(5)) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz);
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, sc, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, w.r, w.part_rz);
+                       w.real, nullptr, w.r, w.part_rz, sc, em);
 }
 
-template <class ZT>
-void run_precond_bf16_big(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
+// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16).
+template <class T, class ZT>
+void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
-  const long long T = (long long)w.S * (n / TM) * (n / TN);
-  const dim3 grid((unsigned)T), block(kBlock);
-  const __bf16* Q = reinterpret_cast<const __bf16*>(t.q);
-  __bf16* u1 = reinterpret_cast<__bf16*>(w.u1);
-  __bf16* u2 = reinterpret_cast<__bf16*>(w.u2);
+  const long long NT = (long long)w.S * (n / TM) * (n / TN);
+  const dim3 grid((unsigned)NT), block(kBlock);
+  const T* Q = reinterpret_cast<const T*>(t.q);
+  T* u1 = reinterpret_cast<T*>(w.u1);
+  T* u2 = reinterpret_cast<T*>(w.u2);
+  const int sc = t.scaled;
+  const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, (const __bf16*)w.rlo, Q,
-                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_bf16<kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                       w.real, t.einv32, (const double*)nullptr, nullptr);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+                       w.real, t.einv32, (const double*)nullptr, nullptr, sc, em);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_bf16<kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                       w.real, nullptr, (const double*)nullptr, nullptr);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+                       w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_bf16<kEpiZ, ZT, __bf16>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const __bf16*)w.rlo, w.part_rz);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+                       nullptr, (const T*)w.rlo, w.part_rz, sc, em);
 }
 
 template <class ZT>
@@ -809,7 +872,7 @@ void run_precond_bf16_sym(const Work& w, const GemmTables& t, hipStream_t st, in
 }  // namespace
 
 size_t gemm_elem_size(int prec) {
-  return prec == kGemmF64 ? sizeof(double) : prec == kGemmF32 ? sizeof(float) : sizeof(__bf16);
+  return prec == kGemmF64 ? sizeof(double) : prec == kGemmF32 ? sizeof(float) : 2;
 }
 
 bool gemm_variant_valid(int n, int prec, int variant) {
@@ -833,16 +896,23 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond3<TrF64, double>(w, t, st, phase);
     else if (prec == kGemmF32)
       run_precond3<TrF32, float>(w, t, st, phase);
+    else if (prec == kGemmF16)
+      run_precond3<TrF16, float>(w, t, st, phase);
     else
       run_precond3<TrBF16, float>(w, t, st, phase);
   } else if (prec == kGemmF64) {
     run_precond<TrF64, double>(w, t, st, phase);
   } else if (prec == kGemmF32) {
     run_precond<TrF32, float>(w, t, st, phase);
+  } else if (prec == kGemmF16) {
+    if (w.gemm_variant == 1)
+      run_precond_h16<_Float16, float>(w, t, st, phase);
+    else
+      run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
     run_precond_bf16_sym<float>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
-    run_precond_bf16_big<float>(w, t, st, phase);
+    run_precond_h16<__bf16, float>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

@@ -51,11 +51,34 @@ template <> struct V4<__bf16> {
     *reinterpret_cast<Pack*>(p) = pk;
   }
 };
+template <> struct V4<_Float16> {
+  __device__ static void store(_Float16* p, const double (&v)[4]) {
+    struct alignas(8) Pack { _Float16 e[4]; } pk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pk.e[k] = (_Float16)(float)v[k];
+    *reinterpret_cast<Pack*>(p) = pk;
+  }
+};
+
+// The GEMM-precision residual copy, written times the system's scale (1
+// except with FP16 transforms).
+template <class LoT>
+__device__ inline void store_lo(LoT* p, const double (&v)[4], double sc) {
+  double w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = v[k] * sc;
+  V4<LoT>::store(p, w);
+}
 
 __global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int stride = gridDim.x * kBlock;
-  for (int i = t; i < S; i += stride) sys[i] = SysState{};
+  for (int i = t; i < S; i += stride) {
+    SysState z{};
+    z.lo_scale = 1.0;
+    z.lo_next = 1.0;
+    sys[i] = z;
+  }
   for (int i = t; i < B; i += stride) real[i] = RealState{};
 }
 
@@ -131,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(const double* __restrict__ a, do
 
 // Per realization: finish the RHS partials (one wave per realization).
 __global__ void k_scalar_init(SysState* sys, RealState* real, const double* __restrict__ part, int P,
-                              int n) {
+                              int n, int scaled) {
   const int b = blockIdx.x, lane = threadIdx.x;
   double s1 = 0, s2 = 0, sa = 0, bad = 0, mn = 1.0e308, mx = -1.0e308;
   for (int t = lane; t < P; t += kWave) {
@@ -164,6 +187,12 @@ __global__ void k_scalar_init(SysState* sys, RealState* real, const double* __re
     sys[2 * b + 1].mean_f = s2 / N2;
     sys[2 * b].valid = valid;
     sys[2 * b + 1].valid = valid;
+    // scaled copies: |f - mean f| <= 2 (a_max - a_min), so the first copy
+    // stays within +-1/2
+    if (scaled && mx > mn) {
+      sys[2 * b].lo_next = 0.25 / (mx - mn);
+      sys[2 * b + 1].lo_next = 0.25 / (mx - mn);
+    }
   }
 }
 
@@ -175,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_meansub(double* __restrict__ r, doub
                                                      double* __restrict__ part) {
   __shared__ double sh[4];
   const int s = blockIdx.y;
-  const double m = sys[s].mean_f;
+  const double m = sys[s].mean_f, sc = sys[s].lo_next;
   const long long off = (long long)s * N2;
   double acc[1] = {0.0};
   const double zero[4] = {0.0, 0.0, 0.0, 0.0};
@@ -190,13 +219,14 @@ __global__ void __launch_bounds__(kBlock) k_meansub(double* __restrict__ r, doub
     }
     V4<double>::store(r + off + i, v);
     V4<double>::store(x + off + i, zero);
-    if constexpr (LO) V4<LoT>::store(rlo + off + i, v);
+    if constexpr (LO) store_lo<LoT>(rlo + off + i, v, sc);
   }
   block_sum<1>(acc, sh);
   if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = acc[0];
 }
 
-__global__ void k_scalar_fnorm(SysState* sys, const double* __restrict__ part, int P) {
+__global__ void k_scalar_fnorm(SysState* sys, const double* __restrict__ part, int P, int scaled,
+                               double sqrt_n) {
   const int s = blockIdx.x, lane = threadIdx.x;
   double v = 0;
   for (int t = lane; t < P; t += kWave) v += part[(long long)s * P + t];
@@ -206,6 +236,10 @@ __global__ void k_scalar_fnorm(SysState* sys, const double* __restrict__ part, i
     S.fnorm = sqrt(v);
     S.iters = 0;
     S.relres = 0.0;
+    // the copy just written carries lo_next; the next one is scaled to the
+    // norm of this residual
+    S.lo_scale = S.lo_next;
+    if (scaled && S.fnorm > 0.0 && isfinite(S.fnorm)) S.lo_next = 0.25 * sqrt_n / S.fnorm;
     if (!S.valid) {
       S.active = 0;
       S.status = -1;   // RVE_EINVAL
@@ -542,7 +576,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
   __shared__ double sh[4 * 2];
   const int s = blockIdx.y;
   if (!sys[s].active) return;
-  const double al = sys[s].alpha;
+  const double al = sys[s].alpha, sc = sys[s].lo_next;
   const long long off = (long long)s * N2;
   double acc[2] = {0.0, 0.0};
   const long long stride = (long long)gridDim.x * kBlock * 4;
@@ -556,7 +590,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
       acc[0] += rv[k] * rv[k];
     }
     V4<double>::store(r + off + i, rv);
-    if constexpr (LO) V4<LoT>::store(rlo + off + i, rv);
+    if constexpr (LO) store_lo<LoT>(rlo + off + i, rv, sc);
     if (flexible) {
       double zv[4];
       V4<ZT>::load(z + off + i, zv);
@@ -619,7 +653,7 @@ __global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const
 }
 
 __global__ void k_scalar_conv(SysState* sys, const double* __restrict__ part, int P, double tol, int maxit,
-                              int* count, const int* kiter) {
+                              int* count, const int* kiter, int scaled, double sqrt_n) {
   // one wave per system; blockDim = 64
   const int s = blockIdx.x, lane = threadIdx.x;
   if (!sys[s].active) return;
@@ -631,6 +665,10 @@ __global__ void k_scalar_conv(SysState* sys, const double* __restrict__ part, in
     SysState& S0 = sys[s];
     S0.iters += 1;
     S0.relres = sqrt(v) / S0.fnorm;
+    // the residual copy written this iteration carries lo_next; scale the
+    // next one to this residual's norm
+    S0.lo_scale = S0.lo_next;
+    if (scaled && v > 0.0 && isfinite(v)) S0.lo_next = 0.25 * sqrt_n / sqrt(v);
     if (S0.relres <= tol) {
       S0.active = 0;
       S0.status = 0;
@@ -964,7 +1002,8 @@ void launch_rhs(const Work& w, hipStream_t st) {
 
 void launch_scalar_init(const Work& w, hipStream_t st) {
   if (w.dim == 3) return launch_scalar_init3(w, st);
-  hipLaunchKernelGGL(k_scalar_init, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, w.P_tile, w.n);
+  hipLaunchKernelGGL(k_scalar_init, dim3(w.B), dim3(kWave), 0, st, w.sys, w.real, w.part_misc, w.P_tile, w.n,
+                     (int)(w.mixed == 3));
 }
 
 void launch_meansub(const Work& w, hipStream_t st) {
@@ -975,13 +1014,17 @@ void launch_meansub(const Work& w, hipStream_t st) {
   else if (w.mixed == 1)
     hipLaunchKernelGGL((k_meansub<float, true>), g, blk, 0, st, w.r, w.x, (float*)w.rlo, w.sys, w.N2,
                        w.part_rr);
+  else if (w.mixed == 3)
+    hipLaunchKernelGGL((k_meansub<_Float16, true>), g, blk, 0, st, w.r, w.x, (_Float16*)w.rlo, w.sys, w.N2,
+                       w.part_rr);
   else
     hipLaunchKernelGGL((k_meansub<__bf16, true>), g, blk, 0, st, w.r, w.x, (__bf16*)w.rlo, w.sys, w.N2,
                        w.part_rr);
 }
 
 void launch_scalar_fnorm(const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar_fnorm, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec);
+  hipLaunchKernelGGL(k_scalar_fnorm, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec,
+                     (int)(w.mixed == 3), sqrt((double)w.N2));
 }
 
 
@@ -1062,6 +1105,9 @@ void launch_update_r_q(const Work& w, int flexible, hipStream_t st) {
   else if (w.mixed == 1)
     hipLaunchKernelGGL((k_update_r<float, float, true, QT>), g, blk, 0, st, w.r, q, (const float*)w.z,
                        (float*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
+  else if (w.mixed == 3)
+    hipLaunchKernelGGL((k_update_r<float, _Float16, true, QT>), g, blk, 0, st, w.r, q, (const float*)w.z,
+                       (_Float16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
   else
     hipLaunchKernelGGL((k_update_r<float, __bf16, true, QT>), g, blk, 0, st, w.r, q, (const float*)w.z,
                        (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
@@ -1083,6 +1129,7 @@ __global__ void __launch_bounds__(kBlock) k_replace_r(double* __restrict__ r, co
                                                        const SysState* sys, long long N2) {
   const int s = blockIdx.y;
   if (!sys[s].active) return;
+  const double sc = sys[s].lo_next;
   const long long off = (long long)s * N2;
   const long long stride = (long long)gridDim.x * kBlock * 4;
   for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
@@ -1092,7 +1139,7 @@ __global__ void __launch_bounds__(kBlock) k_replace_r(double* __restrict__ r, co
 #pragma unroll
     for (int k = 0; k < 4; ++k) fv[k] -= qv[k];
     V4<double>::store(r + off + i, fv);
-    if constexpr (LO) V4<LoT>::store(rlo + off + i, fv);
+    if constexpr (LO) store_lo<LoT>(rlo + off + i, fv, sc);
   }
 }
 
@@ -1106,6 +1153,9 @@ void launch_replace_r(const Work& w, hipStream_t st) {
   else if (w.mixed == 1)
     hipLaunchKernelGGL((k_replace_r<float, true>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
                        (float*)w.rlo, w.sys, w.N2);
+  else if (w.mixed == 3)
+    hipLaunchKernelGGL((k_replace_r<_Float16, true>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
+                       (_Float16*)w.rlo, w.sys, w.N2);
   else
     hipLaunchKernelGGL((k_replace_r<__bf16, true>), g, blk, 0, st, w.r, (const double*)w.f, (const double*)w.q,
                        (__bf16*)w.rlo, w.sys, w.N2);
@@ -1157,7 +1207,7 @@ void launch_scalar_alpha(const Work& w, hipStream_t st) {
 
 void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec, tol, maxit,
-                     w.count, (const int*)w.kiter);
+                     w.count, (const int*)w.kiter, (int)(w.mixed == 3), sqrt((double)w.N2));
 }
 
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) {
@@ -1171,6 +1221,9 @@ void launch_round_lo(const Work& w, hipStream_t st) {
   if (nb > 4096) nb = 4096;
   if (w.mixed == 1)
     hipLaunchKernelGGL((k_round_lo<float>), dim3((unsigned)nb), dim3(kBlock), 0, st, w.r, (float*)w.rlo, total);
+  else if (w.mixed == 3)
+    hipLaunchKernelGGL((k_round_lo<_Float16>), dim3((unsigned)nb), dim3(kBlock), 0, st, w.r, (_Float16*)w.rlo,
+                       total);
   else if (w.mixed == 2)
     hipLaunchKernelGGL((k_round_lo<__bf16>), dim3((unsigned)nb), dim3(kBlock), 0, st, w.r, (__bf16*)w.rlo,
                        total);

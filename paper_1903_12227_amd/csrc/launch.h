@@ -34,7 +34,7 @@ struct Work {
   void* rlo = nullptr;       // mixed modes: r rounded to the GEMM type, the first GEMM's input
   void* u1 = nullptr;        // transform intermediates, [S][n][n] of the GEMM type
   void* u2 = nullptr;
-  int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs
+  int mixed = 0;             // 0: FP64 GEMMs; 1: FP32 GEMMs; 2: BF16 GEMMs; 3: FP16 GEMMs (scaled)
   // FP32 operator apply: a32 holds the coefficients in FP32, q is FP32, and
   // f (the mean-free right-hand sides) serves the periodic r = f - A x
   int sprec = 0;
@@ -151,7 +151,7 @@ void launch_dos_eval(int B, int nv, int K, const double* mu, double lmax, double
                      const double* t, double* S, double* phi, hipStream_t st);
 
 // Transform GEMMs of the preconditioner (kernels_gemm.hip).
-enum GemmPrec { kGemmF64 = 0, kGemmF32 = 1, kGemmBF16 = 2 };
+enum GemmPrec { kGemmF64 = 0, kGemmF32 = 1, kGemmBF16 = 2, kGemmF16 = 3 };
 struct GemmTables {
   const void* q = nullptr;        // [n][n] Hartley matrix in the GEMM operand type
   const double* einv64 = nullptr; // [n][n] 1/E, (0,0) entry 0
@@ -160,6 +160,10 @@ struct GemmTables {
   const __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t/n)/sqrt(n), BF16
   const double* einv3_64 = nullptr;  // [n][n][n] 1/E of the 3D operator (w.dim == 3), (0,0,0) entry 0
   const float* einv3_32 = nullptr;
+  // FP16 transforms: the residual copy is scaled per system (SysState::lo_scale),
+  // einv32 / einv3_32 hold E_min / E and the last transform unscales
+  int scaled = 0;
+  double emin = 1.0;
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.

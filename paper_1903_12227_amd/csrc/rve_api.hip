@@ -46,6 +46,12 @@ struct Tables {
   __bf16* sh16 = nullptr;   // [n/2][n/2] sin(2 pi k t / n)/sqrt(n)
   double* einv3_64 = nullptr;   // [n][n][n] 1/E of the 3D operator, built on first use
   float* einv3_32 = nullptr;
+  // FP16 transforms: Q in FP16 and E_min / E (entries <= 1) per scheme
+  _Float16* qh = nullptr;
+  float* einvh = nullptr;
+  float* einvh_fd = nullptr;
+  float* einv3h = nullptr;
+  double emin = 1.0, emin_fd = 1.0, emin3 = 1.0;
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
@@ -166,7 +172,30 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
       ch[(size_t)k * h + j] = (__bf16)(float)(std::cos(ang) * inv_sqrt);
       sh[(size_t)k * h + j] = (__bf16)(float)(std::sin(ang) * inv_sqrt);
     }
+  // FP16: Q rounded to FP16, and 1/E scaled by the smallest nonzero E
+  std::vector<_Float16> qh(N2);
+  for (size_t i = 0; i < N2; ++i) qh[i] = (_Float16)(float)q[i];
+  double emin = 1e300, emin_fd = 1e300;
+  for (size_t i = 1; i < N2; ++i) {
+    emin = std::min(emin, 1.0 / einv[i]);
+    emin_fd = std::min(emin_fd, 1.0 / einvf[i]);
+  }
+  std::vector<float> einvh(N2), einvh_fd(N2);
+  for (size_t i = 0; i < N2; ++i) {
+    einvh[i] = (float)(einv[i] * emin);
+    einvh_fd[i] = (float)(einvf[i] * emin_fd);
+  }
   Tables t;
+  t.emin = emin;
+  t.emin_fd = emin_fd;
+  if (hipMalloc(&t.qh, N2 * 2) != hipSuccess || hipMalloc(&t.einvh, N2 * 4) != hipSuccess ||
+      hipMalloc(&t.einvh_fd, N2 * 4) != hipSuccess) {
+    ignore(hipFree(t.qh)); ignore(hipFree(t.einvh)); ignore(hipFree(t.einvh_fd));
+    return RVE_ENOMEM;
+  }
+  HIP_TRY(hipMemcpy(t.qh, qh.data(), N2 * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einvh, einvh.data(), N2 * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t.einvh_fd, einvh_fd.data(), N2 * 4, hipMemcpyHostToDevice));
   if (hipMalloc(&t.q64, N2 * 8) != hipSuccess || hipMalloc(&t.q32, N2 * 4) != hipSuccess ||
       hipMalloc(&t.q16, N2 * 2) != hipSuccess || hipMalloc(&t.einv64, N2 * 8) != hipSuccess ||
       hipMalloc(&t.einv32, N2 * 4) != hipSuccess || hipMalloc(&t.ch16, H2 * 2) != hipSuccess ||
@@ -217,19 +246,57 @@ int build_tables3(rve_ctx* ctx, int n, Tables** out) {
         e64[o] = inv;
         e32[o] = (float)inv;
       }
+  double emin3 = 1e300;
+  for (size_t i = 1; i < N3; ++i) emin3 = std::min(emin3, 1.0 / e64[i]);
+  std::vector<float> eh(N3);
+  for (size_t i = 0; i < N3; ++i) eh[i] = (float)(e64[i] * emin3);
   double* d64 = nullptr;
   float* d32 = nullptr;
-  if (hipMalloc(&d64, N3 * 8) != hipSuccess || hipMalloc(&d32, N3 * 4) != hipSuccess) {
+  float* dh = nullptr;
+  if (hipMalloc(&d64, N3 * 8) != hipSuccess || hipMalloc(&d32, N3 * 4) != hipSuccess ||
+      hipMalloc(&dh, N3 * 4) != hipSuccess) {
     ignore(hipFree(d64));
     ignore(hipFree(d32));
+    ignore(hipFree(dh));
     (void)hipGetLastError();
     return RVE_ENOMEM;
   }
   HIP_TRY(hipMemcpy(d64, e64.data(), N3 * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d32, e32.data(), N3 * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dh, eh.data(), N3 * 4, hipMemcpyHostToDevice));
   t->einv3_64 = d64;
   t->einv3_32 = d32;
+  t->einv3h = dh;
+  t->emin3 = emin3;
   return RVE_OK;
+}
+
+// The transform-GEMM type of an rve_precision.
+int gemm_prec(int prec) {
+  return prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : prec == RVE_MIX_FP16 ? kGemmF16 : kGemmBF16;
+}
+
+// The tables one precision, scheme and dimension use.
+GemmTables gemm_tables(const Tables* tb, int prec, int scheme) {
+  GemmTables g;
+  const bool fd = scheme == RVE_SCHEME_FD5;
+  g.einv64 = fd ? tb->einv64_fd : tb->einv64;
+  g.einv3_64 = tb->einv3_64;
+  g.ch16 = tb->ch16;
+  g.sh16 = tb->sh16;
+  if (prec == RVE_MIX_FP16) {
+    g.q = tb->qh;
+    g.einv32 = fd ? tb->einvh_fd : tb->einvh;
+    g.einv3_32 = tb->einv3h;
+    g.scaled = 1;
+    g.emin = fd ? tb->emin_fd : tb->emin;
+  } else {
+    g.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
+                                                                         : (const void*)tb->q16;
+    g.einv32 = fd ? tb->einv32_fd : tb->einv32;
+    g.einv3_32 = tb->einv3_32;
+  }
+  return g;
 }
 
 // Workspace: a control block shared by every batch of a solve (iteration
@@ -251,7 +318,7 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   if (vb > 256) vb = 256;
   if (vb < 1) vb = 1;
   const int P_vec = (int)vb;
-  const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  const int gp = gemm_prec(prec);
   const int gv = dim == 2 && gemm_variant_valid(n, gp, 1) ? 1 : 0;
   const int P_gemm = dim == 3 ? gemm_tiles_per_system3(n) : gemm_tiles_per_system(n, gp, gv);
   const int misc_nv = dim == 3 ? kMiscNV3 : kMiscNV;
@@ -292,7 +359,7 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   w->P_st = P_st;
   w->P_vec = P_vec;
   w->P_gemm = P_gemm;
-  w->mixed = gp == kGemmF64 ? 0 : gp == kGemmF32 ? 1 : 2;
+  w->mixed = gp;   // GemmPrec: 0 FP64, 1 FP32, 2 BF16, 3 FP16
   w->stencil = sc;
   w->m_ring = kRing;
   w->sprec = sprec;
@@ -351,7 +418,7 @@ int check_opts(const rve_opts* o) {
   if (!o) return RVE_EINVAL;
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RVE_EINVAL;
   if (o->maxit < 1 || o->maxit > 1000000) return RVE_EINVAL;
-  if (o->prec < RVE_FP64 || o->prec > RVE_MIX_BF16) return RVE_EINVAL;
+  if (o->prec < RVE_FP64 || o->prec > RVE_MIX_FP16) return RVE_EINVAL;
   if (o->stencil_prec != RVE_STENCIL_FP64 && o->stencil_prec != RVE_STENCIL_FP32) return RVE_EINVAL;
   if (o->scheme != RVE_SCHEME_Q1 && o->scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   if (o->scheme == RVE_SCHEME_FD5 && o->stencil_prec != RVE_STENCIL_FP64) return RVE_EINVAL;
@@ -587,7 +654,7 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
 // statuses, batch after batch.
 int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts* o,
                   std::vector<int>* status_host) {
-  const int prec = o->prec == RVE_FP64 ? kGemmF64 : o->prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  const int prec = gemm_prec(o->prec);
   // automatic: standard beta (the flexible form gave the same iteration counts
   // with the BF16/FP32 transforms at contrast 10 and 100)
   const int flexible = o->flexible < 0 ? 0 : (o->flexible != 0);
@@ -621,14 +688,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     Tables* tb = nullptr;
     rc = b.dim == 3 ? build_tables3(ctx, b.n, &tb) : build_tables(ctx, b.n, &tb);
     if (rc) return rc;
-    b.gt.einv3_64 = tb->einv3_64;
-    b.gt.einv3_32 = tb->einv3_32;
-    b.gt.q = o->prec == RVE_FP64 ? (const void*)tb->q64 : o->prec == RVE_MIX_FP32 ? (const void*)tb->q32
-                                                                                  : (const void*)tb->q16;
-    b.gt.einv64 = o->scheme == RVE_SCHEME_FD5 ? tb->einv64_fd : tb->einv64;
-    b.gt.einv32 = o->scheme == RVE_SCHEME_FD5 ? tb->einv32_fd : tb->einv32;
-    b.gt.ch16 = tb->ch16;
-    b.gt.sh16 = tb->sh16;
+    b.gt = gemm_tables(tb, o->prec, o->scheme);
     b.prec = prec;
   }
 
@@ -841,6 +901,10 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.sh16));
     ignore(hipFree(kv.second.einv3_64));
     ignore(hipFree(kv.second.einv3_32));
+    ignore(hipFree(kv.second.einv3h));
+    ignore(hipFree(kv.second.qh));
+    ignore(hipFree(kv.second.einvh));
+    ignore(hipFree(kv.second.einvh_fd));
   }
   clear_graphs(c);
   if (c->ws) ignore(hipFree(c->ws));
@@ -923,7 +987,7 @@ int rve_apply_precond_3d(rve_ctx* c, int B, int n, const double* a_dev, const do
                          int prec) {
   if (!c || B < 1 || !n_supported3(n) || !fits3(B, n) || !a_dev || !r_dev || !z_dev || r_dev == z_dev)
     return RVE_EINVAL;
-  if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
+  if (prec < RVE_FP64 || prec > RVE_MIX_FP16) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
   const Layout L = plan(B, n, prec, 0, RVE_SCHEME_Q1, 3, &w);
@@ -938,17 +1002,13 @@ int rve_apply_precond_3d(rve_ctx* c, int B, int n, const double* a_dev, const do
   launch_init_state(w, c->stream);
   launch_rhs(w, c->stream);
   launch_scalar_init(w, c->stream);
-  GemmTables gt;
-  gt.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
-                                                                         : (const void*)tb->q16;
-  gt.einv3_64 = tb->einv3_64;
-  gt.einv3_32 = tb->einv3_32;
+  const GemmTables gt = gemm_tables(tb, prec, RVE_SCHEME_Q1);
   w.r = const_cast<double*>(r_dev);
   w.sys = nullptr;
   if (w.mixed) launch_round_lo(w, c->stream);
   void* z_solver = w.z;
   w.z = w.mixed ? z_solver : (void*)z_dev;
-  launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
+  launch_precond(w, gemm_prec(prec), gt, c->stream);
   if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
@@ -1082,7 +1142,7 @@ int rve_apply_operator(rve_ctx* c, int B, int n, const double* a_dev, const doub
 int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const double* r_dev, double* z_dev,
                       int prec, int scheme) {
   if (!c || B < 1 || !n_supported(n) || !a_dev || !r_dev || !z_dev || r_dev == z_dev) return RVE_EINVAL;
-  if (prec < RVE_FP64 || prec > RVE_MIX_BF16) return RVE_EINVAL;
+  if (prec < RVE_FP64 || prec > RVE_MIX_FP16) return RVE_EINVAL;
   if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   Work w;
@@ -1098,17 +1158,11 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   launch_init_state(w, c->stream);
   launch_rhs(w, c->stream);
   launch_scalar_init(w, c->stream);
-  GemmTables gt;
-  gt.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
-                                                                         : (const void*)tb->q16;
-  gt.einv64 = scheme == RVE_SCHEME_FD5 ? tb->einv64_fd : tb->einv64;
-  gt.einv32 = scheme == RVE_SCHEME_FD5 ? tb->einv32_fd : tb->einv32;
-  gt.ch16 = tb->ch16;
-  gt.sh16 = tb->sh16;
+  const GemmTables gt = gemm_tables(tb, prec, scheme);
   w.r = const_cast<double*>(r_dev);
   w.sys = nullptr;
   if (w.mixed) launch_round_lo(w, c->stream);
-  const int gp = prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16;
+  const int gp = gemm_prec(prec);
   if (c->force_gemm >= 0 && gemm_variant_valid(n, gp, c->force_gemm)) {
     w.gemm_variant = c->force_gemm;
     w.P_gemm = gemm_tiles_per_system(n, gp, w.gemm_variant);
@@ -1116,7 +1170,7 @@ int rve_apply_precond(rve_ctx* c, int B, int n, const double* a_dev, const doubl
   // the solver keeps z in FP32 in the mixed modes; the caller wants FP64
   void* z_solver = w.z;
   w.z = w.mixed ? z_solver : (void*)z_dev;
-  launch_precond(w, prec == RVE_FP64 ? kGemmF64 : prec == RVE_MIX_FP32 ? kGemmF32 : kGemmBF16, gt, c->stream);
+  launch_precond(w, gp, gt, c->stream);
   if (w.mixed) launch_widen(static_cast<const float*>(w.z), z_dev, (long long)w.S * w.N2, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;

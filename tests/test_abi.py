@@ -104,6 +104,9 @@ def test_host_argument_validation(lib):
     bad = N.RveOpts(1e-10, 10, 0, -1, 0, 2)
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
+    bad = N.RveOpts(1e-10, 10, 4, -1, 0)
+    assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
+                               None, None) == N.EINVAL
     bad = N.RveOpts(1e-10, 10, 7, -1, 0)
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
@@ -134,7 +137,7 @@ def test_header_constants_match_binding():
     for name, val in (("RVE_OK", N.OK), ("RVE_NOT_CONVERGED", N.NOT_CONVERGED), ("RVE_BREAKDOWN", N.BREAKDOWN),
                       ("RVE_EINVAL", N.EINVAL), ("RVE_EHIP", N.EHIP), ("RVE_ENOMEM", N.ENOMEM),
                       ("RVE_FP64", N.FP64), ("RVE_MIX_FP32", N.MIX_FP32), ("RVE_MIX_BF16", N.MIX_BF16),
-                      ("RVE_STENCIL_FP64", N.STENCIL_FP64), ("RVE_STENCIL_FP32", N.STENCIL_FP32),
+                      ("RVE_MIX_FP16", N.MIX_FP16), ("RVE_STENCIL_FP64", N.STENCIL_FP64), ("RVE_STENCIL_FP32", N.STENCIL_FP32),
                       ("RVE_SCHEME_Q1", N.SCHEME_Q1), ("RVE_SCHEME_FD5", N.SCHEME_FD5)):
         m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
         assert m and int(m.group(1)) == val, name

@@ -49,7 +49,7 @@ def test_operator_matches_oracle_spmv(dev, n):
             assert np.max(np.abs(out[b, i] - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-2)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-2), (3, 3e-3)])
 @pytest.mark.parametrize("n", [64, 128])
 def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
     rve = _rve()
@@ -148,7 +148,7 @@ def test_constant_field_and_laminate(dev):
 
 
 @pytest.mark.parametrize("n", [128, 192])
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_mixed_precision_matches_oracle(dev, prec, n):
     rve = _rve()
     B = 3
@@ -160,7 +160,7 @@ def test_mixed_precision_matches_oracle(dev, prec, n):
         assert rel2(A[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-8
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_true_residual_meets_tolerance(dev, prec):
     # The stopping test reads the recursively updated residual; it must stay
     # the true residual f - A x (to FP64 rounding) in every precision, since
@@ -180,7 +180,7 @@ def test_true_residual_meets_tolerance(dev, prec):
             assert true <= 2.0 * tol, (b, i, true)
 
 
-@pytest.mark.parametrize("prec", [0, 2])
+@pytest.mark.parametrize("prec", [0, 2, 3])
 def test_fp32_stencil_matches_oracle(dev, prec):
     # FP32 operator apply with FP64 partial sums and the residual recomputed
     # as f - A x every 8 iterations: A_hom to the mixed-precision bound and
@@ -418,3 +418,40 @@ def test_autotuner_choices_and_cache(dev, tmp_path, monkeypatch):
     assert len(lines) == 2 and all(line.startswith('{"kind"') for line in lines)
     reload_ctx = rve.Context(0)          # reads the cache at creation
     assert reload_ctx.tuned(n, 2, B) == ch
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
+    # FP16 transforms in both tile variants against the FFT apply, and a
+    # solve at contrast 100 where the scaled FP16 copies take fewer
+    # iterations than BF16 (and no more than a few beyond FP64)
+    rve = _rve()
+    rng = np.random.default_rng(n + 33)
+    a = _fields(n, 2, 54)
+    r = rng.standard_normal((2, 2, n, n))
+    r -= r.mean(axis=(2, 3), keepdims=True)
+    E = q1.symbol(n)
+    for variant in (0, 1):
+        ctx = rve.Context(0)
+        ctx.force_variants(gemm=variant)
+        z = rve.apply_precond(_to(a, dev), _to(r, dev), 3, ctx=ctx).cpu().numpy()
+        ctx.close()
+        for b in range(2):
+            a0 = oa.preconditioner_scale(a[b])
+            for i in range(2):
+                ref = precond_apply(r[b, i], a0, E)
+                zc = z[b, i] - z[b, i].mean()
+                assert np.linalg.norm(zc - ref) <= 3e-3 * np.linalg.norm(ref)
+    a = _fields(n, 2, 55, contrast=100.0)
+    its = {}
+    for prec in (0, 2, 3):
+        res = rve.solve_batch(_to(a, dev), 1.0 / 8, rve.Options(tol=1e-10, prec=prec), want_phi=False)
+        assert res.code == 0
+        its[prec] = res.iters.cpu().numpy().astype(float).mean()
+        if prec == 0:
+            A64 = res.ahom.cpu().numpy()
+        else:
+            A = res.ahom.cpu().numpy()
+            for b in range(2):
+                assert rel2(A[b], A64[b]) <= 1e-8
+    assert its[3] < its[2] and its[3] <= its[0] + 0.15 * its[0], its
