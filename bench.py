@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 
 METRIC = "RVE realizations/sec (2 corrector solves + A_hom) at L=64, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+MFMA_PEAK_TFS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 
 
 def log(msg):
@@ -277,6 +277,13 @@ def main():
                                             args.fp64_steps, ctx, timing=True)
     v64 = args.fp64_steps * B / t64
 
+    log("FP16-transform leg")
+    half = rve.Options(tol=args.tol, prec=rve.MIX_FP16)
+    t16, it16, _, codes16 = timed_steps(rve, torch, batches, h, half, G, args.contrast, L, 1, args.steps, ctx)
+    if max(codes16) != 0:
+        raise SystemExit(f"FP16 leg: non-converged or failed items (codes {codes16})")
+    v16 = args.steps * B / t16
+
     log("B = 64 and host-resident legs")
     b64 = [x[:64].contiguous() for x in batches]
     t_b64, _, _, _ = timed_steps(rve, torch, b64, h, mixed, G[:64].contiguous(), args.contrast, L, 1,
@@ -337,6 +344,8 @@ def main():
                    "precision": "mixed-bf16"},
         "iters_mean": float(it_mix.mean()),
         "tuned": ctx.tuned(n, rve.MIX_BF16, B),
+        "mixed_fp16_transforms": {"value": v16, "ms_per_step": 1e3 * t16 / args.steps,
+                                  "iters_mean": float(it16.mean())},
         "fp64_batched": {"value": v64, "ms_per_step": 1e3 * t64 / args.fp64_steps,
                          "iters_mean": float(it64.mean()), "gemm_TFLOPs": fp64_gemm_tfs},
         "plain_fp64_per_realization": {"value": v_plain, "realizations": args.plain},
@@ -405,7 +414,7 @@ def survey(rve, torch, dev):
     mix = uneven_batch([8, 16, 32, 64], m0=8, a_in=100.0, a_bg=1.0, config=3, per_size=256)
     ft = [torch.from_numpy(f).to(dev) for _, f in mix]
     ref = None
-    for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16")):
+    for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16")):
         for sprec, sname in ((0, "fp64"), (1, "fp32")):
             o = rve.Options(prec=prec, stencil_prec=sprec)
             dt, r = timed(lambda: rve.solve_uneven(ft, 1 / 8, o))
@@ -419,7 +428,7 @@ def survey(rve, torch, dev):
     a = fields(128, 16, 10.0, 16, 14)
     r64 = rve.solve_batch(a, 1 / 16, rve.Options(prec=rve.FP64), want_phi=False)
     ctx4 = rve.Context(0)
-    for prec, pname in ((rve.MIX_BF16, "bf16"), (rve.MIX_FP32, "fp32"), (rve.FP64, "fp64")):
+    for prec, pname in ((rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16"), (rve.MIX_FP32, "fp32"), (rve.FP64, "fp64")):
         dt, r = timed(lambda: rve.solve_batch(a, 1 / 16, rve.Options(prec=prec), want_phi=False, ctx=ctx4))
         # transform-GEMM utilisation from an event-timed solve: 2 n^3 flops per
         # system and transform, four transforms per apply, iters applies per system

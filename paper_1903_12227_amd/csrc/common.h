@@ -20,16 +20,16 @@ struct SysState {
   double relres;    // last recursive ||r||/||f||
   double mean_f;    // mean of the raw right-hand side (removed once)
   double mean_x;    // mean of the final iterate (removed on output)
-  // Scale of the GEMM-precision residual copy (FP16 transforms only; 1
-  // otherwise): lo_scale is the factor of the copy the transforms read,
-  // lo_next the one the next copy is written with (0.25 sqrt(N) / ||r|| of
-  // the latest residual norm).
-  double lo_scale;
-  double lo_next;
   int active;       // 1 while the system iterates
   int iters;
   int status;       // enum rve_status
   int valid;        // coefficient field passed the device check
+  // Scale of the GEMM-precision residual copy (read with FP16 transforms
+  // only; 1 otherwise): lo_scale is the factor of the copy the transforms
+  // read, lo_next the one the next copy is written with (0.25 sqrt(N) / ||r||
+  // of the latest residual norm).
+  double lo_scale;
+  double lo_next;
 };
 
 // Per realization quantities.

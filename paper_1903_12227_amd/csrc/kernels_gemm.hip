@@ -154,8 +154,9 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
                                                      void* __restrict__ out_v, int n, int S, const SysState* sys,
                                                      const RealState* real, const void* __restrict__ einv_v,
                                                      const RT* __restrict__ rres, double* __restrict__ part,
-                                                     int scaled, double emin) {
+                                                     double emin) {
   static_assert(D == 2 || D == 3, "dimension");
+  constexpr int scaled = std::is_same<Tr, TrF16>::value;   // FP16: scaled operands
   using op_t = typename Tr::op_t;
   using acc_t = typename Tr::acc_t;
   using accv_t = typename Tr::accv_t;
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
   acc_t scale = (acc_t)1;
   const int rz = D == 2 ? (s >> 1) : s / 3;
   if constexpr (EPI == kEpiEinv) scale = scaled ? (acc_t)1 : (acc_t)real[rz].inv_a0;
-  EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, rz, emin);
+  const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, rz, emin);
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     acc_t v = Cs[orow * LDC + oc0 + e];
@@ -272,7 +273,9 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
     }
     if constexpr (EPI == kEpiZ) {
       ZT* out = reinterpret_cast<ZT*>(out_v);
-      const ZT zs = scaled ? (ZT)((double)v * es.z) : (ZT)v;
+      ZT zs;
+      if constexpr (scaled) zs = (ZT)((double)v * es.z);
+      else zs = (ZT)v;
       out[obase + e] = zs;
       dot += (double)zs * widen(rres[obase + e]);
     } else {
@@ -313,8 +316,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                                                           const SysState* sys, const RealState* real,
                                                           const float* __restrict__ einv,
                                                           const RT* __restrict__ rres,
-                                                          double* __restrict__ part, int scaled, double emin) {
+                                                          double* __restrict__ part, double emin) {
   typedef typename H16<T>::v8 v8t;
+  constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
   constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(T);
   constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
   static_assert(kCBytes <= kOpBytes, "staging must fit in the operand buffers");
@@ -409,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 
   float scale = 1.f;
   if constexpr (EPI == kEpiEinv) scale = scaled ? 1.f : (float)real[s >> 1].inv_a0;
-  EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
+  const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
   double dot = 0.0;
   const int orow = tid >> 2, oc0 = (tid & 3) * 32;
 #pragma unroll
@@ -444,7 +448,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
       ZT* out = reinterpret_cast<ZT*>(out_v) + obase;
 #pragma unroll
       for (int e = 0; e < 32; ++e) {
-        const ZT zs = scaled ? (ZT)((double)v[e] * es.z) : (ZT)v[e];
+        ZT zs;
+        if constexpr (scaled) zs = (ZT)((double)v[e] * es.z);
+        else zs = (ZT)v[e];
         out[e] = zs;
         dot += (double)zs * widen(rres[obase + e]);
       }
@@ -751,32 +757,31 @@ void run_precond(const Work& w, const GemmTables& t, hipStream_t st, int phase) 
   const void* einv = std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv64 : (const void*)t.einv32;
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
-  const int sc = t.scaled;
   const double em = t.emin;
   // T1 = (R Q)^T, from the FP64 residual or from its GEMM-precision copy
   if (phase >= 0 && phase != 0) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, (const op_t*)w.rlo, Q, (void*)u1,
-                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore>), grid, block, 0, st, w.r, Q, (void*)u1, n, w.S,
-                       w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   // W = (Q R Q) ./ (a0 E)
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                       w.real, einv, (const double*)nullptr, nullptr, sc, em);
+                       w.real, einv, (const double*)nullptr, nullptr, em);
   // T3 = (W Q)^T
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                       w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.real, nullptr, (const double*)nullptr, nullptr, em);
   // z = Q W Q, partial sums of r.z
   if (phase >= 0 && phase != 3) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, sc, em);
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, w.r, w.part_rz, sc, em);
+                       w.real, nullptr, w.r, w.part_rz, em);
 }
 
 // Three dimensions: six transforms out = (X Q)^T of the n^2 x n views; the
@@ -792,35 +797,34 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
       std::is_same<typename Tr::acc_t, double>::value ? (const void*)t.einv3_64 : (const void*)t.einv3_32;
   op_t* u1 = reinterpret_cast<op_t*>(w.u1);
   op_t* u2 = reinterpret_cast<op_t*>(w.u2);
-  const int sc = t.scaled;
   const double em = t.emin;
   auto on = [&](int ph) { return phase < 0 || phase == ph; };
   if (!on(0)) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, (const op_t*)w.rlo,
-                       Q, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       Q, (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, double, kEpiStore, double, double, 3>), grid, block, 0, st, w.r, Q, (void*)u1,
-                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (on(1))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (on(2))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiEinv, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, einv, (const double*)nullptr, nullptr, sc, em);
+                       w.S, w.sys, w.real, einv, (const double*)nullptr, nullptr, em);
   if (on(3))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (on(4))
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiStore, double, double, 3>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (!on(5)) {
   } else if (w.rlo)
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, op_t, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, sc, em);
+                       w.real, nullptr, (const op_t*)w.rlo, w.part_rz, em);
   else
     hipLaunchKernelGGL((k_hartley<Tr, op_t, kEpiZ, ZT, double, 3>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, w.r, w.part_rz, sc, em);
+                       w.real, nullptr, w.r, w.part_rz, em);
 }
 
 // The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16).
@@ -832,20 +836,19 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   const T* Q = reinterpret_cast<const T*>(t.q);
   T* u1 = reinterpret_cast<T*>(w.u1);
   T* u2 = reinterpret_cast<T*>(w.u2);
-  const int sc = t.scaled;
   const double em = t.emin;
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                       w.real, t.einv32, (const double*)nullptr, nullptr, sc, em);
+                       w.real, t.einv32, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                       w.real, nullptr, (const double*)nullptr, nullptr, sc, em);
+                       w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 3)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
-                       nullptr, (const T*)w.rlo, w.part_rz, sc, em);
+                       nullptr, (const T*)w.rlo, w.part_rz, em);
 }
 
 template <class ZT>

@@ -11,6 +11,8 @@
 // neighbours come from the same cache lines. All reductions are written as
 // per-workgroup partials and finished in a fixed order (deterministic, no
 // floating-point atomics).
+#include <type_traits>
+
 #include "launch.h"
 
 namespace rve {
@@ -60,14 +62,24 @@ template <> struct V4<_Float16> {
   }
 };
 
-// The GEMM-precision residual copy, written times the system's scale (1
-// except with FP16 transforms).
+// The GEMM-precision residual copy: FP16 copies are written times the
+// system's scale, the others as they are (their scale is 1).
+template <class LoT> constexpr bool kScaledLo = std::is_same<LoT, _Float16>::value;
+template <class LoT>
+__device__ inline double lo_scale_of(const SysState& S) {
+  if constexpr (kScaledLo<LoT>) return S.lo_next;
+  return 1.0;
+}
 template <class LoT>
 __device__ inline void store_lo(LoT* p, const double (&v)[4], double sc) {
-  double w[4];
+  if constexpr (kScaledLo<LoT>) {
+    double w[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = v[k] * sc;
-  V4<LoT>::store(p, w);
+    for (int k = 0; k < 4; ++k) w[k] = v[k] * sc;
+    V4<LoT>::store(p, w);
+  } else {
+    V4<LoT>::store(p, v);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B) {
@@ -204,7 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_meansub(double* __restrict__ r, doub
                                                      double* __restrict__ part) {
   __shared__ double sh[4];
   const int s = blockIdx.y;
-  const double m = sys[s].mean_f, sc = sys[s].lo_next;
+  const double m = sys[s].mean_f, sc = lo_scale_of<LoT>(sys[s]);
   const long long off = (long long)s * N2;
   double acc[1] = {0.0};
   const double zero[4] = {0.0, 0.0, 0.0, 0.0};
@@ -576,7 +588,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
   __shared__ double sh[4 * 2];
   const int s = blockIdx.y;
   if (!sys[s].active) return;
-  const double al = sys[s].alpha, sc = sys[s].lo_next;
+  const double al = sys[s].alpha, sc = lo_scale_of<LoT>(sys[s]);
   const long long off = (long long)s * N2;
   double acc[2] = {0.0, 0.0};
   const long long stride = (long long)gridDim.x * kBlock * 4;
@@ -1129,7 +1141,7 @@ __global__ void __launch_bounds__(kBlock) k_replace_r(double* __restrict__ r, co
                                                        const SysState* sys, long long N2) {
   const int s = blockIdx.y;
   if (!sys[s].active) return;
-  const double sc = sys[s].lo_next;
+  const double sc = lo_scale_of<LoT>(sys[s]);
   const long long off = (long long)s * N2;
   const long long stride = (long long)gridDim.x * kBlock * 4;
   for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {

@@ -162,7 +162,6 @@ struct GemmTables {
   const float* einv3_32 = nullptr;
   // FP16 transforms: the residual copy is scaled per system (SysState::lo_scale),
   // einv32 / einv3_32 hold E_min / E and the last transform unscales
-  int scaled = 0;
   double emin = 1.0;
 };
 size_t gemm_elem_size(int prec);

@@ -288,7 +288,6 @@ GemmTables gemm_tables(const Tables* tb, int prec, int scheme) {
     g.q = tb->qh;
     g.einv32 = fd ? tb->einvh_fd : tb->einvh;
     g.einv3_32 = tb->einv3h;
-    g.scaled = 1;
     g.emin = fd ? tb->emin_fd : tb->emin;
   } else {
     g.q = prec == RVE_FP64 ? (const void*)tb->q64 : prec == RVE_MIX_FP32 ? (const void*)tb->q32
