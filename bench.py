@@ -9,8 +9,9 @@ derivative, and the ensemble statistics of the batch.
 Workload: L = 64, h = 1/8 (n = 512 nodes per axis), 256 realizations per
 step, Poisson(ln 2 L^2) unit-square inclusions, contrast 10, tolerance 1e-10.
 The headline value runs the preconditioner GEMMs in BF16 (FP32 accumulation)
-with FP64 residuals, dots and A_hom; the same workload in FP64 and the plain
-per-realization FP64 PCG are timed beside it.
+with FP64 residuals, dots and A_hom; beside it: the same step with scaled
+FP16 transforms, in FP64, at B = 64, with the inputs copied from pinned host
+memory in the timed region, and the plain per-realization FP64 PCG.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 Prints one JSON line.
@@ -19,9 +20,12 @@ Prints one JSON line.
 Times the other workloads of the study instead (one JSON line each): one
 realization at L = 8; 256 at L = 32 with their mean and variance; 1024 of
 mixed L in {8, 16, 32, 64} at contrast 100 with FP64 and FP32 operator
-applies; 16 at L = 128, h = 1/16 with BF16 and FP32 transforms against FP64;
-the gradient at L = 64 for 64 realizations and the quartic tensor of 4096
-realizations at L = 16.
+applies; 16 at L = 128, h = 1/16 with BF16, FP16 and FP32 transforms against
+FP64; an FFT comparison point for the preconditioner; the gradient at L = 64
+for 64 realizations and the quartic tensor of 4096 realizations at L = 16;
+on-device sampling and ensembles; the paper's table of standard deviations;
+the spectral density; and the three-dimensional workloads (also alone with
+--survey3d).
 """
 from __future__ import annotations
 
