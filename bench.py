@@ -170,6 +170,7 @@ def roofline_for(name, e, prec_name, n):
 
 
 KERNEL_SOURCES = ("paper_1903_12227_amd/csrc/common.h", "paper_1903_12227_amd/csrc/launch.h",
+                  "paper_1903_12227_amd/csrc/stencil2d.h",
                   "paper_1903_12227_amd/csrc/kernels_vec.hip", "paper_1903_12227_amd/csrc/kernels_gemm.hip",
                   "paper_1903_12227_amd/csrc/rve_api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_L64_n512_b256.json")
@@ -394,13 +395,27 @@ def survey(rve, torch, dev):
     def fields(L, m0, contrast, count, config):
         return torch.from_numpy(batch(BooleanModel(L=L, m0=m0, a_in=contrast), config, count)).to(dev)
 
-    # one realization, L = 8 (n = 64), FP64: latency
+    # one realization, L = 8 (n = 64), FP64: latency, with the
+    # single-workgroup solver (the default at this size) and with the batched
+    # iteration chunks (graph replay or launched one by one); then many
+    # realizations at that size both ways
     a = fields(8, 8, 10.0, 1, 11)
-    for graphs in (True, False):
+    for small, graphs in ((True, True), (False, True), (False, False)):
         ctx = rve.Context(0)
+        ctx.set_small_solver(small)
         ctx.set_graphs(graphs)
         dt, r = timed(lambda: rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.FP64), ctx=ctx), reps=20)
-        emit("L=8 n=64, 1 realization, FP64", graphs=graphs, ms=1e3 * dt, iters_mean=float(r.iters.double().mean()))
+        emit("L=8 n=64, 1 realization, FP64", single_workgroup_solver=small, graphs=graphs, ms=1e3 * dt,
+             iters_mean=float(r.iters.double().mean()))
+        ctx.close()
+    a = fields(8, 8, 10.0, 1024, 18)
+    for small in (True, False):
+        ctx = rve.Context(0)
+        ctx.set_small_solver(small)
+        dt, r = timed(lambda: rve.solve_batch(a, 1 / 8, rve.Options(prec=rve.FP64), want_phi=False, ctx=ctx), reps=3)
+        emit("L=8 n=64, 1024 realizations, FP64", single_workgroup_solver=small, ms=1e3 * dt,
+             realizations_s=1024 / dt, iters_mean=float(r.iters.double().mean()))
+        ctx.close()
 
     # 256 realizations at L = 32 (n = 256) with mean and variance
     a = fields(32, 8, 10.0, 256, 12)

@@ -353,6 +353,15 @@ int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int6
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
 
+/* Single-workgroup solver (default on): when every batch of a solve has
+ * n = 64 in two dimensions with FP64 transforms and the FP64 apply, each
+ * corrector system is solved by one workgroup in one launch (the cells, the
+ * Hartley matrix and the vectors stay on the chip), instead of the batched
+ * iteration chunks. Same iteration and stopping rule; results agree with the
+ * batched path to rounding. mode 0 turns it off, 1 on; anything else
+ * RVE_EINVAL. */
+int rve_set_small_solver(rve_ctx* ctx, int mode);
+
 /* Chunks of PCG iterations: mode 1 (the default) captures each distinct
  * chunk (same batches, pointers, kernel choices and options) once as a HIP
  * graph, cached in the context, and replays it; mode 0 launches every

@@ -25,7 +25,7 @@ EXPORTS = (
     "rve_status_string", "rve_set_timing", "rve_last_timing",
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
-    "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d",
+    "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d", "rve_set_small_solver",
 )
 
 
@@ -67,6 +67,7 @@ def _declare(lib):
     lib.rve_set_autotune.argtypes = [_vp, _i]
     lib.rve_get_tuned.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(_i)]
     lib.rve_set_graphs.argtypes = [_vp, _i]
+    lib.rve_set_small_solver.argtypes = [_vp, _i]
     lib.rve_force_variants.argtypes = [_vp, _i, _i]
     lib.rve_dos_moments.argtypes = [_vp, _i, _i, _i, _vp, _i, _vp, _d, _i, _vp]
     lib.rve_dos_eval.argtypes = [_vp, _i, _i, _i, _vp, _d, _d, _i, _i, _vp, _vp]

@@ -88,6 +88,10 @@ class Context:
         folded 128 x 128 BF16)."""
         N.check(self._lib.rve_force_variants(self.handle, int(stencil), int(gemm)), "rve_force_variants")
 
+    def set_small_solver(self, enable: bool):
+        """Single-workgroup PCG for n = 64 FP64 solves (on by default)."""
+        N.check(self._lib.rve_set_small_solver(self.handle, int(bool(enable))), "rve_set_small_solver")
+
     def set_graphs(self, enable: bool):
         """Replay each chunk of PCG iterations from a captured HIP graph (the
         default) or launch its kernels one by one; results are identical."""

@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ("kernels_vec.hip", "kernels_gemm.hip", "kernels_3d.hip", "kernels_sample.hip", "kernels_dos.hip", "rve_api.hip")
+SOURCES = ("kernels_vec.hip", "kernels_gemm.hip", "kernels_3d.hip", "kernels_small.hip", "kernels_sample.hip", "kernels_dos.hip", "rve_api.hip")
 OUT = os.path.join(HERE, "librve.so")
 ARCH = "gfx950"
 

@@ -137,6 +137,14 @@ void launch_ahom3(const Work& w, hipStream_t st);
 void launch_scalar_ahom3(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
 void launch_finalize3(const Work& w, int* iters, double* relres, int* status, hipStream_t st);
 
+// Single-workgroup PCG (kernels_small.hip): the whole iteration of each
+// system in one launch, for w.dim == 2, n == 64, FP64 transforms and apply.
+// Expects the state the solver's set-up leaves (r = f - mean f, x = 0,
+// fnorm, a0, active flags); writes x, iters, relres and status.
+bool small_solver_fits(const Work& w);
+void launch_pcg_small(const Work& w, const double* q64, const double* einv64, double tol, int maxit,
+                      hipStream_t st);
+
 // On-device sampling of the inclusion model (kernels_sample.hip): B fields
 // [B][n][n] for realizations first .. first + B - 1.
 bool sample_side_valid(int n, int side);

@@ -89,6 +89,7 @@ struct rve_ctx {
   int graphs = 1;                     // replay captured chunks (1) or launch them one by one (0)
   int force_stencil = -1;             // operator-apply shape to use instead of the tuner's (-1: none)
   int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
+  int small_solver = 1;               // single-workgroup PCG where it fits (n = 64, FP64)
   std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
@@ -704,6 +705,14 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     }
   }
 
+  // the smallest grid in FP64: one workgroup per system runs the whole PCG
+  // in one launch (no iteration chunks, tuning or fold)
+  bool small = ctx->small_solver != 0;
+  for (auto& b : bs) small = small && small_solver_fits(b.w);
+  if (small) {
+    for (auto& b : bs)
+      launch_pcg_small(b.w, static_cast<const double*>(b.gt.q), b.gt.einv64, o->tol, o->maxit, st);
+  } else {
   // kernel variants: defaults, or the autotuner's choice for each shape; then
   // z_0 and beta's first call for each batch
   for (auto& b : bs) {
@@ -799,9 +808,10 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     }
     ++polls;
   }
+  }   // not small
 
   for (auto& b : bs) {
-    {
+    if (!small) {
       // the directions since the last fold
       Timed t(ctx, 6);
       launch_fold_x(b.w, 1, st);
@@ -1237,6 +1247,12 @@ int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
   if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
   c->force_stencil = stencil_choice;
   c->force_gemm = gemm_variant;
+  return RVE_OK;
+}
+
+int rve_set_small_solver(rve_ctx* c, int mode) {
+  if (!c || (mode != 0 && mode != 1)) return RVE_EINVAL;
+  c->small_solver = mode;
   return RVE_OK;
 }
 

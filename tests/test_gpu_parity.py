@@ -312,18 +312,23 @@ def test_iterate_after_k_iterations(dev, k):
     # the iterate is folded in from the ring of directions every 8 iterations
     # and at the end: stopping after k iterations must still give the PCG
     # iterate x_k (here against the oracle's PCG stopped after k iterations)
+    # (batched path), and the single-workgroup solver must too
     rve = _rve()
     n, B = 64, 2
     a = _fields(n, B, 13)
     h = 1.0 / 8
-    res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=1e-300, maxit=k))
-    assert res.code == 1 and bool(torch.all(res.iters == k))
-    phi = res.phi.cpu().numpy() / h
-    for b in range(B):
-        ref = oa.solve(a[b], tol=1e-300, maxit=k)
-        assert ref.iters == (k, k)
-        for i in range(2):
-            assert np.max(np.abs(phi[b, i] - ref.phi[i])) <= 1e-10 * np.max(np.abs(ref.phi[i]))
+    for small in (False, True):
+        ctx = rve.Context(0)
+        ctx.set_small_solver(small)
+        res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=1e-300, maxit=k), ctx=ctx)
+        ctx.close()
+        assert res.code == 1 and bool(torch.all(res.iters == k))
+        phi = res.phi.cpu().numpy() / h
+        for b in range(B):
+            ref = oa.solve(a[b], tol=1e-300, maxit=k)
+            assert ref.iters == (k, k)
+            for i in range(2):
+                assert np.max(np.abs(phi[b, i] - ref.phi[i])) <= 1e-10 * np.max(np.abs(ref.phi[i]))
 
 
 def _fixed_ctx(rve, graphs):
@@ -455,3 +460,47 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
             for b in range(2):
                 assert rel2(A[b], A64[b]) <= 1e-8
     assert its[3] < its[2] and its[3] <= its[0] + 0.15 * its[0], its
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_small_solver_matches_batched_path_and_oracle(dev, scheme):
+    # n = 64, FP64: the single-workgroup solver (default) against the batched
+    # iteration chunks and the oracle; same iteration counts
+    rve = _rve()
+    n, B = 64, 5
+    a = _fields(n, B, 60)
+    a[3] = 2.0                                   # constant field: f = 0, no iteration
+    ctx = rve.Context(0)
+    opts = rve.Options(tol=1e-10, scheme=scheme)
+    r1 = rve.solve_batch(_to(a, dev), 0.125, opts, ctx=ctx)
+    ctx.set_small_solver(False)
+    r2 = rve.solve_batch(_to(a, dev), 0.125, opts, ctx=ctx)
+    ctx.close()
+    assert r1.code == 0 and r2.code == 0
+    A1, A2 = r1.ahom.cpu().numpy(), r2.ahom.cpu().numpy()
+    it1, it2 = r1.iters.cpu().numpy(), r2.iters.cpu().numpy()
+    assert np.all(np.abs(it1 - it2) <= 1)
+    assert it1[3].tolist() == [0, 0] and np.array_equal(A1[3], 2.0 * np.eye(2))
+    for b in range(B):
+        assert rel2(A1[b], A2[b]) <= 1e-12
+        if scheme == 0:
+            assert rel2(A1[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-10
+    # the true residual of the returned correctors
+    x = r1.phi.cpu().numpy() / 0.125
+    if scheme == 0:
+        K = q1.assemble(a[0])
+        for i, f in enumerate(q1.rhs(a[0])):
+            f = f - f.mean()
+            assert np.linalg.norm(f.ravel() - K @ x[0, i].ravel()) <= 2e-10 * np.linalg.norm(f)
+
+
+def test_small_solver_status_codes(dev):
+    rve = _rve()
+    n = 64
+    a = _fields(n, 3, 61)
+    a[1, 5, 7] = -1.0
+    res = rve.solve_batch(_to(a, dev), 0.125, rve.Options(tol=1e-10, maxit=3))
+    st = res.status.cpu().numpy().tolist()
+    assert st == [1, -1, 1] and res.code == -1
+    its = res.iters.cpu().numpy()
+    assert its[0].tolist() == [3, 3] and its[1].tolist() == [0, 0]
