@@ -102,7 +102,7 @@ def bytes_per_node(prec_name, flexible):
                 read and write x; per direction, read p once (handled in
                 kernel_entries: 16 ceil(iters / ring) + s_p iters per system)
     """
-    sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
+    sg = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
@@ -596,7 +596,7 @@ def bytes_per_node_3d(prec_name):
     system) and the preconditioner has six transforms: gemm1 the first (reads
     the residual copy), gemm2 the scaling one, gemm3 the four plain ones
     together, gemm4 the last (writes z, re-reads the residual copy)."""
-    sg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_name]
+    sg = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
@@ -622,7 +622,7 @@ def survey_3d(rve, torch, dev, emit):
         N3 = float(n) ** 3
         a = torch.from_numpy(batch_3d(BooleanModel3D(L=L, m0=8, a_in=10.0), 90 + L, B)).to(dev)
         ref = None
-        for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16")):
+        for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16")):
             opts = rve.Options(tol=1e-10, prec=prec)
             rve.solve_batch_3d(a, 0.125, opts, want_phi=False, ctx=ctx)
             torch.cuda.synchronize()
