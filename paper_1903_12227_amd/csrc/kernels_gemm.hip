@@ -311,7 +311,7 @@ template <> struct H16<_Float16> {
 };
 
 template <class T, int EPI, class ZT, class RT = double>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm,
                                                           void* __restrict__ out_v, int n, int S,
                                                           const SysState* sys, const RealState* real,
                                                           const float* __restrict__ einv,
