@@ -348,8 +348,8 @@ int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int6
 /* Use these kernel variants instead of the autotuner's or default choice
  * (-1: no override): an operator-apply shape as encoded for rve_get_tuned
  * kind 0 / 2, and a transform-GEMM variant (0: 64 x 64 tiles; 1: 128 x 128
- * BF16 tiles, n % 128 == 0; 2: even/odd-folded 128 x 128 BF16 tiles, half the
- * MFMA work, n % 256 == 0). An override that is not valid for a shape is
+ * 16-bit tiles, n % 128 == 0; 2: even/odd-folded 128 x 128 BF16 tiles, half
+ * the MFMA work, n % 256 == 0). An override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
 

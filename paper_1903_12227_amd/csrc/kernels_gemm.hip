@@ -310,22 +310,30 @@ template <> struct H16<_Float16> {
   __device__ static v4f mma(v8h a, v8h b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
 
-template <class T, int EPI, class ZT, class RT = double>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm,
-                                                          void* __restrict__ out_v, int n, int S,
-                                                          const SysState* sys, const RealState* real,
-                                                          const float* __restrict__ einv,
-                                                          const RT* __restrict__ rres,
-                                                          double* __restrict__ part, double emin) {
+// KT is the K slice staged per step: 64 (three waves per SIMD, 142 VGPRs)
+// or 32 (half the staging registers and LDS, four waves per SIMD; measured
+// 6-12 % slower per transform than 64, so the launchers use 64).
+template <int KT> constexpr int kWavesH16 = KT == 32 ? 4 : 3;
+
+template <class T, int EPI, class ZT, class RT = double, int KT = TK>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesH16<KT>, kWavesH16<KT>)))
+k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
+              const SysState* sys, const RealState* real, const float* __restrict__ einv,
+              const RT* __restrict__ rres, double* __restrict__ part, double emin) {
+  static_assert(KT == 32 || KT == 64, "K slice");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
-  constexpr size_t kOpBytes = 2 * (size_t)TM * TLDA * sizeof(T);
+  constexpr int LDA = KT + 8;                 // LDS row stride (elements)
+  constexpr int TPR = KT / 8;                 // threads per staged row (8 elements each)
+  constexpr int RPP = kBlock / TPR;           // rows per staging pass
+  constexpr int NPASS = TM / RPP;             // passes per operand tile
+  constexpr size_t kOpBytes = 2 * (size_t)TM * LDA * sizeof(T);
   constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
-  static_assert(kCBytes <= kOpBytes, "staging must fit in the operand buffers");
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
+  constexpr size_t kSmem = kOpBytes > kCBytes ? kOpBytes : kCBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[4];
   T* As = reinterpret_cast<T*>(smem);
-  T* Bs = As + TM * TLDA;
+  T* Bs = As + TM * LDA;
   float* Cs = reinterpret_cast<float*>(smem);
 
   const int NB = n / TN, MB = n / TM;
@@ -343,35 +351,40 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   const T* Qs = Qm + (long long)nb * TN * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int lr = tid >> 3, lc = (tid & 7) * 8;
+  const int lr = tid / TPR, lc = (tid % TPR) * 8;
 
-  // register staging of the next K slice (kept out of lambdas so that it
-  // stays in VGPRs)
+  // register staging of the next K slice in named registers (plain code:
+  // arrays or lambdas put it in scratch); passes 2 and 3 only for KT = 64
+  static_assert(NPASS == 2 || NPASS == 4, "staging passes");
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   const T* xa = Xs + (long long)lr * n + lc;
   const T* qa = Qs + (long long)lr * n + lc;
-  const long long r32 = 32LL * n;
-#define RVE_GLOAD(k0)                                                        \
-  do {                                                                      \
-    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                       \
-    ra1 = *reinterpret_cast<const uint4*>(xa + r32 + (k0));                 \
-    ra2 = *reinterpret_cast<const uint4*>(xa + 2 * r32 + (k0));             \
-    ra3 = *reinterpret_cast<const uint4*>(xa + 3 * r32 + (k0));             \
-    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                       \
-    rb1 = *reinterpret_cast<const uint4*>(qa + r32 + (k0));                 \
-    rb2 = *reinterpret_cast<const uint4*>(qa + 2 * r32 + (k0));             \
-    rb3 = *reinterpret_cast<const uint4*>(qa + 3 * r32 + (k0));             \
+  const long long rstep = (long long)RPP * n;
+#define RVE_GLOAD(k0)                                                     \
+  do {                                                                    \
+    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                     \
+    ra1 = *reinterpret_cast<const uint4*>(xa + rstep + (k0));             \
+    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                     \
+    rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));             \
+    if constexpr (NPASS == 4) {                                           \
+      ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));       \
+      ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));       \
+      rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));       \
+      rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));       \
+    }                                                                     \
   } while (0)
-#define RVE_SSTORE()                                                         \
-  do {                                                                      \
-    *reinterpret_cast<uint4*>(As + (lr + 0) * TLDA + lc) = ra0;             \
-    *reinterpret_cast<uint4*>(As + (lr + 32) * TLDA + lc) = ra1;            \
-    *reinterpret_cast<uint4*>(As + (lr + 64) * TLDA + lc) = ra2;            \
-    *reinterpret_cast<uint4*>(As + (lr + 96) * TLDA + lc) = ra3;            \
-    *reinterpret_cast<uint4*>(Bs + (lr + 0) * TLDA + lc) = rb0;             \
-    *reinterpret_cast<uint4*>(Bs + (lr + 32) * TLDA + lc) = rb1;            \
-    *reinterpret_cast<uint4*>(Bs + (lr + 64) * TLDA + lc) = rb2;            \
-    *reinterpret_cast<uint4*>(Bs + (lr + 96) * TLDA + lc) = rb3;            \
+#define RVE_SSTORE()                                                      \
+  do {                                                                    \
+    *reinterpret_cast<uint4*>(As + lr * LDA + lc) = ra0;                  \
+    *reinterpret_cast<uint4*>(As + (lr + RPP) * LDA + lc) = ra1;          \
+    *reinterpret_cast<uint4*>(Bs + lr * LDA + lc) = rb0;                  \
+    *reinterpret_cast<uint4*>(Bs + (lr + RPP) * LDA + lc) = rb1;          \
+    if constexpr (NPASS == 4) {                                           \
+      *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * LDA + lc) = ra2;    \
+      *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * LDA + lc) = ra3;    \
+      *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * LDA + lc) = rb2;    \
+      *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * LDA + lc) = rb3;    \
+    }                                                                     \
   } while (0)
 
   v4f acc[4][4];
@@ -386,18 +399,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   RVE_GLOAD(0);
   RVE_SSTORE();
   __syncthreads();
-  for (int k0 = 0; k0 < n; k0 += TK) {
-    const bool more = k0 + TK < n;
-    if (more) RVE_GLOAD(k0 + TK);
+  for (int k0 = 0; k0 < n; k0 += KT) {
+    const bool more = k0 + KT < n;
+    if (more) RVE_GLOAD(k0 + KT);
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 32) {
+    for (int kk = 0; kk < KT; kk += 32) {
       v8t bf[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
+        bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * LDA + kk + fk);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
+        const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * LDA + kk + fk);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
       }
@@ -827,8 +840,9 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
                        w.real, nullptr, w.r, w.part_rz, em);
 }
 
-// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16).
-template <class T, class ZT>
+// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16),
+// K slices of KT.
+template <class T, class ZT, int KT>
 void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
   const long long NT = (long long)w.S * (n / TM) * (n / TN);
@@ -838,16 +852,16 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, KT>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, KT>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
                        w.real, t.einv32, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, KT>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
                        w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, KT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
                        nullptr, (const T*)w.rlo, w.part_rz, em);
 }
 
@@ -909,13 +923,13 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond<TrF32, float>(w, t, st, phase);
   } else if (prec == kGemmF16) {
     if (w.gemm_variant == 1)
-      run_precond_h16<_Float16, float>(w, t, st, phase);
+      run_precond_h16<_Float16, float, 64>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
     run_precond_bf16_sym<float>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
-    run_precond_h16<__bf16, float>(w, t, st, phase);
+    run_precond_h16<__bf16, float, 64>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

@@ -42,7 +42,7 @@ struct Work {
   const float* a32 = nullptr;
   double* f = nullptr;
   int stencil = 0;           // operator-apply shape (stencil_choice_*)
-  int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (BF16, n % 128 == 0);
+  int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (16-bit, n % 128 == 0);
                              // 2: even/odd-folded 128 x 128 (BF16, n % 256 == 0)
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
