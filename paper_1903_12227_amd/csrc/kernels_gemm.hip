@@ -294,11 +294,28 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
 // 16-bit transform GEMM (BF16 or FP16 operands, FP32 accumulation) with a
 // 128 x 128 output tile (n % 128 == 0): 2 x 2 waves of 64 x 64, i.e. 4 x 4
 // MFMA 16x16x32 blocks per wave, so each operand fragment read from LDS
-// feeds four MFMAs. Operand tiles (128 x 64, row stride 144 B: conflict-free
-// 16-byte fragment reads) are loaded with 16-byte global loads, the next K
-// slice prefetched into registers. The transposed output goes through LDS
-// in two halves of 64 rows.
+// feeds four MFMAs. Two operand pipelines (PIPE):
+//   0: 64-wide K slices (operand tiles 128 x 64, row stride 144 B:
+//      conflict-free 16-byte fragment reads) loaded with 16-byte global
+//      loads, the next slice prefetched into registers while the current
+//      one feeds the MFMAs; two barriers per slice.
+//   1: 32-wide K slices loaded by the load unit straight into LDS
+//      (global_load_lds, 16 bytes per lane), double-buffered: the next
+//      slice is in flight while the current one feeds the MFMAs; one
+//      barrier per slice and no staging registers. One load instruction of
+//      a wave fills 1 KB of LDS contiguously (lane l at byte 16 l), so the
+//      tile cannot be padded; instead the four 16-byte chunks of each
+//      64-byte row are XOR-swizzled by (row / 2) mod 4, which keeps the
+//      fragment reads conflict-free.
+// Both accumulate over k in the same order (ascending 32-wide MFMA steps),
+// so they give identical outputs. The output (transposed) is stored straight
+// from the accumulators: each lane holds four consecutive output columns of
+// one output row per MFMA block, so a wave's store covers 16 rows x 32 bytes
+// (16-bit) or 64 bytes (FP32 z), and no LDS round trip or barrier is needed.
+// Three waves per SIMD (142 VGPRs with PIPE 0) hide more of the load latency
+// than two; four with 32-wide register-staged slices measured slower.
 constexpr int TM = 128, TN = 128, TK = 64, TLDA = TK + 8, TLDC = TM + 4;
+constexpr int DK = 32;   // K slice of the LDS-DMA pipeline
 
 template <class T> struct H16;
 template <> struct H16<__bf16> {
@@ -310,31 +327,26 @@ template <> struct H16<_Float16> {
   __device__ static v4f mma(v8h a, v8h b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
 
-// KT is the K slice staged per step: 64 (three waves per SIMD, 142 VGPRs)
-// or 32 (half the staging registers and LDS, four waves per SIMD; measured
-// 6-12 % slower per transform than 64, so the launchers use 64).
-template <int KT> constexpr int kWavesH16 = KT == 32 ? 4 : 3;
+// 16 bytes per lane from global memory into LDS at lds_wave + 16 * lane
+// (lds_wave must be the same in every lane of the wave).
+template <class T>
+__device__ inline void lds_dma16(const T* src, T* lds_wave) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)lds_wave, 16, 0, 0);
+}
 
-template <class T, int EPI, class ZT, class RT = double, int KT = TK>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesH16<KT>, kWavesH16<KT>)))
+template <class T, int EPI, class ZT, class RT = double, int PIPE = 0>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ einv,
               const RT* __restrict__ rres, double* __restrict__ part, double emin) {
-  static_assert(KT == 32 || KT == 64, "K slice");
+  static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
-  constexpr int LDA = KT + 8;                 // LDS row stride (elements)
-  constexpr int TPR = KT / 8;                 // threads per staged row (8 elements each)
-  constexpr int RPP = kBlock / TPR;           // rows per staging pass
-  constexpr int NPASS = TM / RPP;             // passes per operand tile
-  constexpr size_t kOpBytes = 2 * (size_t)TM * LDA * sizeof(T);
-  constexpr size_t kCBytes = (size_t)64 * TLDC * sizeof(float);
-  constexpr size_t kSmem = kOpBytes > kCBytes ? kOpBytes : kCBytes;
+  constexpr size_t kSmem = PIPE == 0 ? 2 * (size_t)TM * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[4];
   T* As = reinterpret_cast<T*>(smem);
-  T* Bs = As + TM * LDA;
-  float* Cs = reinterpret_cast<float*>(smem);
 
   const int NB = n / TN, MB = n / TM;
   const long long NT = (long long)S * MB * NB;
@@ -351,41 +363,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   const T* Qs = Qm + (long long)nb * TN * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int lr = tid / TPR, lc = (tid % TPR) * 8;
-
-  // register staging of the next K slice in named registers (plain code:
-  // arrays or lambdas put it in scratch); passes 2 and 3 only for KT = 64
-  static_assert(NPASS == 2 || NPASS == 4, "staging passes");
-  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  const T* xa = Xs + (long long)lr * n + lc;
-  const T* qa = Qs + (long long)lr * n + lc;
-  const long long rstep = (long long)RPP * n;
-#define RVE_GLOAD(k0)                                                     \
-  do {                                                                    \
-    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                     \
-    ra1 = *reinterpret_cast<const uint4*>(xa + rstep + (k0));             \
-    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                     \
-    rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));             \
-    if constexpr (NPASS == 4) {                                           \
-      ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));       \
-      ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));       \
-      rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));       \
-      rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));       \
-    }                                                                     \
-  } while (0)
-#define RVE_SSTORE()                                                      \
-  do {                                                                    \
-    *reinterpret_cast<uint4*>(As + lr * LDA + lc) = ra0;                  \
-    *reinterpret_cast<uint4*>(As + (lr + RPP) * LDA + lc) = ra1;          \
-    *reinterpret_cast<uint4*>(Bs + lr * LDA + lc) = rb0;                  \
-    *reinterpret_cast<uint4*>(Bs + (lr + RPP) * LDA + lc) = rb1;          \
-    if constexpr (NPASS == 4) {                                           \
-      *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * LDA + lc) = ra2;    \
-      *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * LDA + lc) = ra3;    \
-      *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * LDA + lc) = rb2;    \
-      *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * LDA + lc) = rb3;    \
-    }                                                                     \
-  } while (0)
+  const int frow = lane & 15;
 
   v4f acc[4][4];
 #pragma unroll
@@ -395,89 +373,157 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.f;
 
-  const int frow = lane & 15, fk = (lane >> 4) * 8;
-  RVE_GLOAD(0);
-  RVE_SSTORE();
-  __syncthreads();
-  for (int k0 = 0; k0 < n; k0 += KT) {
-    const bool more = k0 + KT < n;
-    if (more) RVE_GLOAD(k0 + KT);
+  if constexpr (PIPE == 0) {
+    constexpr int TPR = TK / 8;                 // threads per staged row (8 elements each)
+    constexpr int RPP = kBlock / TPR;           // rows per staging pass (4 passes per tile)
+    T* Bs = As + TM * TLDA;
+    const int lr = tid / TPR, lc = (tid % TPR) * 8;
+    // register staging of the next K slice in named registers (plain code:
+    // arrays or lambdas put it in scratch)
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    const T* xa = Xs + (long long)lr * n + lc;
+    const T* qa = Qs + (long long)lr * n + lc;
+    const long long rstep = (long long)RPP * n;
+#define RVE_GLOAD(k0)                                                 \
+  do {                                                                \
+    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                 \
+    ra1 = *reinterpret_cast<const uint4*>(xa + rstep + (k0));         \
+    ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));     \
+    ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));     \
+    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                 \
+    rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));         \
+    rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));     \
+    rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));     \
+  } while (0)
+#define RVE_SSTORE()                                                  \
+  do {                                                                \
+    *reinterpret_cast<uint4*>(As + lr * TLDA + lc) = ra0;             \
+    *reinterpret_cast<uint4*>(As + (lr + RPP) * TLDA + lc) = ra1;     \
+    *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * TLDA + lc) = ra2; \
+    *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * TLDA + lc) = ra3; \
+    *reinterpret_cast<uint4*>(Bs + lr * TLDA + lc) = rb0;             \
+    *reinterpret_cast<uint4*>(Bs + (lr + RPP) * TLDA + lc) = rb1;     \
+    *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * TLDA + lc) = rb2; \
+    *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * TLDA + lc) = rb3; \
+  } while (0)
+    const int fk = (lane >> 4) * 8;
+    RVE_GLOAD(0);
+    RVE_SSTORE();
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += TK) {
+      const bool more = k0 + TK < n;
+      if (more) RVE_GLOAD(k0 + TK);
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 32) {
+      for (int kk = 0; kk < TK; kk += 32) {
+        v8t bf[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
+        }
+      }
+      __syncthreads();
+      if (more) {
+        RVE_SSTORE();
+        __syncthreads();
+      }
+    }
+#undef RVE_GLOAD
+#undef RVE_SSTORE
+  } else {
+    // buffer b holds the A tile (128 x 32) then the B tile; 16-byte chunk g
+    // of a tile sits at LDS chunk g and holds row g / 4, K chunk
+    // (g % 4) ^ ((row / 2) % 4). Lane l of wave w loads chunks 128 w + l and
+    // 128 w + 64 + l of both tiles.
+    constexpr int kBuf = 2 * TM * DK;
+    const int g0 = 128 * w + lane, g1 = g0 + 64;
+    const int r0 = g0 >> 2, r1 = g1 >> 2;
+    const int c0 = (g0 & 3) ^ ((r0 >> 1) & 3), c1 = (g1 & 3) ^ ((r1 >> 1) & 3);
+    const T* xa0 = Xs + (long long)r0 * n + 8 * c0;
+    const T* xa1 = Xs + (long long)r1 * n + 8 * c1;
+    const T* qa0 = Qs + (long long)r0 * n + 8 * c0;
+    const T* qa1 = Qs + (long long)r1 * n + 8 * c1;
+    auto issue = [&](int b, int k0) {
+      T* base = As + b * kBuf + 1024 * w;
+      lds_dma16(xa0 + k0, base);
+      lds_dma16(xa1 + k0, base + 512);
+      lds_dma16(qa0 + k0, base + TM * DK);
+      lds_dma16(qa1 + k0, base + TM * DK + 512);
+    };
+    // fragment reads: row (.. + frow), K chunk lane / 16 of the slice
+    const int fc = (lane >> 4) ^ ((frow >> 1) & 3);
+    const int nk = n / DK;
+    issue(0, 0);
+    for (int ks = 0; ks < nk; ++ks) {
+      // this wave's loads of slice ks have landed and its reads of slice
+      // ks - 1 are done; after the barrier the same holds for every wave, so
+      // slice ks is complete and the other buffer is free for slice ks + 1
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      if (ks + 1 < nk) issue((ks + 1) & 1, (ks + 1) * DK);
+      const T* Ab = As + (ks & 1) * kBuf;
+      const T* Bb = Ab + TM * DK;
       v8t bf[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * LDA + kk + fk);
+        bf[j] = *reinterpret_cast<const v8t*>(Bb + ((wn * 64 + j * 16 + frow) * 4 + fc) * 8);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * LDA + kk + fk);
+        const v8t af = *reinterpret_cast<const v8t*>(Ab + ((wm * 64 + i * 16 + frow) * 4 + fc) * 8);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
       }
     }
-    __syncthreads();
-    if (more) {
-      RVE_SSTORE();
-      __syncthreads();
-    }
   }
-#undef RVE_GLOAD
-#undef RVE_SSTORE
 
   float scale = 1.f;
   if constexpr (EPI == kEpiEinv) scale = scaled ? 1.f : (float)real[s >> 1].inv_a0;
   const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
   double dot = 0.0;
-  const int orow = tid >> 2, oc0 = (tid & 3) * 32;
+  // straight from the accumulators: block (i, j) of lane l holds output
+  // row nb*128 + 64 wn + 16 j + l % 16 at the four consecutive columns
+  // mb*128 + 64 wm + 16 i + 4 (l / 16) + e
+  const int lr = lane & 15, m4 = 4 * (lane >> 4);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (wn == h) {
+  for (int j = 0; j < 4; ++j) {
+    const long long l = (long long)nb * TN + wn * 64 + j * 16 + lr;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      const long long m = (long long)mb * TM + wm * 64 + i * 16 + m4;
+      const long long o = (long long)s * N2 + l * n + m;
+      float v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+      if constexpr (EPI == kEpiEinv) {
+        const float4 g = *reinterpret_cast<const float4*>(einv + l * n + m);
+        v[0] *= g.x * scale; v[1] *= g.y * scale; v[2] *= g.z * scale; v[3] *= g.w * scale;
+      }
+      if constexpr (EPI == kEpiZ) {
+        ZT* out = reinterpret_cast<ZT*>(out_v) + o;
+        ZT zs[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (scaled) zs[e] = (ZT)((double)v[e] * es.z);
+          else zs[e] = (ZT)v[e];
+          dot += (double)zs[e] * widen(rres[o + e]);
+        }
+        if constexpr (sizeof(ZT) == 4) {
+          float4 st;
+          st.x = zs[0]; st.y = zs[1]; st.z = zs[2]; st.w = zs[3];
+          *reinterpret_cast<float4*>(out) = st;
+        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            Cs[(j * 16 + (lane & 15)) * TLDC + wm * 64 + i * 16 + 4 * (lane >> 4) + e] = acc[i][j][e];
-    }
-    __syncthreads();
-    const long long l = (long long)nb * TN + h * 64 + orow;
-    const long long m0 = (long long)mb * TM + oc0;
-    const long long obase = (long long)s * N2 + l * n + m0;
-    float v[32];
+          for (int e = 0; e < 4; ++e) out[e] = zs[e];
+        }
+      } else {
+        typedef T v4t __attribute__((ext_vector_type(4)));
+        v4t pk;
 #pragma unroll
-    for (int e = 0; e < 32; e += 4) {
-      const float4 c = *reinterpret_cast<const float4*>(Cs + orow * TLDC + oc0 + e);
-      v[e] = c.x; v[e + 1] = c.y; v[e + 2] = c.z; v[e + 3] = c.w;
-    }
-    if constexpr (EPI == kEpiEinv) {
-#pragma unroll
-      for (int e = 0; e < 32; e += 4) {
-        const float4 g = *reinterpret_cast<const float4*>(einv + l * n + m0 + e);
-        v[e] *= g.x * scale; v[e + 1] *= g.y * scale; v[e + 2] *= g.z * scale; v[e + 3] *= g.w * scale;
+        for (int e = 0; e < 4; ++e) pk[e] = (T)v[e];
+        *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
       }
     }
-    if constexpr (EPI == kEpiZ) {
-      ZT* out = reinterpret_cast<ZT*>(out_v) + obase;
-#pragma unroll
-      for (int e = 0; e < 32; ++e) {
-        ZT zs;
-        if constexpr (scaled) zs = (ZT)((double)v[e] * es.z);
-        else zs = (ZT)v[e];
-        out[e] = zs;
-        dot += (double)zs * widen(rres[obase + e]);
-      }
-    } else {
-      T* out = reinterpret_cast<T*>(out_v) + obase;
-#pragma unroll
-      for (int e = 0; e < 32; e += 8) {
-        v8t pk;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) pk[k] = (T)v[e + k];
-        *reinterpret_cast<v8t*>(out + e) = pk;
-      }
-    }
-    __syncthreads();
   }
   if constexpr (EPI == kEpiZ) {
     double d[1] = {dot};
@@ -500,8 +546,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 // is rounded to BF16 once more than the plain transform's input.
 // Tile: 128 rows r x 128 columns k < h, two accumulator sets (C and S) per
 // wave, operand tiles Xe, Xo, c, s of 128 x 32 BF16 in LDS; the epilogue
-// writes output rows k and n - k through LDS, transposed as in
-// k_hartley_h16.
+// writes output rows k and n - k transposed through LDS (as the 64 x 64
+// kernel does).
 constexpr int SK = 32, SLDA = SK + 8;   // K slice and operand row stride of the folded kernel
 
 template <int EPI, class ZT, class RT = double>
@@ -840,9 +886,9 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
                        w.real, nullptr, w.r, w.part_rz, em);
 }
 
-// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16),
-// K slices of KT.
-template <class T, class ZT, int KT>
+// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16)
+// and operand pipeline PIPE.
+template <class T, class ZT, int PIPE>
 void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
   const long long NT = (long long)w.S * (n / TM) * (n / TN);
@@ -852,16 +898,16 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, KT>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, KT>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
                        w.real, t.einv32, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, KT>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
                        w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, KT>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, PIPE>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
                        nullptr, (const T*)w.rlo, w.part_rz, em);
 }
 
@@ -893,11 +939,14 @@ size_t gemm_elem_size(int prec) {
 }
 
 bool gemm_variant_valid(int n, int prec, int variant) {
-  return variant == 0 || (variant == 1 && big_bf16_tiles(n, prec)) || (variant == 2 && folded_bf16_tiles(n, prec));
+  return variant == 0 || ((variant == 1 || variant == 3) && big_bf16_tiles(n, prec)) ||
+         (variant == 2 && folded_bf16_tiles(n, prec));
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
-  return variant == 2 ? (n / TM) * (n / (2 * TN)) : variant == 1 ? (n / TM) * (n / TN) : (n / BM) * (n / BN);
+  return variant == 2                      ? (n / TM) * (n / (2 * TN))
+         : (variant == 1 || variant == 3) ? (n / TM) * (n / TN)
+                                           : (n / BM) * (n / BN);
 }
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }
@@ -923,13 +972,17 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond<TrF32, float>(w, t, st, phase);
   } else if (prec == kGemmF16) {
     if (w.gemm_variant == 1)
-      run_precond_h16<_Float16, float, 64>(w, t, st, phase);
+      run_precond_h16<_Float16, float, 0>(w, t, st, phase);
+    else if (w.gemm_variant == 3)
+      run_precond_h16<_Float16, float, 1>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
     run_precond_bf16_sym<float>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
-    run_precond_h16<__bf16, float, 64>(w, t, st, phase);
+    run_precond_h16<__bf16, float, 0>(w, t, st, phase);
+  } else if (w.gemm_variant == 3) {
+    run_precond_h16<__bf16, float, 1>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

@@ -1242,7 +1242,7 @@ int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_
 }
 
 int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
-  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 2) return RVE_EINVAL;
+  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 3) return RVE_EINVAL;
   // a well-formed shape code (every shape tiles the largest supported grid)
   if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
   c->force_stencil = stencil_choice;

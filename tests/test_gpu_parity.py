@@ -67,11 +67,12 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
             assert np.linalg.norm(zc - ref) <= tol * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
-    # 128-row tiles (1) and the even/odd-folded tiles (2, half the MFMA work,
-    # one more BF16 rounding of the folded input) against the FFT apply
+    # 128-row tiles (1; 3 with the operands loaded straight into LDS) and the
+    # even/odd-folded tiles (2, half the MFMA work, one more BF16 rounding of
+    # the folded input) against the FFT apply
     rve = _rve()
     rng = np.random.default_rng(n + variant)
     a = _fields(n, 2, 52)
@@ -436,7 +437,7 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
     r = rng.standard_normal((2, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     E = q1.symbol(n)
-    for variant in (0, 1):
+    for variant in (0, 1, 3):
         ctx = rve.Context(0)
         ctx.force_variants(gemm=variant)
         z = rve.apply_precond(_to(a, dev), _to(r, dev), 3, ctx=ctx).cpu().numpy()
@@ -460,6 +461,39 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
             for b in range(2):
                 assert rel2(A[b], A64[b]) <= 1e-8
     assert its[3] < its[2] and its[3] <= its[0] + 0.15 * its[0], its
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("n", [384, 512])
+def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
+    # the two 128 x 128 operand pipelines accumulate in the same order, so
+    # the preconditioner and whole solves agree bit for bit (n = 384: three
+    # tiles per axis, twelve K slices, no XCD remap of the tile order)
+    rve = _rve()
+    rng = np.random.default_rng(n + 7 * prec)
+    a = _fields(n, 3, 56)
+    r = rng.standard_normal((3, 2, n, n))
+    r -= r.mean(axis=(2, 3), keepdims=True)
+    out = {}
+    for variant in (1, 3):
+        ctx = rve.Context(0)
+        ctx.set_autotune(False)
+        ctx.force_variants(gemm=variant)
+        z = rve.apply_precond(_to(a, dev), _to(r, dev), prec, ctx=ctx).cpu().numpy()
+        res = rve.solve_batch(_to(a, dev), 1.0 / 8, rve.Options(tol=1e-10, prec=prec), ctx=ctx)
+        assert res.code == 0
+        out[variant] = (z, res.ahom.cpu().numpy(), res.ahom_flux.cpu().numpy(), res.iters.cpu().numpy(),
+                        res.phi.cpu().numpy())
+        ctx.close()
+    for x1, x3 in zip(out[1], out[3]):
+        assert np.array_equal(x1, x3)
+    E = q1.symbol(n)
+    z = out[3][0]
+    for b in range(3):
+        a0 = oa.preconditioner_scale(a[b])
+        ref = precond_apply(r[b, 1], a0, E)
+        zc = z[b, 1] - z[b, 1].mean()
+        assert np.linalg.norm(zc - ref) <= (3e-2 if prec == 2 else 3e-3) * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
