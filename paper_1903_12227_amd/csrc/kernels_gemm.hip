@@ -335,6 +335,26 @@ __device__ inline void lds_dma16(const T* src, T* lds_wave) {
   __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)lds_wave, 16, 0, 0);
 }
 
+// One 32-wide K step of a wave's 4 x 4 MFMA blocks: the eight fragment
+// reads (rd(0, i): A rows 16 i.., rd(1, j): B rows 16 j..) are all issued
+// before the first MFMA, and a scheduling barrier keeps them there; left to
+// itself the compiler reused one register set for the A fragments and waited
+// for each read in turn, exposing the LDS latency four times per step.
+template <class T, class RD>
+__device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
+  typedef typename H16<T>::v8 v8t;
+  v8t bf[4], af[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bf[j] = rd(1, j);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) af[i] = rd(0, i);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af[i], bf[j], acc[i][j]);
+}
+
 template <class T, int EPI, class ZT, class RT = double, int PIPE = 0>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
@@ -414,18 +434,11 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       const bool more = k0 + TK < n;
       if (more) RVE_GLOAD(k0 + TK);
 #pragma unroll
-      for (int kk = 0; kk < TK; kk += 32) {
-        v8t bf[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bf[j] = *reinterpret_cast<const v8t*>(Bs + (wn * 64 + j * 16 + frow) * TLDA + kk + fk);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const v8t af = *reinterpret_cast<const v8t*>(As + (wm * 64 + i * 16 + frow) * TLDA + kk + fk);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
-        }
-      }
+      for (int kk = 0; kk < TK; kk += 32)
+        h16_kstep<T>(acc, [&](int isb, int q) {
+          const T* row = isb ? Bs + (wn * 64 + q * 16 + frow) * TLDA : As + (wm * 64 + q * 16 + frow) * TLDA;
+          return *reinterpret_cast<const v8t*>(row + kk + fk);
+        });
       __syncthreads();
       if (more) {
         RVE_SSTORE();
@@ -466,16 +479,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       if (ks + 1 < nk) issue((ks + 1) & 1, (ks + 1) * DK);
       const T* Ab = As + (ks & 1) * kBuf;
       const T* Bb = Ab + TM * DK;
-      v8t bf[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bf[j] = *reinterpret_cast<const v8t*>(Bb + ((wn * 64 + j * 16 + frow) * 4 + fc) * 8);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const v8t af = *reinterpret_cast<const v8t*>(Ab + ((wm * 64 + i * 16 + frow) * 4 + fc) * 8);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
-      }
+      h16_kstep<T>(acc, [&](int isb, int q) {
+        const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * 64 + q * 16 + frow) * DK;
+        return *reinterpret_cast<const v8t*>(row + fc * 8);
+      });
     }
   }
 
