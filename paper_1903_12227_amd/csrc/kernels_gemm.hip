@@ -340,35 +340,55 @@ __device__ inline void lds_dma16(const T* src, T* lds_wave) {
 // before the first MFMA, and a scheduling barrier keeps them there; left to
 // itself the compiler reused one register set for the A fragments and waited
 // for each read in turn, exposing the LDS latency four times per step.
-template <class T, class RD>
+// GROUPED = false (for the register-tight 256 x 128 tile) reads the A
+// fragments one at a time, 16 fewer live registers.
+template <class T, bool GROUPED = true, class RD>
 __device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
   typedef typename H16<T>::v8 v8t;
-  v8t bf[4], af[4];
+  v8t bf[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) bf[j] = rd(1, j);
+  if constexpr (GROUPED) {
+    v8t af[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) af[i] = rd(0, i);
-  __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < 4; ++i) af[i] = rd(0, i);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af[i], bf[j], acc[i][j]);
+      for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af[i], bf[j], acc[i][j]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const v8t af = rd(0, i);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
+    }
+  }
 }
 
-template <class T, int EPI, class ZT, class RT = double, int PIPE = 0>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
+// WMR is the number of 64-row wave rows: 2 (128 x 128 tile, 256 threads,
+// three waves per SIMD) or 4 (256 x 128 tile, 512 threads, four waves per
+// SIMD, PIPE 0 only): the taller tile loads a quarter fewer operand bytes per
+// output, which is what the load path of this kernel is short of. At 128
+// VGPRs it reads the A fragments one at a time, and the z epilogue (EPI 2)
+// spills there, so that transform stays at WMR = 2.
+template <class T, int EPI, class ZT, class RT = double, int PIPE = 0, int WMR = 2>
+__global__ void __launch_bounds__(128 * WMR) __attribute__((amdgpu_waves_per_eu(WMR == 2 ? 3 : 4, WMR == 2 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ einv,
               const RT* __restrict__ rres, double* __restrict__ part, double emin) {
   static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
+  static_assert(WMR == 2 || (WMR == 4 && PIPE == 0), "tile height");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
-  constexpr size_t kSmem = PIPE == 0 ? 2 * (size_t)TM * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
+  constexpr int TMR = 64 * WMR, NTH = 128 * WMR, NW = NTH / kWave;
+  constexpr size_t kSmem = PIPE == 0 ? (size_t)(TMR + TN) * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
-  __shared__ double red[4];
+  __shared__ double red[NW];
   T* As = reinterpret_cast<T*>(smem);
 
-  const int NB = n / TN, MB = n / TM;
+  const int NB = n / TN, MB = n / TMR;
   const long long NT = (long long)S * MB * NB;
   long long t = blockIdx.x;
   if ((NT & 7) == 0) t = (t & 7) * (NT >> 3) + (t >> 3);   // XCD-contiguous tile ranges
@@ -379,7 +399,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   if (sys && !sys[s].active) return;
 
   const long long N2 = (long long)n * n;
-  const T* Xs = X + (long long)s * N2 + (long long)mb * TM * n;
+  const T* Xs = X + (long long)s * N2 + (long long)mb * TMR * n;
   const T* Qs = Qm + (long long)nb * TN * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
@@ -395,8 +415,9 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 
   if constexpr (PIPE == 0) {
     constexpr int TPR = TK / 8;                 // threads per staged row (8 elements each)
-    constexpr int RPP = kBlock / TPR;           // rows per staging pass (4 passes per tile)
-    T* Bs = As + TM * TLDA;
+    constexpr int RPP = NTH / TPR;              // rows per staging pass: 4 passes for A,
+                                                // 4 (WMR = 2) or 2 (WMR = 4) for B
+    T* Bs = As + TMR * TLDA;
     const int lr = tid / TPR, lc = (tid % TPR) * 8;
     // register staging of the next K slice in named registers (plain code:
     // arrays or lambdas put it in scratch)
@@ -412,8 +433,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));     \
     rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                 \
     rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));         \
-    rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));     \
-    rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));     \
+    if constexpr (WMR == 2) {                                         \
+      rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));   \
+      rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));   \
+    }                                                                 \
   } while (0)
 #define RVE_SSTORE()                                                  \
   do {                                                                \
@@ -423,8 +446,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * TLDA + lc) = ra3; \
     *reinterpret_cast<uint4*>(Bs + lr * TLDA + lc) = rb0;             \
     *reinterpret_cast<uint4*>(Bs + (lr + RPP) * TLDA + lc) = rb1;     \
-    *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * TLDA + lc) = rb2; \
-    *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * TLDA + lc) = rb3; \
+    if constexpr (WMR == 2) {                                         \
+      *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * TLDA + lc) = rb2; \
+      *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * TLDA + lc) = rb3; \
+    }                                                                 \
   } while (0)
     const int fk = (lane >> 4) * 8;
     RVE_GLOAD(0);
@@ -435,7 +460,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       if (more) RVE_GLOAD(k0 + TK);
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 32)
-        h16_kstep<T>(acc, [&](int isb, int q) {
+        h16_kstep<T, WMR == 2>(acc, [&](int isb, int q) {
           const T* row = isb ? Bs + (wn * 64 + q * 16 + frow) * TLDA : As + (wm * 64 + q * 16 + frow) * TLDA;
           return *reinterpret_cast<const v8t*>(row + kk + fk);
         });
@@ -499,7 +524,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     const long long l = (long long)nb * TN + wn * 64 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const long long m = (long long)mb * TM + wm * 64 + i * 16 + m4;
+      const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
       const long long o = (long long)s * N2 + l * n + m;
       float v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
       if constexpr (EPI == kEpiEinv) {
@@ -533,9 +558,16 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     }
   }
   if constexpr (EPI == kEpiZ) {
-    double d[1] = {dot};
-    block_sum<1>(d, red);
-    if (tid == 0) part[(long long)s * (MB * NB) + mb * NB + nb] = scaled ? d[0] * es.dot : d[0];
+    // wave sums, then the NW wave totals added in a fixed order
+    dot = wave_sum(dot);
+    if (lane == 0) red[w] = dot;
+    __syncthreads();
+    if (tid == 0) {
+      double d = red[0];
+#pragma unroll
+      for (int k = 1; k < NW; ++k) d += red[k];
+      part[(long long)s * (MB * NB) + mb * NB + nb] = scaled ? d * es.dot : d;
+    }
   }
 }
 
@@ -893,29 +925,32 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
                        w.real, nullptr, w.r, w.part_rz, em);
 }
 
-// The four transforms with the 128 x 128 16-bit kernel (T = BF16 or FP16)
-// and operand pipeline PIPE.
-template <class T, class ZT, int PIPE>
+// The four transforms with the 16-bit kernel (T = BF16 or FP16), operand
+// pipeline PIPE and 64 WMR x 128 tiles.
+template <class T, class ZT, int PIPE, int WMR = 2>
 void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
-  const long long NT = (long long)w.S * (n / TM) * (n / TN);
-  const dim3 grid((unsigned)NT), block(kBlock);
+  const long long NT = (long long)w.S * (n / (64 * WMR)) * (n / TN);
+  const long long NT2 = (long long)w.S * (n / TM) * (n / TN);
+  const dim3 grid((unsigned)NT), block(128 * WMR), grid2((unsigned)NT2), block2(kBlock);
   const T* Q = reinterpret_cast<const T*>(t.q);
   T* u1 = reinterpret_cast<T*>(w.u1);
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE>), grid, block, 0, st, (const T*)w.rlo, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, (const T*)w.rlo, Q,
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE>), grid, block, 0, st, u1, Q, (void*)u2, n, w.S, w.sys,
-                       w.real, t.einv32, (const double*)nullptr, nullptr, em);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE, WMR>), grid, block, 0, st, u1, Q, (void*)u2, n,
+                       w.S, w.sys, w.real, t.einv32, (const double*)nullptr, nullptr, em);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE>), grid, block, 0, st, u2, Q, (void*)u1, n, w.S, w.sys,
-                       w.real, nullptr, (const double*)nullptr, nullptr, em);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, u2, Q, (void*)u1, n,
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
+  // the last transform (z and the r.z partials) always in 128 x 128 tiles:
+  // its epilogue does not fit the 256 x 128 tile's register budget
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, PIPE>), grid, block, 0, st, u1, Q, w.z, n, w.S, w.sys, w.real,
-                       nullptr, (const T*)w.rlo, w.part_rz, em);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, PIPE, 2>), grid2, block2, 0, st, u1, Q, w.z, n, w.S, w.sys,
+                       w.real, nullptr, (const T*)w.rlo, w.part_rz, em);
 }
 
 template <class ZT>
@@ -947,12 +982,13 @@ size_t gemm_elem_size(int prec) {
 
 bool gemm_variant_valid(int n, int prec, int variant) {
   return variant == 0 || ((variant == 1 || variant == 3) && big_bf16_tiles(n, prec)) ||
-         (variant == 2 && folded_bf16_tiles(n, prec));
+         (variant == 2 && folded_bf16_tiles(n, prec)) || (variant == 4 && big_bf16_tiles(n, prec) && n % 256 == 0);
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
-  return variant == 2                      ? (n / TM) * (n / (2 * TN))
-         : (variant == 1 || variant == 3) ? (n / TM) * (n / TN)
+  // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3)
+  return variant == 2                                    ? (n / TM) * (n / (2 * TN))
+         : (variant == 1 || variant == 3 || variant == 4) ? (n / TM) * (n / TN)
                                            : (n / BM) * (n / BN);
 }
 
@@ -982,6 +1018,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond_h16<_Float16, float, 0>(w, t, st, phase);
     else if (w.gemm_variant == 3)
       run_precond_h16<_Float16, float, 1>(w, t, st, phase);
+    else if (w.gemm_variant == 4)
+      run_precond_h16<_Float16, float, 0, 4>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
@@ -990,6 +1028,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond_h16<__bf16, float, 0>(w, t, st, phase);
   } else if (w.gemm_variant == 3) {
     run_precond_h16<__bf16, float, 1>(w, t, st, phase);
+  } else if (w.gemm_variant == 4) {
+    run_precond_h16<__bf16, float, 0, 4>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }
