@@ -371,13 +371,13 @@ __device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
 // three waves per SIMD) or 4 (256 x 128 tile, 512 threads, four waves per
 // SIMD, PIPE 0 only): the taller tile loads a quarter fewer operand bytes per
 // output, which is what the load path of this kernel is short of. At 128
-// VGPRs it reads the A fragments one at a time, and the z epilogue (EPI 2)
-// spills there, so that transform stays at WMR = 2.
+// VGPRs it reads the A fragments one at a time, and the EPI 1 and EPI 2
+// epilogues spill there, so those transforms stay at WMR = 2.
 template <class T, int EPI, class ZT, class RT = double, int PIPE = 0, int WMR = 2>
 __global__ void __launch_bounds__(128 * WMR) __attribute__((amdgpu_waves_per_eu(WMR == 2 ? 3 : 4, WMR == 2 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
-              const SysState* sys, const RealState* real, const float* __restrict__ einv,
-              const RT* __restrict__ rres, double* __restrict__ part, double emin) {
+              const SysState* sys, const RealState* real, const float* __restrict__ sin2,
+              const RT* __restrict__ rres, double* __restrict__ part, double emin, int fd) {
   static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
   static_assert(WMR == 2 || (WMR == 4 && PIPE == 0), "tile height");
   typedef typename H16<T>::v8 v8t;
@@ -511,8 +511,16 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     }
   }
 
-  float scale = 1.f;
-  if constexpr (EPI == kEpiEinv) scale = scaled ? 1.f : (float)real[s >> 1].inv_a0;
+  // EPI 1 scales output (l, m) by f / E(l, m), E formed from s_k =
+  // sin^2(pi k / n) (no cancellation near the zero mode): the Q1 symbol
+  // (8 - 2c_l - 2c_m - 4 c_l c_m)/3 = 4 (s_l + s_m) - (16/3) s_l s_m, the
+  // five-point one (2 - 2c_l) + (2 - 2c_m) = 4 (s_l + s_m); E(0, 0) = 0 gives
+  // 0 (the pseudo-inverse). f = 1/a0, or E_min for the scaled FP16 operands.
+  float fscale = 1.f, cq = 0.f;
+  if constexpr (EPI == kEpiEinv) {
+    fscale = scaled ? (float)emin : (float)real[s >> 1].inv_a0;
+    cq = fd ? 0.f : 16.f / 3.f;
+  }
   const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
   double dot = 0.0;
   // straight from the accumulators: block (i, j) of lane l holds output
@@ -528,8 +536,14 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       const long long o = (long long)s * N2 + l * n + m;
       float v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
       if constexpr (EPI == kEpiEinv) {
-        const float4 g = *reinterpret_cast<const float4*>(einv + l * n + m);
-        v[0] *= g.x * scale; v[1] *= g.y * scale; v[2] *= g.z * scale; v[3] *= g.w * scale;
+        const float sl = sin2[l];
+        const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
+        const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
+          v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
+        }
       }
       if constexpr (EPI == kEpiZ) {
         ZT* out = reinterpret_cast<ZT*>(out_v) + o;
@@ -939,18 +953,19 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   const double em = t.emin;
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, (const T*)w.rlo, Q,
-                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em, 0);
+  // the transform scaling by 1/E and the last one (z and the r.z partials)
+  // always in 128 x 128 tiles: their epilogues do not fit the 256 x 128
+  // tile's register budget
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE, WMR>), grid, block, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, t.einv32, (const double*)nullptr, nullptr, em);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE, 2>), grid2, block2, 0, st, u1, Q, (void*)u2, n,
+                       w.S, w.sys, w.real, t.sin2, (const double*)nullptr, nullptr, em, t.fd);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em);
-  // the last transform (z and the r.z partials) always in 128 x 128 tiles:
-  // its epilogue does not fit the 256 x 128 tile's register budget
+                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 3)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, PIPE, 2>), grid2, block2, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const T*)w.rlo, w.part_rz, em);
+                       w.real, nullptr, (const T*)w.rlo, w.part_rz, em, 0);
 }
 
 template <class ZT>

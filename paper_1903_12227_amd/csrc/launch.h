@@ -173,6 +173,10 @@ struct GemmTables {
   // FP16 transforms: the residual copy is scaled per system (SysState::lo_scale),
   // einv32 / einv3_32 hold E_min / E and the last transform unscales
   double emin = 1.0;
+  // [n] sin^2(pi k / n), from which the 16-bit 2D transforms form 1/E
+  // (fd = 1: the five-point symbol) instead of reading an n x n table
+  const float* sin2 = nullptr;
+  int fd = 0;
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.

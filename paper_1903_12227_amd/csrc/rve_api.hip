@@ -52,6 +52,7 @@ struct Tables {
   float* einvh_fd = nullptr;
   float* einv3h = nullptr;
   double emin = 1.0, emin_fd = 1.0, emin3 = 1.0;
+  float* sin2 = nullptr;   // [n] sin^2(pi k / n) (the 16-bit transforms form 1/E from it)
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
@@ -186,9 +187,16 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
     einvh[i] = (float)(einv[i] * emin);
     einvh_fd[i] = (float)(einvf[i] * emin_fd);
   }
+  std::vector<float> sin2(n);
+  for (int k = 0; k < n; ++k) {
+    const double sk = std::sin(0.5 * two_pi * (double)k / (double)n);
+    sin2[k] = (float)(sk * sk);
+  }
   Tables t;
   t.emin = emin;
   t.emin_fd = emin_fd;
+  if (hipMalloc(&t.sin2, (size_t)n * 4) != hipSuccess) return RVE_ENOMEM;
+  HIP_TRY(hipMemcpy(t.sin2, sin2.data(), (size_t)n * 4, hipMemcpyHostToDevice));
   if (hipMalloc(&t.qh, N2 * 2) != hipSuccess || hipMalloc(&t.einvh, N2 * 4) != hipSuccess ||
       hipMalloc(&t.einvh_fd, N2 * 4) != hipSuccess) {
     ignore(hipFree(t.qh)); ignore(hipFree(t.einvh)); ignore(hipFree(t.einvh_fd));
@@ -285,6 +293,8 @@ GemmTables gemm_tables(const Tables* tb, int prec, int scheme) {
   g.einv3_64 = tb->einv3_64;
   g.ch16 = tb->ch16;
   g.sh16 = tb->sh16;
+  g.sin2 = tb->sin2;
+  g.fd = fd ? 1 : 0;
   if (prec == RVE_MIX_FP16) {
     g.q = tb->qh;
     g.einv32 = fd ? tb->einvh_fd : tb->einvh;
@@ -914,6 +924,7 @@ int rve_destroy(rve_ctx* c) {
     ignore(hipFree(kv.second.qh));
     ignore(hipFree(kv.second.einvh));
     ignore(hipFree(kv.second.einvh_fd));
+    ignore(hipFree(kv.second.sin2));
   }
   clear_graphs(c);
   if (c->ws) ignore(hipFree(c->ws));
