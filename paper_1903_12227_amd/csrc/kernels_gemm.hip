@@ -371,13 +371,14 @@ __device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
 // three waves per SIMD) or 4 (256 x 128 tile, 512 threads, four waves per
 // SIMD, PIPE 0 only): the taller tile loads a quarter fewer operand bytes per
 // output, which is what the load path of this kernel is short of. At 128
-// VGPRs it reads the A fragments one at a time, and the EPI 1 and EPI 2
-// epilogues spill there, so those transforms stay at WMR = 2.
-template <class T, int EPI, class ZT, class RT = double, int PIPE = 0, int WMR = 2>
+// VGPRs it reads the A fragments one at a time; the EPI 1 epilogue, and the
+// EPI 2 one with the scaled FP16 operands, spill there, so those transforms
+// stay at WMR = 2.
+template <class T, int EPI, class ZT, int PIPE = 0, int WMR = 2>
 __global__ void __launch_bounds__(128 * WMR) __attribute__((amdgpu_waves_per_eu(WMR == 2 ? 3 : 4, WMR == 2 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ sin2,
-              const RT* __restrict__ rres, double* __restrict__ part, double emin, int fd) {
+              double* __restrict__ part, double emin, int fd) {
   static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
   static_assert(WMR == 2 || (WMR == 4 && PIPE == 0), "tile height");
   typedef typename H16<T>::v8 v8t;
@@ -516,10 +517,21 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   // (8 - 2c_l - 2c_m - 4 c_l c_m)/3 = 4 (s_l + s_m) - (16/3) s_l s_m, the
   // five-point one (2 - 2c_l) + (2 - 2c_m) = 4 (s_l + s_m); E(0, 0) = 0 gives
   // 0 (the pseudo-inverse). f = 1/a0, or E_min for the scaled FP16 operands.
+  // It also forms the r.z partials: its input X = (R Q)^T, so its product
+  // X Q is the two-dimensional transform R^ = Q R Q of the residual copy R,
+  // its output U = R^ ./ (a0 E) (as stored), and z = Q U Q; since Q is
+  // symmetric and orthogonal, r.z = sum R^ .* U (FP64 sum). With the scaled
+  // FP16 operands R = sigma r and U = R^ E_min / E, so the sum is multiplied
+  // by 1 / (sigma^2 E_min a0).
   float fscale = 1.f, cq = 0.f;
+  double dfac = 1.0;
   if constexpr (EPI == kEpiEinv) {
     fscale = scaled ? (float)emin : (float)real[s >> 1].inv_a0;
     cq = fd ? 0.f : 16.f / 3.f;
+    if constexpr (scaled) {
+      const double sig = sys ? sys[s].lo_scale : 1.0;
+      dfac = real[s >> 1].inv_a0 / (sig * sig * emin);
+    }
   }
   const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
   double dot = 0.0;
@@ -534,25 +546,14 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     for (int i = 0; i < 4; ++i) {
       const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
       const long long o = (long long)s * N2 + l * n + m;
-      float v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
-      if constexpr (EPI == kEpiEinv) {
-        const float sl = sin2[l];
-        const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
-        const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
-          v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
-        }
-      }
+      const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
       if constexpr (EPI == kEpiZ) {
         ZT* out = reinterpret_cast<ZT*>(out_v) + o;
         ZT zs[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          if constexpr (scaled) zs[e] = (ZT)((double)v[e] * es.z);
-          else zs[e] = (ZT)v[e];
-          dot += (double)zs[e] * widen(rres[o + e]);
+          if constexpr (scaled) zs[e] = (ZT)((double)r[e] * es.z);
+          else zs[e] = (ZT)r[e];
         }
         if constexpr (sizeof(ZT) == 4) {
           float4 st;
@@ -563,15 +564,30 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           for (int e = 0; e < 4; ++e) out[e] = zs[e];
         }
       } else {
+        float v[4] = {r[0], r[1], r[2], r[3]};
+        if constexpr (EPI == kEpiEinv) {
+          const float sl = sin2[l];
+          const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
+          const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
+            v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
+          }
+        }
         typedef T v4t __attribute__((ext_vector_type(4)));
         v4t pk;
 #pragma unroll
         for (int e = 0; e < 4; ++e) pk[e] = (T)v[e];
         *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
+        if constexpr (EPI == kEpiEinv) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dot += (double)r[e] * (double)(float)pk[e];
+        }
       }
     }
   }
-  if constexpr (EPI == kEpiZ) {
+  if constexpr (EPI == kEpiEinv) {
     // wave sums, then the NW wave totals added in a fixed order
     dot = wave_sum(dot);
     if (lane == 0) red[w] = dot;
@@ -580,7 +596,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       double d = red[0];
 #pragma unroll
       for (int k = 1; k < NW; ++k) d += red[k];
-      part[(long long)s * (MB * NB) + mb * NB + nb] = scaled ? d * es.dot : d;
+      part[(long long)s * (MB * NB) + mb * NB + nb] = d * dfac;
     }
   }
 }
@@ -952,20 +968,23 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, (const T*)w.rlo, Q,
-                       (void*)u1, n, w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em, 0);
-  // the transform scaling by 1/E and the last one (z and the r.z partials)
-  // always in 128 x 128 tiles: their epilogues do not fit the 256 x 128
-  // tile's register budget
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR>), grid, block, 0, st, (const T*)w.rlo, Q,
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
+  // the transform scaling by 1/E (which also forms the r.z partials) always
+  // in 128 x 128 tiles: its epilogue does not fit the 256 x 128 tile's
+  // register budget
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, double, PIPE, 2>), grid2, block2, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, t.sin2, (const double*)nullptr, nullptr, em, t.fd);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, 2>), grid2, block2, 0, st, u1, Q, (void*)u2, n,
+                       w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, double, PIPE, WMR>), grid, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, (const double*)nullptr, nullptr, em, 0);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR>), grid, block, 0, st, u2, Q, (void*)u1, n,
+                       w.S, w.sys, w.real, nullptr, nullptr, em, 0);
+  // the last transform (z) in 256 x 128 tiles too, except with the scaled
+  // FP16 operands, whose epilogue spills there
+  constexpr int WZ = std::is_same<T, _Float16>::value ? 2 : WMR;
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, T, PIPE, 2>), grid2, block2, 0, st, u1, Q, w.z, n, w.S, w.sys,
-                       w.real, nullptr, (const T*)w.rlo, w.part_rz, em, 0);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ>), WZ == WMR ? grid : grid2, WZ == WMR ? block : block2, 0,
+                       st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
 }
 
 template <class ZT>

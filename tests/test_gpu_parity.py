@@ -71,7 +71,7 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
     # 128-row tiles (1; 3 with the operands loaded straight into LDS; 4 with
-    # 256-row tiles for the first and third transforms) and the even/odd-folded
+    # 256-row tiles for three of the four transforms) and the even/odd-folded
     # tiles (2, half the MFMA work, one more BF16 rounding of the folded
     # input) against the FFT apply
     rve = _rve()
@@ -468,7 +468,7 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
 @pytest.mark.parametrize("n", [384, 512])
 def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     # the 16-bit transform variants (1: 128 x 128 register-staged, 3: LDS
-    # loaded, 4: 256 x 128 for the first and third transforms, n % 256 == 0)
+    # loaded, 4: 256 x 128 for three of the four transforms, n % 256 == 0)
     # accumulate every output in the same order, so the preconditioner and
     # whole solves agree bit for bit (n = 384: three tiles per axis, twelve K
     # slices, no XCD remap of the tile order)
