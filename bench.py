@@ -93,10 +93,13 @@ def bytes_per_node(prec_name, flexible):
       stencil   fused direction step + operator apply: read z, p_old;
                 write p_new, q (per system), read a (once)
       gemm1     read the r copy (FP64 r on the FP64 path), write T1
-      gemm2     read T1, write W = (Q R Q)./(a0 E)   (1/E is one shared n x n table)
+      gemm2     read T1, write W = (Q R Q)./(a0 E)   (1/E: a shared table, or
+                formed in the 16-bit kernels; those also take r.z here, as
+                the sum of (Q R Q) .* W)
       gemm3     read W, write T3
-      gemm4     read T3, write z, re-read the residual the transforms started
-                from (the r copy; FP64 r on the FP64 path) for r.z
+      gemm4     read T3, write z; FP64 / FP32 transforms also re-read the
+                residual the transforms started from (FP64 r, or the r copy)
+                for r.z
       update_r  read r, q [+ z for flexible beta]; write r [+ r copy]
       fold_x    x += sum alpha_j p_j over the direction ring: per fold,
                 read and write x; per direction, read p once (handled in
@@ -111,7 +114,7 @@ def bytes_per_node(prec_name, flexible):
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
-        "gemm4": sg + sp + first_in,
+        "gemm4": sg + sp + (0 if sg == 2 else first_in),
         "update_r": 8 + 8 + 8 + lo + (sp if flexible else 0),
         "fold_x": sp,
     }
