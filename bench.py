@@ -89,9 +89,11 @@ def bytes_per_node(prec_name, flexible):
 
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
-    precision (s_g bytes) that the first transform reads; x, r, q stay FP64.
+    precision (s_g bytes) that the first transform reads; x, r stay FP64.
+    With the FP64 operator apply (all workloads timed here) q = A p is never
+    stored: the residual update recomputes it from p_new and a.
       stencil   fused direction step + operator apply: read z, p_old;
-                write p_new, q (per system), read a (once)
+                write p_new (per system), read a (once)
       gemm1     read the r copy (FP64 r on the FP64 path), write T1
       gemm2     read T1, write W = (Q R Q)./(a0 E)   (1/E: a shared table, or
                 formed in the 16-bit kernels; those also take r.z here, as
@@ -100,7 +102,8 @@ def bytes_per_node(prec_name, flexible):
       gemm4     read T3, write z; FP64 / FP32 transforms also re-read the
                 residual the transforms started from (FP64 r, or the r copy)
                 for r.z
-      update_r  read r, q [+ z for flexible beta]; write r [+ r copy]
+      update_r  read r, p_new, a (shared by the two systems: 4 bytes each)
+                [+ z for flexible beta]; write r [+ r copy]
       fold_x    x += sum alpha_j p_j over the direction ring: per fold,
                 read and write x; per direction, read p once (handled in
                 kernel_entries: 16 ceil(iters / ring) + s_p iters per system)
@@ -110,12 +113,12 @@ def bytes_per_node(prec_name, flexible):
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": 2 * (sp + sp + sp + 8) + 8,
+        "stencil": 2 * (sp + sp + sp) + 8,
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
         "gemm4": sg + sp + (0 if sg == 2 else first_in),
-        "update_r": 8 + 8 + 8 + lo + (sp if flexible else 0),
+        "update_r": 8 + sp + 4 + 8 + lo + (sp if flexible else 0),
         "fold_x": sp,
     }
 

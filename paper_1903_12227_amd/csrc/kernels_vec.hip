@@ -353,7 +353,8 @@ __device__ inline void raw_load(const T* p, T* v) {
 // iteration would; its outputs are rewritten by the real iteration 0.
 // Not FUSED: the operand is p_in.
 // SCH selects the operator: 0 the consistent Q1 nine-point stencil, 1 the
-// lumped five-point one.
+// lumped five-point one. wq = 0 (FUSED only) skips the store of q: the
+// residual update then recomputes it (k_update_r_st).
 // CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
 // FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
 // FP64 either way (the product of two FP32 values is exact in FP64).
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
                                                        long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part,
-                                                       int probe) {
+                                                       int probe, int wq) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
   int first = 0;
@@ -488,7 +489,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
           qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
       }
       if (act[i]) {
-        VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
+        if (wq) VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
         if constexpr (FUSED) {
           CT pn[V];
 #pragma unroll
@@ -523,6 +524,173 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
       part[(long long)s0 * P + tile] = d[0];
       part[(long long)s1 * P + tile] = d[1];
     }
+  }
+}
+
+// V values of the GEMM-precision residual copy (scaled for FP16).
+template <class LoT, int V>
+__device__ inline void store_lo_v(LoT* p, const double* v, double sc) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) p[k] = (LoT)(float)(kScaledLo<LoT> ? v[k] * sc : v[k]);
+}
+
+// Residual update in the operator apply's tile shape, with A p_k recomputed:
+// r -= alpha_k A p_k for both systems of a realization, r.r partials per tile,
+// the GEMM-precision copy of r, and r.z_old partials for the flexible beta.
+// The operand is the direction p_k the fused apply stored into ring slot
+// k mod m (its values are those the apply used, already rounded to their
+// storage type), and A p_k comes from the same coefficient reads and
+// arithmetic as there; so the apply need not store q (8 bytes per node and
+// system) and this kernel reads p_k (4 bytes with FP32 directions) and the
+// coefficients (shared by both systems) instead of q. Tiles, XCD remap and
+// the sliding three-row window as in k_stencil_v; each row's r (and z) is
+// loaded with the coefficient row, one row ahead with D = 2.
+template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH>
+__global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a, const PT* ring,
+                                                         long long slot_stride, int m, const int* kiter,
+                                                         const ZT* __restrict__ z, double* __restrict__ r,
+                                                         LoT* __restrict__ rlo, int n, int H, const SysState* sys,
+                                                         double* __restrict__ part_rr,
+                                                         double* __restrict__ part_rzo, int flexible) {
+  static_assert(D == 1 || D == 2, "prefetch depth");
+  __shared__ double sh[4 * 4];
+  const PT* __restrict__ pk = ring + (long long)(kiter[0] % m) * slot_stride;
+  const int gx = n / (kWave * V), gy = n / (4 * H);
+  const unsigned T = gridDim.x, L = blockIdx.x;
+  const unsigned t = (T & 7u) ? L : (L & 7u) * (T >> 3) + (L >> 3);
+  const int bx = (int)(t % (unsigned)gx);
+  const int by = (int)((t / (unsigned)gx) % (unsigned)gy);
+  const int b = (int)(t / (unsigned)(gx * gy));
+  const int s0 = 2 * b, s1 = s0 + 1;
+  const int act[2] = {sys[s0].active, sys[s1].active};
+  if (!act[0] && !act[1]) return;   // uniform over the workgroup
+  const double al[2] = {sys[s0].alpha, sys[s1].alpha};
+  const double sc[2] = {lo_scale_of<LoT>(sys[s0]), lo_scale_of<LoT>(sys[s1])};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long N2 = (long long)n * n;
+  const int c0 = (bx * kWave + lane) * V;
+  const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
+  const int row0 = by * 4 * H + w * H;
+  const CT* A = a + (long long)b * N2;
+  const PT* P[2] = {pk + (long long)s0 * N2, pk + (long long)s1 * N2};
+
+  // operand row o (V + 2 values per system), coefficient row oa (V + 1
+  // values) and, with_r, that row's r (and z for the flexible beta)
+  struct Raw {
+    PT p[2][V + 2];
+    CT a[V + 1];
+    double r[2][V];
+    ZT z[2][V];
+  };
+  auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a, bool with_r) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      raw_load<PT, V>(P[i] + o + c0, &R.p[i][1]);
+      R.p[i][0] = P[i][o + cl];
+      R.p[i][V + 1] = P[i][o + cr];
+    }
+    if (with_a) {
+      R.a[0] = A[oa + cl];
+      raw_load<CT, V>(A + oa + c0, &R.a[1]);
+    }
+    if (with_r) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (act[i]) {
+          raw_load<double, V>(r + (long long)(s0 + i) * N2 + oa + c0, R.r[i]);
+          if (flexible) raw_load<ZT, V>(z + (long long)(s0 + i) * N2 + oa + c0, R.z[i]);
+        }
+    }
+  };
+  auto cook = [&](const Raw& R, int i, CT* u) {
+#pragma unroll
+    for (int k = 0; k < V + 2; ++k) u[k] = (CT)R.p[i][k];
+  };
+
+  const int rm = wrap_dec(row0, n);
+  CT um[2][V + 2], uc[2][V + 2], am[V + 1];
+  Raw R0, R1;
+  {
+    load_raw(R0, (long long)rm * n, (long long)rm * n, true, false);
+    load_raw(R1, (long long)row0 * n, 0, false, false);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      cook(R0, i, um[i]);
+      cook(R1, i, uc[i]);
+    }
+#pragma unroll
+    for (int k = 0; k < V + 1; ++k) am[k] = R0.a[k];
+  }
+  if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true, true);
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};   // r.r and r.z_old of both systems
+  auto step = [&](int j, Raw& use, Raw& fill) {
+    const int row = row0 + j;
+    const long long oc = (long long)row * n;
+    if constexpr (D == 1) {
+      load_raw(use, (long long)wrap_inc(row, n) * n, oc, true, true);
+    } else {
+      if (j + 1 < H) {
+        const int r1 = wrap_inc(row, n);
+        load_raw(fill, (long long)wrap_inc(r1, n) * n, (long long)r1 * n, true, true);
+      }
+    }
+    CT up[2][V + 2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) cook(use, i, up[i]);
+    const CT* ac = use.a;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      CT qv[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const CT sm[3] = {um[i][k], um[i][k + 1], um[i][k + 2]};
+        const CT sc3[3] = {uc[i][k], uc[i][k + 1], uc[i][k + 2]};
+        const CT sp[3] = {up[i][k], up[i][k + 1], up[i][k + 2]};
+        if constexpr (SCH == 1)
+          qv[k] = fd5_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc3, sp);
+        else
+          qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc3, sp);
+      }
+      if (act[i]) {
+        double rv[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          rv[k] = fma(-al[i], (double)qv[k], use.r[i][k]);
+          acc[i] += rv[k] * rv[k];
+        }
+        VecIO<double, V>::store(r + (long long)(s0 + i) * N2 + oc + c0, rv);
+        if constexpr (LO) store_lo_v<LoT, V>(rlo + (long long)(s0 + i) * N2 + oc + c0, rv, sc[i]);
+        if (flexible) {
+#pragma unroll
+          for (int k = 0; k < V; ++k) acc[2 + i] += rv[k] * (double)use.z[i][k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < V + 2; ++k) {
+        um[i][k] = uc[i][k];
+        uc[i][k] = up[i][k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
+  };
+  if constexpr (D == 1) {
+    for (int j = 0; j < H; ++j) step(j, R0, R0);
+  } else {
+    for (int j = 0; j < H; j += 2) {   // H is even; the two buffers swap roles
+      step(j, R0, R1);
+      step(j + 1, R1, R0);
+    }
+  }
+  block_sum<4>(acc, sh);
+  if (threadIdx.x == 0) {
+    const int Pt = gx * gy;
+    const int tile = by * gx + bx;
+    part_rr[(long long)s0 * Pt + tile] = acc[0];
+    part_rr[(long long)s1 * Pt + tile] = acc[1];
+    part_rzo[(long long)s0 * Pt + tile] = acc[2];
+    part_rzo[(long long)s1 * Pt + tile] = acc[3];
   }
 }
 
@@ -1023,30 +1191,30 @@ bool stencil_choice_valid(int n, int c) {
 template <bool FUSED, class PT, class ZT, int D, class CT, int SCH>
 void launch_stencil_d(int B, int n, int V, int H, const CT* a, const PT* pin, PT* ring, long long slot_stride,
                       int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
-                      int probe, hipStream_t st) {
+                      int probe, int wq, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe);
+                       kiter, z, q, n, H, sys, part, probe, wq);
   else if (V == 2)
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe);
+                       kiter, z, q, n, H, sys, part, probe, wq);
   else
     hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe);
+                       kiter, z, q, n, H, sys, part, probe, wq);
 }
 
 template <bool FUSED, class PT, class ZT, class CT, int SCH>
 void launch_stencil_t(int B, int n, int c, const CT* a, const PT* pin, PT* ring, long long slot_stride, int m,
                       const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
-                      hipStream_t st) {
+                      hipStream_t st, int wq = 1) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
     launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                probe, st);
+                                                probe, wq, st);
   else
     launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                probe, st);
+                                                probe, wq, st);
 }
 
 template <class PT>
@@ -1058,10 +1226,12 @@ void launch_stencil_fused_p(const Work& w, int probe, hipStream_t st) {
                                              probe, st);
   else if (w.scheme == 1)
     launch_stencil_t<true, PT, PT, double, 1>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
+                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
+                                              !w.qfree);
   else
     launch_stencil_t<true, PT, PT, double, 0>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st);
+                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
+                                              !w.qfree);
 }
 
 void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
@@ -1076,6 +1246,47 @@ void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
 
 int stencil_tiles_per_realization(int n, int c) {
   return (n / (kWave * stencil_choice_V(c))) * (n / (4 * stencil_choice_H(c)));
+}
+
+template <class PT, class LoT, bool LO, int D, int SCH>
+void launch_update_r_st_d(const Work& w, int flexible, hipStream_t st) {
+  const int V = stencil_choice_V(w.stencil), H = stencil_choice_H(w.stencil);
+  const dim3 g((unsigned)((w.n / (kWave * V)) * (w.n / (4 * H)) * w.B)), blk(kBlock);
+  const long long slot = (long long)w.S * w.N2;
+  const PT* ring = (const PT*)w.pring;
+  const PT* z = (const PT*)w.z;
+  LoT* rlo = (LoT*)w.rlo;
+  if (V == 4)
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
+                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
+                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+  else
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
+                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+}
+
+template <class PT, class LoT, bool LO>
+void launch_update_r_st_l(const Work& w, int flexible, hipStream_t st) {
+  const bool d2 = stencil_choice_D(w.stencil) == 2;
+  if (w.scheme == 1) {
+    if (d2) launch_update_r_st_d<PT, LoT, LO, 2, 1>(w, flexible, st);
+    else launch_update_r_st_d<PT, LoT, LO, 1, 1>(w, flexible, st);
+  } else {
+    if (d2) launch_update_r_st_d<PT, LoT, LO, 2, 0>(w, flexible, st);
+    else launch_update_r_st_d<PT, LoT, LO, 1, 0>(w, flexible, st);
+  }
+}
+
+// the residual update with A p_k recomputed (w.qfree: FP64 operator apply,
+// two dimensions); r.r and r.z_old partials per apply tile (w.P_rr = w.P_st)
+template <class PT>
+void launch_update_r_st_p(const Work& w, int flexible, hipStream_t st) {
+  if (w.mixed == 0) launch_update_r_st_l<PT, double, false>(w, flexible, st);
+  else if (w.mixed == 1) launch_update_r_st_l<PT, float, true>(w, flexible, st);
+  else if (w.mixed == 3) launch_update_r_st_l<PT, _Float16, true>(w, flexible, st);
+  else launch_update_r_st_l<PT, __bf16, true>(w, flexible, st);
 }
 
 template <class QT>
@@ -1097,6 +1308,11 @@ void launch_update_r_q(const Work& w, int flexible, hipStream_t st) {
 }
 
 void launch_update_r(const Work& w, int flexible, hipStream_t st) {
+  if (w.qfree) {
+    if (w.mixed == 0) launch_update_r_st_p<double>(w, flexible, st);
+    else launch_update_r_st_p<float>(w, flexible, st);
+    return;
+  }
   // q = A p is FP32 with the FP32 operator apply
   if (w.sprec)
     launch_update_r_q<float>(w, flexible, st);
@@ -1189,13 +1405,13 @@ void launch_scalar_alpha(const Work& w, hipStream_t st) {
 
 
 void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_vec, tol, maxit,
+  hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_rr, tol, maxit,
                      w.count, (const int*)w.kiter, (int)(w.mixed == 3), sqrt((double)w.N2));
 }
 
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_beta, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rz, w.P_gemm, w.part_rzo,
-                     w.P_vec, flexible, first);
+                     w.P_rr, flexible, first);
 }
 
 void launch_round_lo(const Work& w, hipStream_t st) {

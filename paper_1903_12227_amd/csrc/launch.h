@@ -62,6 +62,11 @@ struct Work {
   int P_tile = 0;   // workgroups per realization of the RHS / A_hom / gradient kernels
   int P_st = 0;     // workgroups per realization of the operator apply
   int P_vec = 0;    // workgroups per system of the vector kernels
+  // qfree = 1 (two dimensions, FP64 operator apply): the fused apply does not
+  // store q = A p and the residual update recomputes it in the apply's tile
+  // shape; its r.r / r.z_old partials then number P_st per system, else P_vec
+  int qfree = 0;
+  int P_rr = 0;
   int P_gemm = 0;   // output tiles per system of the transform GEMMs
 };
 

@@ -354,8 +354,11 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   L.off_sys = o; o += align_up(S * sizeof(SysState));
   L.off_real = o; o += align_up(B * sizeof(RealState));
   L.off_pq = o; o += align_up(S * std::max(P_tile, P_st) * 8);
-  L.off_rr = o; o += align_up(S * P_vec * 8);
-  L.off_rzo = o; o += align_up(S * P_vec * 8);
+  // r.r / r.z_old partials: per vector workgroup, or per apply tile of the
+  // recomputing residual update (at most (n/64)^2 tiles per realization)
+  const long long P_rr_max = dim == 3 ? P_vec : std::max<long long>(P_vec, (long long)(n / kWave) * (n / kWave));
+  L.off_rr = o; o += align_up(S * P_rr_max * 8);
+  L.off_rzo = o; o += align_up(S * P_rr_max * 8);
   L.off_rz = o; o += align_up(S * (dim == 3 ? gemm_tiles_per_system3(n) : gemm_tiles_per_system_max(n)) * 8);
   L.off_misc = o; o += align_up((size_t)B * P_tile * misc_nv * 8);
   L.off_status = o; o += align_up((size_t)B * sizeof(int));
@@ -368,6 +371,8 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   w->P_tile = P_tile;
   w->P_st = P_st;
   w->P_vec = P_vec;
+  w->P_rr = P_vec;
+  w->qfree = 0;
   w->P_gemm = P_gemm;
   w->mixed = gp;   // GemmPrec: 0 FP64, 1 FP32, 2 BF16, 3 FP16
   w->stencil = sc;
@@ -784,6 +789,11 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     if (ctx->force_stencil >= 0 && stencil_choice_valid(n, ctx->force_stencil)) sc = ctx->force_stencil;
     w.stencil = sc;
     w.P_st = stencil_tiles_per_realization(n, sc);
+    // the residual update recomputes A p in the apply's tile shape (FP64 apply)
+    if (!w.sprec) {
+      w.qfree = 1;
+      w.P_rr = w.P_st;
+    }
   }
 
   // iterations in chunks of kRing, replayed from a captured graph unless
