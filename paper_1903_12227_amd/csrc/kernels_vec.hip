@@ -327,6 +327,19 @@ __device__ inline void raw_load(const T* p, T* v) {
   }
 }
 
+// Streaming accesses (read once, written once per iteration, no reuse
+// within a launch): non-temporal, so they do not displace reused lines in L2.
+template <class T, int V>
+__device__ inline void load_nt(const T* p, T* v) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) v[k] = __builtin_nontemporal_load(p + k);
+}
+template <class T, int V>
+__device__ inline void store_nt(T* p, const T* v) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) __builtin_nontemporal_store(v[k], p + k);
+}
+
 // Operator apply over V consecutive columns per lane for both systems of a
 // realization. A workgroup covers 64V columns x 4H rows; each of its four
 // waves slides a three-row register window down an H-row strip, so every
@@ -597,7 +610,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         if (act[i]) {
-          raw_load<double, V>(r + (long long)(s0 + i) * N2 + oa + c0, R.r[i]);
+          load_nt<double, V>(r + (long long)(s0 + i) * N2 + oa + c0, R.r[i]);
           if (flexible) raw_load<ZT, V>(z + (long long)(s0 + i) * N2 + oa + c0, R.z[i]);
         }
     }
@@ -659,7 +672,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
           rv[k] = fma(-al[i], (double)qv[k], use.r[i][k]);
           acc[i] += rv[k] * rv[k];
         }
-        VecIO<double, V>::store(r + (long long)(s0 + i) * N2 + oc + c0, rv);
+        store_nt<double, V>(r + (long long)(s0 + i) * N2 + oc + c0, rv);
         if constexpr (LO) store_lo_v<LoT, V>(rlo + (long long)(s0 + i) * N2 + oc + c0, rv, sc[i]);
         if (flexible) {
 #pragma unroll
