@@ -331,8 +331,18 @@ __device__ inline void raw_load(const T* p, T* v) {
 // within a launch): non-temporal, so they do not displace reused lines in L2.
 template <class T, int V>
 __device__ inline void load_nt(const T* p, T* v) {
+  constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;   // elements per load
+  typedef T vec_t __attribute__((ext_vector_type(C)));
 #pragma unroll
-  for (int k = 0; k < V; ++k) v[k] = __builtin_nontemporal_load(p + k);
+  for (int k = 0; k < V; k += C) {
+    if constexpr (C == 1) {
+      v[k] = __builtin_nontemporal_load(p + k);
+    } else {
+      const vec_t t = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(p + k));
+#pragma unroll
+      for (int e = 0; e < C; ++e) v[k + e] = t[e];
+    }
+  }
 }
 template <class T, int V>
 __device__ inline void store_nt(T* p, const T* v) {
@@ -803,16 +813,21 @@ __global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const
   }
   for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
     double xv[4], pv[kRing][4];
-    V4<double>::load(x + off + i, xv);
+    load_nt<double, 4>(x + off + i, xv);
 #pragma unroll
-    for (int t = 0; t < kRing; ++t) V4<PT>::load(ring + so[t] + i, pv[t]);
+    for (int t = 0; t < kRing; ++t) {
+      PT pt[4];
+      load_nt<PT, 4>(ring + so[t] + i, pt);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pv[t][k] = (double)pt[k];
+    }
 #pragma unroll
     for (int t = 0; t < kRing; ++t)
       if (j0 + t < hi) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) xv[k] = fma(al[t], pv[t][k], xv[k]);
       }
-    V4<double>::store(x + off + i, xv);
+    store_nt<double, 4>(x + off + i, xv);
   }
 }
 
