@@ -292,7 +292,7 @@ const char* rve_status_string(int status);
  * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
  * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128,
  * 2 = folded 128 x 128, 3 = 128 x 128 loaded straight into LDS, 4 = 256 x
- * 128), 2 (FP32
+ * 128, 5 = 256 x 256), 2 (FP32
  * operator-apply shape) or 3 (five-point
  * operator-apply shape), the last two encoded as kind 0, of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
@@ -354,7 +354,7 @@ int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int6
  * the MFMA work, n % 256 == 0; 3: 128 x 128 16-bit tiles with the operands
  * loaded straight into LDS, n % 128 == 0, the same results as 1; 4: 256 x 128
  * 16-bit tiles for all transforms but the one scaling by 1/E (BF16; FP16:
- * the first and third), n % 256 == 0). An
+ * the first and third), n % 256 == 0; 5: as 4 with 256 x 256 tiles). An
  * override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);

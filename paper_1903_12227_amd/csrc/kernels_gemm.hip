@@ -374,22 +374,26 @@ __device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
 // VGPRs it reads the A fragments one at a time; the EPI 1 epilogue, and the
 // EPI 2 one with the scaled FP16 operands, spill there, so those transforms
 // stay at WMR = 2.
-template <class T, int EPI, class ZT, int PIPE = 0, int WMR = 2>
-__global__ void __launch_bounds__(128 * WMR) __attribute__((amdgpu_waves_per_eu(WMR == 2 ? 3 : 4, WMR == 2 ? 3 : 4)))
+// WNR is the number of 64-column wave columns: 2, or 4 with WMR = 4 (a
+// 256 x 256 tile, 1024 threads: a third fewer operand bytes per output
+// than 256 x 128).
+template <class T, int EPI, class ZT, int PIPE = 0, int WMR = 2, int WNR = 2>
+__global__ void __launch_bounds__(64 * WMR * WNR)
+__attribute__((amdgpu_waves_per_eu(WMR * WNR == 4 ? 3 : 4, WMR * WNR == 4 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ sin2,
               double* __restrict__ part, double emin, int fd) {
   static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
-  static_assert(WMR == 2 || (WMR == 4 && PIPE == 0), "tile height");
+  static_assert((WMR == 2 && WNR == 2) || (WMR == 4 && (WNR == 2 || WNR == 4) && PIPE == 0), "tile shape");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
-  constexpr int TMR = 64 * WMR, NTH = 128 * WMR, NW = NTH / kWave;
-  constexpr size_t kSmem = PIPE == 0 ? (size_t)(TMR + TN) * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
+  constexpr int TMR = 64 * WMR, TNR = 64 * WNR, NTH = 64 * WMR * WNR, NW = WMR * WNR;
+  constexpr size_t kSmem = PIPE == 0 ? (size_t)(TMR + TNR) * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[NW];
   T* As = reinterpret_cast<T*>(smem);
 
-  const int NB = n / TN, MB = n / TMR;
+  const int NB = n / TNR, MB = n / TMR;
   const long long NT = (long long)S * MB * NB;
   long long t = blockIdx.x;
   if ((NT & 7) == 0) t = (t & 7) * (NT >> 3) + (t >> 3);   // XCD-contiguous tile ranges
@@ -401,9 +405,9 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 
   const long long N2 = (long long)n * n;
   const T* Xs = X + (long long)s * N2 + (long long)mb * TMR * n;
-  const T* Qs = Qm + (long long)nb * TN * n;
+  const T* Qs = Qm + (long long)nb * TNR * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WNR, wn = w % WNR;
   const int frow = lane & 15;
 
   v4f acc[4][4];
@@ -416,8 +420,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 
   if constexpr (PIPE == 0) {
     constexpr int TPR = TK / 8;                 // threads per staged row (8 elements each)
-    constexpr int RPP = NTH / TPR;              // rows per staging pass: 4 passes for A,
-                                                // 4 (WMR = 2) or 2 (WMR = 4) for B
+    constexpr int RPP = NTH / TPR;              // rows per staging pass: 8 / WNR passes
+                                                // for A, 8 / WMR for B (4 or 2)
+    constexpr int PA = TMR / RPP, PB = TNR / RPP;
+    static_assert((PA == 2 || PA == 4) && (PB == 2 || PB == 4), "staging passes");
     T* Bs = As + TMR * TLDA;
     const int lr = tid / TPR, lc = (tid % TPR) * 8;
     // register staging of the next K slice in named registers (plain code:
@@ -430,11 +436,13 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   do {                                                                \
     ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                 \
     ra1 = *reinterpret_cast<const uint4*>(xa + rstep + (k0));         \
-    ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));     \
-    ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));     \
+    if constexpr (PA == 4) {                                          \
+      ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));   \
+      ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));   \
+    }                                                                 \
     rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                 \
     rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));         \
-    if constexpr (WMR == 2) {                                         \
+    if constexpr (PB == 4) {                                          \
       rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));   \
       rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));   \
     }                                                                 \
@@ -443,11 +451,13 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   do {                                                                \
     *reinterpret_cast<uint4*>(As + lr * TLDA + lc) = ra0;             \
     *reinterpret_cast<uint4*>(As + (lr + RPP) * TLDA + lc) = ra1;     \
-    *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * TLDA + lc) = ra2; \
-    *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * TLDA + lc) = ra3; \
+    if constexpr (PA == 4) {                                          \
+      *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * TLDA + lc) = ra2; \
+      *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * TLDA + lc) = ra3; \
+    }                                                                 \
     *reinterpret_cast<uint4*>(Bs + lr * TLDA + lc) = rb0;             \
     *reinterpret_cast<uint4*>(Bs + (lr + RPP) * TLDA + lc) = rb1;     \
-    if constexpr (WMR == 2) {                                         \
+    if constexpr (PB == 4) {                                          \
       *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * TLDA + lc) = rb2; \
       *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * TLDA + lc) = rb3; \
     }                                                                 \
@@ -461,7 +471,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       if (more) RVE_GLOAD(k0 + TK);
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 32)
-        h16_kstep<T, WMR == 2>(acc, [&](int isb, int q) {
+        h16_kstep<T, NW == 4>(acc, [&](int isb, int q) {
           const T* row = isb ? Bs + (wn * 64 + q * 16 + frow) * TLDA : As + (wm * 64 + q * 16 + frow) * TLDA;
           return *reinterpret_cast<const v8t*>(row + kk + fk);
         });
@@ -541,7 +551,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   const int lr = lane & 15, m4 = 4 * (lane >> 4);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const long long l = (long long)nb * TN + wn * 64 + j * 16 + lr;
+    const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
@@ -957,18 +967,18 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
 
 // The four transforms with the 16-bit kernel (T = BF16 or FP16), operand
 // pipeline PIPE and 64 WMR x 128 tiles.
-template <class T, class ZT, int PIPE, int WMR = 2>
+template <class T, class ZT, int PIPE, int WMR = 2, int WNR = 2>
 void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
-  const long long NT = (long long)w.S * (n / (64 * WMR)) * (n / TN);
+  const long long NT = (long long)w.S * (n / (64 * WMR)) * (n / (64 * WNR));
   const long long NT2 = (long long)w.S * (n / TM) * (n / TN);
-  const dim3 grid((unsigned)NT), block(128 * WMR), grid2((unsigned)NT2), block2(kBlock);
+  const dim3 grid((unsigned)NT), block(64 * WMR * WNR), grid2((unsigned)NT2), block2(kBlock);
   const T* Q = reinterpret_cast<const T*>(t.q);
   T* u1 = reinterpret_cast<T*>(w.u1);
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR>), grid, block, 0, st, (const T*)w.rlo, Q,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, (const T*)w.rlo, Q,
                        (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   // the transform scaling by 1/E (which also forms the r.z partials) always
   // in 128 x 128 tiles: its epilogue does not fit the 256 x 128 tile's
@@ -977,13 +987,14 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, 2>), grid2, block2, 0, st, u1, Q, (void*)u2, n,
                        w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR>), grid, block, 0, st, u2, Q, (void*)u1, n,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, u2, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   // the last transform (z) in 256 x 128 tiles too, except with the scaled
   // FP16 operands, whose epilogue spills there
-  constexpr int WZ = std::is_same<T, _Float16>::value ? 2 : WMR;
+  constexpr bool tallz = !std::is_same<T, _Float16>::value;
+  constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2;
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ>), WZ == WMR ? grid : grid2, WZ == WMR ? block : block2, 0,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN>), tallz ? grid : grid2, tallz ? block : block2, 0,
                        st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
 }
 
@@ -1016,13 +1027,14 @@ size_t gemm_elem_size(int prec) {
 
 bool gemm_variant_valid(int n, int prec, int variant) {
   return variant == 0 || ((variant == 1 || variant == 3) && big_bf16_tiles(n, prec)) ||
-         (variant == 2 && folded_bf16_tiles(n, prec)) || (variant == 4 && big_bf16_tiles(n, prec) && n % 256 == 0);
+         (variant == 2 && folded_bf16_tiles(n, prec)) ||
+         ((variant == 4 || variant == 5) && big_bf16_tiles(n, prec) && n % 256 == 0);
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
   // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3)
   return variant == 2                                    ? (n / TM) * (n / (2 * TN))
-         : (variant == 1 || variant == 3 || variant == 4) ? (n / TM) * (n / TN)
+         : (variant == 1 || variant == 3 || variant == 4 || variant == 5) ? (n / TM) * (n / TN)
                                            : (n / BM) * (n / BN);
 }
 
@@ -1054,6 +1066,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond_h16<_Float16, float, 1>(w, t, st, phase);
     else if (w.gemm_variant == 4)
       run_precond_h16<_Float16, float, 0, 4>(w, t, st, phase);
+    else if (w.gemm_variant == 5)
+      run_precond_h16<_Float16, float, 0, 4, 4>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
@@ -1064,6 +1078,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond_h16<__bf16, float, 1>(w, t, st, phase);
   } else if (w.gemm_variant == 4) {
     run_precond_h16<__bf16, float, 0, 4>(w, t, st, phase);
+  } else if (w.gemm_variant == 5) {
+    run_precond_h16<__bf16, float, 0, 4, 4>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

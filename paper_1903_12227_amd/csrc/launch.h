@@ -45,7 +45,7 @@ struct Work {
   int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (16-bit, n % 128 == 0);
                              // 2: even/odd-folded 128 x 128 (BF16, n % 256 == 0);
                              // 3: as 1 with the operands loaded straight into LDS;
-                             // 4: 256 x 128 (16-bit, n % 256 == 0)
+                             // 4: 256 x 128 (16-bit, n % 256 == 0); 5: 256 x 256
   SysState* sys = nullptr;   // [S]
   RealState* real = nullptr; // [B]
   double* part_pq = nullptr;   // [S][P] partial sums of p.Ap

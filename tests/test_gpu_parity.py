@@ -67,11 +67,11 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
             assert np.linalg.norm(zc - ref) <= tol * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
     # 128-row tiles (1; 3 with the operands loaded straight into LDS; 4 with
-    # 256-row tiles for three of the four transforms) and the even/odd-folded
+    # 256 x 128 / 5: 256 x 256 tiles for three of the four transforms) and the even/odd-folded
     # tiles (2, half the MFMA work, one more BF16 rounding of the folded
     # input) against the FFT apply
     rve = _rve()
@@ -420,7 +420,7 @@ def test_autotuner_choices_and_cache(dev, tmp_path, monkeypatch):
     ch = tuned_ctx.tuned(n, 2, B)
     assert ch["stencil_columns_per_lane"] in (1, 2, 4) and ch["stencil_rows_per_strip"] in (16, 64)
     assert ch["stencil_prefetch_rows"] in (1, 2)
-    assert ch["gemm_variant"] in (0, 1, 4)
+    assert ch["gemm_variant"] in (0, 1, 4, 5)
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 2 and all(line.startswith('{"kind"') for line in lines)
     reload_ctx = rve.Context(0)          # reads the cache at creation
@@ -438,7 +438,7 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
     r = rng.standard_normal((2, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     E = q1.symbol(n)
-    for variant in (0, 1, 3, 4):
+    for variant in (0, 1, 3, 4, 5):
         ctx = rve.Context(0)
         ctx.force_variants(gemm=variant)
         z = rve.apply_precond(_to(a, dev), _to(r, dev), 3, ctx=ctx).cpu().numpy()
@@ -468,7 +468,8 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
 @pytest.mark.parametrize("n", [384, 512])
 def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     # the 16-bit transform variants (1: 128 x 128 register-staged, 3: LDS
-    # loaded, 4: 256 x 128 for three of the four transforms, n % 256 == 0)
+    # loaded, 4 / 5: 256 x 128 / 256 x 256 for three of the four transforms,
+    # n % 256 == 0)
     # accumulate every output in the same order, so the preconditioner and
     # whole solves agree bit for bit (n = 384: three tiles per axis, twelve K
     # slices, no XCD remap of the tile order)
@@ -478,7 +479,7 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     r = rng.standard_normal((3, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     out = {}
-    variants = (1, 3, 4) if n % 256 == 0 else (1, 3)
+    variants = (1, 3, 4, 5) if n % 256 == 0 else (1, 3)
     for variant in variants:
         ctx = rve.Context(0)
         ctx.set_autotune(False)
