@@ -354,7 +354,8 @@ int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int6
  * the MFMA work, n % 256 == 0; 3: 128 x 128 16-bit tiles with the operands
  * loaded straight into LDS, n % 128 == 0, the same results as 1; 4: 256 x 128
  * 16-bit tiles for all transforms but the one scaling by 1/E (BF16; FP16:
- * the first and third), n % 256 == 0; 5: as 4 with 256 x 256 tiles). An
+ * the first and third), n % 256 == 0; 5: 256 x 256 16-bit tiles for all four,
+ * n % 256 == 0). An
  * override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);

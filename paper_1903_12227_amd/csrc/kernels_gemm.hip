@@ -551,6 +551,9 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   const int lr = lane & 15, m4 = 4 * (lane >> 4);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
+    // (the 16-wave tile has no registers to spare for hoisting every block's
+    // loads of the scaling epilogue to the top)
+    if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
     const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -977,22 +980,24 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   T* u1 = reinterpret_cast<T*>(w.u1);
   T* u2 = reinterpret_cast<T*>(w.u2);
   const double em = t.emin;
+  // Tile shape of each transform: the plain ones always take 64 WMR x 64 WNR.
+  // The epilogues of the scaling transform (which also forms the r.z
+  // partials) and of the last one (z) spill in 256 x 128 tiles (the latter
+  // only with the scaled FP16 operands), so there those stay at 128 x 128;
+  // the 256 x 256 tile has the registers for all four.
+  constexpr bool big = WMR == 4 && WNR == 4;
+  constexpr int WE = big ? 4 : 2, WEN = big ? 4 : 2;
+  constexpr bool tallz = big || !std::is_same<T, _Float16>::value;
+  constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2;
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, (const T*)w.rlo, Q,
                        (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
-  // the transform scaling by 1/E (which also forms the r.z partials) always
-  // in 128 x 128 tiles: its epilogue does not fit the 256 x 128 tile's
-  // register budget
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, 2>), grid2, block2, 0, st, u1, Q, (void*)u2, n,
-                       w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN>), big ? grid : grid2, big ? block : block2, 0,
+                       st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, u2, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, nullptr, em, 0);
-  // the last transform (z) in 256 x 128 tiles too, except with the scaled
-  // FP16 operands, whose epilogue spills there
-  constexpr bool tallz = !std::is_same<T, _Float16>::value;
-  constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2;
   if (phase < 0 || phase == 3)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN>), tallz ? grid : grid2, tallz ? block : block2, 0,
                        st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
@@ -1032,9 +1037,11 @@ bool gemm_variant_valid(int n, int prec, int variant) {
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
-  // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3)
+  // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3;
+  // variant 5 from its 256 x 256 tiles)
   return variant == 2                                    ? (n / TM) * (n / (2 * TN))
-         : (variant == 1 || variant == 3 || variant == 4 || variant == 5) ? (n / TM) * (n / TN)
+         : variant == 5                                  ? (n / 256) * (n / 256)
+         : (variant == 1 || variant == 3 || variant == 4) ? (n / TM) * (n / TN)
                                            : (n / BM) * (n / BN);
 }
 

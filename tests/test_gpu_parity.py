@@ -71,7 +71,8 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
     # 128-row tiles (1; 3 with the operands loaded straight into LDS; 4 with
-    # 256 x 128 / 5: 256 x 256 tiles for three of the four transforms) and the even/odd-folded
+    # 256 x 128 tiles for three of the four transforms, 5 with 256 x 256 for
+    # all four) and the even/odd-folded
     # tiles (2, half the MFMA work, one more BF16 rounding of the folded
     # input) against the FFT apply
     rve = _rve()
@@ -468,11 +469,11 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
 @pytest.mark.parametrize("n", [384, 512])
 def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     # the 16-bit transform variants (1: 128 x 128 register-staged, 3: LDS
-    # loaded, 4 / 5: 256 x 128 / 256 x 256 for three of the four transforms,
-    # n % 256 == 0)
-    # accumulate every output in the same order, so the preconditioner and
-    # whole solves agree bit for bit (n = 384: three tiles per axis, twelve K
-    # slices, no XCD remap of the tile order)
+    # loaded, 4: 256 x 128 for three of the four transforms, 5: 256 x 256
+    # for all four; 4 and 5 need n % 256 == 0) accumulate every output in the
+    # same order, so the preconditioner agrees bit for bit, and whole solves
+    # too except for variant 5's r.z partial sums (n = 384: three tiles per
+    # axis, twelve K slices, no XCD remap of the tile order)
     rve = _rve()
     rng = np.random.default_rng(n + 7 * prec)
     a = _fields(n, 3, 56)
@@ -491,6 +492,14 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
                         res.phi.cpu().numpy())
         ctx.close()
     for v in variants[1:]:
+        if v == 5:
+            # z bit for bit; the r.z partials come from 256 x 256 tiles, so the
+            # solve differs only by the summation order of those partials
+            assert np.array_equal(out[1][0], out[5][0])
+            for x1, xv in zip(out[1][1:3], out[5][1:3]):
+                assert np.max(np.abs(x1 - xv)) <= 1e-12 * np.max(np.abs(x1))
+            assert np.max(np.abs(out[1][3].astype(int) - out[5][3])) <= 1
+            continue
         for x1, xv in zip(out[1], out[v]):
             assert np.array_equal(x1, xv), v
     E = q1.symbol(n)
