@@ -514,10 +514,10 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
       if (act[i]) {
         if (wq) VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
         if constexpr (FUSED) {
-          CT pn[V];
+          PT pn[V];
 #pragma unroll
-          for (int k = 0; k < V; ++k) pn[k] = uc[i][k + 1];
-          VecIO<PT, V>::store(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
+          for (int k = 0; k < V; ++k) pn[k] = (PT)uc[i][k + 1];
+          store_nt<PT, V>(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
         }
       }
 #pragma unroll
