@@ -388,230 +388,297 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
   constexpr int TMR = 64 * WMR, TNR = 64 * WNR, NTH = 64 * WMR * WNR, NW = WMR * WNR;
-  constexpr size_t kSmem = PIPE == 0 ? (size_t)(TMR + TNR) * TLDA * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
+  // the 16-wave tile stages its operands in two LDS buffers (147 KB): the
+  // next slice is stored while other waves still read the current one, one
+  // barrier per K slice instead of two; the smaller tiles keep one buffer
+  // (two would cost them a workgroup per CU)
+  constexpr int NSTG = (PIPE == 0 && NW == 16) ? 2 : 1;
+  constexpr size_t kStage = (size_t)(TMR + TNR) * TLDA;
+  constexpr size_t kSmem = PIPE == 0 ? NSTG * kStage * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[NW];
   T* As = reinterpret_cast<T*>(smem);
 
+  // Tiles of this workgroup: local indices li, li + lstep, ... below lend,
+  // counted from tile base. With NT and the grid multiples of 8, workgroup b
+  // (on XCD b % 8) takes tiles from range b % 8 of eight contiguous ones, so
+  // the tiles that share operand rows meet in one XCD's L2. One workgroup
+  // per tile (the grid must then cover every tile), except the plain
+  // transform in 16-wave tiles (PERS): there the grid may be smaller (one
+  // workgroup per CU), and each workgroup loads the first K slice of its
+  // next tile while it computes the last slice of this one and stores its
+  // outputs. (The scaling and last transforms gained nothing from it: their
+  // epilogues are longer and need the registers.)
+  constexpr bool PERS = PIPE == 0 && NW == 16 && EPI == kEpiStore;
   const int NB = n / TNR, MB = n / TMR;
-  const long long NT = (long long)S * MB * NB;
-  long long t = blockIdx.x;
-  if ((NT & 7) == 0) t = (t & 7) * (NT >> 3) + (t >> 3);   // XCD-contiguous tile ranges
-  const int nb = (int)(t % NB);
-  const long long rest = t / NB;
-  const int mb = (int)(rest % MB);
-  const int s = (int)(rest / MB);
-  if (sys && !sys[s].active) return;
+  const long long NT = (long long)S * MB * NB, N2 = (long long)n * n;
+  long long base = 0, li = blockIdx.x, lend = NT, lstep = gridDim.x;
+  if ((NT & 7) == 0 && (gridDim.x & 7) == 0) {
+    base = (long long)(blockIdx.x & 7) * (NT >> 3);
+    li = blockIdx.x >> 3;
+    lend = NT >> 3;
+    lstep = gridDim.x >> 3;
+  }
+  // first local index at or after l whose system is active (lend if none)
+  auto seek = [&](long long l) {
+    while (l < lend && sys && !sys[(base + l) / ((long long)MB * NB)].active) l += lstep;
+    return l;
+  };
 
-  const long long N2 = (long long)n * n;
-  const T* Xs = X + (long long)s * N2 + (long long)mb * TMR * n;
-  const T* Qs = Qm + (long long)nb * TNR * n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WNR, wn = w % WNR;
   const int frow = lane & 15;
 
-  v4f acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.f;
+  constexpr int TPR = TK / 8;                 // threads per staged row (8 elements each)
+  constexpr int RPP = NTH / TPR;              // rows per staging pass: 8 / WNR passes
+                                              // for A, 8 / WMR for B (4 or 2)
+  constexpr int PA = TMR / RPP, PB = TNR / RPP;
+  static_assert(PIPE == 1 || ((PA == 2 || PA == 4) && (PB == 2 || PB == 4)), "staging passes");
+  const int lr = tid / TPR, lc = (tid % TPR) * 8;
+  const int loff = lr * n + lc;   // (lr < 128 and n <= 4096: well inside 32 bits)
+  const long long rstep = (long long)RPP * n;
+  // register staging of the next K slice in named registers (plain code:
+  // arrays or lambdas put it in scratch)
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define RVE_GLOAD(xp, qp, k0)                                         \
+  do {                                                                \
+    ra0 = *reinterpret_cast<const uint4*>((xp) + (k0));               \
+    ra1 = *reinterpret_cast<const uint4*>((xp) + rstep + (k0));       \
+    if constexpr (PA == 4) {                                          \
+      ra2 = *reinterpret_cast<const uint4*>((xp) + 2 * rstep + (k0)); \
+      ra3 = *reinterpret_cast<const uint4*>((xp) + 3 * rstep + (k0)); \
+    }                                                                 \
+    rb0 = *reinterpret_cast<const uint4*>((qp) + (k0));               \
+    rb1 = *reinterpret_cast<const uint4*>((qp) + rstep + (k0));       \
+    if constexpr (PB == 4) {                                          \
+      rb2 = *reinterpret_cast<const uint4*>((qp) + 2 * rstep + (k0)); \
+      rb3 = *reinterpret_cast<const uint4*>((qp) + 3 * rstep + (k0)); \
+    }                                                                 \
+  } while (0)
+#define RVE_SSTORE(Ad)                                                \
+  do {                                                                \
+    T* const Bd = (Ad) + TMR * TLDA;                                  \
+    *reinterpret_cast<uint4*>((Ad) + lr * TLDA + lc) = ra0;           \
+    *reinterpret_cast<uint4*>((Ad) + (lr + RPP) * TLDA + lc) = ra1;   \
+    if constexpr (PA == 4) {                                          \
+      *reinterpret_cast<uint4*>((Ad) + (lr + 2 * RPP) * TLDA + lc) = ra2; \
+      *reinterpret_cast<uint4*>((Ad) + (lr + 3 * RPP) * TLDA + lc) = ra3; \
+    }                                                                 \
+    *reinterpret_cast<uint4*>(Bd + lr * TLDA + lc) = rb0;             \
+    *reinterpret_cast<uint4*>(Bd + (lr + RPP) * TLDA + lc) = rb1;     \
+    if constexpr (PB == 4) {                                          \
+      *reinterpret_cast<uint4*>(Bd + (lr + 2 * RPP) * TLDA + lc) = rb2; \
+      *reinterpret_cast<uint4*>(Bd + (lr + 3 * RPP) * TLDA + lc) = rb3; \
+    }                                                                 \
+  } while (0)
 
-  if constexpr (PIPE == 0) {
-    constexpr int TPR = TK / 8;                 // threads per staged row (8 elements each)
-    constexpr int RPP = NTH / TPR;              // rows per staging pass: 8 / WNR passes
-                                                // for A, 8 / WMR for B (4 or 2)
-    constexpr int PA = TMR / RPP, PB = TNR / RPP;
-    static_assert((PA == 2 || PA == 4) && (PB == 2 || PB == 4), "staging passes");
-    T* Bs = As + TMR * TLDA;
-    const int lr = tid / TPR, lc = (tid % TPR) * 8;
-    // register staging of the next K slice in named registers (plain code:
-    // arrays or lambdas put it in scratch)
-    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-    const T* xa = Xs + (long long)lr * n + lc;
-    const T* qa = Qs + (long long)lr * n + lc;
-    const long long rstep = (long long)RPP * n;
-#define RVE_GLOAD(k0)                                                 \
-  do {                                                                \
-    ra0 = *reinterpret_cast<const uint4*>(xa + (k0));                 \
-    ra1 = *reinterpret_cast<const uint4*>(xa + rstep + (k0));         \
-    if constexpr (PA == 4) {                                          \
-      ra2 = *reinterpret_cast<const uint4*>(xa + 2 * rstep + (k0));   \
-      ra3 = *reinterpret_cast<const uint4*>(xa + 3 * rstep + (k0));   \
-    }                                                                 \
-    rb0 = *reinterpret_cast<const uint4*>(qa + (k0));                 \
-    rb1 = *reinterpret_cast<const uint4*>(qa + rstep + (k0));         \
-    if constexpr (PB == 4) {                                          \
-      rb2 = *reinterpret_cast<const uint4*>(qa + 2 * rstep + (k0));   \
-      rb3 = *reinterpret_cast<const uint4*>(qa + 3 * rstep + (k0));   \
-    }                                                                 \
-  } while (0)
-#define RVE_SSTORE()                                                  \
-  do {                                                                \
-    *reinterpret_cast<uint4*>(As + lr * TLDA + lc) = ra0;             \
-    *reinterpret_cast<uint4*>(As + (lr + RPP) * TLDA + lc) = ra1;     \
-    if constexpr (PA == 4) {                                          \
-      *reinterpret_cast<uint4*>(As + (lr + 2 * RPP) * TLDA + lc) = ra2; \
-      *reinterpret_cast<uint4*>(As + (lr + 3 * RPP) * TLDA + lc) = ra3; \
-    }                                                                 \
-    *reinterpret_cast<uint4*>(Bs + lr * TLDA + lc) = rb0;             \
-    *reinterpret_cast<uint4*>(Bs + (lr + RPP) * TLDA + lc) = rb1;     \
-    if constexpr (PB == 4) {                                          \
-      *reinterpret_cast<uint4*>(Bs + (lr + 2 * RPP) * TLDA + lc) = rb2; \
-      *reinterpret_cast<uint4*>(Bs + (lr + 3 * RPP) * TLDA + lc) = rb3; \
-    }                                                                 \
-  } while (0)
-    const int fk = (lane >> 4) * 8;
-    RVE_GLOAD(0);
-    RVE_SSTORE();
-    __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += TK) {
-      const bool more = k0 + TK < n;
-      if (more) RVE_GLOAD(k0 + TK);
+  bool pref = false;   // the first K slice of the tile is already in LDS
+  int cur = 0;         // operand buffer of the current K slice (two stages)
+  for (li = seek(li); li < lend;) {
+    const long long t = base + li;
+    const int nb = (int)(t % NB);
+    const long long rest = t / NB;
+    const int mb = (int)(rest % MB);
+    const int s = (int)(rest / MB);
+    const long long lnext = PERS ? seek(li + lstep) : lend;
+    const T* Xs = X + (long long)s * N2 + (long long)mb * TMR * n;
+    const T* Qs = Qm + (long long)nb * TNR * n;
+
+    v4f acc[4][4];
 #pragma unroll
-      for (int kk = 0; kk < TK; kk += 32)
-        h16_kstep<T, NW == 4>(acc, [&](int isb, int q) {
-          const T* row = isb ? Bs + (wn * 64 + q * 16 + frow) * TLDA : As + (wm * 64 + q * 16 + frow) * TLDA;
-          return *reinterpret_cast<const v8t*>(row + kk + fk);
-        });
-      __syncthreads();
-      if (more) {
-        RVE_SSTORE();
-        __syncthreads();
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.f;
+
+    if constexpr (PIPE == 0) {
+      // (the empty asm keeps the per-lane offset out of the loop-invariant
+      // addresses the compiler would hoist out of the tile loop and spill)
+      int lo = loff;
+      if constexpr (PERS) asm volatile("" : "+v"(lo));
+      const T* xa = Xs + lo;
+      const T* qa = Qs + lo;
+      const int fk = (lane >> 4) * 8;
+      if (!pref) {
+        RVE_GLOAD(xa, qa, 0);
+        RVE_SSTORE(As + cur * kStage);
       }
-    }
-#undef RVE_GLOAD
-#undef RVE_SSTORE
-  } else {
-    // buffer b holds the A tile (128 x 32) then the B tile; 16-byte chunk g
-    // of a tile sits at LDS chunk g and holds row g / 4, K chunk
-    // (g % 4) ^ ((row / 2) % 4). Lane l of wave w loads chunks 128 w + l and
-    // 128 w + 64 + l of both tiles.
-    constexpr int kBuf = 2 * TM * DK;
-    const int g0 = 128 * w + lane, g1 = g0 + 64;
-    const int r0 = g0 >> 2, r1 = g1 >> 2;
-    const int c0 = (g0 & 3) ^ ((r0 >> 1) & 3), c1 = (g1 & 3) ^ ((r1 >> 1) & 3);
-    const T* xa0 = Xs + (long long)r0 * n + 8 * c0;
-    const T* xa1 = Xs + (long long)r1 * n + 8 * c1;
-    const T* qa0 = Qs + (long long)r0 * n + 8 * c0;
-    const T* qa1 = Qs + (long long)r1 * n + 8 * c1;
-    auto issue = [&](int b, int k0) {
-      T* base = As + b * kBuf + 1024 * w;
-      lds_dma16(xa0 + k0, base);
-      lds_dma16(xa1 + k0, base + 512);
-      lds_dma16(qa0 + k0, base + TM * DK);
-      lds_dma16(qa1 + k0, base + TM * DK + 512);
-    };
-    // fragment reads: row (.. + frow), K chunk lane / 16 of the slice
-    const int fc = (lane >> 4) ^ ((frow >> 1) & 3);
-    const int nk = n / DK;
-    issue(0, 0);
-    for (int ks = 0; ks < nk; ++ks) {
-      // this wave's loads of slice ks have landed and its reads of slice
-      // ks - 1 are done; after the barrier the same holds for every wave, so
-      // slice ks is complete and the other buffer is free for slice ks + 1
-      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      if (ks + 1 < nk) issue((ks + 1) & 1, (ks + 1) * DK);
-      const T* Ab = As + (ks & 1) * kBuf;
-      const T* Bb = Ab + TM * DK;
-      h16_kstep<T>(acc, [&](int isb, int q) {
-        const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * 64 + q * 16 + frow) * DK;
-        return *reinterpret_cast<const v8t*>(row + fc * 8);
-      });
-    }
-  }
-
-  // EPI 1 scales output (l, m) by f / E(l, m), E formed from s_k =
-  // sin^2(pi k / n) (no cancellation near the zero mode): the Q1 symbol
-  // (8 - 2c_l - 2c_m - 4 c_l c_m)/3 = 4 (s_l + s_m) - (16/3) s_l s_m, the
-  // five-point one (2 - 2c_l) + (2 - 2c_m) = 4 (s_l + s_m); E(0, 0) = 0 gives
-  // 0 (the pseudo-inverse). f = 1/a0, or E_min for the scaled FP16 operands.
-  // It also forms the r.z partials: its input X = (R Q)^T, so its product
-  // X Q is the two-dimensional transform R^ = Q R Q of the residual copy R,
-  // its output U = R^ ./ (a0 E) (as stored), and z = Q U Q; since Q is
-  // symmetric and orthogonal, r.z = sum R^ .* U (FP64 sum). With the scaled
-  // FP16 operands R = sigma r and U = R^ E_min / E, so the sum is multiplied
-  // by 1 / (sigma^2 E_min a0).
-  float fscale = 1.f, cq = 0.f;
-  double dfac = 1.0;
-  if constexpr (EPI == kEpiEinv) {
-    fscale = scaled ? (float)emin : (float)real[s >> 1].inv_a0;
-    cq = fd ? 0.f : 16.f / 3.f;
-    if constexpr (scaled) {
-      const double sig = sys ? sys[s].lo_scale : 1.0;
-      dfac = real[s >> 1].inv_a0 / (sig * sig * emin);
-    }
-  }
-  const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
-  double dot = 0.0;
-  // straight from the accumulators: block (i, j) of lane l holds output
-  // row nb*128 + 64 wn + 16 j + l % 16 at the four consecutive columns
-  // mb*128 + 64 wm + 16 i + 4 (l / 16) + e
-  const int lr = lane & 15, m4 = 4 * (lane >> 4);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    // (the 16-wave tile has no registers to spare for hoisting every block's
-    // loads of the scaling epilogue to the top)
-    if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
-    const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
-      const long long o = (long long)s * N2 + l * n + m;
-      const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
-      if constexpr (EPI == kEpiZ) {
-        ZT* out = reinterpret_cast<ZT*>(out_v) + o;
-        ZT zs[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if constexpr (scaled) zs[e] = (ZT)((double)r[e] * es.z);
-          else zs[e] = (ZT)r[e];
-        }
-        if constexpr (sizeof(ZT) == 4) {
-          float4 st;
-          st.x = zs[0]; st.y = zs[1]; st.z = zs[2]; st.w = zs[3];
-          *reinterpret_cast<float4*>(out) = st;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) out[e] = zs[e];
-        }
-      } else {
-        float v[4] = {r[0], r[1], r[2], r[3]};
-        if constexpr (EPI == kEpiEinv) {
-          const float sl = sin2[l];
-          const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
-          const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
-            v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
+      __syncthreads();
+      for (int k0 = 0; k0 < n; k0 += TK) {
+        const bool more = k0 + TK < n;
+        // last slice: load the first slice of the next tile instead (stored
+        // to the free buffer like any other, before the epilogue)
+        const bool ahead = PERS && !more && lnext < lend;
+        if (more) {
+          RVE_GLOAD(xa, qa, k0 + TK);
+        } else if constexpr (PERS) {
+          if (ahead) {
+            // (the empty asm keeps the next tile's addresses here, out of
+            // the registers live across the loop)
+            int lo = loff;
+            asm volatile("" : "+v"(lo));
+            const long long tn = base + lnext, rn = tn / NB;
+            const T* xn = X + (rn / MB) * N2 + (rn % MB) * TMR * n + lo;
+            const T* qn = Qm + (tn % NB) * TNR * n + lo;
+            RVE_GLOAD(xn, qn, 0);
           }
         }
-        typedef T v4t __attribute__((ext_vector_type(4)));
-        v4t pk;
+        const T* Ab = As + cur * kStage;
+        const T* Bb = Ab + TMR * TLDA;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) pk[e] = (T)v[e];
-        *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
-        if constexpr (EPI == kEpiEinv) {
+        for (int kk = 0; kk < TK; kk += 32)
+          h16_kstep<T, NW == 4>(acc, [&](int isb, int q) {
+            const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * TLDA : Ab + (wm * 64 + q * 16 + frow) * TLDA;
+            return *reinterpret_cast<const v8t*>(row + kk + fk);
+          });
+        if constexpr (NSTG == 2) {
+          // the other buffer was last read before the previous barrier
+          if (more || ahead) RVE_SSTORE(As + (cur ^ 1) * kStage);
+          __syncthreads();
+          cur ^= 1;
+        } else {
+          __syncthreads();
+          if (more) {
+            RVE_SSTORE(As);
+            __syncthreads();
+          }
+        }
+      }
+      pref = PERS && lnext < lend;   // (already in buffer cur)
+    } else {
+      // buffer b holds the A tile (128 x 32) then the B tile; 16-byte chunk g
+      // of a tile sits at LDS chunk g and holds row g / 4, K chunk
+      // (g % 4) ^ ((row / 2) % 4). Lane l of wave w loads chunks 128 w + l and
+      // 128 w + 64 + l of both tiles.
+      constexpr int kBuf = 2 * TM * DK;
+      const int g0 = 128 * w + lane, g1 = g0 + 64;
+      const int r0 = g0 >> 2, r1 = g1 >> 2;
+      const int c0 = (g0 & 3) ^ ((r0 >> 1) & 3), c1 = (g1 & 3) ^ ((r1 >> 1) & 3);
+      const T* xa0 = Xs + (long long)r0 * n + 8 * c0;
+      const T* xa1 = Xs + (long long)r1 * n + 8 * c1;
+      const T* qa0 = Qs + (long long)r0 * n + 8 * c0;
+      const T* qa1 = Qs + (long long)r1 * n + 8 * c1;
+      auto issue = [&](int b, int k0) {
+        T* base = As + b * kBuf + 1024 * w;
+        lds_dma16(xa0 + k0, base);
+        lds_dma16(xa1 + k0, base + 512);
+        lds_dma16(qa0 + k0, base + TM * DK);
+        lds_dma16(qa1 + k0, base + TM * DK + 512);
+      };
+      // fragment reads: row (.. + frow), K chunk lane / 16 of the slice
+      const int fc = (lane >> 4) ^ ((frow >> 1) & 3);
+      const int nk = n / DK;
+      issue(0, 0);
+      for (int ks = 0; ks < nk; ++ks) {
+        // this wave's loads of slice ks have landed and its reads of slice
+        // ks - 1 are done; after the barrier the same holds for every wave, so
+        // slice ks is complete and the other buffer is free for slice ks + 1
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (ks + 1 < nk) issue((ks + 1) & 1, (ks + 1) * DK);
+        const T* Ab = As + (ks & 1) * kBuf;
+        const T* Bb = Ab + TM * DK;
+        h16_kstep<T>(acc, [&](int isb, int q) {
+          const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * 64 + q * 16 + frow) * DK;
+          return *reinterpret_cast<const v8t*>(row + fc * 8);
+        });
+      }
+    }
+
+    // EPI 1 scales output (l, m) by f / E(l, m), E formed from s_k =
+    // sin^2(pi k / n) (no cancellation near the zero mode): the Q1 symbol
+    // (8 - 2c_l - 2c_m - 4 c_l c_m)/3 = 4 (s_l + s_m) - (16/3) s_l s_m, the
+    // five-point one (2 - 2c_l) + (2 - 2c_m) = 4 (s_l + s_m); E(0, 0) = 0 gives
+    // 0 (the pseudo-inverse). f = 1/a0, or E_min for the scaled FP16 operands.
+    // It also forms the r.z partials: its input X = (R Q)^T, so its product
+    // X Q is the two-dimensional transform R^ = Q R Q of the residual copy R,
+    // its output U = R^ ./ (a0 E) (as stored), and z = Q U Q; since Q is
+    // symmetric and orthogonal, r.z = sum R^ .* U (FP64 sum). With the scaled
+    // FP16 operands R = sigma r and U = R^ E_min / E, so the sum is multiplied
+    // by 1 / (sigma^2 E_min a0).
+    float fscale = 1.f, cq = 0.f;
+    double dfac = 1.0;
+    if constexpr (EPI == kEpiEinv) {
+      fscale = scaled ? (float)emin : (float)real[s >> 1].inv_a0;
+      cq = fd ? 0.f : 16.f / 3.f;
+      if constexpr (scaled) {
+        const double sig = sys ? sys[s].lo_scale : 1.0;
+        dfac = real[s >> 1].inv_a0 / (sig * sig * emin);
+      }
+    }
+    const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
+    double dot = 0.0;
+    // straight from the accumulators: block (i, j) of lane l holds output
+    // row nb*128 + 64 wn + 16 j + l % 16 at the four consecutive columns
+    // mb*128 + 64 wm + 16 i + 4 (l / 16) + e
+    const int lr = lane & 15, m4 = 4 * (lane >> 4);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) dot += (double)r[e] * (double)(float)pk[e];
+    for (int j = 0; j < 4; ++j) {
+      // (the 16-wave tile has no registers to spare for hoisting every block's
+      // loads of the scaling epilogue to the top)
+      if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
+      const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
+        const long long o = (long long)s * N2 + l * n + m;
+        const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+        if constexpr (EPI == kEpiZ) {
+          ZT* out = reinterpret_cast<ZT*>(out_v) + o;
+          ZT zs[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if constexpr (scaled) zs[e] = (ZT)((double)r[e] * es.z);
+            else zs[e] = (ZT)r[e];
+          }
+          if constexpr (sizeof(ZT) == 4) {
+            float4 st;
+            st.x = zs[0]; st.y = zs[1]; st.z = zs[2]; st.w = zs[3];
+            *reinterpret_cast<float4*>(out) = st;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[e] = zs[e];
+          }
+        } else {
+          float v[4] = {r[0], r[1], r[2], r[3]};
+          if constexpr (EPI == kEpiEinv) {
+            const float sl = sin2[l];
+            const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
+            const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
+              v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
+            }
+          }
+          typedef T v4t __attribute__((ext_vector_type(4)));
+          v4t pk;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pk[e] = (T)v[e];
+          *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
+          if constexpr (EPI == kEpiEinv) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dot += (double)r[e] * (double)(float)pk[e];
+          }
         }
       }
     }
-  }
-  if constexpr (EPI == kEpiEinv) {
-    // wave sums, then the NW wave totals added in a fixed order
-    dot = wave_sum(dot);
-    if (lane == 0) red[w] = dot;
-    __syncthreads();
-    if (tid == 0) {
-      double d = red[0];
+    if constexpr (EPI == kEpiEinv) {
+      // wave sums, then the NW wave totals added in a fixed order
+      dot = wave_sum(dot);
+      if (lane == 0) red[w] = dot;
+      __syncthreads();
+      if (tid == 0) {
+        double d = red[0];
 #pragma unroll
-      for (int k = 1; k < NW; ++k) d += red[k];
-      part[(long long)s * (MB * NB) + mb * NB + nb] = d * dfac;
+        for (int k = 1; k < NW; ++k) d += red[k];
+        part[(long long)s * (MB * NB) + mb * NB + nb] = d * dfac;
+      }
     }
+    li = lnext;
   }
+#undef RVE_GLOAD
+#undef RVE_SSTORE
 }
 
 // Even/odd-folded BF16 transform (n % 256 == 0), half the MFMA work of
@@ -975,7 +1042,13 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   const int n = w.n;
   const long long NT = (long long)w.S * (n / (64 * WMR)) * (n / (64 * WNR));
   const long long NT2 = (long long)w.S * (n / TM) * (n / TN);
-  const dim3 grid((unsigned)NT), block(64 * WMR * WNR), grid2((unsigned)NT2), block2(kBlock);
+  constexpr bool big = WMR == 4 && WNR == 4;
+  // The plain transforms in 256 x 256 tiles run one workgroup per CU (a
+  // multiple of 8 of them, one set per XCD), each looping over at least four
+  // tiles; with fewer tiles one workgroup per tile balances better. The
+  // other launches take one workgroup per tile.
+  const long long G = big && t.cus >= 8 && NT >= 4LL * (t.cus & ~7) ? (long long)(t.cus & ~7) : NT;
+  const dim3 gridp((unsigned)G), grid((unsigned)NT), block(64 * WMR * WNR), grid2((unsigned)NT2), block2(kBlock);
   const T* Q = reinterpret_cast<const T*>(t.q);
   T* u1 = reinterpret_cast<T*>(w.u1);
   T* u2 = reinterpret_cast<T*>(w.u2);
@@ -985,18 +1058,17 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   // partials) and of the last one (z) spill in 256 x 128 tiles (the latter
   // only with the scaled FP16 operands), so there those stay at 128 x 128;
   // the 256 x 256 tile has the registers for all four.
-  constexpr bool big = WMR == 4 && WNR == 4;
   constexpr int WE = big ? 4 : 2, WEN = big ? 4 : 2;
   constexpr bool tallz = big || !std::is_same<T, _Float16>::value;
   constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, (const T*)w.rlo, Q,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), gridp, block, 0, st, (const T*)w.rlo, Q,
                        (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN>), big ? grid : grid2, big ? block : block2, 0,
                        st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), grid, block, 0, st, u2, Q, (void*)u1, n,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), gridp, block, 0, st, u2, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 3)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN>), tallz ? grid : grid2, tallz ? block : block2, 0,

@@ -182,6 +182,9 @@ struct GemmTables {
   // (fd = 1: the five-point symbol) instead of reading an n x n table
   const float* sin2 = nullptr;
   int fd = 0;
+  // compute units: the 256 x 256 16-bit transform runs one workgroup per CU
+  // that loops over tiles (0: one workgroup per tile)
+  int cus = 0;
 };
 size_t gemm_elem_size(int prec);
 // z = (a0 A_Delta)^+ r for every active system, with partial sums of r.z.

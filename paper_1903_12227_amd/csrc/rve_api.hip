@@ -53,6 +53,7 @@ struct Tables {
   float* einv3h = nullptr;
   double emin = 1.0, emin_fd = 1.0, emin3 = 1.0;
   float* sin2 = nullptr;   // [n] sin^2(pi k / n) (the 16-bit transforms form 1/E from it)
+  int cus = 0;             // compute units of the device
 };
 
 // Timed kernels: 0 fused direction step + operator apply, 1..4 the four
@@ -195,6 +196,7 @@ int build_tables(rve_ctx* ctx, int n, Tables** out) {
   Tables t;
   t.emin = emin;
   t.emin_fd = emin_fd;
+  HIP_TRY(hipDeviceGetAttribute(&t.cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
   if (hipMalloc(&t.sin2, (size_t)n * 4) != hipSuccess) return RVE_ENOMEM;
   HIP_TRY(hipMemcpy(t.sin2, sin2.data(), (size_t)n * 4, hipMemcpyHostToDevice));
   if (hipMalloc(&t.qh, N2 * 2) != hipSuccess || hipMalloc(&t.einvh, N2 * 4) != hipSuccess ||
@@ -295,6 +297,7 @@ GemmTables gemm_tables(const Tables* tb, int prec, int scheme) {
   g.sh16 = tb->sh16;
   g.sin2 = tb->sin2;
   g.fd = fd ? 1 : 0;
+  g.cus = tb->cus;
   if (prec == RVE_MIX_FP16) {
     g.q = tb->qh;
     g.einv32 = fd ? tb->einvh_fd : tb->einvh;
