@@ -511,6 +511,44 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
         assert np.linalg.norm(zc - ref) <= (3e-2 if prec == 2 else 3e-3) * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("prec", [2, 3])
+def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
+    # with at least four 256 x 256 tiles per CU (here 160 realizations, 320
+    # systems, 1280 tiles at n = 512) the plain transforms of variant 5 run
+    # one workgroup per CU over a range of tiles, loading each next tile's
+    # first slice early; z must still equal variant 1's bit for bit, also in
+    # a solve where systems converge at different iterations (skipped tiles:
+    # half the realizations at contrast 2, half at 10)
+    rve = _rve()
+    n, B = 512, 160
+    rng = np.random.default_rng(11 + prec)
+    a = np.concatenate([_fields(n, B // 2, 57), _fields(n, B // 2, 58, contrast=2.0)])
+    r = rng.standard_normal((B, 2, n, n))
+    r -= r.mean(axis=(2, 3), keepdims=True)
+    ad, rd = _to(a, dev), _to(r, dev)
+    out = {}
+    for variant in (1, 5):
+        ctx = rve.Context(0)
+        ctx.set_autotune(False)
+        ctx.force_variants(gemm=variant)
+        z = rve.apply_precond(ad, rd, prec, ctx=ctx).cpu().numpy()
+        res = rve.solve_batch(ad, 1.0 / 8, rve.Options(tol=1e-10, prec=prec), want_phi=False, ctx=ctx)
+        assert res.code == 0
+        out[variant] = (z, res.ahom.cpu().numpy(), res.iters.cpu().numpy())
+        ctx.close()
+    assert np.array_equal(out[1][0], out[5][0])
+    assert np.max(np.abs(out[1][1] - out[5][1])) <= 1e-12 * np.max(np.abs(out[1][1]))
+    assert np.max(np.abs(out[1][2].astype(int) - out[5][2])) <= 1
+    assert out[5][2].min() < out[5][2].max()   # systems did converge at different iterations
+    # sampled systems against the oracle's preconditioner
+    E = q1.symbol(n)
+    z = out[5][0]
+    for b, c in ((0, 0), (77, 1), (159, 1)):
+        ref = precond_apply(r[b, c], oa.preconditioner_scale(a[b]), E)
+        zc = z[b, c] - z[b, c].mean()
+        assert np.linalg.norm(zc - ref) <= (3e-2 if prec == 2 else 3e-3) * np.linalg.norm(ref)
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_small_solver_matches_batched_path_and_oracle(dev, scheme):
     # n = 64, FP64: the single-workgroup solver (default) against the batched
