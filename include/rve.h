@@ -355,7 +355,8 @@ int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int6
  * loaded straight into LDS, n % 128 == 0, the same results as 1; 4: 256 x 128
  * 16-bit tiles for all transforms but the one scaling by 1/E (BF16; FP16:
  * the first and third), n % 256 == 0; 5: 256 x 256 16-bit tiles for all four,
- * n % 256 == 0). An
+ * n % 256 == 0; 6: the same tiles from 8 waves of 128 x 64 instead of 16 of
+ * 64 x 64, n % 256 == 0, the same z as 5). An
  * override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);

@@ -86,7 +86,8 @@ class Context:
         override): an operator-apply shape code (see tuned()) and a
         transform-GEMM variant (0: 64 x 64, 1: 128 x 128 16-bit, 2: even/odd
         folded 128 x 128 BF16, 3: 128 x 128 16-bit with the operands loaded
-        straight into LDS, 4: 256 x 128 16-bit, 5: 256 x 256 16-bit)."""
+        straight into LDS, 4: 256 x 128 16-bit, 5: 256 x 256 16-bit, 6: 256 x 256
+        16-bit from 8 waves)."""
         N.check(self._lib.rve_force_variants(self.handle, int(stencil), int(gemm)), "rve_force_variants")
 
     def set_small_solver(self, enable: bool):

@@ -342,24 +342,29 @@ __device__ inline void lds_dma16(const T* src, T* lds_wave) {
 // for each read in turn, exposing the LDS latency four times per step.
 // GROUPED = false (for the register-tight 256 x 128 tile) reads the A
 // fragments one at a time, 16 fewer live registers.
-template <class T, bool GROUPED = true, class RD>
-__device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
+// BI (4 or 8) is the wave's count of 16-row A blocks; grouped reads go four
+// A fragments at a time.
+template <class T, bool GROUPED = true, int BI = 4, class RD>
+__device__ inline void h16_kstep(v4f (&acc)[BI][4], RD rd) {
   typedef typename H16<T>::v8 v8t;
   v8t bf[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) bf[j] = rd(1, j);
   if constexpr (GROUPED) {
-    v8t af[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = rd(0, i);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int g = 0; g < BI; g += 4) {
+      v8t af[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) af[i] = rd(0, g + i);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af[i], bf[j], acc[i][j]);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g + i][j] = H16<T>::mma(af[i], bf[j], acc[g + i][j]);
+    }
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < BI; ++i) {
       const v8t af = rd(0, i);
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = H16<T>::mma(af, bf[j], acc[i][j]);
@@ -377,22 +382,30 @@ __device__ inline void h16_kstep(v4f (&acc)[4][4], RD rd) {
 // WNR is the number of 64-column wave columns: 2, or 4 with WMR = 4 (a
 // 256 x 256 tile, 1024 threads: a third fewer operand bytes per output
 // than 256 x 128).
-template <class T, int EPI, class ZT, int PIPE = 0, int WMR = 2, int WNR = 2>
+// BI = 8 (with WMR = 2, WNR = 4) gives each wave 128 rows instead of 64: the
+// same 256 x 256 tile from 8 waves at two per SIMD, a quarter fewer LDS
+// fragment reads per K slice than 16 waves of 64 x 64, and the registers
+// for grouped reads.
+template <class T, int EPI, class ZT, int PIPE = 0, int WMR = 2, int WNR = 2, int BI = 4>
 __global__ void __launch_bounds__(64 * WMR * WNR)
-__attribute__((amdgpu_waves_per_eu(WMR * WNR == 4 ? 3 : 4, WMR * WNR == 4 ? 3 : 4)))
+__attribute__((amdgpu_waves_per_eu(BI == 8 ? 2 : WMR * WNR == 4 ? 3 : 4, BI == 8 ? 2 : WMR * WNR == 4 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ sin2,
               double* __restrict__ part, double emin, int fd) {
   static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
-  static_assert((WMR == 2 && WNR == 2) || (WMR == 4 && (WNR == 2 || WNR == 4) && PIPE == 0), "tile shape");
+  static_assert((BI == 4 && ((WMR == 2 && WNR == 2) || (WMR == 4 && (WNR == 2 || WNR == 4) && PIPE == 0))) ||
+                    (BI == 8 && WMR == 2 && WNR == 4 && PIPE == 0),
+                "tile shape");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
-  constexpr int TMR = 64 * WMR, TNR = 64 * WNR, NTH = 64 * WMR * WNR, NW = WMR * WNR;
-  // the 16-wave tile stages its operands in two LDS buffers (147 KB): the
+  constexpr int WR = 16 * BI;   // rows of a wave's block
+  constexpr int TMR = WR * WMR, TNR = 64 * WNR, NTH = 64 * WMR * WNR, NW = WMR * WNR;
+  constexpr bool T256 = PIPE == 0 && TMR == 256 && TNR == 256;
+  // the 256 x 256 tile stages its operands in two LDS buffers (147 KB): the
   // next slice is stored while other waves still read the current one, one
   // barrier per K slice instead of two; the smaller tiles keep one buffer
   // (two would cost them a workgroup per CU)
-  constexpr int NSTG = (PIPE == 0 && NW == 16) ? 2 : 1;
+  constexpr int NSTG = T256 ? 2 : 1;
   constexpr size_t kStage = (size_t)(TMR + TNR) * TLDA;
   constexpr size_t kSmem = PIPE == 0 ? NSTG * kStage * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
@@ -409,7 +422,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   // next tile while it computes the last slice of this one and stores its
   // outputs. (The scaling and last transforms gained nothing from it: their
   // epilogues are longer and need the registers.)
-  constexpr bool PERS = PIPE == 0 && NW == 16 && EPI == kEpiStore;
+  constexpr bool PERS = T256 && EPI == kEpiStore;
   const int NB = n / TNR, MB = n / TMR;
   const long long NT = (long long)S * MB * NB, N2 = (long long)n * n;
   long long base = 0, li = blockIdx.x, lend = NT, lstep = gridDim.x;
@@ -484,9 +497,9 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     const T* Xs = X + (long long)s * N2 + (long long)mb * TMR * n;
     const T* Qs = Qm + (long long)nb * TNR * n;
 
-    v4f acc[4][4];
+    v4f acc[BI][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -528,8 +541,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
         const T* Bb = Ab + TMR * TLDA;
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 32)
-          h16_kstep<T, NW == 4>(acc, [&](int isb, int q) {
-            const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * TLDA : Ab + (wm * 64 + q * 16 + frow) * TLDA;
+          h16_kstep<T, NW == 4 || BI == 8, BI>(acc, [&](int isb, int q) {
+            const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * TLDA : Ab + (wm * WR + q * 16 + frow) * TLDA;
             return *reinterpret_cast<const v8t*>(row + kk + fk);
           });
         if constexpr (NSTG == 2) {
@@ -579,7 +592,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
         const T* Ab = As + (ks & 1) * kBuf;
         const T* Bb = Ab + TM * DK;
         h16_kstep<T>(acc, [&](int isb, int q) {
-          const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * 64 + q * 16 + frow) * DK;
+          const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * WR + q * 16 + frow) * DK;
           return *reinterpret_cast<const v8t*>(row + fc * 8);
         });
       }
@@ -619,8 +632,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
       const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const long long m = (long long)mb * TMR + wm * 64 + i * 16 + m4;
+      for (int i = 0; i < BI; ++i) {
+        const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
         const long long o = (long long)s * N2 + l * n + m;
         const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
         if constexpr (EPI == kEpiZ) {
@@ -1037,12 +1050,13 @@ void run_precond3(const Work& w, const GemmTables& t, hipStream_t st, int phase)
 
 // The four transforms with the 16-bit kernel (T = BF16 or FP16), operand
 // pipeline PIPE and 64 WMR x 128 tiles.
-template <class T, class ZT, int PIPE, int WMR = 2, int WNR = 2>
+template <class T, class ZT, int PIPE, int WMR = 2, int WNR = 2, int BI = 4>
 void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int phase) {
   const int n = w.n;
-  const long long NT = (long long)w.S * (n / (64 * WMR)) * (n / (64 * WNR));
+  constexpr int TMR = 16 * BI * WMR, TNR = 64 * WNR;
+  const long long NT = (long long)w.S * (n / TMR) * (n / TNR);
   const long long NT2 = (long long)w.S * (n / TM) * (n / TN);
-  constexpr bool big = WMR == 4 && WNR == 4;
+  constexpr bool big = TMR == 256 && TNR == 256;
   // The plain transforms in 256 x 256 tiles run one workgroup per CU (a
   // multiple of 8 of them, one set per XCD), each looping over at least four
   // tiles; with fewer tiles one workgroup per tile balances better. The
@@ -1058,20 +1072,20 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   // partials) and of the last one (z) spill in 256 x 128 tiles (the latter
   // only with the scaled FP16 operands), so there those stay at 128 x 128;
   // the 256 x 256 tile has the registers for all four.
-  constexpr int WE = big ? 4 : 2, WEN = big ? 4 : 2;
+  constexpr int WE = big ? WMR : 2, WEN = big ? WNR : 2, BE = big ? BI : 4;
   constexpr bool tallz = big || !std::is_same<T, _Float16>::value;
-  constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2;
+  constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2, BZ = tallz ? BI : 4;
   if (phase < 0 || phase == 0)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), gridp, block, 0, st, (const T*)w.rlo, Q,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, (const T*)w.rlo, Q,
                        (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN>), big ? grid : grid2, big ? block : block2, 0,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN, BE>), big ? grid : grid2, big ? block : block2, 0,
                        st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR>), gridp, block, 0, st, u2, Q, (void*)u1, n,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, u2, Q, (void*)u1, n,
                        w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 3)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN>), tallz ? grid : grid2, tallz ? block : block2, 0,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN, BZ>), tallz ? grid : grid2, tallz ? block : block2, 0,
                        st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
 }
 
@@ -1105,14 +1119,14 @@ size_t gemm_elem_size(int prec) {
 bool gemm_variant_valid(int n, int prec, int variant) {
   return variant == 0 || ((variant == 1 || variant == 3) && big_bf16_tiles(n, prec)) ||
          (variant == 2 && folded_bf16_tiles(n, prec)) ||
-         ((variant == 4 || variant == 5) && big_bf16_tiles(n, prec) && n % 256 == 0);
+         ((variant == 4 || variant == 5 || variant == 6) && big_bf16_tiles(n, prec) && n % 256 == 0);
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
   // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3;
   // variant 5 from its 256 x 256 tiles)
   return variant == 2                                    ? (n / TM) * (n / (2 * TN))
-         : variant == 5                                  ? (n / 256) * (n / 256)
+         : variant == 5 || variant == 6                  ? (n / 256) * (n / 256)
          : (variant == 1 || variant == 3 || variant == 4) ? (n / TM) * (n / TN)
                                            : (n / BM) * (n / BN);
 }
@@ -1147,6 +1161,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond_h16<_Float16, float, 0, 4>(w, t, st, phase);
     else if (w.gemm_variant == 5)
       run_precond_h16<_Float16, float, 0, 4, 4>(w, t, st, phase);
+    else if (w.gemm_variant == 6)
+      run_precond_h16<_Float16, float, 0, 2, 4, 8>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
@@ -1159,6 +1175,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond_h16<__bf16, float, 0, 4>(w, t, st, phase);
   } else if (w.gemm_variant == 5) {
     run_precond_h16<__bf16, float, 0, 4, 4>(w, t, st, phase);
+  } else if (w.gemm_variant == 6) {
+    run_precond_h16<__bf16, float, 0, 2, 4, 8>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

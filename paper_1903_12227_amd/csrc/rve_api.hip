@@ -751,7 +751,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       // the even/odd-folded variant (2) is faster per apply but its extra BF16
       // rounding costs iterations (n = 512: 39.3 vs 38.0; n = 2048: 149 vs
       // 100), which a per-apply timing cannot see: it is used only on request
-      for (int v : {0, 1, 4, 5})
+      for (int v : {0, 1, 4, 5, 6})
         if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
       if (ctx->tune.count(kgm) || tune_now)
         w.gemm_variant = tune_pick(ctx, kgm, gc, [&](int v) {
@@ -1266,7 +1266,7 @@ int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_
 }
 
 int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
-  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 5) return RVE_EINVAL;
+  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 6) return RVE_EINVAL;
   // a well-formed shape code (every shape tiles the largest supported grid)
   if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
   c->force_stencil = stencil_choice;

@@ -67,12 +67,12 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
             assert np.linalg.norm(zc - ref) <= tol * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
     # 128-row tiles (1; 3 with the operands loaded straight into LDS; 4 with
     # 256 x 128 tiles for three of the four transforms, 5 with 256 x 256 for
-    # all four) and the even/odd-folded
+    # all four, 6 the same from 8 waves) and the even/odd-folded
     # tiles (2, half the MFMA work, one more BF16 rounding of the folded
     # input) against the FFT apply
     rve = _rve()
@@ -421,7 +421,7 @@ def test_autotuner_choices_and_cache(dev, tmp_path, monkeypatch):
     ch = tuned_ctx.tuned(n, 2, B)
     assert ch["stencil_columns_per_lane"] in (1, 2, 4) and ch["stencil_rows_per_strip"] in (16, 64)
     assert ch["stencil_prefetch_rows"] in (1, 2)
-    assert ch["gemm_variant"] in (0, 1, 4, 5)
+    assert ch["gemm_variant"] in (0, 1, 4, 5, 6)
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 2 and all(line.startswith('{"kind"') for line in lines)
     reload_ctx = rve.Context(0)          # reads the cache at creation
@@ -439,7 +439,7 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
     r = rng.standard_normal((2, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     E = q1.symbol(n)
-    for variant in (0, 1, 3, 4, 5):
+    for variant in (0, 1, 3, 4, 5, 6):
         ctx = rve.Context(0)
         ctx.force_variants(gemm=variant)
         z = rve.apply_precond(_to(a, dev), _to(r, dev), 3, ctx=ctx).cpu().numpy()
@@ -470,9 +470,10 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
 def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     # the 16-bit transform variants (1: 128 x 128 register-staged, 3: LDS
     # loaded, 4: 256 x 128 for three of the four transforms, 5: 256 x 256
-    # for all four; 4 and 5 need n % 256 == 0) accumulate every output in the
-    # same order, so the preconditioner agrees bit for bit, and whole solves
-    # too except for variant 5's r.z partial sums (n = 384: three tiles per
+    # for all four, 6: the same from 8 waves; 4, 5 and 6 need n % 256 == 0)
+    # accumulate every output in the same order, so the preconditioner agrees
+    # bit for bit, and whole solves too except for the r.z partial sums of
+    # 5 and 6 (n = 384: three tiles per
     # axis, twelve K slices, no XCD remap of the tile order)
     rve = _rve()
     rng = np.random.default_rng(n + 7 * prec)
@@ -480,7 +481,7 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     r = rng.standard_normal((3, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     out = {}
-    variants = (1, 3, 4, 5) if n % 256 == 0 else (1, 3)
+    variants = (1, 3, 4, 5, 6) if n % 256 == 0 else (1, 3)
     for variant in variants:
         ctx = rve.Context(0)
         ctx.set_autotune(False)
@@ -492,13 +493,13 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
                         res.phi.cpu().numpy())
         ctx.close()
     for v in variants[1:]:
-        if v == 5:
+        if v in (5, 6):
             # z bit for bit; the r.z partials come from 256 x 256 tiles, so the
             # solve differs only by the summation order of those partials
-            assert np.array_equal(out[1][0], out[5][0])
-            for x1, xv in zip(out[1][1:3], out[5][1:3]):
+            assert np.array_equal(out[1][0], out[v][0])
+            for x1, xv in zip(out[1][1:3], out[v][1:3]):
                 assert np.max(np.abs(x1 - xv)) <= 1e-12 * np.max(np.abs(x1))
-            assert np.max(np.abs(out[1][3].astype(int) - out[5][3])) <= 1
+            assert np.max(np.abs(out[1][3].astype(int) - out[v][3])) <= 1
             continue
         for x1, xv in zip(out[1], out[v]):
             assert np.array_equal(x1, xv), v
@@ -514,7 +515,7 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
 @pytest.mark.parametrize("prec", [2, 3])
 def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
     # with at least four 256 x 256 tiles per CU (here 160 realizations, 320
-    # systems, 1280 tiles at n = 512) the plain transforms of variant 5 run
+    # systems, 1280 tiles at n = 512) the plain transforms of variants 5 and 6 run
     # one workgroup per CU over a range of tiles, loading each next tile's
     # first slice early; z must still equal variant 1's bit for bit, also in
     # a solve where systems converge at different iterations (skipped tiles:
@@ -527,7 +528,7 @@ def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
     r -= r.mean(axis=(2, 3), keepdims=True)
     ad, rd = _to(a, dev), _to(r, dev)
     out = {}
-    for variant in (1, 5):
+    for variant in (1, 5, 6):
         ctx = rve.Context(0)
         ctx.set_autotune(False)
         ctx.force_variants(gemm=variant)
@@ -536,9 +537,10 @@ def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
         assert res.code == 0
         out[variant] = (z, res.ahom.cpu().numpy(), res.iters.cpu().numpy())
         ctx.close()
-    assert np.array_equal(out[1][0], out[5][0])
-    assert np.max(np.abs(out[1][1] - out[5][1])) <= 1e-12 * np.max(np.abs(out[1][1]))
-    assert np.max(np.abs(out[1][2].astype(int) - out[5][2])) <= 1
+    for v in (5, 6):
+        assert np.array_equal(out[1][0], out[v][0]), v
+        assert np.max(np.abs(out[1][1] - out[v][1])) <= 1e-12 * np.max(np.abs(out[1][1])), v
+        assert np.max(np.abs(out[1][2].astype(int) - out[v][2])) <= 1, v
     assert out[5][2].min() < out[5][2].max()   # systems did converge at different iterations
     # sampled systems against the oracle's preconditioner
     E = q1.symbol(n)
