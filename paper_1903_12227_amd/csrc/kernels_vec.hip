@@ -101,9 +101,6 @@ __global__ void __launch_bounds__(kBlock) k_ctl_reset(int* kiter, int* count, in
   for (int i = t; i < count_len; i += stride) count[i] = 0;
 }
 
-__global__ void k_advance(int* kiter) {
-  if (threadIdx.x == 0) kiter[0] += 1;
-}
 
 // Galerkin right-hand sides f_i = -int a d(psi)/dx_i, integrated exactly per
 // cell (eqn. FEM_discr_RHS): with a11 = a[p][q], a10 = a[p][q-1],
@@ -863,9 +860,13 @@ __global__ void k_scalar_conv(SysState* sys, const double* __restrict__ part, in
   }
 }
 
+// advance (may be null): the shared iteration counter, advanced once by the
+// last batch's beta of an iteration (no block of this kernel reads it)
 __global__ void k_scalar_beta(SysState* sys, const double* __restrict__ part_rz, int Pz,
-                              const double* __restrict__ part_rzo, int Po, int flexible, int first) {
+                              const double* __restrict__ part_rzo, int Po, int flexible, int first,
+                              int* advance) {
   const int s = blockIdx.x, lane = threadIdx.x;
+  if (advance && s == 0 && lane == 0) advance[0] += 1;
   if (!sys[s].active) return;
   double v = 0, o = 0;
   for (int t = lane; t < Pz; t += kWave) v += part_rz[(long long)s * Pz + t];
@@ -1171,7 +1172,6 @@ void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st) {
   hipLaunchKernelGGL(k_ctl_reset, dim3(blocks), dim3(kBlock), 0, st, kiter, count, count_len);
 }
 
-void launch_advance(int* kiter, hipStream_t st) { hipLaunchKernelGGL(k_advance, dim3(1), dim3(kWave), 0, st, kiter); }
 
 void launch_rhs(const Work& w, hipStream_t st) {
   if (w.dim == 3) return launch_rhs3(w, st);
@@ -1437,9 +1437,9 @@ void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st) {
                      w.count, (const int*)w.kiter, (int)(w.mixed == 3), sqrt((double)w.N2));
 }
 
-void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st) {
+void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st, int* advance) {
   hipLaunchKernelGGL(k_scalar_beta, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rz, w.P_gemm, w.part_rzo,
-                     w.P_rr, flexible, first);
+                     w.P_rr, flexible, first, advance);
 }
 
 void launch_round_lo(const Work& w, hipStream_t st) {

@@ -76,7 +76,6 @@ constexpr int kMiscNV3 = 18;   // per-realization partials of the three-dimensio
 // Elementwise and stencil kernels (kernels_vec.hip).
 void launch_init_state(const Work& w, hipStream_t st);
 void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st);
-void launch_advance(int* kiter, hipStream_t st);
 void launch_rhs(const Work& w, hipStream_t st);
 void launch_scalar_init(const Work& w, hipStream_t st);
 void launch_meansub(const Work& w, hipStream_t st);
@@ -86,7 +85,7 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st);
 void launch_scalar_alpha(const Work& w, hipStream_t st);
 // stopping test of iteration k; counts the systems that go on in count[k]
 void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st);
-void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st);
+void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st, int* advance = nullptr);
 void launch_round_lo(const Work& w, hipStream_t st);
 // Fused direction step + operator apply of the current PCG iteration in the
 // shape w.stencil (w.P_st must equal stencil_tiles_per_realization(n,

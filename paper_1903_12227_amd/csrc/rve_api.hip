@@ -624,9 +624,9 @@ void run_chunk(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int flex
       }
       launch_scalar_conv(b.w, o->tol, o->maxit, st);
       precond_timed(ctx, b.w, b.prec, b.gt, st);
-      launch_scalar_beta(b.w, flexible, 0, st);
+      // the last batch's beta also advances the shared iteration counter
+      launch_scalar_beta(b.w, flexible, 0, st, &b == &bs.back() ? bs[0].w.kiter : nullptr);
     }
-    launch_advance(bs[0].w.kiter, st);
   }
 }
 
