@@ -183,11 +183,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_L64_n512_b256.json")
 
 
 def kernel_source_hash():
+    """Fingerprint of the code of the kernel sources: comments and whitespace
+    are left out, so an edit of a comment keeps the committed counters valid
+    while any change of code invalidates them."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            t = f.read()
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(re.sub(r"\s+", " ", t).strip().encode())
     return h.hexdigest()[:16]
 
 

@@ -417,7 +417,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   // (on XCD b % 8) takes tiles from range b % 8 of eight contiguous ones, so
   // the tiles that share operand rows meet in one XCD's L2. One workgroup
   // per tile (the grid must then cover every tile), except the plain
-  // transform in 16-wave tiles (PERS): there the grid may be smaller (one
+  // transform in 256 x 256 tiles (PERS): there the grid may be smaller (one
   // workgroup per CU), and each workgroup loads the first K slice of its
   // next tile while it computes the last slice of this one and stores its
   // outputs. (The scaling and last transforms gained nothing from it: their
@@ -622,8 +622,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
     double dot = 0.0;
     // straight from the accumulators: block (i, j) of lane l holds output
-    // row nb*128 + 64 wn + 16 j + l % 16 at the four consecutive columns
-    // mb*128 + 64 wm + 16 i + 4 (l / 16) + e
+    // row nb TNR + 64 wn + 16 j + l % 16 at the four consecutive columns
+    // mb TMR + WR wm + 16 i + 4 (l / 16) + e
     const int lr = lane & 15, m4 = 4 * (lane >> 4);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
