@@ -372,7 +372,8 @@ __device__ inline void h16_kstep(v4f (&acc)[BI][4], RD rd) {
   }
 }
 
-// WMR is the number of 64-row wave rows: 2 (128 x 128 tile, 256 threads,
+// WMR is the number of wave rows (64 rows each, 128 with BI = 8): 2 (128 x
+// 128 tile, 256 threads,
 // three waves per SIMD) or 4 (256 x 128 tile, 512 threads, four waves per
 // SIMD, PIPE 0 only): the taller tile loads a quarter fewer operand bytes per
 // output, which is what the load path of this kernel is short of. At 128
