@@ -421,9 +421,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   // transform in 256 x 256 tiles (PERS): there the grid may be smaller (one
   // workgroup per CU), and each workgroup loads the first K slice of its
   // next tile while it computes the last slice of this one and stores its
-  // outputs. (The scaling and last transforms gained nothing from it: their
-  // epilogues are longer and need the registers.)
-  constexpr bool PERS = T256 && EPI == kEpiStore;
+  // outputs. The scaling transform does so too in the 8-wave shape, which
+  // has the registers for it; in the 16-wave one its epilogue spilled under
+  // the loop, and the last transform gained nothing from it in either.
+  constexpr bool PERS = T256 && (EPI == kEpiStore || (EPI == kEpiEinv && BI == 8));
   const int NB = n / TNR, MB = n / TMR;
   const long long NT = (long long)S * MB * NB, N2 = (long long)n * n;
   long long base = 0, li = blockIdx.x, lend = NT, lstep = gridDim.x;
@@ -1080,7 +1081,7 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, (const T*)w.rlo, Q,
                        (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
   if (phase < 0 || phase == 1)
-    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN, BE>), big ? grid : grid2, big ? block : block2, 0,
+    hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN, BE>), big ? (BI == 8 ? gridp : grid) : grid2, big ? block : block2, 0,
                        st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, u2, Q, (void*)u1, n,
