@@ -54,3 +54,37 @@ def test_gershgorin_bounds_hold():
     a = _field(n, 5)
     assert np.linalg.eigvalsh(q1.assemble(a).toarray()).max() <= 16.0 / 3.0 * a.max()
     assert np.linalg.eigvalsh(fd5.assemble(a).toarray()).max() <= 8.0 * a.max()
+
+
+def test_gaussian_is_the_normal_density_of_width_eta():
+    # eqn. DOS_gauss: g_eta is the centred normal density with standard
+    # deviation eta. Pinned by quadrature (unit mass, second moment eta^2,
+    # zero first moment), its peak 1 / (sqrt(2 pi) eta), the ratio
+    # exp(-1/2) one width out, and the library's normal density.
+    from scipy import integrate, stats
+    for eta in (0.05, 0.3, 2.0):
+        mass = integrate.quad(lambda t: dos.gaussian(t, eta), -np.inf, np.inf)[0]
+        first = integrate.quad(lambda t: t * dos.gaussian(t, eta), -np.inf, np.inf)[0]
+        second = integrate.quad(lambda t: t * t * dos.gaussian(t, eta), -np.inf, np.inf)[0]
+        assert abs(mass - 1.0) <= 1e-10
+        assert abs(first) <= 1e-10 * eta
+        assert abs(second - eta * eta) <= 1e-10 * eta * eta
+        assert abs(dos.gaussian(0.0, eta) - 1.0 / (np.sqrt(2.0 * np.pi) * eta)) <= 1e-15 / eta
+        assert abs(dos.gaussian(eta, eta) / dos.gaussian(0.0, eta) - np.exp(-0.5)) <= 1e-15
+        t = np.linspace(-5 * eta, 5 * eta, 101)
+        assert np.allclose(dos.gaussian(t, eta), stats.norm.pdf(t, loc=0.0, scale=eta), rtol=1e-13, atol=0)
+
+
+def test_exact_density_integrates_to_one_and_peaks_at_eigenvalues():
+    # eqn. DOS: (1/m) sum_j delta(t - lambda_j) broadened by g_eta has unit
+    # mass; for well separated eigenvalues and a small width it is a sum of
+    # bumps of mass 1/m (weights counted with multiplicity)
+    from scipy import integrate
+    lam = np.array([0.0, 1.0, 1.0, 3.0])
+    eta = 0.01
+    mass = integrate.quad(lambda t: dos.dos_exact(lam, np.array([t]), eta)[0], -1.0, 4.0,
+                          points=[0.0, 1.0, 3.0], limit=200)[0]
+    assert abs(mass - 1.0) <= 1e-9
+    peaks = dos.dos_exact(lam, np.array([0.0, 1.0, 3.0]), eta)
+    g0 = 1.0 / (np.sqrt(2.0 * np.pi) * eta)
+    assert np.allclose(peaks, np.array([0.25, 0.5, 0.25]) * g0, rtol=1e-12)
