@@ -66,3 +66,20 @@ def dos_from_moments(mu: np.ndarray, t: np.ndarray, lmax: float, eta: float, Q: 
     """phi_eta(t) ~ sum_k a_k(t) mu_k (mu averaged over probes)."""
     mu = np.asarray(mu, dtype=np.float64)
     return chebyshev_coefficients(t, lmax, eta, mu.size, Q) @ mu
+
+
+def philox_probes(count: int, seed: int) -> np.ndarray:
+    """Probe vectors with entries +-1 drawn from Philox4x32-10 (Salmon et
+    al., SC'11; the generator of lattice_sample), flat: entry i is -1 iff
+    bit i mod 32 of word (i div 32) mod 4 of Philox4x32-10 with counter
+    (i div 128 mod 2^32, i div 2^39, 0, 0x50524F42) and key (seed mod 2^32,
+    seed div 2^32) is set. Reshape to (B, nv, n, n) as needed."""
+    from .lattice_sample import philox4x32_10
+    i = np.arange(int(count), dtype=np.uint64)
+    t = i // np.uint64(128)
+    words = np.stack(philox4x32_10(t & np.uint64(0xFFFFFFFF), t >> np.uint64(32), np.zeros_like(t),
+                                   np.full_like(t, 0x50524F42), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    k = (i % np.uint64(128)).astype(np.int64)
+    w = words[k // 32, np.arange(int(count))]
+    bit = (w >> (k % 32).astype(np.uint32)) & np.uint32(1)
+    return np.where(bit == 1, -1.0, 1.0)

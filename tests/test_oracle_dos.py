@@ -88,3 +88,21 @@ def test_exact_density_integrates_to_one_and_peaks_at_eigenvalues():
     peaks = dos.dos_exact(lam, np.array([0.0, 1.0, 3.0]), eta)
     g0 = 1.0 / (np.sqrt(2.0 * np.pi) * eta)
     assert np.allclose(peaks, np.array([0.25, 0.5, 0.25]) * g0, rtol=1e-12)
+
+
+def test_philox_probes_bit_rule_by_brute_force():
+    # the probe rule evaluated entry by entry with Python integers, on the
+    # generator pinned by its known-answer vectors (test_oracle_sample)
+    from oracle.lattice_sample import philox4x32_10
+    seed = (7 << 32) | 12345
+    count = 300
+    v = dos.philox_probes(count, seed)
+    assert set(np.unique(v)) <= {-1.0, 1.0}
+    for i in range(count):
+        t = i // 128
+        w = philox4x32_10([t & 0xFFFFFFFF], [t >> 32], [0], [0x50524F42], seed & 0xFFFFFFFF, seed >> 32)
+        word = int(w[(i % 128) // 32][0])
+        assert v[i] == (-1.0 if (word >> (i % 32)) & 1 else 1.0), i
+    big = dos.philox_probes(1 << 16, 99)
+    assert abs(big.mean()) <= 5.0 / np.sqrt(big.size)       # fair signs
+    assert not np.array_equal(big[:1000], dos.philox_probes(1000, 98))
