@@ -137,6 +137,29 @@ int rve_destroy(rve_ctx* ctx);
 int rve_set_stream(rve_ctx* ctx, void* hip_stream);
 
 /*
+ * One realization, synchronous (Sec. 2, corrector problem eqn. RHS_grad1 /
+ * scaled_setting; Sec. 4.1 eqns. A_hom_m and Ahom_m_entry): the coefficient
+ * field in, the two correctors (optionally) and the homogenized matrix out.
+ *
+ *   n              as for rve_solve_batch
+ *   a_dev          [n][n] FP64 per-cell coefficients on the device, each > 0
+ *   h              mesh width (> 0); phi is returned in physical units (x h)
+ *   phi_dev        [2][n][n] FP64 correctors (device, mean zero), or NULL
+ *   ahom_host      [2][2] FP64 energy-form A_hom (host, required)
+ *   ahom_flux_host [2][2] FP64 flux-form A_hom (host), or NULL
+ *   iters_host     [2] PCG iterations per direction (host), or NULL
+ *   relres_host    [2] final recursive ||r||/||f|| per direction (host), or NULL
+ *
+ * Returns the realization's status: RVE_OK, RVE_NOT_CONVERGED or
+ * RVE_BREAKDOWN (host outputs written), RVE_EINVAL for a bad argument
+ * (nothing enqueued) or for a coefficient <= 0 / NaN found on the device
+ * (host outputs written, with phi = 0), RVE_EHIP / RVE_ENOMEM (outputs
+ * undefined). Blocks until the host outputs are written.
+ */
+int rve_solve(rve_ctx* ctx, int n, double h, const double* a_dev, const rve_opts* opts, double* phi_dev,
+              double* ahom_host, double* ahom_flux_host, int* iters_host, double* relres_host);
+
+/*
  * Solve B independent realizations of equal size n (one batch: every kernel
  * launch covers all 2B corrector systems).
  *
@@ -226,21 +249,44 @@ int rve_solve_uneven(rve_ctx* ctx, int B, const int* n_host,
  * Derivative of the energy-form A_hom with respect to every cell value
  * (vector-Jacobian product). The energy form is stationary in the
  * correctors (eqn. wg03), so d A_ij / d a_e = (1/n^2) int_e (e_i + grad
- * phi_i) . (e_j + grad phi_j) and no adjoint solve is needed.
+ * phi_i) . (e_j + grad phi_j) and no adjoint solve is needed. The
+ * derivative in the inclusion value (Sec. 2, eqns. Stoch-decomp and
+ * ahm_coef: the covered set carries one value, which moves all its cells
+ * together) is the sum of the per-cell derivative over the covered cells.
  *
- *   a_dev        [B][n][n] coefficients used for the solve
- *   phi_dev      [B][2][n][n] correctors as returned by rve_solve_batch (x h)
- *   h            the same mesh width
- *   G_dev        [B][2][2] upstream weights G_ij
- *   grad_a_dev   [B][n][n] output: sum_ij G_ij d A_ij / d a_e
- *   a_in         coefficient value of the inclusion cells
- *   grad_in_dev  [B] output: sum_ij G_ij d A_ij / d a_in, where every cell
- *                with a_e == a_in moves with a_in; or NULL
- *   scheme       enum rve_scheme the correctors were computed with
+ *   a_dev           [B][n][n] coefficients used for the solve (device)
+ *   phi_dev         [B][2][n][n] correctors as returned by rve_solve_batch (x h)
+ *   h               the same mesh width
+ *   G_dev           [B][2][2] upstream weights G_ij
+ *   grad_a_dev      [B][n][n] output: sum_ij G_ij d A_ij / d a_e
+ *   incl_mask_dev   [B][n][n] bytes, nonzero on the covered cells (device);
+ *                   or NULL: the covered cells are those with a_e == a_in
+ *   a_in            inclusion value, read only when incl_mask_dev is NULL
+ *                   and an inclusion derivative is asked for (must be finite)
+ *   grad_in_dev     [B] output: sum_ij G_ij d A_ij / d a_in per realization,
+ *                   or NULL
+ *   grad_in_sum_dev [1] output: the sum of those B values (fixed order), for
+ *                   one inclusion value shared by the batch; or NULL
+ *   scheme          enum rve_scheme the correctors were computed with
+ * Asynchronous. Scratch for the partial sums comes from the context's
+ * workspace (allocated or grown on demand).
  */
 int rve_grad(rve_ctx* ctx, int B, int n, const double* a_dev,
              const double* phi_dev, double h, const double* G_dev,
-             double* grad_a_dev, double a_in, double* grad_in_dev, int scheme);
+             double* grad_a_dev, const unsigned char* incl_mask_dev, double a_in,
+             double* grad_in_dev, double* grad_in_sum_dev, int scheme);
+
+/*
+ * Coefficient fields of the two-valued model from their covered sets (Sec. 2,
+ * eqns. Stoch-decomp and ahm_coef): a_dev[b][e] = a_in_dev[b] where
+ * mask_dev[b][e] != 0, else a_bg. cells = cells per field (n^2, or n^3 in
+ * three dimensions); mask_dev [B][cells] bytes, a_in_dev [B], a_dev
+ * [B][cells] (all device). 1 <= B <= 65535, a_bg > 0 and finite (the
+ * values a_in_dev[b] are checked by the solver like any coefficient).
+ * Asynchronous.
+ */
+int rve_field_from_mask(rve_ctx* ctx, int B, long long cells, const unsigned char* mask_dev,
+                        const double* a_in_dev, double a_bg, double* a_dev);
 
 /*
  * Ensemble statistics of N homogenized matrices at RVE size L (Sec. 4.2
@@ -287,12 +333,16 @@ const char* rve_status_string(int status);
  * apply is outweighed by extra iterations). Choices are cached in the context
  * and, if the environment variable RVE_TUNE_CACHE names a file, appended
  * there as JSON lines and read back by rve_create. Mode 0 uses fixed
- * defaults. Results do not depend on the choice beyond rounding order.
+ * defaults. The 16-bit transform tile variants the tuner chooses among
+ * (1, 4, 5, 6; the 64 x 64 kernel only where none of them fits) give
+ * identical results, so that choice never changes a solve; the operator-apply
+ * shape sets the summation order of the PCG dot products' partial sums, so
+ * its choice changes results at rounding level only.
  *
  * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
  * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128,
  * 2 = folded 128 x 128, 3 = 128 x 128 loaded straight into LDS, 4 = 256 x
- * 128, 5 = 256 x 256), 2 (FP32
+ * 128, 5 = 256 x 256, 6 = 256 x 256 from 8 waves), 2 (FP32
  * operator-apply shape) or 3 (five-point
  * operator-apply shape), the last two encoded as kind 0, of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
@@ -317,12 +367,29 @@ int rve_set_autotune(rve_ctx* ctx, int mode);
  * rve_dos_eval: phi_dev [B][nt] (device) receives
  * sum_k a_k(t) mubar_k at the points t_dev [nt] (device), mubar the mean of
  * the nv probes' moments and a_k(t) the Chebyshev coefficients of
- * x -> g_eta(t - c (1 + x)) by a Chebyshev-Gauss rule with Q >= K nodes.
+ * x -> g_eta(t - c (1 + x)) by a Chebyshev-Gauss rule with Q >= K nodes
+ * (Q <= 0: Q = 4 K).
+ *
+ * rve_dos_plan: the spectral bound and the moment count for fields a_dev
+ * [B][n][n] (device) and width eta > 0: *lmax_host = (16/3) max a (Q1) or
+ * 8 max a (five-point), the Gershgorin bound of every eigenvalue, and
+ * *K_host = min(20000, max(64, floor(6 lmax / eta))), about six moments per
+ * width over the spectrum. RVE_EINVAL if a cell is <= 0 or NaN. Blocks until
+ * the results are on the host.
+ *
+ * rve_dos_probes: v_dev [B][nv][n][n] (device) receives probe vectors with
+ * entries +1 or -1: entry i (flat index) is -1 iff bit i mod 32 of word
+ * (i div 32) mod 4 of Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (i div 128 mod 2^32, i div 2^39, 0, 0x50524F42) and key (seed mod 2^32,
+ * seed div 2^32) is set. Asynchronous.
  */
 int rve_dos_moments(rve_ctx* ctx, int B, int n, int scheme, const double* a_dev, int nv,
                     const double* v_dev, double lmax, int K, double* mu_dev);
 int rve_dos_eval(rve_ctx* ctx, int B, int nv, int K, const double* mu_dev, double lmax,
                  double eta, int Q, int nt, const double* t_dev, double* phi_dev);
+int rve_dos_plan(rve_ctx* ctx, int B, int n, int scheme, const double* a_dev, double eta,
+                 double* lmax_host, int* K_host);
+int rve_dos_probes(rve_ctx* ctx, int B, int nv, int n, uint64_t seed, double* v_dev);
 
 /*
  * Sample B coefficient fields of the random inclusion model (Sec. 2, covered
@@ -346,6 +413,11 @@ int rve_dos_eval(rve_ctx* ctx, int B, int nv, int K, const double* mu_dev, doubl
  */
 int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int64_t first,
                        uint32_t occ_threshold, double a_in, double a_bg, double* a_dev);
+
+/* Site-occupancy threshold of rve_sample_lattice for Poisson centres with
+ * mean mu per lattice site: round(2^32 (1 - exp(-mu))) (ties to even),
+ * clamped to [0, 2^32 - 1]; 0 for mu <= 0 or NaN. Host only. */
+uint32_t rve_occupancy_threshold(double mu);
 
 /* Use these kernel variants instead of the autotuner's or default choice
  * (-1: no override): an operator-apply shape as encoded for rve_get_tuned

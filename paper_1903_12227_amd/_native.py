@@ -26,6 +26,7 @@ EXPORTS = (
     "rve_apply_operator", "rve_apply_precond", "rve_set_autotune", "rve_get_tuned",
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
     "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d", "rve_set_small_solver",
+    "rve_solve", "rve_field_from_mask", "rve_dos_plan", "rve_dos_probes", "rve_occupancy_threshold",
 )
 
 
@@ -56,7 +57,13 @@ def _declare(lib):
     lib.rve_apply_precond_3d.argtypes = [_vp, _i, _i, _vp, _vp, _vp, _i]
     lib.rve_solve_uneven.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_int64),
                                      _d, _vp, ctypes.POINTER(RveOpts), _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _d, _vp, _i]
+    lib.rve_solve.argtypes = [_vp, _i, _d, _vp, ctypes.POINTER(RveOpts), _vp, ctypes.POINTER(_d),
+                              ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_d)]
+    lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _d, _vp, _vp, _i]
+    lib.rve_field_from_mask.argtypes = [_vp, _i, ctypes.c_longlong, _vp, _vp, _d, _vp]
+    lib.rve_dos_plan.argtypes = [_vp, _i, _i, _i, _vp, _d, ctypes.POINTER(_d), ctypes.POINTER(_i)]
+    lib.rve_dos_probes.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, _vp]
+    lib.rve_occupancy_threshold.argtypes = [_d]
     lib.rve_stats.argtypes = [_vp, _i, _d, _vp, _vp]
     lib.rve_status_string.argtypes = [_i]
     lib.rve_status_string.restype = ctypes.c_char_p
@@ -74,8 +81,9 @@ def _declare(lib):
     lib.rve_sample_lattice.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
                                        _d, _d, _vp]
     for name in EXPORTS:
-        if name not in ("rve_default_opts", "rve_status_string"):
+        if name not in ("rve_default_opts", "rve_status_string", "rve_occupancy_threshold"):
             getattr(lib, name).restype = _i
+    lib.rve_occupancy_threshold.restype = ctypes.c_uint32
     return lib
 
 

@@ -164,6 +164,40 @@ def _need(t: torch.Tensor, name: str, dtype=torch.float64):
         raise ValueError(f"{name} must be contiguous")
 
 
+@dataclass
+class SingleResult:
+    ahom: torch.Tensor                  # (2, 2) energy form, host
+    ahom_flux: torch.Tensor             # (2, 2) flux form, host
+    phi: Optional[torch.Tensor]         # (2, n, n) correctors x h (device), mean zero
+    iters: tuple                        # PCG iterations per direction
+    relres: tuple                       # final recursive relative residuals
+    code: int                           # RVE_OK, or the warning RVE_NOT_CONVERGED / RVE_BREAKDOWN
+
+
+def solve(a: torch.Tensor, h: float = 1.0, opts: Optional[Options] = None, *, want_phi: bool = True,
+          ctx: Optional[Context] = None) -> SingleResult:
+    """One realization a (n, n) FP64 on the device, synchronously (see
+    rve_solve): A_hom and the iteration data come back on the host. Errors,
+    including a coefficient <= 0 or NaN, raise RveError."""
+    _need(a, "a")
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must have shape (n, n)")
+    n = a.shape[0]
+    opts = opts or Options()
+    ctx = ctx or context(a.device.index)
+    phi = torch.empty((2, n, n), dtype=torch.float64, device=a.device) if want_phi else None
+    A = (ctypes.c_double * 4)()
+    F = (ctypes.c_double * 4)()
+    its = (ctypes.c_int * 2)()
+    rr = (ctypes.c_double * 2)()
+    c_opts = opts.to_c()
+    code = N.check(ctx._lib.rve_solve(ctx.bind_stream(), n, float(h), _p(a), ctypes.byref(c_opts), _p(phi), A, F,
+                                      its, rr), "rve_solve")
+    return SingleResult(torch.tensor(list(A), dtype=torch.float64).view(2, 2),
+                        torch.tensor(list(F), dtype=torch.float64).view(2, 2), phi, (its[0], its[1]),
+                        (rr[0], rr[1]), code)
+
+
 def solve_batch(a: torch.Tensor, h: float = 1.0, opts: Optional[Options] = None, *,
                 want_phi: bool = True, want_flux: bool = True,
                 ctx: Optional[Context] = None) -> Result:
@@ -287,22 +321,67 @@ def solve_uneven(fields: Sequence[torch.Tensor], h: float = 1.0, opts: Optional[
     return Result(ahom, flux, phis, iters, relres, status, code)
 
 
+def _mask_bytes(mask: torch.Tensor, shape, dev) -> torch.Tensor:
+    if not isinstance(mask, torch.Tensor) or mask.device != dev:
+        raise ValueError("mask must be a tensor on the fields' device")
+    if mask.dtype not in (torch.bool, torch.uint8):
+        raise ValueError("mask must have dtype bool or uint8")
+    if tuple(mask.shape) != tuple(shape):
+        raise ValueError(f"mask must have shape {tuple(shape)}")
+    return mask.contiguous()
+
+
 def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
-         a_in: Optional[float] = None, ctx: Optional[Context] = None, scheme: int = 0):
-    """sum_ij G_ij dA_ij/da per cell, (B, n, n); and, if a_in is given, the
-    derivative with respect to the common value of the cells equal to a_in."""
+         a_in: Optional[float] = None, *, mask: Optional[torch.Tensor] = None, want_sum: bool = False,
+         ctx: Optional[Context] = None, scheme: int = 0):
+    """sum_ij G_ij dA_ij/da per cell, (B, n, n); and, if a covered set is
+    given (mask (B, n, n) bool/uint8, or else the cells equal to a_in), the
+    derivative with respect to the inclusion value per realization (B,),
+    and with want_sum its sum over the batch (a 1-element tensor).
+    Returns (grad_a, grad_in or None, grad_in_sum or None)."""
     _need(a, "a")
     _need(phi, "phi")
     _need(G, "G")
+    if a.dim() != 3 or a.shape[1] != a.shape[2]:
+        raise ValueError("a must have shape (B, n, n)")
     B, n = a.shape[0], a.shape[1]
     if phi.shape != (B, 2, n, n) or G.shape != (B, 2, 2):
         raise ValueError("phi must be (B, 2, n, n) and G (B, 2, 2)")
+    if mask is not None:
+        mask = _mask_bytes(mask, (B, n, n), a.device)
+    want_in = mask is not None or a_in is not None
+    if want_sum and not want_in:
+        raise ValueError("want_sum needs a covered set (mask or a_in)")
     ctx = ctx or context(a.device.index)
     out = torch.empty_like(a)
-    gin = torch.empty((B,), dtype=torch.float64, device=a.device) if a_in is not None else None
-    N.check(ctx._lib.rve_grad(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out),
-                              float(a_in if a_in is not None else 0.0), _p(gin), int(scheme)), "rve_grad")
-    return out, gin
+    gin = torch.empty((B,), dtype=torch.float64, device=a.device) if want_in else None
+    gsum = torch.empty((1,), dtype=torch.float64, device=a.device) if want_sum else None
+    N.check(ctx._lib.rve_grad(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out), _p(mask),
+                              float(a_in if a_in is not None else 0.0), _p(gin), _p(gsum), int(scheme)),
+            "rve_grad")
+    return out, gin, gsum
+
+
+def field_from_mask(mask: torch.Tensor, a_in, a_bg: float = 1.0, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Fields (B, ...) FP64 with a_in[b] on the cells where mask[b] is set and
+    a_bg elsewhere (see rve_field_from_mask); a_in a float or a (B,) FP64
+    device tensor."""
+    if not isinstance(mask, torch.Tensor) or not mask.is_cuda or mask.dim() < 2:
+        raise ValueError("mask must be a (B, ...) device tensor")
+    B = mask.shape[0]
+    mask = _mask_bytes(mask, mask.shape, mask.device)
+    if isinstance(a_in, torch.Tensor):
+        _need(a_in, "a_in")
+        if a_in.shape != (B,):
+            raise ValueError("a_in must have shape (B,)")
+        ain = a_in
+    else:
+        ain = torch.full((B,), float(a_in), dtype=torch.float64, device=mask.device)
+    ctx = ctx or context(mask.device.index)
+    out = torch.empty(mask.shape, dtype=torch.float64, device=mask.device)
+    N.check(ctx._lib.rve_field_from_mask(ctx.bind_stream(), B, mask[0].numel(), _p(mask), _p(ain), float(a_bg),
+                                         _p(out)), "rve_field_from_mask")
+    return out
 
 
 def stats(ahom: torch.Tensor, L: float, ctx: Optional[Context] = None) -> dict:
@@ -352,11 +431,12 @@ def dos_moments(a: torch.Tensor, v: torch.Tensor, lmax: float, K: int, scheme: i
 def dos_eval(mu: torch.Tensor, t: torch.Tensor, lmax: float, eta: float, Q: Optional[int] = None,
              ctx: Optional[Context] = None) -> torch.Tensor:
     """Gaussian-broadened spectral density (B, nt) at the points t (nt,)
-    from moments mu (B, nv, K), averaged over the probes."""
+    from moments mu (B, nv, K), averaged over the probes (Q quadrature
+    nodes; None: the library's default)."""
     _need(mu, "mu")
     _need(t, "t")
     B, nv, K = mu.shape
-    Q = int(Q) if Q is not None else 4 * K
+    Q = int(Q) if Q is not None else 0
     ctx = ctx or context(mu.device.index)
     phi = torch.empty((B, t.numel()), dtype=torch.float64, device=mu.device)
     N.check(ctx._lib.rve_dos_eval(ctx.bind_stream(), B, nv, K, _p(mu), float(lmax), float(eta), Q, t.numel(),
@@ -364,27 +444,44 @@ def dos_eval(mu: torch.Tensor, t: torch.Tensor, lmax: float, eta: float, Q: Opti
     return phi
 
 
+def dos_plan(a: torch.Tensor, eta: float, scheme: int = 0, ctx: Optional[Context] = None):
+    """(lmax, K): the Gershgorin bound of the spectrum of the fields a
+    (B, n, n) and the moment count that resolves width eta (rve_dos_plan)."""
+    _need(a, "a")
+    if a.dim() != 3 or a.shape[1] != a.shape[2]:
+        raise ValueError("a must have shape (B, n, n)")
+    ctx = ctx or context(a.device.index)
+    lmax = ctypes.c_double()
+    K = ctypes.c_int()
+    N.check(ctx._lib.rve_dos_plan(ctx.bind_stream(), a.shape[0], a.shape[1], int(scheme), _p(a), float(eta),
+                                  ctypes.byref(lmax), ctypes.byref(K)), "rve_dos_plan")
+    return lmax.value, K.value
+
+
+def dos_probes(B: int, nv: int, n: int, seed: int, device=None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """+-1 probe vectors (B, nv, n, n) drawn on the device (rve_dos_probes)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ctx = ctx or context(dev.index)
+    v = torch.empty((int(B), int(nv), int(n), int(n)), dtype=torch.float64, device=dev)
+    N.check(ctx._lib.rve_dos_probes(ctx.bind_stream(), int(B), int(nv), int(n), int(seed) & (2**64 - 1), _p(v)),
+            "rve_dos_probes")
+    return v
+
+
 def spectral_density(a: torch.Tensor, t: torch.Tensor, eta: float, *, probes: int = 8, K: Optional[int] = None,
                      scheme: int = 0, seed: int = 0, ctx: Optional[Context] = None) -> torch.Tensor:
     """Spectral density (B, nt) of the stiffness matrix of each field, with
-    `probes` random +-1 probe vectors (seeded, drawn on the host) and enough
-    moments to resolve the width eta."""
-    B, n = a.shape[0], a.shape[1]
-    amax = float(a.max().item())
-    lmax = (8.0 if scheme == 1 else 16.0 / 3.0) * amax
-    if K is None:
-        K = int(min(20000, max(64, 6.0 * lmax / eta)))
-    import numpy as np
-    g = np.random.default_rng(seed)
-    v = torch.from_numpy(g.choice([-1.0, 1.0], size=(B, probes, n, n))).to(a.device)
-    return dos_eval(dos_moments(a, v, lmax, K, scheme, ctx), t, lmax, eta, ctx=ctx)
+    `probes` +-1 probe vectors drawn on the device from `seed`, and (K None)
+    enough moments to resolve the width eta."""
+    lmax, K_auto = dos_plan(a, eta, scheme, ctx)
+    v = dos_probes(a.shape[0], probes, a.shape[1], seed, a.device, ctx)
+    return dos_eval(dos_moments(a, v, lmax, K_auto if K is None else int(K), scheme, ctx), t, lmax, eta, ctx=ctx)
 
 
 def occupancy_threshold(mu: float) -> int:
     """Integer site-occupancy threshold of rve_sample_lattice for Poisson
-    centres with mean mu per lattice site: round(2^32 (1 - exp(-mu)))."""
-    import math
-    return int(min(max(round(4294967296.0 * -math.expm1(-float(mu))), 0), 0xFFFFFFFF))
+    centres with mean mu per lattice site (rve_occupancy_threshold)."""
+    return int(N.lib().rve_occupancy_threshold(float(mu)))
 
 
 def sample_lattice(B: int, n: int, side: int, *, seed: int, first: int = 0, occ_threshold: int,

@@ -106,7 +106,61 @@ __global__ void k_dos_phi(const double* __restrict__ S, int Q, double c, double 
   phi[(long long)b * nt + i] = acc / (double)Q;
 }
 
+// Per-workgroup max of the cell values and count of invalid cells (<= 0 or
+// NaN) over `total` cells: part[2 blk] = max, part[2 blk + 1] = count.
+__global__ void __launch_bounds__(kBlock) k_field_max(const double* __restrict__ a, long long total,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[4 * 2];
+  double mx = 0.0, bad = 0.0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
+    const double v = a[i];
+    if (v > 0.0) mx = fmax(mx, v);
+    else bad += 1.0;
+  }
+  mx = wave_max(mx);
+  bad = wave_sum(bad);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[2 * w] = mx;
+    sh[2 * w + 1] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = fmax(fmax(sh[0], sh[2]), fmax(sh[4], sh[6]));
+    part[2 * blockIdx.x + 1] = (sh[1] + sh[3]) + (sh[5] + sh[7]);
+  }
+}
+
+__global__ void k_field_max_final(const double* __restrict__ part, int P, double* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double mx = 0.0, bad = 0.0;
+  for (int t = lane; t < P; t += kWave) {
+    mx = fmax(mx, part[2 * t]);
+    bad += part[2 * t + 1];
+  }
+  mx = wave_max(mx);
+  bad = wave_sum(bad);
+  if (lane == 0) {
+    out[0] = mx;
+    out[1] = bad;
+  }
+}
+
 }  // namespace
+
+int field_max_blocks(long long total) {
+  long long b = (total + kBlock - 1) / kBlock;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void launch_field_max(const double* a, long long total, double* part, double* out, hipStream_t st) {
+  const int P = field_max_blocks(total);
+  hipLaunchKernelGGL(k_field_max, dim3(P), dim3(kBlock), 0, st, a, total, part);
+  hipLaunchKernelGGL(k_field_max_final, dim3(1), dim3(kWave), 0, st, part, P, out);
+}
 
 int dos_vec_tiles(long long N2) {
   long long vb = N2 / 1024;

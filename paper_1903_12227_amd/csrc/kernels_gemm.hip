@@ -410,7 +410,6 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   constexpr size_t kStage = (size_t)(TMR + TNR) * TLDA;
   constexpr size_t kSmem = PIPE == 0 ? NSTG * kStage * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
-  __shared__ double red[NW];
   T* As = reinterpret_cast<T*>(smem);
 
   // Tiles of this workgroup: local indices li, li + lstep, ... below lend,
@@ -622,7 +621,13 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       }
     }
     const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
-    double dot = 0.0;
+    // r.z partials per 64 x 64 output block (a wave's block, or each half of
+    // the 128-row block with BI = 8), accumulated per lane in the same order
+    // (j, then i, then e) in every tile shape: the partials do not depend on
+    // the tile variant
+    double dot[BI / 4];
+#pragma unroll
+    for (int hh = 0; hh < BI / 4; ++hh) dot[hh] = 0.0;
     // straight from the accumulators: block (i, j) of lane l holds output
     // row nb TNR + 64 wn + 16 j + l % 16 at the four consecutive columns
     // mb TMR + WR wm + 16 i + 4 (l / 16) + e
@@ -673,21 +678,21 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
           if constexpr (EPI == kEpiEinv) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dot += (double)r[e] * (double)(float)pk[e];
+            for (int e = 0; e < 4; ++e) dot[i >> 2] += (double)r[e] * (double)(float)pk[e];
           }
         }
       }
     }
     if constexpr (EPI == kEpiEinv) {
-      // wave sums, then the NW wave totals added in a fixed order
-      dot = wave_sum(dot);
-      if (lane == 0) red[w] = dot;
-      __syncthreads();
-      if (tid == 0) {
-        double d = red[0];
+      // one wave sum per 64 x 64 block, stored at [s][l block][m block]
+      const int nbl = n >> 6;
 #pragma unroll
-        for (int k = 1; k < NW; ++k) d += red[k];
-        part[(long long)s * (MB * NB) + mb * NB + nb] = d * dfac;
+      for (int hh = 0; hh < BI / 4; ++hh) {
+        const double d = wave_sum(dot[hh]);
+        if (lane == 0) {
+          const int lblk = (nb * TNR + wn * 64) >> 6, mblk = (mb * TMR + wm * WR + hh * 64) >> 6;
+          part[(long long)s * nbl * nbl + (long long)lblk * nbl + mblk] = d * dfac;
+        }
       }
     }
     li = lnext;
@@ -1125,12 +1130,11 @@ bool gemm_variant_valid(int n, int prec, int variant) {
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
-  // (variant 4 writes its r.z partials from 128 x 128 tiles, as 1 and 3;
-  // variant 5 from its 256 x 256 tiles)
-  return variant == 2                                    ? (n / TM) * (n / (2 * TN))
-         : variant == 5 || variant == 6                  ? (n / 256) * (n / 256)
-         : (variant == 1 || variant == 3 || variant == 4) ? (n / TM) * (n / TN)
-                                           : (n / BM) * (n / BN);
+  // r.z partials per system: one per 64 x 64 output block for the 64 x 64
+  // kernel and every 16-bit tile variant (1, 3, 4, 5, 6 write the same
+  // values), one per folded 128 x 256 tile for variant 2
+  (void)prec;
+  return variant == 2 ? (n / TM) * (n / (2 * TN)) : (n / BM) * (n / BN);
 }
 
 int gemm_tiles_per_system_max(int n) { return (n / BM) * (n / BN); }

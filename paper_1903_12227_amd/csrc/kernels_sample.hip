@@ -80,7 +80,33 @@ __global__ void __launch_bounds__(kBlock) k_sample_lattice(int n, int side, unsi
   }
 }
 
+// Probe vectors with entries +-1: entry i of the [total] array takes bit
+// (i mod 32) of word (i div 32) mod 4 of Philox4x32-10 with counter
+// (i div 128 mod 2^32, i div 2^39, 0, kProbeTag) and key (seed mod 2^32,
+// seed div 2^32); a set bit gives -1. Thread t writes entries 128 t ..
+// 128 t + 127.
+constexpr unsigned kProbeTag = 0x50524F42u;   // distinguishes these counters from the lattice sampler's
+__global__ void __launch_bounds__(kBlock) k_probes(long long total, unsigned seed_lo, unsigned seed_hi,
+                                                   double* __restrict__ v) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long i0 = t * 128;
+  if (i0 >= total) return;
+  const uint4 wv = philox4x32_10(make_uint4((unsigned)((unsigned long long)t & 0xFFFFFFFFull),
+                                            (unsigned)((unsigned long long)t >> 32), 0u, kProbeTag),
+                                 seed_lo, seed_hi);
+  const unsigned words[4] = {wv.x, wv.y, wv.z, wv.w};
+  for (int k = 0; k < 128 && i0 + k < total; ++k)
+    v[i0 + k] = ((words[k >> 5] >> (k & 31)) & 1u) ? -1.0 : 1.0;
+}
+
 }  // namespace
+
+void launch_probes(long long total, unsigned long long seed, double* v, hipStream_t st) {
+  const long long threads = (total + 127) / 128;
+  const long long blocks = (threads + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_probes, dim3((unsigned)blocks), dim3(kBlock), 0, st, total,
+                     (unsigned)(seed & 0xFFFFFFFFull), (unsigned)(seed >> 32), v);
+}
 
 bool sample_side_valid(int n, int side) { return side >= 1 && side <= kMaxSide && side <= n; }
 

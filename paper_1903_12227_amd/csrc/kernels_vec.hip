@@ -1052,11 +1052,13 @@ __global__ void k_finalize(const SysState* sys, int B, int* iters, double* relre
 }
 
 // grad[e] = sum_ij G_ij dA_ij/da_e = (G11 E11 + (G12 + G21) E12 + G22 E22)/n^2,
-// plus per-tile partial sums over the cells with a_e == a_in.
+// plus per-tile partial sums over the inclusion cells: those with
+// mask[e] != 0, or (mask == nullptr) those with a_e == a_in.
 template <int SCH>
 __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ a, const double* __restrict__ phi,
                                                   double inv_h, const double* __restrict__ G,
-                                                  double* __restrict__ grad, double a_in, int n,
+                                                  double* __restrict__ grad, double a_in,
+                                                  const unsigned char* __restrict__ mask, int n,
                                                   double* __restrict__ part, int want_in) {
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1083,7 +1085,7 @@ __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ a, c
     const double g = g11 * E.e11 + g12 * E.e12 + g22 * E.e22;
     const long long oc = (long long)row * n + col;
     Gr[oc] = g;
-    if (A[oc] == a_in) acc[0] += g;
+    if (want_in && (mask ? mask[(long long)b * N2 + oc] != 0 : A[oc] == a_in)) acc[0] += g;
     u00 = u10; u01 = u11; v00 = v10; v01 = v11;
   }
   if (want_in) {
@@ -1101,6 +1103,28 @@ __global__ void k_scalar_grad(const double* __restrict__ part, int P, double* gr
   for (int t = lane; t < P; t += kWave) v += part[(long long)b * P + t];
   v = wave_sum(v);
   if (lane == 0) grad_in[b] = v;
+}
+
+// out[0] = sum_b v[b], one wave, fixed order.
+__global__ void k_sum_items(const double* __restrict__ v, int B, double* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double s = 0;
+  for (int b = lane; b < B; b += kWave) s += v[b];
+  s = wave_sum(s);
+  if (lane == 0) out[0] = s;
+}
+
+// a[b][e] = mask[b][e] ? a_in[b] : a_bg (the covered set of eqn. Stoch-decomp
+// carries the inclusion value, eqn. ahm_coef).
+__global__ void __launch_bounds__(kBlock) k_field_from_mask(const unsigned char* __restrict__ mask,
+                                                             const double* __restrict__ a_in, double a_bg,
+                                                             long long N2, double* __restrict__ a) {
+  const int b = blockIdx.y;
+  const double ain = a_in[b];
+  const long long off = (long long)b * N2;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < N2; i += stride)
+    a[off + i] = mask[off + i] ? ain : a_bg;
 }
 
 // Ensemble statistics in one workgroup (fixed-order reductions).
@@ -1489,17 +1513,27 @@ void launch_finalize(const Work& w, int* iters, double* relres, int* status, hip
 }
 
 void launch_grad(int B, int n, int scheme, const double* a, const double* phi, double inv_h, const double* G,
-                 double* grad, double a_in, double* part, int want_in, hipStream_t st) {
+                 double* grad, double a_in, const unsigned char* mask, double* part, int want_in, hipStream_t st) {
   dim3 g(n / kTile, n / kTile, B);
   if (scheme == 1)
-    hipLaunchKernelGGL(k_grad<1>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
+    hipLaunchKernelGGL(k_grad<1>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, mask, n, part, want_in);
   else
-    hipLaunchKernelGGL(k_grad<0>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, n, part, want_in);
+    hipLaunchKernelGGL(k_grad<0>, g, dim3(kBlock), 0, st, a, phi, inv_h, G, grad, a_in, mask, n, part, want_in);
 }
 
-void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st) {
-  const int P = (n / kTile) * (n / kTile);
+int grad_tiles_per_realization(int n) { return (n / kTile) * (n / kTile); }
+
+void launch_scalar_grad(int B, int n, const double* part, double* grad_in, double* grad_in_sum, hipStream_t st) {
+  const int P = grad_tiles_per_realization(n);
   hipLaunchKernelGGL(k_scalar_grad, dim3(B), dim3(kWave), 0, st, part, P, grad_in);
+  if (grad_in_sum) hipLaunchKernelGGL(k_sum_items, dim3(1), dim3(kWave), 0, st, grad_in, B, grad_in_sum);
+}
+
+void launch_field_from_mask(int B, long long N2, const unsigned char* mask, const double* a_in, double a_bg,
+                            double* a, hipStream_t st) {
+  long long blocks = (N2 + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_field_from_mask, dim3((unsigned)blocks, B), dim3(kBlock), 0, st, mask, a_in, a_bg, N2, a);
 }
 
 void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t st) {

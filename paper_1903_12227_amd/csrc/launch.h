@@ -118,10 +118,18 @@ void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);
 void launch_phi_out(const Work& w, double* phi, double h, hipStream_t st);
 void launch_finalize(const Work& w, int* iters, double* relres, int* status, hipStream_t st);
+// Per-cell gradient; with want_in, per-tile partial sums over the inclusion
+// cells (mask[e] != 0, or a_e == a_in when mask is null) into part
+// [B][grad_tiles_per_realization(n)].
 void launch_grad(int B, int n, int scheme, const double* a, const double* phi, double inv_h,
-                 const double* G, double* grad, double a_in, double* part, int want_in,
-                 hipStream_t st);
-void launch_scalar_grad(int B, int n, const double* part, double* grad_in, hipStream_t st);
+                 const double* G, double* grad, double a_in, const unsigned char* mask, double* part,
+                 int want_in, hipStream_t st);
+int grad_tiles_per_realization(int n);
+// grad_in[b] = sum of realization b's partials; grad_in_sum (optional) = sum_b grad_in[b]
+void launch_scalar_grad(int B, int n, const double* part, double* grad_in, double* grad_in_sum, hipStream_t st);
+// a[b][e] = mask[b][e] ? a_in[b] : a_bg for B fields of N2 cells
+void launch_field_from_mask(int B, long long N2, const unsigned char* mask, const double* a_in, double a_bg,
+                            double* a, hipStream_t st);
 void launch_stats(int N, double L, const double* ahom, double* out, hipStream_t st);
 void launch_apply_stencil(int B, int n, int scheme, const double* a, const double* u, double* out,
                           hipStream_t st);
@@ -157,8 +165,16 @@ bool sample_side_valid(int n, int side);
 void launch_sample_lattice(int B, int n, int side, unsigned long long seed, long long first, unsigned occ_threshold,
                            double a_in, double a_bg, double* a, hipStream_t st);
 
+// +-1 probe vectors from Philox4x32-10 words (kernels_sample.hip): total
+// entries, at most 2^39 * 128.
+void launch_probes(long long total, unsigned long long seed, double* v, hipStream_t st);
+
 // Spectral density by Chebyshev moments (kernels_dos.hip).
 int dos_vec_tiles(long long N2);
+// out[0] = max of the positive cells, out[1] = count of cells <= 0 or NaN,
+// over `total` cells; part holds 2 field_max_blocks(total) doubles
+int field_max_blocks(long long total);
+void launch_field_max(const double* a, long long total, double* part, double* out, hipStream_t st);
 void launch_dos_moments(int B, int n, int scheme, const double* a, int nv, double* W, double* Wp, double* AW,
                         double lmax, int K, double* part, double* mu, hipStream_t st);
 void launch_dos_eval(int B, int nv, int K, const double* mu, double lmax, double eta, int Q, int nt,

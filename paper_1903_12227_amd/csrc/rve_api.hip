@@ -103,6 +103,7 @@ struct rve_ctx {
   hipEvent_t chunk_ev[2] = {nullptr, nullptr};
   bool timing = false;
   EventTimer timer;
+  double* one_out = nullptr;   // device staging of rve_solve's and rve_dos_plan's host outputs (16 doubles)
 };
 
 namespace {
@@ -432,6 +433,17 @@ void bind(char* base, const Layout& L, Work* w) {
   w->f = w->sprec ? reinterpret_cast<double*>(base + L.off_f) : nullptr;
 }
 
+// The context's small device buffer for results that go to the host.
+int ensure_one_out(rve_ctx* ctx) {
+  if (ctx->one_out) return RVE_OK;
+  if (hipMalloc(reinterpret_cast<void**>(&ctx->one_out), 16 * sizeof(double)) != hipSuccess) {
+    ctx->one_out = nullptr;
+    (void)hipGetLastError();
+    return RVE_ENOMEM;
+  }
+  return RVE_OK;
+}
+
 int check_opts(const rve_opts* o) {
   if (!o) return RVE_EINVAL;
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RVE_EINVAL;
@@ -751,8 +763,13 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       // the even/odd-folded variant (2) is faster per apply but its extra BF16
       // rounding costs iterations (n = 512: 39.3 vs 38.0; n = 2048: 149 vs
       // 100), which a per-apply timing cannot see: it is used only on request
+      // the 16-bit tile variants 1, 4, 5 and 6 accumulate every output and
+      // every r.z partial in the same order, so the pick among them cannot
+      // change a result; the 64 x 64 kernel (0), which forms r.z from the z
+      // it writes instead, is a candidate only where none of them fits
+      const bool h16_tiles = gemm_variant_valid(n, prec, 1);
       for (int v : {0, 1, 4, 5, 6})
-        if (gemm_variant_valid(n, prec, v)) gc.push_back(v);
+        if (gemm_variant_valid(n, prec, v) && !(h16_tiles && v == 0)) gc.push_back(v);
       if (ctx->tune.count(kgm) || tune_now)
         w.gemm_variant = tune_pick(ctx, kgm, gc, [&](int v) {
           Work t2 = w;
@@ -946,6 +963,7 @@ int rve_destroy(rve_ctx* c) {
   ignore(hipEventDestroy(c->chunk_ev[0]));
   ignore(hipEventDestroy(c->chunk_ev[1]));
   ignore(hipHostFree(c->h_count));
+  if (c->one_out) ignore(hipFree(c->one_out));
   delete c;
   return RVE_OK;
 }
@@ -975,6 +993,39 @@ int rve_solve_batch(rve_ctx* c, int B, int n, double h, const double* a_dev, con
   b.relres = relres_dev;
   b.status = status_dev;
   return solve_batches(c, bs, h, o, nullptr);
+}
+
+int rve_solve(rve_ctx* c, int n, double h, const double* a_dev, const rve_opts* o, double* phi_dev,
+              double* ahom_host, double* ahom_flux_host, int* iters_host, double* relres_host) {
+  if (!c || !n_supported(n) || !(h > 0.0) || !std::isfinite(h) || !a_dev || !ahom_host) return RVE_EINVAL;
+  if (check_opts(o)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  int rc = ensure_one_out(c);
+  if (rc) return rc;
+  // staging: [0..3] A_hom, [4..7] flux form, [8..9] relres, then the ints
+  // iters[2] and status in the bytes of [10..11]
+  double* out = c->one_out;
+  std::vector<Batch> bs(1);
+  Batch& b = bs[0];
+  b.B = 1;
+  b.n = n;
+  b.a = a_dev;
+  b.phi = phi_dev;
+  b.ahom = out;
+  b.flux = out + 4;
+  b.relres = out + 8;
+  b.iters = reinterpret_cast<int*>(out + 10);
+  b.status = reinterpret_cast<int*>(out + 11);
+  rc = solve_batches(c, bs, h, o, nullptr);
+  if (rc == RVE_EHIP || rc == RVE_ENOMEM) return rc;
+  double host[12];
+  HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(ahom_host, host, 4 * sizeof(double));
+  if (ahom_flux_host) std::memcpy(ahom_flux_host, host + 4, 4 * sizeof(double));
+  if (relres_host) std::memcpy(relres_host, host + 8, 2 * sizeof(double));
+  if (iters_host) std::memcpy(iters_host, host + 10, 2 * sizeof(int));
+  return rc;
 }
 
 // Launch-size bound of the 3D kernels: every grid stays below 2^31 workgroups.
@@ -1137,19 +1188,60 @@ int rve_solve_uneven(rve_ctx* c, int B, const int* n_host, const int64_t* off, d
   return rc;
 }
 
-int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
-             const double* G_dev, double* grad_a_dev, double a_in, double* grad_in_dev, int scheme) {
-  if (!c || B < 1 || !n_supported(n) || !(h > 0.0) || !a_dev || !phi_dev || !G_dev || !grad_a_dev)
+// Argument checks of the gradient call, and the bytes of
+// scratch the call needs (partials, and per-item totals when the caller
+// wants only their sum).
+int grad_args(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
+              const double* G_dev, double* grad_a_dev, const unsigned char* mask, double a_in,
+              double* grad_in_dev, double* grad_in_sum_dev, int scheme, size_t* scratch_bytes) {
+  if (!c || B < 1 || !n_supported(n) || !(h > 0.0) || !std::isfinite(h) || !a_dev || !phi_dev || !G_dev ||
+      !grad_a_dev)
     return RVE_EINVAL;
   if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
-  HIP_TRY(hipSetDevice(c->device));
-  const int P = (n / kTile) * (n / kTile);
-  const int rc = ensure_ws(c, align_up((size_t)B * P * 8));
-  if (rc) return rc;
-  double* part = static_cast<double*>(c->ws);
-  launch_grad(B, n, scheme, a_dev, phi_dev, 1.0 / h, G_dev, grad_a_dev, a_in, part, grad_in_dev != nullptr,
+  const bool want_in = grad_in_dev || grad_in_sum_dev;
+  if (want_in && !mask && !std::isfinite(a_in)) return RVE_EINVAL;
+  const size_t P = (size_t)grad_tiles_per_realization(n);
+  *scratch_bytes = want_in ? align_up((size_t)B * P * 8) + (grad_in_dev ? 0 : align_up((size_t)B * 8)) : 0;
+  return RVE_OK;
+}
+
+void grad_launch(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
+                 const double* G_dev, double* grad_a_dev, const unsigned char* mask, double a_in,
+                 double* grad_in_dev, double* grad_in_sum_dev, int scheme, char* scratch) {
+  const bool want_in = grad_in_dev || grad_in_sum_dev;
+  const size_t P = (size_t)grad_tiles_per_realization(n);
+  double* part = reinterpret_cast<double*>(scratch);
+  double* totals = grad_in_dev ? grad_in_dev
+                               : (want_in ? reinterpret_cast<double*>(scratch + align_up((size_t)B * P * 8)) : nullptr);
+  launch_grad(B, n, scheme, a_dev, phi_dev, 1.0 / h, G_dev, grad_a_dev, a_in, mask, part, want_in ? 1 : 0,
               c->stream);
-  if (grad_in_dev) launch_scalar_grad(B, n, part, grad_in_dev, c->stream);
+  if (want_in) launch_scalar_grad(B, n, part, totals, grad_in_sum_dev, c->stream);
+}
+
+int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
+             const double* G_dev, double* grad_a_dev, const unsigned char* incl_mask_dev, double a_in,
+             double* grad_in_dev, double* grad_in_sum_dev, int scheme) {
+  size_t bytes = 0;
+  int rc = grad_args(c, B, n, a_dev, phi_dev, h, G_dev, grad_a_dev, incl_mask_dev, a_in, grad_in_dev,
+                     grad_in_sum_dev, scheme, &bytes);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(c->device));
+  if (bytes) {
+    rc = ensure_ws(c, bytes);
+    if (rc) return rc;
+  }
+  grad_launch(c, B, n, a_dev, phi_dev, h, G_dev, grad_a_dev, incl_mask_dev, a_in, grad_in_dev, grad_in_sum_dev,
+              scheme, static_cast<char*>(c->ws));
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_field_from_mask(rve_ctx* c, int B, long long cells, const unsigned char* mask_dev, const double* a_in_dev,
+                        double a_bg, double* a_dev) {
+  if (!c || B < 1 || B > 65535 || cells < 1 || !mask_dev || !a_in_dev || !a_dev) return RVE_EINVAL;
+  if (!(a_bg > 0.0) || !std::isfinite(a_bg)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_field_from_mask(B, cells, mask_dev, a_in_dev, a_bg, a_dev, c->stream);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
 }
@@ -1238,8 +1330,54 @@ int rve_dos_moments(rve_ctx* c, int B, int n, int scheme, const double* a_dev, i
   return RVE_OK;
 }
 
+int rve_dos_plan(rve_ctx* c, int B, int n, int scheme, const double* a_dev, double eta, double* lmax_host,
+                 int* K_host) {
+  if (!c || B < 1 || !n_supported(n) || !a_dev || !lmax_host || !K_host) return RVE_EINVAL;
+  if (scheme != RVE_SCHEME_Q1 && scheme != RVE_SCHEME_FD5) return RVE_EINVAL;
+  if (!(eta > 0.0) || !std::isfinite(eta)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  int rc = ensure_one_out(c);
+  if (rc) return rc;
+  const long long total = (long long)B * n * n;
+  rc = ensure_ws(c, align_up((size_t)field_max_blocks(total) * 2 * 8));
+  if (rc) return rc;
+  launch_field_max(a_dev, total, static_cast<double*>(c->ws), c->one_out, c->stream);
+  double host[2];
+  HIP_TRY(hipMemcpyAsync(host, c->one_out, sizeof host, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (host[1] != 0.0 || !(host[0] > 0.0) || !std::isfinite(host[0])) return RVE_EINVAL;
+  // Gershgorin: a row of the Q1 stiffness has diagonal (2/3) sum of its four
+  // cells and off-diagonal magnitudes summing to the same, so every
+  // eigenvalue is at most (4/3) 4 max a; the five-point operator's rows give
+  // 2 * 4 max a
+  const double lmax = (scheme == RVE_SCHEME_FD5 ? 8.0 : 16.0 / 3.0) * host[0];
+  // enough moments to resolve the width eta: about 6 per eta over [0, lmax]
+  const double k = std::min(20000.0, std::max(64.0, 6.0 * lmax / eta));
+  *lmax_host = lmax;
+  *K_host = (int)k;
+  return RVE_OK;
+}
+
+int rve_dos_probes(rve_ctx* c, int B, int nv, int n, uint64_t seed, double* v_dev) {
+  if (!c || B < 1 || nv < 1 || !n_supported(n) || !v_dev) return RVE_EINVAL;
+  const long long total = (long long)B * nv * n * n;
+  if (total / nv / B != (long long)n * n || (total + 127) / 128 / kBlock >= (1LL << 31)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  launch_probes(total, (unsigned long long)seed, v_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+uint32_t rve_occupancy_threshold(double mu) {
+  if (!(mu > 0.0)) return 0u;
+  if (!std::isfinite(mu)) return 0xFFFFFFFFu;
+  const double t = std::nearbyint(4294967296.0 * -std::expm1(-mu));
+  return t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
 int rve_dos_eval(rve_ctx* c, int B, int nv, int K, const double* mu_dev, double lmax, double eta, int Q, int nt,
                  const double* t_dev, double* phi_dev) {
+  if (Q <= 0 && K >= 1 && K <= 2500000) Q = 4 * K;   // default rule
   if (!c || B < 1 || B > 65535 || nv < 1 || K < 1 || Q < K || Q > 10000000 || nt < 1 || !mu_dev || !t_dev ||
       !phi_dev)
     return RVE_EINVAL;

@@ -100,6 +100,14 @@ def batch(model: BooleanModel, config: int, count: int, start: int = 0) -> np.nd
     return out
 
 
+def uneven_sizes(sizes, config: int, per_size: int) -> np.ndarray:
+    """RVE size L of each realization of :func:`uneven_batch` (equal shares
+    of ``sizes`` in a seeded random order)."""
+    Ls = np.repeat(np.asarray(sizes, dtype=np.int64), per_size)
+    order = _rng(config, _ORDER_KEY).permutation(len(Ls))
+    return Ls[order]
+
+
 def uneven_batch(sizes, m0: int, a_in: float, a_bg: float, config: int,
                  per_size: int):
     """Equal shares of several RVE sizes in a seeded random order.
@@ -107,9 +115,7 @@ def uneven_batch(sizes, m0: int, a_in: float, a_bg: float, config: int,
     Returns a list of (L, field) pairs; realization ``r`` of the shuffled list
     uses key (config, r) whatever its size.
     """
-    Ls = np.repeat(np.asarray(sizes, dtype=np.int64), per_size)
-    order = _rng(config, _ORDER_KEY).permutation(len(Ls))
-    Ls = Ls[order]
+    Ls = uneven_sizes(sizes, config, per_size)
     out = []
     for r, L in enumerate(Ls):
         model = BooleanModel(L=int(L), m0=m0, a_in=a_in, a_bg=a_bg)

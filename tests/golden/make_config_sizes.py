@@ -1,0 +1,68 @@
+"""Writes config_sizes.json: the oracle's homogenized matrices for the seeded
+inputs of the full-size GPU parity tests (tests/test_gpu_config_sizes.py).
+
+The oracle needs about a minute per item at these sizes (n = 2048 in two
+dimensions, n = 128 in three), so its results are stored once. This script
+calls only oracle/ (the CPU reference) and sampler/ (the seeded inputs);
+each entry records a hash of its input field so the tests can tell that they
+regenerated the same input.
+
+    python tests/golden/make_config_sizes.py
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import ahom as oracle_ahom  # noqa: E402
+from oracle import q1_3d  # noqa: E402
+from sampler import BooleanModel, BooleanModel3D, realization, realization_3d, uneven_sizes  # noqa: E402
+
+OUT = os.path.join(HERE, "config_sizes.json")
+
+
+def field_hash(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()[:16]
+
+
+def inputs():
+    """(name, description, field) of every stored item; the tests build the
+    same fields with the same calls."""
+    yield ("c4_n2048", {"L": 128, "m0": 16, "contrast": 10.0, "config": 4, "index": 0},
+           realization(BooleanModel(L=128, m0=16, a_in=10.0), 4, 0))
+    Ls = uneven_sizes([8, 16, 32, 64], 3, 256)
+    for L in (32, 64):
+        r = int(np.nonzero(Ls == L)[0][0])
+        yield (f"c3_n{8 * L}_contrast100", {"L": L, "m0": 8, "contrast": 100.0, "config": 3, "index": r},
+               realization(BooleanModel(L=L, m0=8, a_in=100.0), 3, r))
+    yield ("3d_n128", {"L": 16, "m0": 8, "contrast": 10.0, "config": 96, "index": 0, "dim": 3},
+           realization_3d(BooleanModel3D(L=16, m0=8, a_in=10.0), 96, 0))
+
+
+def main():
+    out = {}
+    for name, desc, a in inputs():
+        if a.ndim == 3:
+            energy, flux, _phi, its = q1_3d.homogenize(a, tol=1e-12)
+            res = {"ahom": energy.tolist(), "ahom_flux": flux.tolist(), "iters": list(its), "tol": 1e-12}
+        else:
+            r = oracle_ahom.solve(a, tol=1e-13)
+            res = {"ahom": r.ahom.tolist(), "ahom_flux": r.ahom_flux.tolist(), "iters": list(r.iters),
+                   "tol": 1e-13}
+        out[name] = {"input": desc, "field_sha256_16": field_hash(a), **res}
+        print(name, res["ahom"], flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
+if __name__ == "__main__":
+    main()

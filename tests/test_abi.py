@@ -121,12 +121,25 @@ def test_host_argument_validation(lib):
     assert lib.rve_solve_uneven(fake, 2, ns, offs, 0.125, fake, ctypes.byref(o), None, fake, None, None,
                                 None, None) == N.EINVAL
     assert lib.rve_stats(fake, 1, 16.0, fake, fake) == N.EINVAL
-    assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, 10.0, None, 0) == N.EINVAL
+    assert lib.rve_grad(fake, 1, 48, fake, fake, 0.125, fake, fake, None, 10.0, None, None, 0) == N.EINVAL
+    # an inclusion derivative by value needs a finite inclusion value
+    assert lib.rve_grad(fake, 1, 64, fake, fake, 0.125, fake, fake, None, float("nan"), fake, None, 0) == N.EINVAL
+    # rve_solve: unsupported n, missing host output, bad h
+    A = (ctypes.c_double * 4)()
+    assert lib.rve_solve(fake, 48, 0.125, fake, ctypes.byref(o), None, A, None, None, None) == N.EINVAL
+    assert lib.rve_solve(fake, 64, 0.125, fake, ctypes.byref(o), None, None, None, None, None) == N.EINVAL
+    assert lib.rve_solve(fake, 64, 0.0, fake, ctypes.byref(o), None, A, None, None, None) == N.EINVAL
+    assert lib.rve_field_from_mask(fake, 1, 4096, fake, fake, 0.0, fake) == N.EINVAL
+    assert lib.rve_field_from_mask(fake, 0, 4096, fake, fake, 1.0, fake) == N.EINVAL
+    lmax, K = ctypes.c_double(), ctypes.c_int()
+    assert lib.rve_dos_plan(fake, 1, 64, 0, fake, 0.0, ctypes.byref(lmax), ctypes.byref(K)) == N.EINVAL
+    assert lib.rve_dos_plan(fake, 1, 64, 2, fake, 0.1, ctypes.byref(lmax), ctypes.byref(K)) == N.EINVAL
+    assert lib.rve_dos_probes(fake, 1, 1, 48, 0, fake) == N.EINVAL
     assert lib.rve_apply_operator(fake, 1, 64, fake, fake, fake, 0) == N.EINVAL   # u aliases out
     assert lib.rve_apply_precond(fake, 1, 64, fake, fake, fake, 0, 0) == N.EINVAL
     # unknown scheme
     other = ctypes.c_void_p(2)
-    assert lib.rve_grad(fake, 1, 64, fake, fake, 0.125, fake, other, 10.0, None, 2) == N.EINVAL
+    assert lib.rve_grad(fake, 1, 64, fake, fake, 0.125, fake, other, None, 10.0, None, None, 2) == N.EINVAL
     assert lib.rve_apply_operator(fake, 1, 64, fake, fake, other, 2) == N.EINVAL
     assert lib.rve_apply_precond(fake, 1, 64, fake, fake, other, 0, 2) == N.EINVAL
 
@@ -143,3 +156,16 @@ def test_header_constants_match_binding():
                       ("RVE_SCHEME_Q1", N.SCHEME_Q1), ("RVE_SCHEME_FD5", N.SCHEME_FD5)):
         m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
         assert m and int(m.group(1)) == val, name
+
+
+def test_occupancy_threshold_host_rule(lib):
+    # Poisson centres with mean mu per site: a site is a centre with
+    # probability 1 - exp(-mu), scaled to the 32-bit comparison threshold
+    import math
+    for mu in (1e-6, math.log(2.0) / 64, math.log(2.0) / 4, 0.5, 3.0):
+        want = round(4294967296.0 * -math.expm1(-mu))
+        assert lib.rve_occupancy_threshold(mu) == min(want, 0xFFFFFFFF)
+    assert lib.rve_occupancy_threshold(0.0) == 0
+    assert lib.rve_occupancy_threshold(-1.0) == 0
+    assert lib.rve_occupancy_threshold(float("nan")) == 0
+    assert lib.rve_occupancy_threshold(800.0) == 0xFFFFFFFF

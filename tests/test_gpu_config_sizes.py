@@ -1,0 +1,224 @@
+"""Parity with the oracle at the full sizes of the study's workloads.
+
+* gradient at L = 64 (n = 512), 64 realizations, contrast 10: per-cell and
+  inclusion-value derivatives against the oracle on sampled items, the Euler
+  identity on every item, central differences with step 1e-6 (Sec. 4.3,
+  eqns. wg03, wg01; Sec. 2, eqn. Stoch-decomp);
+* L = 128, h = 1/16 (n = 2048): one realization in every transform
+  precision against the oracle's A_hom (Sec. 3.5, Lemma Cond_Number);
+* three dimensions at n = 128: the operator element by element against the
+  oracle's assembled matrix, and A_hom against the oracle's (Sec. 2 for
+  d = 3, eqn. As_Kron_d);
+* an uneven batch holding n = 256 and n = 512 items at contrast 100.
+
+The oracle's A_hom at n = 2048, for the contrast-100 items and in three
+dimensions (about a minute of host time each) is stored in
+tests/golden/config_sizes.json by tests/golden/make_config_sizes.py, which
+calls only the oracle; each entry carries a hash of its input field, checked
+here. Relative error of a d x d result: max |dA_ij| / max_i |A_ii|.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ahom as oa
+from oracle import q1_3d
+from sampler import (BooleanModel, BooleanModel3D, covered_mask, realization, realization_3d,
+                     uneven_sizes)
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "config_sizes.json")) as _f:
+    GOLD = json.load(_f)
+
+
+def _rve():
+    import paper_1903_12227_amd as rve
+    return rve
+
+
+def _to(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _hash(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()[:16]
+
+
+def rel(A, R):
+    A, R = np.asarray(A), np.asarray(R)
+    return float(np.max(np.abs(A - R)) / np.max(np.abs(np.diagonal(R))))
+
+
+def _gold(name, a):
+    g = GOLD[name]
+    assert _hash(a) == g["field_sha256_16"], f"{name}: the sampler no longer gives the stored input"
+    return np.array(g["ahom"])
+
+
+# ---------------------------------------------------------------- gradient
+
+
+@pytest.mark.timeout(900)
+def test_gradient_n512_b64_against_oracle_euler_and_fd(dev):
+    rve = _rve()
+    B, n, h, c = 64, 512, 1.0 / 8, 10.0
+    model = BooleanModel(L=64, m0=8, a_in=c)
+    masks = np.stack([covered_mask(model, 5, b) for b in range(B)])
+    a = np.where(masks, c, 1.0)
+    ad, md = _to(a, dev), _to(masks, dev)
+    # d(A_11 + A_12), the workload's upstream weights
+    G = np.zeros((B, 2, 2))
+    G[:, 0, 0] = 1.0
+    G[:, 0, 1] = 1.0
+    Gd = _to(G, dev)
+    res = rve.solve_batch(ad, h, rve.Options(tol=1e-12, prec=rve.MIX_BF16))
+    assert res.code == 0
+    g, gin, gsum = rve.grad(ad, res.phi, h, Gd, mask=md, want_sum=True)
+    g, gin, gsum = g.cpu().numpy(), gin.cpu().numpy(), float(gsum.item())
+    A = res.ahom.cpu().numpy()
+    # per-cell and inclusion-value derivatives against the oracle on sampled
+    # items (8 x 8 tiles of 64 x 64 cells: seams and multi-tile partial sums)
+    for b in (0, 41):
+        ref = oa.solve(a[b], tol=1e-13)
+        d = oa.dahom_da(a[b], ref.phi)
+        gref = np.einsum("ij,ijxy->xy", G[b], d)
+        assert np.max(np.abs(g[b] - gref)) <= 1e-9 * np.max(np.abs(gref)), b
+        cref = np.einsum("ij,ij->", G[b], oa.dahom_dcontrast(d, masks[b]))
+        assert abs(gin[b] - cref) <= 1e-9 * abs(cref), b
+    # Euler identity (A_hom is homogeneous of degree one in a), every item
+    for b in range(B):
+        lhs = float(np.sum(a[b] * g[b]))
+        rhs = float(np.sum(G[b] * A[b]))
+        assert abs(lhs - rhs) <= 1e-11 * abs(rhs), b
+    # the batch sum of the inclusion derivative
+    assert abs(gsum - float(np.sum(gin))) <= 1e-13 * float(np.sum(np.abs(gin)))
+    # central differences with step s = 1e-6 at the workload's tolerance, on
+    # two items: along a random +-1 field, and in the inclusion value. An
+    # A_hom entry at n = 512 carries a rounding error below 1e-13, so a
+    # difference quotient is good to about 1e-13 / s = 1e-7 in absolute terms;
+    # the bound allows ten times that plus 1e-6 relative.
+    s = 1e-6
+    opts = rve.Options(tol=1e-10, prec=rve.MIX_BF16)
+    items = (0, 41)
+    rng = np.random.default_rng(512)
+    v = rng.choice([-1.0, 1.0], size=(len(items), n, n))
+    pm = np.concatenate([a[list(items)] + s * v, a[list(items)] - s * v])
+    Apm = rve.solve_batch(_to(pm, dev), h, opts, want_phi=False).ahom.cpu().numpy()
+    for k, b in enumerate(items):
+        fd = float(np.sum(G[b] * (Apm[k] - Apm[len(items) + k]))) / (2 * s)
+        an = float(np.sum(g[b] * v[k]))
+        assert abs(fd - an) <= 1e-6 + 1e-6 * abs(an), (b, fd, an)
+    mk = _to(masks[list(items)], dev)
+    cp = torch.full((len(items),), c + s, dtype=torch.float64, device=dev)
+    cm = torch.full((len(items),), c - s, dtype=torch.float64, device=dev)
+    Ap = rve.solve_batch(rve.field_from_mask(mk, cp, 1.0), h, opts, want_phi=False).ahom.cpu().numpy()
+    Am = rve.solve_batch(rve.field_from_mask(mk, cm, 1.0), h, opts, want_phi=False).ahom.cpu().numpy()
+    for k, b in enumerate(items):
+        fd = float(np.sum(G[b] * (Ap[k] - Am[k]))) / (2 * s)
+        assert abs(fd - gin[b]) <= 1e-6 + 1e-6 * abs(gin[b]), (b, fd, gin[b])
+
+
+def test_contrast_derivative_uses_the_covered_set(dev):
+    # a_bg = contrast = 1: every cell has the same value, but only the
+    # covered cells move with the contrast; and a float32 contrast (10.1 is
+    # not a double) still finds its cells
+    rve = _rve()
+    n, h = 128, 1.0 / 8
+    model = BooleanModel(L=16, m0=8)
+    masks = np.stack([covered_mask(model, 7, b) for b in range(2)])
+    md = _to(masks, dev)
+    opts = rve.Options(tol=1e-12)
+    for c, dt in ((1.0, torch.float64), (10.1, torch.float32)):
+        cval = torch.tensor(c, dtype=dt, device=dev, requires_grad=True)
+        A = rve.ahom_contrast(cval, md, 1.0, h, opts)
+        A[:, 0, 0].sum().backward()
+        cexact = float(torch.tensor(c, dtype=dt).double())
+
+        def a11(cc):
+            f = rve.field_from_mask(md, cc, 1.0)
+            return rve.solve_batch(f, h, opts, want_phi=False).ahom[:, 0, 0].sum().item()
+        s = 1e-6
+        fd = (a11(cexact + s) - a11(cexact - s)) / (2 * s)
+        assert abs(cval.grad.item() - fd) <= 1e-6 + 1e-6 * abs(fd), (c, cval.grad.item(), fd)
+        if c == 1.0:
+            # all cells equal: the value-matching rule would give the Euler sum
+            # A_11 = 1 per item instead of the covered cells' share
+            assert abs(cval.grad.item() - 2.0) > 0.1
+    # one contrast per realization
+    cvec = torch.tensor([4.0, 12.0], dtype=torch.float64, device=dev, requires_grad=True)
+    A = rve.ahom_contrast(cvec, md, 1.0, h, opts)
+    A[:, 0, 1].sum().backward()
+    for k in range(2):
+        def a12(cc):
+            vals = cvec.detach().clone()
+            vals[k] = cc
+            return rve.solve_batch(rve.field_from_mask(md, vals, 1.0), h, opts,
+                                   want_phi=False).ahom[k, 0, 1].item()
+        fd = (a12(float(cvec[k]) + 1e-6) - a12(float(cvec[k]) - 1e-6)) / 2e-6
+        assert abs(cvec.grad[k].item() - fd) <= 1e-6 + 1e-6 * abs(fd)
+
+
+# ---------------------------------------------------------------- n = 2048
+
+
+@pytest.mark.timeout(900)
+def test_n2048_every_precision_against_oracle(dev):
+    rve = _rve()
+    a = realization(BooleanModel(L=128, m0=16, a_in=10.0), 4, 0)
+    ref = _gold("c4_n2048", a)
+    ad = _to(a, dev).unsqueeze(0).contiguous()
+    for prec, bound in ((rve.MIX_BF16, 1e-8), (rve.MIX_FP16, 1e-8), (rve.MIX_FP32, 1e-8), (rve.FP64, 1e-10)):
+        res = rve.solve_batch(ad, 1.0 / 16, rve.Options(tol=1e-10, prec=prec), want_phi=False)
+        assert res.code == 0, prec
+        assert rel(res.ahom.cpu().numpy()[0], ref) <= bound, (prec, rel(res.ahom.cpu().numpy()[0], ref))
+
+
+# ---------------------------------------------------------------- 3D n = 128
+
+
+@pytest.mark.timeout(900)
+def test_3d_n128_operator_and_ahom_against_oracle(dev):
+    rve = _rve()
+    n = 128
+    a = realization_3d(BooleanModel3D(L=16, m0=8, a_in=10.0), 96, 0)
+    ref = _gold("3d_n128", a)
+    ad = _to(a, dev).unsqueeze(0).contiguous()
+    # the operator alone, element by element (x3 tile seams, every x1 strip)
+    u = np.random.default_rng(128).standard_normal((1, n, n, n))
+    out = rve.apply_operator_3d(ad, _to(u, dev)).cpu().numpy()[0]
+    K = q1_3d.assemble(a)
+    want = (K @ u[0].ravel()).reshape(n, n, n)
+    assert np.max(np.abs(out - want)) <= 1e-13 * np.max(np.abs(want))
+    del K
+    for prec, bound in ((rve.FP64, 1e-10), (rve.MIX_BF16, 1e-8)):
+        res = rve.solve_batch_3d(ad, 0.125, rve.Options(tol=1e-10, prec=prec), want_phi=False)
+        assert res.code == 0, prec
+        assert rel(res.ahom.cpu().numpy()[0], ref) <= bound, (prec, rel(res.ahom.cpu().numpy()[0], ref))
+
+
+# ---------------------------------------------------------------- uneven, contrast 100
+
+
+def test_uneven_n256_n512_contrast100_against_oracle(dev):
+    rve = _rve()
+    Ls = uneven_sizes([8, 16, 32, 64], 3, 256)
+    items, names = [], []
+    for L in (32, 64, 8, 16):
+        r = int(np.nonzero(Ls == L)[0][0])
+        items.append(realization(BooleanModel(L=L, m0=8, a_in=100.0), 3, r))
+        names.append(f"c3_n{8 * L}_contrast100" if L >= 32 else None)
+    fields = [_to(f, dev) for f in items]
+    for prec, sprec, bound in ((rve.FP64, 0, 1e-10), (rve.MIX_BF16, 0, 1e-8), (rve.MIX_FP16, 1, 1e-8)):
+        res = rve.solve_uneven(fields, 0.125, rve.Options(tol=1e-10, prec=prec, stencil_prec=sprec))
+        assert res.code == 0
+        A = res.ahom.cpu().numpy()
+        for k, name in enumerate(names):
+            if name is None:
+                continue
+            assert rel(A[k], _gold(name, items[k])) <= bound, (prec, sprec, name)

@@ -50,3 +50,26 @@ def test_density_estimate_close_to_exact_eigenvalues(dev):
     est = rve.spectral_density(at, torch.from_numpy(t).to(dev), eta, probes=32, seed=3).cpu().numpy()[0]
     exact = dos.dos_exact(lam, t, eta)
     assert np.max(np.abs(est - exact)) <= 0.05 * np.max(exact)
+
+
+def test_plan_and_device_probes(dev):
+    # rve_dos_plan: the Gershgorin bound and the moment count rule; probes
+    # drawn on the device equal the oracle's Philox probe rule bit for bit
+    rve = _rve()
+    n, B = 128, 3
+    a = batch(BooleanModel(L=16, m0=8, a_in=7.0), 76, B)
+    at = torch.from_numpy(a).to(dev)
+    for scheme, c in ((0, 16.0 / 3.0), (1, 8.0)):
+        lmax, K = rve.dos_plan(at, 0.05, scheme)
+        assert lmax == c * 7.0
+        assert K == int(min(20000.0, max(64.0, 6.0 * lmax / 0.05)))
+    _, K = rve.dos_plan(at, 100.0)
+    assert K == 64
+    bad = a.copy()
+    bad[2, 3, 4] = 0.0
+    with pytest.raises(rve.RveError):
+        rve.dos_plan(torch.from_numpy(bad).to(dev), 0.05)
+    seed = (3 << 32) | 77
+    v = rve.dos_probes(B, 4, n, seed, dev).cpu().numpy()
+    assert np.array_equal(v.ravel(), dos.philox_probes(v.size, seed))
+    assert not np.array_equal(v, rve.dos_probes(B, 4, n, seed + 1, dev).cpu().numpy())

@@ -100,7 +100,7 @@ def test_fd5_gradient_matches_oracle(dev):
     a = _fields(n, B, 63)
     res = rve.solve_batch(_to(a, dev), h, rve.Options(tol=1e-12, scheme=1))
     G = np.random.default_rng(4).standard_normal((B, 2, 2))
-    g, gin = rve.grad(_to(a, dev), res.phi, h, _to(G, dev), a_in=10.0, scheme=1)
+    g, gin, _ = rve.grad(_to(a, dev), res.phi, h, _to(G, dev), a_in=10.0, scheme=1)
     g, gin = g.cpu().numpy(), gin.cpu().numpy()
     for b in range(B):
         ref = fd5.solve(a[b], tol=1e-13)
