@@ -277,6 +277,24 @@ int rve_grad(rve_ctx* ctx, int B, int n, const double* a_dev,
              double* grad_in_dev, double* grad_in_sum_dev, int scheme);
 
 /*
+ * rve_grad without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, kernels and results as rve_grad; the partial
+ * sums go to a fixed scratch array of 4 MiB per GPU (a static device array,
+ * held by the process until it ends) instead of the context's workspace.
+ * Needs 8 B (n/64)^2 per realization when an inclusion derivative is asked
+ * for (plus 8 B per realization when only its sum is); a call needing more
+ * than 4 MiB returns RVE_EINVAL (and says so on stderr) with nothing
+ * enqueued. All calls on one GPU share that GPU's array: calls that overlap
+ * on one GPU (different streams or threads without ordering) race. Every
+ * scratch byte a call reads it writes first. Asynchronous.
+ */
+int rve_grad_noalloc(rve_ctx* ctx, int B, int n, const double* a_dev,
+                     const double* phi_dev, double h, const double* G_dev,
+                     double* grad_a_dev, const unsigned char* incl_mask_dev, double a_in,
+                     double* grad_in_dev, double* grad_in_sum_dev, int scheme);
+
+/*
  * Coefficient fields of the two-valued model from their covered sets (Sec. 2,
  * eqns. Stoch-decomp and ahm_coef): a_dev[b][e] = a_in_dev[b] where
  * mask_dev[b][e] != 0, else a_bg. cells = cells per field (n^2, or n^3 in

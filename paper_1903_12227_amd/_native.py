@@ -27,6 +27,7 @@ EXPORTS = (
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
     "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d", "rve_set_small_solver",
     "rve_solve", "rve_field_from_mask", "rve_dos_plan", "rve_dos_probes", "rve_occupancy_threshold",
+    "rve_grad_noalloc",
 )
 
 
@@ -60,6 +61,7 @@ def _declare(lib):
     lib.rve_solve.argtypes = [_vp, _i, _d, _vp, ctypes.POINTER(RveOpts), _vp, ctypes.POINTER(_d),
                               ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_d)]
     lib.rve_grad.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _d, _vp, _vp, _i]
+    lib.rve_grad_noalloc.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _d, _vp, _vp, _i]
     lib.rve_field_from_mask.argtypes = [_vp, _i, ctypes.c_longlong, _vp, _vp, _d, _vp]
     lib.rve_dos_plan.argtypes = [_vp, _i, _i, _i, _vp, _d, ctypes.POINTER(_d), ctypes.POINTER(_i)]
     lib.rve_dos_probes.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, _vp]

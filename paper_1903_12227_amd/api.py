@@ -333,11 +333,13 @@ def _mask_bytes(mask: torch.Tensor, shape, dev) -> torch.Tensor:
 
 def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
          a_in: Optional[float] = None, *, mask: Optional[torch.Tensor] = None, want_sum: bool = False,
-         ctx: Optional[Context] = None, scheme: int = 0):
+         ctx: Optional[Context] = None, scheme: int = 0, noalloc: bool = False):
     """sum_ij G_ij dA_ij/da per cell, (B, n, n); and, if a covered set is
     given (mask (B, n, n) bool/uint8, or else the cells equal to a_in), the
     derivative with respect to the inclusion value per realization (B,),
     and with want_sum its sum over the batch (a 1-element tensor).
+    noalloc: use rve_grad_noalloc (the library allocates no device memory;
+    outputs are still allocated here).
     Returns (grad_a, grad_in or None, grad_in_sum or None)."""
     _need(a, "a")
     _need(phi, "phi")
@@ -356,9 +358,10 @@ def grad(a: torch.Tensor, phi: torch.Tensor, h: float, G: torch.Tensor,
     out = torch.empty_like(a)
     gin = torch.empty((B,), dtype=torch.float64, device=a.device) if want_in else None
     gsum = torch.empty((1,), dtype=torch.float64, device=a.device) if want_sum else None
-    N.check(ctx._lib.rve_grad(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out), _p(mask),
-                              float(a_in if a_in is not None else 0.0), _p(gin), _p(gsum), int(scheme)),
-            "rve_grad")
+    fn = ctx._lib.rve_grad_noalloc if noalloc else ctx._lib.rve_grad
+    N.check(fn(ctx.bind_stream(), B, n, _p(a), _p(phi), float(h), _p(G), _p(out), _p(mask),
+               float(a_in if a_in is not None else 0.0), _p(gin), _p(gsum), int(scheme)),
+            "rve_grad_noalloc" if noalloc else "rve_grad")
     return out, gin, gsum
 
 

@@ -34,6 +34,13 @@ namespace {
 constexpr int kMinN = 64, kMaxN = 4096;
 constexpr int kMaxN3 = 256;   // three dimensions: n^3 nodes per system
 
+// Scratch of rve_grad_noalloc: a fixed device array, one per GPU, held until
+// the process ends. Host code never passes this name to a kernel (on the
+// host it is only a stand-in for the symbol): rve_create looks up its device
+// address with hipGetSymbolAddress and keeps it in the context.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 struct Tables {
   double* q64 = nullptr;
   float* q32 = nullptr;
@@ -104,6 +111,7 @@ struct rve_ctx {
   bool timing = false;
   EventTimer timer;
   double* one_out = nullptr;   // device staging of rve_solve's and rve_dos_plan's host outputs (16 doubles)
+  char* noalloc_scratch = nullptr;   // device address of this device's `scratch` array
 };
 
 namespace {
@@ -916,6 +924,17 @@ int rve_create(rve_ctx** out, int device, void* hip_stream) {
   if (!c) return RVE_ENOMEM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // the device address of this device's copy of the fixed scratch array
+  {
+    void* sp = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !sp) {
+      fprintf(stderr, "librve: hipGetSymbolAddress(scratch) failed: %s\n", hipGetErrorString(e));
+      delete c;
+      return RVE_EHIP;
+    }
+    c->noalloc_scratch = static_cast<char*>(sp);
+  }
   if (const char* tp = std::getenv("RVE_TUNE_CACHE")) c->tune_path = tp;
   load_tune_cache(c);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_count), 2 * sizeof(int), hipHostMallocDefault) !=
@@ -1232,6 +1251,27 @@ int rve_grad(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_de
   }
   grad_launch(c, B, n, a_dev, phi_dev, h, G_dev, grad_a_dev, incl_mask_dev, a_in, grad_in_dev, grad_in_sum_dev,
               scheme, static_cast<char*>(c->ws));
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
+int rve_grad_noalloc(rve_ctx* c, int B, int n, const double* a_dev, const double* phi_dev, double h,
+                     const double* G_dev, double* grad_a_dev, const unsigned char* incl_mask_dev, double a_in,
+                     double* grad_in_dev, double* grad_in_sum_dev, int scheme) {
+  size_t bytes = 0;
+  const int rc = grad_args(c, B, n, a_dev, phi_dev, h, G_dev, grad_a_dev, incl_mask_dev, a_in, grad_in_dev,
+                           grad_in_sum_dev, scheme, &bytes);
+  if (rc) return rc;
+  if (bytes > kNoAllocScratchBytes) {
+    fprintf(stderr, "librve: rve_grad_noalloc needs %zu bytes of scratch for B = %d, n = %d; its fixed "
+            "scratch holds %zu (use rve_grad)\n", bytes, B, n, kNoAllocScratchBytes);
+    return RVE_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  // every scratch byte read is written first by the same call (tile partials,
+  // then per-item totals), so nothing needs clearing
+  grad_launch(c, B, n, a_dev, phi_dev, h, G_dev, grad_a_dev, incl_mask_dev, a_in, grad_in_dev, grad_in_sum_dev,
+              scheme, c->noalloc_scratch);
   HIP_TRY(hipGetLastError());
   return RVE_OK;
 }
