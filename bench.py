@@ -83,9 +83,13 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
     return (t1 - t0), it, tim, codes
 
 
-def bytes_per_node(prec_name, flexible):
+def bytes_per_node(prec_name, flexible, coef_bytes=8):
     """Algorithmic HBM bytes per node of each kernel, per corrector system
     (the operator apply: per realization, both systems).
+
+    coef_bytes: bytes per cell of the coefficients the operator kernels read:
+    8 (FP64), or 1 when every field of the batch is two-valued (the library
+    then reads one byte per cell, decoded exactly).
 
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
@@ -113,17 +117,17 @@ def bytes_per_node(prec_name, flexible):
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": 2 * (sp + sp + sp) + 8,
+        "stencil": 2 * (sp + sp + sp) + coef_bytes,
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
         "gemm4": sg + sp + (0 if sg == 2 else first_in),
-        "update_r": 8 + sp + 4 + 8 + lo + (sp if flexible else 0),
+        "update_r": 8 + sp + coef_bytes / 2 + 8 + lo + (sp if flexible else 0),
         "fold_x": sp,
     }
 
 
-def kernel_entries(tim, it_all, n, prec_name, flexible):
+def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8):
     """Per-kernel algorithmic bytes (and flops) summed over the timed launches.
 
     it_all: (steps, B, 2) iteration counts. A realization takes part in the
@@ -138,7 +142,7 @@ def kernel_entries(tim, it_all, n, prec_name, flexible):
     real_iters = float(it_all.max(dim=2).values.sum())
     sys_iters = float(it_all.sum())
     folds = float(sum(math.ceil(v / DIRECTION_RING) for v in it_all.flatten().tolist()))
-    bpn = bytes_per_node(prec_name, flexible)
+    bpn = bytes_per_node(prec_name, flexible, coef_bytes)
     units = {"stencil": real_iters, "gemm1": sys_iters, "gemm2": sys_iters, "gemm3": sys_iters,
              "gemm4": sys_iters, "update_r": sys_iters, "fold_x": sys_iters}
     out = {}
@@ -333,7 +337,13 @@ def main():
     v_plain = args.plain / (time.perf_counter() - t0)
 
     # roofline of the dominant kernel (largest total event time) of the headline leg
-    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False)
+    # every field here takes two values only, so the operator kernels read
+    # one byte per cell (the library's rule: each cell equals its field's
+    # minimum or maximum)
+    two_valued = all(bool(np.all((x == x.min(axis=(1, 2), keepdims=True)) | (x == x.max(axis=(1, 2), keepdims=True))))
+                     for x in host)
+    coef_bytes = 1 if two_valued else 8
+    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False, coef_bytes=coef_bytes)
     dom = max(ent, key=lambda k: ent[k]["ms"])
     roof = roofline_for(dom, ent[dom], "bf16", n)
     roof["traffic"] = measured_traffic(dom)
@@ -342,7 +352,7 @@ def main():
         r = roofline_for(k, v, "bf16", n)
         kernels[k] = {"ms_total": v["ms"], "launches": v["launches"], "bytes_per_node": v["bytes_per_node"],
                       "bound": r["bound"], "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
-    ent64 = kernel_entries(tim64, it64, n, "fp64", flexible=False)
+    ent64 = kernel_entries(tim64, it64, n, "fp64", flexible=False, coef_bytes=coef_bytes)
     g64 = [ent64[k] for k in ("gemm1", "gemm2", "gemm3", "gemm4")]
     fp64_gemm_tfs = sum(e["flops"] for e in g64) / (sum(e["ms"] for e in g64) * 1e-3) / 1e12
 
@@ -389,6 +399,7 @@ def main():
         "ahom_rel_err_vs_oracle": oracle_err,
         "roofline": roof,
         "kernels": kernels,
+        "coefficient_bytes_per_cell": coef_bytes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -80,6 +80,47 @@ __device__ inline void store_lo(LoT* p, const double (&v)[4], double sc) {
   }
 }
 
+// Coefficients as the operator kernels read them: FP64 values (AT = CT), or
+// one byte per cell for a two-valued field (AT = uint8_t: 1 on cells with the
+// realization's largest value, 0 on those with its smallest), decoded
+// exactly to those two values.
+template <class CT, class AT>
+struct CoefDec {
+  CT lo = (CT)0, hi = (CT)0;
+  __device__ CoefDec(const RealState* real, int b) {
+    if constexpr (std::is_same<AT, uint8_t>::value) {
+      lo = (CT)real[b].a_min;
+      hi = (CT)real[b].a_max;
+    }
+  }
+  __device__ CT operator()(AT v) const {
+    if constexpr (std::is_same<AT, uint8_t>::value) return v ? hi : lo;
+    else return (CT)v;
+  }
+};
+
+// code[b][e] = 1 where a = max a of realization b, 0 where a = min a; a cell
+// with any other value sets *not_two_valued (one atomic per workgroup).
+__global__ void __launch_bounds__(kBlock) k_encode_two_valued(const double* __restrict__ a,
+                                                               const RealState* __restrict__ real, long long N2,
+                                                               uint8_t* __restrict__ code, int* not_two_valued) {
+  const int b = blockIdx.y;
+  const double lo = real[b].a_min, hi = real[b].a_max;
+  const long long off = (long long)b * N2;
+  const long long stride = (long long)gridDim.x * kBlock * 4;
+  int bad = 0;
+  for (long long i = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; i < N2; i += stride) {
+    double v[4];
+    V4<double>::load(a + off + i, v);
+    uchar4 c;
+    c.x = v[0] == hi; c.y = v[1] == hi; c.z = v[2] == hi; c.w = v[3] == hi;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bad |= !(v[k] == hi || v[k] == lo);
+    *reinterpret_cast<uchar4*>(code + off + i) = c;
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(not_two_valued, 1);
+}
+
 __global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState* real, int S, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int stride = gridDim.x * kBlock;
@@ -97,7 +138,10 @@ __global__ void __launch_bounds__(kBlock) k_init_state(SysState* sys, RealState*
 __global__ void __launch_bounds__(kBlock) k_ctl_reset(int* kiter, int* count, int count_len) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int stride = gridDim.x * kBlock;
-  if (t == 0) kiter[0] = 0;
+  if (t == 0) {
+    kiter[0] = 0;
+    kiter[16] = 0;   // the not-two-valued flag of the batch encoding (byte 64)
+  }
   for (int i = t; i < count_len; i += stride) count[i] = 0;
 }
 
@@ -378,12 +422,12 @@ __device__ inline void store_nt(T* p, const T* v) {
 // CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
 // FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
 // FP64 either way (the product of two FP32 values is exact in FP64).
-template <bool FUSED, class PT, class ZT, int V, int D, class CT, int SCH>
-__global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, const PT* p_in, PT* ring,
+template <bool FUSED, class PT, class ZT, int V, int D, class CT, int SCH, class AT = CT>
+__global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, const PT* p_in, PT* ring,
                                                        long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part,
-                                                       int probe, int wq) {
+                                                       int probe, int wq, const RealState* real) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 2];
   int first = 0;
@@ -411,7 +455,8 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
   const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = by * 4 * H + w * H;
-  const CT* A = a + (long long)b * N2;
+  const AT* A = a + (long long)b * N2;
+  const CoefDec<CT, AT> dec(real, b);
   const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
   const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
   const bool need_p = !FUSED || !first;
@@ -421,7 +466,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
   struct Raw {
     ZT z[2][V + 2];
     PT p[2][V + 2];
-    CT a[V + 1];
+    AT a[V + 1];
   };
   auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a) {
 #pragma unroll
@@ -439,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
     }
     if (with_a) {
       R.a[0] = A[oa + cl];
-      raw_load<CT, V>(A + oa + c0, &R.a[1]);
+      raw_load<AT, V>(A + oa + c0, &R.a[1]);
     }
   };
   // operand values of system i from a raw row
@@ -473,7 +518,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
       cook(R1, i, uc[i]);
     }
 #pragma unroll
-    for (int k = 0; k < V + 1; ++k) am[k] = R0.a[k];   // a[row-1][c0-1 .. c0+V-1]
+    for (int k = 0; k < V + 1; ++k) am[k] = dec(R0.a[k]);   // a[row-1][c0-1 .. c0+V-1]
   }
   if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true);
 
@@ -494,7 +539,9 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const CT* __restrict__ a, 
     CT up[2][V + 2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) cook(use, i, up[i]);
-    const CT* ac = use.a;
+    CT ac[V + 1];
+#pragma unroll
+    for (int k = 0; k < V + 1; ++k) ac[k] = dec(use.a[k]);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       CT qv[V];
@@ -565,13 +612,14 @@ __device__ inline void store_lo_v(LoT* p, const double* v, double sc) {
 // coefficients (shared by both systems) instead of q. Tiles, XCD remap and
 // the sliding three-row window as in k_stencil_v; each row's r (and z) is
 // loaded with the coefficient row, one row ahead with D = 2.
-template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH>
-__global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a, const PT* ring,
+template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH, class AT = CT>
+__global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a, const PT* ring,
                                                          long long slot_stride, int m, const int* kiter,
                                                          const ZT* __restrict__ z, double* __restrict__ r,
                                                          LoT* __restrict__ rlo, int n, int H, const SysState* sys,
                                                          double* __restrict__ part_rr,
-                                                         double* __restrict__ part_rzo, int flexible) {
+                                                         double* __restrict__ part_rzo, int flexible,
+                                                         const RealState* real) {
   static_assert(D == 1 || D == 2, "prefetch depth");
   __shared__ double sh[4 * 4];
   const PT* __restrict__ pk = ring + (long long)(kiter[0] % m) * slot_stride;
@@ -591,14 +639,15 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
   const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = by * 4 * H + w * H;
-  const CT* A = a + (long long)b * N2;
+  const AT* A = a + (long long)b * N2;
+  const CoefDec<CT, AT> dec(real, b);
   const PT* P[2] = {pk + (long long)s0 * N2, pk + (long long)s1 * N2};
 
   // operand row o (V + 2 values per system), coefficient row oa (V + 1
   // values) and, with_r, that row's r (and z for the flexible beta)
   struct Raw {
     PT p[2][V + 2];
-    CT a[V + 1];
+    AT a[V + 1];
     double r[2][V];
     ZT z[2][V];
   };
@@ -611,7 +660,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
     }
     if (with_a) {
       R.a[0] = A[oa + cl];
-      raw_load<CT, V>(A + oa + c0, &R.a[1]);
+      raw_load<AT, V>(A + oa + c0, &R.a[1]);
     }
     if (with_r) {
 #pragma unroll
@@ -639,7 +688,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
       cook(R1, i, uc[i]);
     }
 #pragma unroll
-    for (int k = 0; k < V + 1; ++k) am[k] = R0.a[k];
+    for (int k = 0; k < V + 1; ++k) am[k] = dec(R0.a[k]);
   }
   if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true, true);
 
@@ -658,7 +707,9 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const CT* __restrict__ a
     CT up[2][V + 2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) cook(use, i, up[i]);
-    const CT* ac = use.a;
+    CT ac[V + 1];
+#pragma unroll
+    for (int k = 0; k < V + 1; ++k) ac[k] = dec(use.a[k]);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       CT qv[V];
@@ -1189,6 +1240,13 @@ void launch_init_state(const Work& w, hipStream_t st) {
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(kBlock), 0, st, w.sys, w.real, w.S, w.B);
 }
 
+void launch_encode_two_valued(const Work& w, uint8_t* code, int* not_two_valued, hipStream_t st) {
+  long long blocks = (w.N2 / 4 + kBlock - 1) / kBlock;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(k_encode_two_valued, dim3((unsigned)blocks, w.B), dim3(kBlock), 0, st, w.a, w.real, w.N2, code,
+                     not_two_valued);
+}
+
 void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st) {
   int blocks = (count_len + kBlock - 1) / kBlock;
   if (blocks > 1024) blocks = 1024;
@@ -1240,33 +1298,47 @@ bool stencil_choice_valid(int n, int c) {
   return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
-template <bool FUSED, class PT, class ZT, int D, class CT, int SCH>
-void launch_stencil_d(int B, int n, int V, int H, const CT* a, const PT* pin, PT* ring, long long slot_stride,
+template <bool FUSED, class PT, class ZT, int D, class CT, int SCH, class AT>
+void launch_stencil_d(int B, int n, int V, int H, const AT* a, const PT* pin, PT* ring, long long slot_stride,
                       int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
-                      int probe, int wq, hipStream_t st) {
+                      int probe, int wq, const RealState* real, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe, wq, real);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe, wq, real);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
+                       kiter, z, q, n, H, sys, part, probe, wq, real);
 }
 
-template <bool FUSED, class PT, class ZT, class CT, int SCH>
-void launch_stencil_t(int B, int n, int c, const CT* a, const PT* pin, PT* ring, long long slot_stride, int m,
+template <bool FUSED, class PT, class ZT, class CT, int SCH, class AT = CT>
+void launch_stencil_t(int B, int n, int c, const AT* a, const PT* pin, PT* ring, long long slot_stride, int m,
                       const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
-                      hipStream_t st, int wq = 1) {
+                      hipStream_t st, int wq = 1, const RealState* real = nullptr) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                probe, wq, st);
+    launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH, AT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
+                                                    probe, wq, real, st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                probe, wq, st);
+    launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH, AT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
+                                                    probe, wq, real, st);
+}
+
+template <class PT, int SCH>
+void launch_stencil_fused_s(const Work& w, int probe, hipStream_t st) {
+  const long long slot = (long long)w.S * w.N2;
+  // two-valued fields: one byte per cell instead of eight
+  if (w.a8)
+    launch_stencil_t<true, PT, PT, double, SCH, uint8_t>(w.B, w.n, w.stencil, w.a8, (const PT*)nullptr,
+                                                         (PT*)w.pring, slot, w.m_ring, w.kiter, (const PT*)w.z, w.q,
+                                                         w.sys, w.part_pq, probe, st, !w.qfree, w.real);
+  else
+    launch_stencil_t<true, PT, PT, double, SCH>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
+                                                w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
+                                                !w.qfree);
 }
 
 template <class PT>
@@ -1277,13 +1349,9 @@ void launch_stencil_fused_p(const Work& w, int probe, hipStream_t st) {
                                              w.m_ring, w.kiter, (const PT*)w.z, (float*)w.q, w.sys, w.part_pq,
                                              probe, st);
   else if (w.scheme == 1)
-    launch_stencil_t<true, PT, PT, double, 1>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
-                                              !w.qfree);
+    launch_stencil_fused_s<PT, 1>(w, probe, st);
   else
-    launch_stencil_t<true, PT, PT, double, 0>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                              w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
-                                              !w.qfree);
+    launch_stencil_fused_s<PT, 0>(w, probe, st);
 }
 
 void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
@@ -1300,8 +1368,8 @@ int stencil_tiles_per_realization(int n, int c) {
   return (n / (kWave * stencil_choice_V(c))) * (n / (4 * stencil_choice_H(c)));
 }
 
-template <class PT, class LoT, bool LO, int D, int SCH>
-void launch_update_r_st_d(const Work& w, int flexible, hipStream_t st) {
+template <class PT, class LoT, bool LO, int D, int SCH, class AT>
+void launch_update_r_st_a(const Work& w, const AT* a, int flexible, hipStream_t st) {
   const int V = stencil_choice_V(w.stencil), H = stencil_choice_H(w.stencil);
   const dim3 g((unsigned)((w.n / (kWave * V)) * (w.n / (4 * H)) * w.B)), blk(kBlock);
   const long long slot = (long long)w.S * w.N2;
@@ -1309,14 +1377,23 @@ void launch_update_r_st_d(const Work& w, int flexible, hipStream_t st) {
   const PT* z = (const PT*)w.z;
   LoT* rlo = (LoT*)w.rlo;
   if (V == 4)
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
-                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
+                       w.real);
   else if (V == 2)
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
-                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
+                       w.real);
   else
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH>), g, blk, 0, st, w.a, ring, slot, w.m_ring,
-                       (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
+                       w.real);
+}
+
+template <class PT, class LoT, bool LO, int D, int SCH>
+void launch_update_r_st_d(const Work& w, int flexible, hipStream_t st) {
+  if (w.a8) launch_update_r_st_a<PT, LoT, LO, D, SCH, uint8_t>(w, w.a8, flexible, st);
+  else launch_update_r_st_a<PT, LoT, LO, D, SCH, double>(w, w.a, flexible, st);
 }
 
 template <class PT, class LoT, bool LO>

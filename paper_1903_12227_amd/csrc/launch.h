@@ -16,6 +16,10 @@ struct Work {
   int dim = 2;               // 2: n x n grids; 3: n x n x n grids (x3 contiguous)
   long long N2 = 0;          // nodes per system: n^dim
   const double* a = nullptr; // [B][n^dim] cells
+  // two dimensions, FP64 apply: if every field of the batch takes only its
+  // minimum and maximum value, one byte per cell (1 = maximum), which the
+  // operator kernels read instead of a; else null
+  const uint8_t* a8 = nullptr;
   double* x = nullptr;       // [S][n^dim] iterate (grid units)
   double* r = nullptr;       // residual
   // Search directions p and preconditioned residual z are FP64 when the
@@ -75,6 +79,10 @@ constexpr int kMiscNV3 = 18;   // per-realization partials of the three-dimensio
 
 // Elementwise and stencil kernels (kernels_vec.hip).
 void launch_init_state(const Work& w, hipStream_t st);
+// code[b][e] = (a == max a of b); *not_two_valued |= 1 if a cell of the batch
+// equals neither its realization's minimum nor its maximum (w.N2 % 4 == 0;
+// after launch_scalar_init)
+void launch_encode_two_valued(const Work& w, uint8_t* code, int* not_two_valued, hipStream_t st);
 void launch_ctl_reset(int* kiter, int* count, int count_len, hipStream_t st);
 void launch_rhs(const Work& w, hipStream_t st);
 void launch_scalar_init(const Work& w, hipStream_t st);

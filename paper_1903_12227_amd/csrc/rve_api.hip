@@ -106,7 +106,7 @@ struct rve_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::map<int, Tables> tables;
-  int* h_count = nullptr;   // pinned, 2 slots
+  int* h_count = nullptr;   // pinned: 2 convergence-poll slots, then the not-two-valued flag
   hipEvent_t chunk_ev[2] = {nullptr, nullptr};
   bool timing = false;
   EventTimer timer;
@@ -325,7 +325,8 @@ GemmTables gemm_tables(const Tables* tb, int prec, int scheme) {
 // counter, per-iteration counts of systems still iterating), then one region
 // per equal-n batch, carved by plan() with offsets from the region start.
 struct Layout {
-  size_t off_a, off_a32, off_f, off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys, off_real;
+  size_t off_a, off_a8, off_a32, off_f, off_x, off_r, off_ring, off_ahist, off_q, off_z, off_rlo, off_u1, off_u2, off_sys,
+      off_real;
   size_t off_pq, off_rr, off_rzo, off_rz, off_misc, off_status, total;
 };
 
@@ -351,6 +352,8 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   // the batch's coefficients, copied in at the start of a solve: the
   // captured chunks then reference workspace memory only
   L.off_a = o; o += align_up((size_t)(B * N2) * 8);
+  // one byte per cell for two-valued fields (FP64 operator apply, 2D)
+  L.off_a8 = o; o += (dim == 2 && !sprec) ? align_up((size_t)(B * N2)) : 0;
   // FP32 operator apply: FP32 coefficients and the right-hand sides
   L.off_a32 = o; o += sprec ? align_up((size_t)(B * N2) * 4) : 0;
   L.off_f = o; o += sprec ? vec : 0;
@@ -395,7 +398,9 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   return L;
 }
 
-// Control block: kiter at the start, count[count_len] after it.
+// Control block: kiter at the start, the not-two-valued flag at byte
+// kTwoValuedFlagOffset, count[count_len] after the first 256 bytes.
+constexpr size_t kTwoValuedFlagOffset = 64;
 size_t ctl_bytes(int count_len) { return align_up(256) + align_up((size_t)count_len * sizeof(int)); }
 
 void clear_graphs(rve_ctx* ctx) {
@@ -659,7 +664,8 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
   key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec, o->scheme,
                          (long long)bs.size()});
   for (auto& b : bs)
-    key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant});
+    key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant,
+                           b.w.a8 != nullptr});
   auto it = ctx->graph_cache.find(key);
   if (it != ctx->graph_cache.end()) {
     *out = it->second;
@@ -730,11 +736,24 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     b.prec = prec;
   }
 
+  // the smallest grid in FP64: one workgroup per system runs the whole PCG
+  // in one launch (no iteration chunks, tuning or fold)
+  bool small = ctx->small_solver != 0;
+  for (auto& b : bs) small = small && small_solver_fits(b.w);
+  // two-valued fields (every cell its realization's minimum or maximum, the
+  // model of Sec. 2 eqns. Stoch-decomp and coef_diag): the operator kernels
+  // read one byte per cell instead of eight, decoded exactly
+  bool encode = !small;
+  for (auto& b : bs) encode = encode && b.dim == 2 && !b.w.sprec;
+  int* not_two_valued = reinterpret_cast<int*>(ws + kTwoValuedFlagOffset);
+
   launch_ctl_reset(kiter, count, count_len, st);
   for (auto& b : bs) {
     launch_init_state(b.w, st);
     launch_rhs(b.w, st);
     launch_scalar_init(b.w, st);
+    if (encode)
+      launch_encode_two_valued(b.w, reinterpret_cast<uint8_t*>(ws + b.base + b.L.off_a8), not_two_valued, st);
     launch_meansub(b.w, st);
     launch_scalar_fnorm(b.w, st);
     if (b.w.sprec) {
@@ -742,11 +761,13 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       launch_to_f32(b.w.a, const_cast<float*>(b.w.a32), (long long)b.B * b.w.N2, st);
     }
   }
+  if (encode) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_count + 2, not_two_valued, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->h_count[2] == 0)
+      for (auto& b : bs) b.w.a8 = reinterpret_cast<const uint8_t*>(ws + b.base + b.L.off_a8);
+  }
 
-  // the smallest grid in FP64: one workgroup per system runs the whole PCG
-  // in one launch (no iteration chunks, tuning or fold)
-  bool small = ctx->small_solver != 0;
-  for (auto& b : bs) small = small && small_solver_fits(b.w);
   if (small) {
     for (auto& b : bs)
       launch_pcg_small(b.w, static_cast<const double*>(b.gt.q), b.gt.einv64, o->tol, o->maxit, st);
@@ -937,7 +958,7 @@ int rve_create(rve_ctx** out, int device, void* hip_stream) {
   }
   if (const char* tp = std::getenv("RVE_TUNE_CACHE")) c->tune_path = tp;
   load_tune_cache(c);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_count), 2 * sizeof(int), hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_count), 4 * sizeof(int), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
     return RVE_ENOMEM;

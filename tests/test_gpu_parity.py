@@ -639,3 +639,27 @@ def test_single_realization_call_matches_batch(dev, prec):
         rve.solve(_to(bad, dev), 0.125, opts, ctx=ctx)
     short = rve.solve(_to(a[0], dev), 0.125, rve.Options(tol=1e-10, maxit=3), ctx=ctx)
     assert short.code == 1 and list(short.iters) == [3, 3]
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_two_valued_byte_coefficients_exact(dev, prec):
+    # A batch of two-valued fields runs the operator on one byte per cell
+    # (decoded to each field's two values); one three-valued field sends the
+    # whole batch through the FP64 coefficients. Decoding is exact, so the
+    # two-valued items come out bit for bit the same either way.
+    rve = _rve()
+    n = 256
+    a = _fields(n, 3, 64)
+    b = a.copy()
+    b[2, 7, 9] = 0.5 * (b[2].min() + b[2].max())
+    opts = rve.Options(tol=1e-10, prec=prec)
+    ctx = rve.Context(0)
+    ctx.set_autotune(False)
+    ra = rve.solve_batch(_to(a, dev), 0.125, opts, ctx=ctx)
+    rb = rve.solve_batch(_to(b, dev), 0.125, opts, ctx=ctx)
+    ctx.close()
+    assert ra.code == 0 and rb.code == 0
+    for k in ("ahom", "ahom_flux", "phi", "iters", "relres"):
+        assert torch.equal(getattr(ra, k)[:2], getattr(rb, k)[:2]), k
+    bound = 1e-10 if prec == 0 else 1e-8
+    assert rel2(rb.ahom.cpu().numpy()[2], oa.solve(b[2], tol=1e-13).ahom) <= bound
