@@ -5,7 +5,9 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librve.so")
+# RVE_LIBRARY may name another build of the same library (the host-sanitizer
+# build, librve_asan.so, for the argument-check tests)
+LIB_PATH = os.environ.get("RVE_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "librve.so")
 
 # Iterations per update of the PCG iterate from the ring of search directions
 # (RVE_DIRECTION_RING in the header).
