@@ -18,9 +18,14 @@ key = (seed mod 2^32, seed div 2^32)); it is occupied iff that word is
 below occ_threshold. Every step is integer arithmetic, so a correct device
 implementation reproduces these fields bit for bit.
 
+The paper's fixed-count law (exactly L^2 squares) draws its centres from the
+same generator with another counter tag (fixed_count_centres).
+
 Pins (tests/test_oracle_sample.py): the generator's published known-answer
 vectors; the painting rule against a brute-force double loop; occupancy and
-coverage frequencies against p and 1 - (1 - p)^(side^2).
+coverage frequencies against p and 1 - (1 - p)^(side^2); the fixed-count
+centres by Python-integer arithmetic, their uniformity, and the coverage
+1 - (1 - side^2/n^2)^K of the fixed-count law.
 """
 import numpy as np
 
@@ -72,3 +77,36 @@ def paint(occ: np.ndarray, side: int, a_in: float, a_bg: float) -> np.ndarray:
 def field(n: int, side: int, seed: int, realization: int, occ_threshold: int, a_in: float,
           a_bg: float) -> np.ndarray:
     return paint(occupancy(n, seed, realization, occ_threshold), side, a_in, a_bg)
+
+
+# The paper's own law (Sec. 2, eqn. Stoch-decomp; Sec. 3.1): exactly K = L^2
+# squares per realization, each centred at a grid node drawn uniformly (the
+# nodes drawn independently, so two squares may share a centre).
+FIXED_TAG = 0x46495843   # fourth counter word of the fixed-count centres
+
+
+def fixed_count_centres(n: int, K: int, seed: int, realization: int) -> np.ndarray:
+    """(K,) linear node indices c = i n + j of the K square centres of a
+    realization: centre k takes words 0 and 1 of Philox4x32-10 with counter
+    (k, r mod 2^32, r div 2^32, FIXED_TAG) and key (seed mod 2^32,
+    seed div 2^32) as the 64-bit v = w0 + 2^32 w1, and c = floor(v n^2 / 2^64)
+    (uniform on the n^2 nodes up to a bias below n^2 / 2^64)."""
+    k = np.arange(int(K), dtype=np.uint64)
+    r = int(realization)
+    w = philox4x32_10(k, np.full_like(k, r & 0xFFFFFFFF), np.full_like(k, (r >> 32) & 0xFFFFFFFF),
+                      np.full_like(k, FIXED_TAG), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    out = np.empty(int(K), dtype=np.int64)
+    nn = n * n
+    for i in range(int(K)):
+        v = int(w[0][i]) | (int(w[1][i]) << 32)
+        out[i] = (v * nn) >> 64
+    return out
+
+
+def fixed_count_field(n: int, side: int, K: int, seed: int, realization: int, a_in: float,
+                      a_bg: float) -> np.ndarray:
+    """The field of the fixed-count law: squares of side `side` cells around
+    the K centres, painted as :func:`paint` does."""
+    occ = np.zeros(n * n, dtype=bool)
+    occ[fixed_count_centres(n, K, seed, realization)] = True
+    return paint(occ.reshape(n, n), side, a_in, a_bg)

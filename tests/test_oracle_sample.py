@@ -75,3 +75,36 @@ def test_fields_depend_only_on_seed_and_index():
     # realization indices beyond 2^32 use the second counter word
     assert not np.array_equal(ls.field(64, 8, 5, 2**32 + 1000, thr, 10.0, 1.0), a)
     assert np.all(ls.field(64, 8, 5, 7, 0, 10.0, 1.0) == 1.0)
+
+
+def test_fixed_count_centres_by_integer_arithmetic():
+    # each centre from its own Philox call and an exact 64 x 64 -> 128-bit
+    # product, in plain Python integers
+    n, K, seed, r = 96, 50, (9 << 32) | 31337, (1 << 33) + 5
+    got = ls.fixed_count_centres(n, K, seed, r)
+    for k in range(K):
+        w = ls.philox4x32_10([k], [r & 0xFFFFFFFF], [r >> 32], [ls.FIXED_TAG], seed & 0xFFFFFFFF, seed >> 32)
+        v = int(w[0][0]) + (int(w[1][0]) << 32)
+        assert got[k] == (v * n * n) // 2**64
+    assert got.min() >= 0 and got.max() < n * n
+
+
+def test_fixed_count_centres_uniform_and_coverage():
+    # centres uniform over the nodes (chi-square over 16 row bands, and over
+    # the residues mod 16 of the column); coverage of the painted field
+    # against 1 - (1 - side^2 / n^2)^K, the covered fraction of K squares
+    # with independent uniform centres
+    n, side = 64, 2
+    K = (n // 4) ** 2            # L^2 squares at m0 = 4
+    c = np.concatenate([ls.fixed_count_centres(n, K, 3, r) for r in range(64)])
+    for stat in ((c // n) // (n // 16), (c % n) % 16):
+        counts = np.bincount(stat, minlength=16)
+        e = c.size / 16
+        chi2 = float(np.sum((counts - e) ** 2 / e))
+        assert chi2 < 45.0          # 15 degrees of freedom: p < 1e-4
+    cov = np.mean([(ls.fixed_count_field(n, side, K, 3, r, 1.0, 0.4) == 1.0).mean() for r in range(64)])
+    want = 1.0 - (1.0 - side * side / (n * n)) ** K
+    assert abs(cov - want) < 0.01
+    f = ls.fixed_count_field(n, side, K, 3, 0, 1.0, 0.4)
+    assert set(np.unique(f)) <= {0.4, 1.0}
+    assert not np.array_equal(f, ls.fixed_count_field(n, side, K, 3, 1, 1.0, 0.4))
