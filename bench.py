@@ -244,6 +244,11 @@ def main():
                          "(lets profiling runs replay the choices of a normal run)")
     ap.add_argument("--survey", action="store_true", help="time the other workloads instead")
     ap.add_argument("--survey3d", action="store_true", help="time only the three-dimensional workloads")
+    ap.add_argument("--systematic", action="store_true",
+                    help="the paper's systematic-error study: ensemble means at L = 16..128 (N realizations "
+                         "each, checkpointed) under the fixed-count and Poisson-count laws")
+    ap.add_argument("--systematic-n", type=int, default=100000)
+    ap.add_argument("--checkpoint-dir", default=None)
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["RVE_TUNE_CACHE"] = args.tune_cache
@@ -267,6 +272,9 @@ def main():
         return
     if args.survey3d:
         survey_3d(rve, torch, dev, lambda name, **kw: print(json.dumps({"survey": name, **kw}), flush=True))
+        return
+    if args.systematic:
+        systematic(rve, torch, dev, args.systematic_n, args.checkpoint_dir)
         return
     L, m0, B = args.L, args.m0, args.batch
     n, h = L * m0, 1.0 / m0
@@ -626,6 +634,43 @@ def survey(rve, torch, dev):
     emit("spectral density: relative L1 distance of the mean curves at L=8 and L=16", distance=d)
 
     survey_3d(rve, torch, dev, emit)
+
+
+def systematic(rve, torch, dev, N_total, ck_dir):
+    """The systematic-error study of Sec. 5 (Table a_sys_er_L1, Fig.
+    sys_a11_vsL): <a_11>_L - <a_11>_2L over N realizations per size, with the
+    paper's ensemble (alpha = 1/4, lambda = 0.4 as a = 1 on the covered set
+    and 0.4 elsewhere, m0 = 4, the lumped five-point scheme), under the
+    fixed-count law (exactly L^2 squares) and its Poisson-count counterpart.
+    One JSON line per (law, L) and per difference, with 95 % intervals."""
+    import numpy as np
+
+    from paper_1903_12227_amd import ensemble
+    paper = {16: 0.000277, 32: 0.000067}    # Table a_sys_er_L1, N = 10^5 column
+    for law in ("fixed", "poisson"):
+        means = {}
+        for L in (16, 32, 64, 128):
+            ck = os.path.join(ck_dir, f"sys_{law}_L{L}.npz") if ck_dir else None
+            t0 = time.perf_counter()
+            out = ensemble.run_ensemble(L, 4, 1.0, N_total, batch=4096 if L <= 32 else 1024, seed=1903 + L,
+                                        device=dev, law=law, alpha=0.25, a_bg=0.4, scheme=rve.SCHEME_FD5,
+                                        checkpoint=ck)
+            dt = time.perf_counter() - t0
+            A = out["ahom"]
+            a11, iso = A[:, 0, 0], 0.5 * (A[:, 0, 0] + A[:, 1, 1])
+            means[L] = (float(a11.mean()), float(a11.std(ddof=1) / np.sqrt(len(a11))),
+                        float(iso.mean()), float(iso.std(ddof=1) / np.sqrt(len(iso))))
+            print(json.dumps({"systematic": law, "L": L, "n": 4 * L, "N": len(a11), "s": dt,
+                              "mean_a11": means[L][0], "se_a11": means[L][1],
+                              "mean_iso": means[L][2], "se_iso": means[L][3]}), flush=True)
+        for L in (16, 32, 64):
+            d = means[L][0] - means[2 * L][0]
+            se = float(np.hypot(means[L][1], means[2 * L][1]))
+            di = means[L][2] - means[2 * L][2]
+            sei = float(np.hypot(means[L][3], means[2 * L][3]))
+            print(json.dumps({"systematic_difference": law, "L": L, "a11_L_minus_a11_2L": d, "ci95": 1.96 * se,
+                              "iso_L_minus_iso_2L": di, "iso_ci95": 1.96 * sei,
+                              "paper_N1e5": paper.get(L)}), flush=True)
 
 
 def bytes_per_node_3d(prec_name):

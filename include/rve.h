@@ -432,6 +432,23 @@ int rve_dos_probes(rve_ctx* ctx, int B, int nv, int n, uint64_t seed, double* v_
 int rve_sample_lattice(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int64_t first,
                        uint32_t occ_threshold, double a_in, double a_bg, double* a_dev);
 
+/*
+ * The paper's own law (Sec. 2, eqn. Stoch-decomp: exactly L^2 squares of side
+ * 2 alpha; Sec. 3.1: centres at grid nodes): B fields a_dev [B][n][n] (FP64,
+ * device) for realizations first .. first + B - 1, each with exactly K
+ * side x side squares (side = 2 alpha m0 cells, K = L^2) whose centres are
+ * drawn independently and uniformly from the n^2 nodes. Centre k of
+ * realization r is node floor(v n^2 / 2^64), v = w0 + 2^32 w1 from words 0 and
+ * 1 of Philox4x32-10 with counter (k, r mod 2^32, r div 2^32, 0x46495843) and
+ * key (seed mod 2^32, seed div 2^32); a square centred at node s covers cells
+ * s - side/2 + u, u = 0 .. side-1, in each direction (mod n), as in
+ * rve_sample_lattice. Needs B n^2 bytes of the context's workspace.
+ * Requires n as for rve_solve_batch, 1 <= side <= min(32, n),
+ * 1 <= B <= 65535, first >= 0, K >= 0, a_in and a_bg > 0 and finite.
+ */
+int rve_sample_fixed_count(rve_ctx* ctx, int B, int n, int side, uint64_t seed, int64_t first, int K,
+                           double a_in, double a_bg, double* a_dev);
+
 /* Site-occupancy threshold of rve_sample_lattice for Poisson centres with
  * mean mu per lattice site: round(2^32 (1 - exp(-mu))) (ties to even),
  * clamped to [0, 2^32 - 1]; 0 for mu <= 0 or NaN. Host only. */

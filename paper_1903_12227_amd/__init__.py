@@ -16,7 +16,7 @@ from ._native import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Context, Options, Result, SingleResult, context, solve, solve_batch, solve_uneven, grad, stats,
-    field_from_mask, apply_operator, apply_precond, occupancy_threshold, sample_lattice, dos_moments, dos_eval,
+    field_from_mask, apply_operator, apply_precond, occupancy_threshold, sample_lattice, sample_fixed_count, dos_moments, dos_eval,
     dos_plan, dos_probes, spectral_density, solve_batch_3d, apply_operator_3d, apply_precond_3d,
 )
 from .autograd import RveAhom, RveAhomContrast, ahom, ahom_contrast  # noqa: F401

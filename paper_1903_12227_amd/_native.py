@@ -29,7 +29,7 @@ EXPORTS = (
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
     "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d", "rve_set_small_solver",
     "rve_solve", "rve_field_from_mask", "rve_dos_plan", "rve_dos_probes", "rve_occupancy_threshold",
-    "rve_grad_noalloc",
+    "rve_grad_noalloc", "rve_sample_fixed_count",
 )
 
 
@@ -68,6 +68,7 @@ def _declare(lib):
     lib.rve_dos_plan.argtypes = [_vp, _i, _i, _i, _vp, _d, ctypes.POINTER(_d), ctypes.POINTER(_i)]
     lib.rve_dos_probes.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, _vp]
     lib.rve_occupancy_threshold.argtypes = [_d]
+    lib.rve_sample_fixed_count.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, ctypes.c_int64, _i, _d, _d, _vp]
     lib.rve_stats.argtypes = [_vp, _i, _d, _vp, _vp]
     lib.rve_status_string.argtypes = [_i]
     lib.rve_status_string.restype = ctypes.c_char_p

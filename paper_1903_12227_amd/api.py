@@ -500,6 +500,20 @@ def sample_lattice(B: int, n: int, side: int, *, seed: int, first: int = 0, occ_
     return a
 
 
+def sample_fixed_count(B: int, n: int, side: int, K: int, *, seed: int, first: int = 0, a_in: float,
+                       a_bg: float = 1.0, device=None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """B fields (B, n, n) FP64 of the paper's fixed-count law (exactly K
+    squares of side `side` cells at uniform grid nodes) for realizations
+    first .. first + B - 1 (see rve_sample_fixed_count)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ctx = ctx or context(dev.index)
+    a = torch.empty((int(B), int(n), int(n)), dtype=torch.float64, device=dev)
+    N.check(ctx._lib.rve_sample_fixed_count(ctx.bind_stream(), int(B), int(n), int(side), int(seed) & (2**64 - 1),
+                                            int(first), int(K), float(a_in), float(a_bg), _p(a)),
+            "rve_sample_fixed_count")
+    return a
+
+
 def apply_precond(a: torch.Tensor, r: torch.Tensor, prec: int = FP64,
                   ctx: Optional[Context] = None, scheme: int = 0) -> torch.Tensor:
     """(a0 A_Delta)^+ r with a0 from each field a: a (B, n, n), r (B, 2, n, n)."""

@@ -39,10 +39,13 @@ constexpr int kSH = kST + kMaxSide - 1;   // site rows / columns a tile can need
 
 // One 64 x 64 cell tile of one realization: occupancy of the sites the tile
 // needs (rows and columns c - side/2 + 1 .. c + side/2 of its cells) into
-// LDS, then the window OR along rows and along columns.
+// LDS, then the window OR along rows and along columns. The occupancy comes
+// from one Philox word per site (lattice Poisson law), or (occ_in non-null)
+// from a byte per site written by k_fixed_centres.
 __global__ void __launch_bounds__(kBlock) k_sample_lattice(int n, int side, unsigned seed_lo, unsigned seed_hi,
                                                              long long first, unsigned occ_threshold, double a_in,
-                                                             double a_bg, double* __restrict__ a) {
+                                                             double a_bg, double* __restrict__ a,
+                                                             const uint8_t* __restrict__ occ_in) {
   __shared__ unsigned char occ[kSH][kSH + 1];
   __shared__ unsigned char row_or[kSH][kST + 1];
   const int b = blockIdx.z;
@@ -58,9 +61,13 @@ __global__ void __launch_bounds__(kBlock) k_sample_lattice(int n, int side, unsi
     i = (i % n + n) % n;
     j = (j % n + n) % n;
     const unsigned s = (unsigned)i * (unsigned)n + (unsigned)j;
-    const uint4 wv = philox4x32_10(make_uint4(s >> 2, r_lo, r_hi, 0u), seed_lo, seed_hi);
-    const unsigned x = (s & 3u) == 0 ? wv.x : (s & 3u) == 1 ? wv.y : (s & 3u) == 2 ? wv.z : wv.w;
-    occ[ai][bj] = x < occ_threshold ? 1 : 0;
+    if (occ_in) {
+      occ[ai][bj] = occ_in[(long long)b * n * n + s];
+    } else {
+      const uint4 wv = philox4x32_10(make_uint4(s >> 2, r_lo, r_hi, 0u), seed_lo, seed_hi);
+      const unsigned x = (s & 3u) == 0 ? wv.x : (s & 3u) == 1 ? wv.y : (s & 3u) == 2 ? wv.z : wv.w;
+      occ[ai][bj] = x < occ_threshold ? 1 : 0;
+    }
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < hw * kST; idx += kBlock) {
@@ -78,6 +85,31 @@ __global__ void __launch_bounds__(kBlock) k_sample_lattice(int n, int side, unsi
     for (int t = 0; t < side; ++t) v |= row_or[rr + t][c];
     A[(long long)(R0 + rr) * n + C0 + c] = v ? a_in : a_bg;
   }
+}
+
+// The paper's fixed-count law: exactly K square centres per realization at
+// uniformly drawn grid nodes (independent draws, so centres may coincide).
+// Centre k of realization r: words 0 and 1 of Philox4x32-10 with counter
+// (k, r mod 2^32, r div 2^32, kFixedTag) form v = w0 + 2^32 w1, and the node
+// is floor(v n^2 / 2^64). One thread per (realization, centre) sets its
+// node's byte in occ [B][n^2] (all writers store the same value).
+constexpr unsigned kFixedTag = 0x46495843u;
+__global__ void __launch_bounds__(kBlock) k_fixed_centres(int B, long long n2, int K, unsigned seed_lo,
+                                                          unsigned seed_hi, long long first, uint8_t* __restrict__ occ) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)B * K) return;
+  const int b = (int)(t / K), k = (int)(t % K);
+  const unsigned long long r = (unsigned long long)(first + b);
+  const uint4 wv = philox4x32_10(make_uint4((unsigned)k, (unsigned)(r & 0xFFFFFFFFull), (unsigned)(r >> 32), kFixedTag),
+                                 seed_lo, seed_hi);
+  const unsigned long long v = (unsigned long long)wv.x | ((unsigned long long)wv.y << 32);
+  const unsigned long long c = __umul64hi(v, (unsigned long long)n2);
+  occ[(long long)b * n2 + (long long)c] = 1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero_bytes(uint8_t* __restrict__ p, long long count) {
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) p[i] = 0;
 }
 
 // Probe vectors with entries +-1: entry i of the [total] array takes bit
@@ -114,7 +146,22 @@ void launch_sample_lattice(int B, int n, int side, unsigned long long seed, long
                            double a_in, double a_bg, double* a, hipStream_t st) {
   const dim3 g(n / kST, n / kST, B);
   hipLaunchKernelGGL(k_sample_lattice, g, dim3(kBlock), 0, st, n, side, (unsigned)(seed & 0xFFFFFFFFull),
-                     (unsigned)(seed >> 32), first, occ_threshold, a_in, a_bg, a);
+                     (unsigned)(seed >> 32), first, occ_threshold, a_in, a_bg, a, (const uint8_t*)nullptr);
+}
+
+void launch_sample_fixed(int B, int n, int side, unsigned long long seed, long long first, int K, double a_in,
+                         double a_bg, uint8_t* occ, double* a, hipStream_t st) {
+  const long long n2 = (long long)n * n;
+  long long zb = (B * n2 + kBlock - 1) / kBlock;
+  if (zb > 4096) zb = 4096;
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)zb), dim3(kBlock), 0, st, occ, B * n2);
+  const long long threads = (long long)B * K;
+  if (threads > 0)
+    hipLaunchKernelGGL(k_fixed_centres, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, B, n2,
+                       K, (unsigned)(seed & 0xFFFFFFFFull), (unsigned)(seed >> 32), first, occ);
+  const dim3 g(n / kST, n / kST, B);
+  hipLaunchKernelGGL(k_sample_lattice, g, dim3(kBlock), 0, st, n, side, 0u, 0u, first, 0u, a_in, a_bg, a,
+                     (const uint8_t*)occ);
 }
 
 }  // namespace rve

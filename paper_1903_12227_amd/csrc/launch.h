@@ -172,6 +172,9 @@ void launch_pcg_small(const Work& w, const double* q64, const double* einv64, do
 bool sample_side_valid(int n, int side);
 void launch_sample_lattice(int B, int n, int side, unsigned long long seed, long long first, unsigned occ_threshold,
                            double a_in, double a_bg, double* a, hipStream_t st);
+// the fixed-count law: K centres per realization; occ is scratch of B n^2 bytes
+void launch_sample_fixed(int B, int n, int side, unsigned long long seed, long long first, int K, double a_in,
+                         double a_bg, uint8_t* occ, double* a, hipStream_t st);
 
 // +-1 probe vectors from Philox4x32-10 words (kernels_sample.hip): total
 // entries, at most 2^39 * 128.

@@ -1429,6 +1429,21 @@ int rve_dos_probes(rve_ctx* c, int B, int nv, int n, uint64_t seed, double* v_de
   return RVE_OK;
 }
 
+int rve_sample_fixed_count(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_t first, int K, double a_in,
+                           double a_bg, double* a_dev) {
+  if (!c || B < 1 || B > 65535 || !n_supported(n) || !sample_side_valid(n, side) || first < 0 || K < 0 ||
+      (long long)B * K >= (1LL << 31) * kBlock || !a_dev)
+    return RVE_EINVAL;
+  if (!(a_in > 0.0) || !(a_bg > 0.0) || !std::isfinite(a_in) || !std::isfinite(a_bg)) return RVE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  const int rc = ensure_ws(c, align_up((size_t)B * n * n));
+  if (rc) return rc;
+  launch_sample_fixed(B, n, side, (unsigned long long)seed, (long long)first, K, a_in, a_bg,
+                      static_cast<uint8_t*>(c->ws), a_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return RVE_OK;
+}
+
 uint32_t rve_occupancy_threshold(double mu) {
   if (!(mu > 0.0)) return 0u;
   if (!std::isfinite(mu)) return 0xFFFFFFFFu;
