@@ -463,7 +463,9 @@ uint32_t rve_occupancy_threshold(double mu);
  * 16-bit tiles for all transforms but the one scaling by 1/E (BF16; FP16:
  * the first and third), n % 256 == 0; 5: 256 x 256 16-bit tiles for all four,
  * n % 256 == 0; 6: the same tiles from 8 waves of 128 x 64 instead of 16 of
- * 64 x 64, n % 256 == 0, the same z as 5). An
+ * 64 x 64, n % 256 == 0, the same z as 5; 7: the tiles of 6 with the operands
+ * loaded straight into LDS through a four-stage ring of 32-wide K slices,
+ * n % 256 == 0, the same z as 5). An
  * override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
 int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
@@ -476,6 +478,16 @@ int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
  * batched path to rounding. mode 0 turns it off, 1 on; anything else
  * RVE_EINVAL. */
 int rve_set_small_solver(rve_ctx* ctx, int mode);
+
+/* Where the next search direction p_{k+1} = z_{k+1} + beta_k p_k is formed:
+ * mode 1 (the default) in the epilogue of the preconditioner's last
+ * transform wherever that is a 16-bit tile variant, the standard beta and
+ * the FP64 operator apply are used (beta is summed between the second and
+ * the third transform; the operator apply then reads p_k alone); mode 0
+ * always in the operator apply, from z_k and p_{k-1}. Both round p to its
+ * storage type in the same way, so results are identical to the last bit.
+ * Anything else: RVE_EINVAL. */
+int rve_set_direction_update(rve_ctx* ctx, int mode);
 
 /* Chunks of PCG iterations: mode 1 (the default) captures each distinct
  * chunk (same batches, pointers, kernel choices and options) once as a HIP

@@ -94,6 +94,13 @@ class Context:
         """Single-workgroup PCG for n = 64 FP64 solves (on by default)."""
         N.check(self._lib.rve_set_small_solver(self.handle, int(bool(enable))), "rve_set_small_solver")
 
+    def set_direction_update(self, in_transform: bool):
+        """Form the next search direction in the last transform's epilogue
+        where possible (the default) or always in the operator apply; the
+        results are identical."""
+        N.check(self._lib.rve_set_direction_update(self.handle, int(bool(in_transform))),
+                "rve_set_direction_update")
+
     def set_graphs(self, enable: bool):
         """Replay each chunk of PCG iterations from a captured HIP graph (the
         default) or launch its kernels one by one; results are identical."""

@@ -141,6 +141,20 @@ struct EpiScale {
   }
 };
 
+// The last transform may write the next search direction instead of z (the
+// driver's pdirect mode): p = z at the first apply, else
+// p_{k+1} = z_{k+1} + beta_k p_k with beta_k from the system state, rounded to
+// the direction type exactly as the operator apply would form it, into ring
+// slot k+1 mod m (k from the iteration counter; the first apply writes slot
+// k mod m). ring == nullptr: z is written as usual.
+struct PDir {
+  void* ring = nullptr;
+  long long slot = 0;   // elements per ring slot
+  int m = 1;
+  const int* kiter = nullptr;
+  int first = 0;
+};
+
 // Elements of one K-slice per thread: (BM x BK) / 256.
 template <class Tr> struct Stage {
   static constexpr int PER = (BM * Tr::BK) / kBlock;   // 4 (FP64/FP32) or 16 (BF16)
@@ -392,11 +406,12 @@ __global__ void __launch_bounds__(64 * WMR * WNR)
 __attribute__((amdgpu_waves_per_eu(BI == 8 ? 2 : WMR * WNR == 4 ? 3 : 4, BI == 8 ? 2 : WMR * WNR == 4 ? 3 : 4)))
 k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restrict__ out_v, int n, int S,
               const SysState* sys, const RealState* real, const float* __restrict__ sin2,
-              double* __restrict__ part, double emin, int fd) {
-  static_assert(PIPE == 0 || PIPE == 1, "operand pipeline");
+              double* __restrict__ part, double emin, int fd, PDir pd) {
+  static_assert(PIPE == 0 || PIPE == 1 || PIPE == 2, "operand pipeline");
   static_assert((BI == 4 && ((WMR == 2 && WNR == 2) || (WMR == 4 && (WNR == 2 || WNR == 4) && PIPE == 0))) ||
-                    (BI == 8 && WMR == 2 && WNR == 4 && PIPE == 0),
+                    (BI == 8 && WMR == 2 && WNR == 4 && (PIPE == 0 || PIPE == 2)),
                 "tile shape");
+  static_assert(PIPE != 2 || BI == 8, "the four-stage ring is built for the 8-wave 256 x 256 tile");
   typedef typename H16<T>::v8 v8t;
   constexpr int scaled = std::is_same<T, _Float16>::value;   // FP16: scaled operands
   constexpr int WR = 16 * BI;   // rows of a wave's block
@@ -408,7 +423,11 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
   // (two would cost them a workgroup per CU)
   constexpr int NSTG = T256 ? 2 : 1;
   constexpr size_t kStage = (size_t)(TMR + TNR) * TLDA;
-  constexpr size_t kSmem = PIPE == 0 ? NSTG * kStage * sizeof(T) : 2 * 2 * (size_t)TM * DK * sizeof(T);
+  // operands loaded straight into LDS (PIPE 1, 2): a ring of NRING stages
+  // of 32-wide K slices
+  constexpr int NRING = PIPE == 2 ? 4 : 2;
+  constexpr size_t kSmem =
+      PIPE == 0 ? NSTG * kStage * sizeof(T) : (size_t)NRING * (TMR + TNR) * DK * sizeof(T);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   T* As = reinterpret_cast<T*>(smem);
 
@@ -561,11 +580,12 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       }
       pref = PERS && lnext < lend;   // (already in buffer cur)
     } else {
-      // buffer b holds the A tile (128 x 32) then the B tile; 16-byte chunk g
-      // of a tile sits at LDS chunk g and holds row g / 4, K chunk
-      // (g % 4) ^ ((row / 2) % 4). Lane l of wave w loads chunks 128 w + l and
-      // 128 w + 64 + l of both tiles.
-      constexpr int kBuf = 2 * TM * DK;
+      // stage b holds the A tile (TMR x 32) then the B tile (TNR x 32);
+      // 16-byte chunk g of a tile sits at LDS chunk g and holds row g / 4, K
+      // chunk (g % 4) ^ ((row / 2) % 4). Lane l of wave w loads chunks
+      // 128 w + l and 128 w + 64 + l of both tiles (4 waves: 128 rows,
+      // 8 waves: 256 rows), four load instructions per wave and slice.
+      constexpr int kA = TMR * DK, kBuf = (TMR + TNR) * DK;
       const int g0 = 128 * w + lane, g1 = g0 + 64;
       const int r0 = g0 >> 2, r1 = g1 >> 2;
       const int c0 = (g0 & 3) ^ ((r0 >> 1) & 3), c1 = (g1 & 3) ^ ((r1 >> 1) & 3);
@@ -577,22 +597,31 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
         T* base = As + b * kBuf + 1024 * w;
         lds_dma16(xa0 + k0, base);
         lds_dma16(xa1 + k0, base + 512);
-        lds_dma16(qa0 + k0, base + TM * DK);
-        lds_dma16(qa1 + k0, base + TM * DK + 512);
+        lds_dma16(qa0 + k0, base + kA);
+        lds_dma16(qa1 + k0, base + kA + 512);
       };
       // fragment reads: row (.. + frow), K chunk lane / 16 of the slice
       const int fc = (lane >> 4) ^ ((frow >> 1) & 3);
       const int nk = n / DK;
-      issue(0, 0);
+      for (int k = 0; k < NRING - 1 && k < nk; ++k) issue(k, k * DK);
       for (int ks = 0; ks < nk; ++ks) {
-        // this wave's loads of slice ks have landed and its reads of slice
-        // ks - 1 are done; after the barrier the same holds for every wave, so
-        // slice ks is complete and the other buffer is free for slice ks + 1
-        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        if (ks + 1 < nk) issue((ks + 1) & 1, (ks + 1) * DK);
-        const T* Ab = As + (ks & 1) * kBuf;
-        const T* Bb = Ab + TM * DK;
-        h16_kstep<T>(acc, [&](int isb, int q) {
+        // this wave's loads of slice ks have landed (loads complete in the
+        // order they were issued: waiting until at most the four loads of
+        // each later slice still in flight remain) and its reads of slice
+        // ks - 1 are done; after the barrier the same holds for every wave,
+        // so slice ks is complete and the stage of slice ks - 1 is free for
+        // slice ks + NRING - 1
+        const int ahead = NRING - 2 < nk - 1 - ks ? NRING - 2 : nk - 1 - ks;
+        if (ahead >= 2)
+          asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        else if (ahead == 1)
+          asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        else
+          asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (ks + NRING - 1 < nk) issue((ks + NRING - 1) % NRING, (ks + NRING - 1) * DK);
+        const T* Ab = As + (ks % NRING) * kBuf;
+        const T* Bb = Ab + kA;
+        h16_kstep<T, true, BI>(acc, [&](int isb, int q) {
           const T* row = isb ? Bb + (wn * 64 + q * 16 + frow) * DK : Ab + (wm * WR + q * 16 + frow) * DK;
           return *reinterpret_cast<const v8t*>(row + fc * 8);
         });
@@ -621,6 +650,21 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       }
     }
     const EpiScale es(EPI == kEpiZ ? scaled : 0, sys, real, s, s >> 1, emin);
+    // pdirect: where this tile's direction goes, and the old one
+    ZT* pnew = nullptr;
+    const ZT* pold = nullptr;
+    double pbeta = 0.0;
+    if constexpr (EPI == kEpiZ) {
+      if (pd.ring) {
+        const int kk = pd.kiter[0];
+        ZT* ring = reinterpret_cast<ZT*>(pd.ring);
+        pnew = ring + (long long)((pd.first ? kk : kk + 1) % pd.m) * pd.slot;
+        if (!pd.first) {
+          pold = ring + (long long)(kk % pd.m) * pd.slot;
+          pbeta = sys[s].beta;
+        }
+      }
+    }
     // r.z partials per 64 x 64 output block (a wave's block, or each half of
     // the 128-row block with BI = 8), accumulated per lane in the same order
     // (j, then i, then e) in every tile shape: the partials do not depend on
@@ -644,12 +688,24 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
         const long long o = (long long)s * N2 + l * n + m;
         const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
         if constexpr (EPI == kEpiZ) {
-          ZT* out = reinterpret_cast<ZT*>(out_v) + o;
+          ZT* out = (pnew ? pnew : reinterpret_cast<ZT*>(out_v)) + o;
           ZT zs[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             if constexpr (scaled) zs[e] = (ZT)((double)r[e] * es.z);
             else zs[e] = (ZT)r[e];
+          }
+          if (pold) {
+            ZT po[4];
+            if constexpr (sizeof(ZT) == 4) {
+              const float4 pv = *reinterpret_cast<const float4*>(pold + o);
+              po[0] = pv.x; po[1] = pv.y; po[2] = pv.z; po[3] = pv.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) po[e] = pold[o + e];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zs[e] = (ZT)fma(pbeta, (double)po[e], (double)zs[e]);
           }
           if constexpr (sizeof(ZT) == 4) {
             float4 st;
@@ -1068,7 +1124,7 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   // multiple of 8 of them, one set per XCD), each looping over at least four
   // tiles; with fewer tiles one workgroup per tile balances better. The
   // other launches take one workgroup per tile.
-  const long long G = big && t.cus >= 8 && NT >= 4LL * (t.cus & ~7) ? (long long)(t.cus & ~7) : NT;
+  const long long G = big && PIPE == 0 && t.cus >= 8 && NT >= 4LL * (t.cus & ~7) ? (long long)(t.cus & ~7) : NT;
   const dim3 gridp((unsigned)G), grid((unsigned)NT), block(64 * WMR * WNR), grid2((unsigned)NT2), block2(kBlock);
   const T* Q = reinterpret_cast<const T*>(t.q);
   T* u1 = reinterpret_cast<T*>(w.u1);
@@ -1082,18 +1138,26 @@ void run_precond_h16(const Work& w, const GemmTables& t, hipStream_t st, int pha
   constexpr int WE = big ? WMR : 2, WEN = big ? WNR : 2, BE = big ? BI : 4;
   constexpr bool tallz = big || !std::is_same<T, _Float16>::value;
   constexpr int WZ = tallz ? WMR : 2, WZN = tallz ? WNR : 2, BZ = tallz ? BI : 4;
+  PDir none, pd;
+  if (w.pdirect) {
+    pd.ring = w.pring;
+    pd.slot = (long long)w.S * w.N2;
+    pd.m = w.m_ring;
+    pd.kiter = w.kiter;
+    pd.first = w.pdir_first;
+  }
   if (phase < 0 || phase == 0)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, (const T*)w.rlo, Q,
-                       (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
+                       (void*)u1, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0, none);
   if (phase < 0 || phase == 1)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiEinv, float, PIPE, WE, WEN, BE>), big ? (BI == 8 ? gridp : grid) : grid2, big ? block : block2, 0,
-                       st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd);
+                       st, u1, Q, (void*)u2, n, w.S, w.sys, w.real, t.sin2, w.part_rz, em, t.fd, none);
   if (phase < 0 || phase == 2)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiStore, float, PIPE, WMR, WNR, BI>), gridp, block, 0, st, u2, Q, (void*)u1, n,
-                       w.S, w.sys, w.real, nullptr, nullptr, em, 0);
+                       w.S, w.sys, w.real, nullptr, nullptr, em, 0, none);
   if (phase < 0 || phase == 3)
     hipLaunchKernelGGL((k_hartley_h16<T, kEpiZ, ZT, PIPE, WZ, WZN, BZ>), tallz ? grid : grid2, tallz ? block : block2, 0,
-                       st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0);
+                       st, u1, Q, w.z, n, w.S, w.sys, w.real, nullptr, nullptr, em, 0, pd);
 }
 
 template <class ZT>
@@ -1126,7 +1190,12 @@ size_t gemm_elem_size(int prec) {
 bool gemm_variant_valid(int n, int prec, int variant) {
   return variant == 0 || ((variant == 1 || variant == 3) && big_bf16_tiles(n, prec)) ||
          (variant == 2 && folded_bf16_tiles(n, prec)) ||
-         ((variant == 4 || variant == 5 || variant == 6) && big_bf16_tiles(n, prec) && n % 256 == 0);
+         ((variant >= 4 && variant <= 7) && big_bf16_tiles(n, prec) && n % 256 == 0);
+}
+
+bool gemm_variant_writes_direction(int n, int prec, int variant) {
+  return (prec == kGemmBF16 || prec == kGemmF16) && variant != 0 && variant != 2 &&
+         gemm_variant_valid(n, prec, variant);
 }
 
 int gemm_tiles_per_system(int n, int prec, int variant) {
@@ -1169,6 +1238,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond_h16<_Float16, float, 0, 4, 4>(w, t, st, phase);
     else if (w.gemm_variant == 6)
       run_precond_h16<_Float16, float, 0, 2, 4, 8>(w, t, st, phase);
+    else if (w.gemm_variant == 7)
+      run_precond_h16<_Float16, float, 2, 2, 4, 8>(w, t, st, phase);
     else
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
@@ -1183,6 +1254,8 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
     run_precond_h16<__bf16, float, 0, 4, 4>(w, t, st, phase);
   } else if (w.gemm_variant == 6) {
     run_precond_h16<__bf16, float, 0, 2, 4, 8>(w, t, st, phase);
+  } else if (w.gemm_variant == 7) {
+    run_precond_h16<__bf16, float, 2, 2, 4, 8>(w, t, st, phase);
   } else {
     run_precond<TrBF16, float>(w, t, st, phase);
   }

@@ -422,18 +422,25 @@ __device__ inline void store_nt(T* p, const T* v) {
 // CT is the arithmetic type of the apply (coefficients a, operand, q = A p):
 // FP64, or FP32 with p rounded to FP32 before use; the p.q partial sums are
 // FP64 either way (the product of two FP32 values is exact in FP64).
-template <bool FUSED, class PT, class ZT, int V, int D, class CT, int SCH, class AT = CT>
+// PDIR (FUSED only): the direction p_k is already in ring slot k mod m (the
+// last transform formed it); the apply reads it alone and stores nothing but
+// the p.q partials (and q with wq).
+template <bool FUSED, class PT, class ZT, int V, int D, class CT, int SCH, class AT = CT, bool PDIR = false>
 __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, const PT* p_in, PT* ring,
                                                        long long slot_stride, int m, const int* kiter,
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part,
                                                        int probe, int wq, const RealState* real) {
   static_assert(D == 1 || D == 2, "prefetch depth");
+  static_assert(FUSED || !PDIR, "PDIR is a mode of the fused apply");
+  constexpr bool FORM = FUSED && !PDIR;   // p_k formed here from z_k and p_{k-1}
   __shared__ double sh[4 * 2];
   int first = 0;
   const PT* __restrict__ p_old = p_in;
   PT* __restrict__ p_new = nullptr;
-  if constexpr (FUSED) {
+  if constexpr (PDIR) {
+    p_old = ring + (long long)(kiter[0] % m) * slot_stride;
+  } else if constexpr (FUSED) {
     const int k = kiter[0];
     first = k == 0 && !probe;   // a probe does the work of a later iteration
     p_new = ring + (long long)(k % m) * slot_stride;
@@ -448,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   const int s0 = 2 * b, s1 = s0 + 1;
   const int act0 = FUSED ? sys[s0].active : 1, act1 = FUSED ? sys[s1].active : 1;
   if (!act0 && !act1) return;   // uniform over the workgroup
-  const double be[2] = {FUSED && !first ? sys[s0].beta : 0.0, FUSED && !first ? sys[s1].beta : 0.0};
+  const double be[2] = {FORM && !first ? sys[s0].beta : 0.0, FORM && !first ? sys[s1].beta : 0.0};
   const int act[2] = {act0, act1};
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long N2 = (long long)n * n;
@@ -458,8 +465,8 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   const AT* A = a + (long long)b * N2;
   const CoefDec<CT, AT> dec(real, b);
   const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
-  const ZT* Zs[2] = {FUSED ? z + (long long)s0 * N2 : nullptr, FUSED ? z + (long long)s1 * N2 : nullptr};
-  const bool need_p = !FUSED || !first;
+  const ZT* Zs[2] = {FORM ? z + (long long)s0 * N2 : nullptr, FORM ? z + (long long)s1 * N2 : nullptr};
+  const bool need_p = !FORM || !first;
 
   // raw operand row o (V + 2 values per system: column c0-1, c0..c0+V-1,
   // c0+V) and coefficient row oa (V + 1 values: c0-1 .. c0+V-1)
@@ -471,7 +478,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      if constexpr (FUSED) {
+      if constexpr (FORM) {
         raw_load<ZT, V>(Zs[i] + o + c0, &R.z[i][1]);
         R.z[i][0] = Zs[i][o + cl];
         R.z[i][V + 1] = Zs[i][o + cr];
@@ -489,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   };
   // operand values of system i from a raw row
   auto cook = [&](const Raw& R, int i, CT* u) {
-    if constexpr (FUSED) {
+    if constexpr (FORM) {
       if (first) {
 #pragma unroll
         for (int k = 0; k < V + 2; ++k) u[k] = (CT)(PT)R.z[i][k];
@@ -557,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
       }
       if (act[i]) {
         if (wq) VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
-        if constexpr (FUSED) {
+        if constexpr (FORM) {
           PT pn[V];
 #pragma unroll
           for (int k = 0; k < V; ++k) pn[k] = (PT)uc[i][k + 1];
@@ -828,23 +835,25 @@ __global__ void __launch_bounds__(kBlock) k_update_r(double* __restrict__ r, con
 }
 
 // x += alpha_j p_j for j = j0 .. min(j1, iters) - 1 in increasing j, each
-// direction read from its ring slot j mod m (m <= kRing, hi - j0 <= m). A system's iters counts the
+// direction read from its ring slot j mod m (m >= kRing, hi - j0 <= kRing). A system's iters counts the
 // iterations that produced a direction with a valid step length, so the
 // direction of a breakdown (alpha = 0) is never folded in.
 //
-// final = 0: the fold at the start of iteration k (a multiple of m), over the
-// m directions before it; final = 1: the fold after the last iteration K,
-// over the directions since the last multiple of m.
+// final = 0: the fold at the start of iteration k (a multiple of kRing), over
+// the kRing directions before it; final = 1: the fold after the last
+// iteration K, over the directions since the last multiple of kRing.
 template <class PT>
 __global__ void __launch_bounds__(kBlock) k_fold_x(double* __restrict__ x, const PT* __restrict__ ring,
                                                     long long slot_stride, int m,
                                                     const double* __restrict__ alpha_hist, const SysState* sys,
                                                     long long N2, const int* kiter, int final) {
+  // folds happen every kRing iterations; the ring may hold more slots
+  // (m = kRing + 1 when the last transform writes the next direction early)
   const int s = blockIdx.y;
   const int k = kiter[0];
-  const int j0 = final ? (k > 0 ? ((k - 1) / m) * m : 0) : (k > m ? k - m : 0);
+  const int j0 = final ? (k > 0 ? ((k - 1) / kRing) * kRing : 0) : (k > kRing ? k - kRing : 0);
   const int j1 = k;
-  const int hi = min(min(j1, sys[s].iters), j0 + m);
+  const int hi = min(min(j1, sys[s].iters), j0 + kRing);
   if (hi <= j0) return;
   const long long off = (long long)s * N2;
   const long long stride = (long long)gridDim.x * kBlock * 4;
@@ -1298,47 +1307,53 @@ bool stencil_choice_valid(int n, int c) {
   return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
-template <bool FUSED, class PT, class ZT, int D, class CT, int SCH, class AT>
+template <bool FUSED, class PT, class ZT, int D, class CT, int SCH, class AT, bool PDIR>
 void launch_stencil_d(int B, int n, int V, int H, const AT* a, const PT* pin, PT* ring, long long slot_stride,
                       int m, const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part,
                       int probe, int wq, const RealState* real, hipStream_t st) {
   const dim3 g((unsigned)((n / (kWave * V)) * (n / (4 * H)) * B)), blk(kBlock);
   if (V == 4)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq, real);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 4, D, CT, SCH, AT, PDIR>), g, blk, 0, st, a, pin, ring,
+                       slot_stride, m, kiter, z, q, n, H, sys, part, probe, wq, real);
   else if (V == 2)
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq, real);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 2, D, CT, SCH, AT, PDIR>), g, blk, 0, st, a, pin, ring,
+                       slot_stride, m, kiter, z, q, n, H, sys, part, probe, wq, real);
   else
-    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH, AT>), g, blk, 0, st, a, pin, ring, slot_stride, m,
-                       kiter, z, q, n, H, sys, part, probe, wq, real);
+    hipLaunchKernelGGL((k_stencil_v<FUSED, PT, ZT, 1, D, CT, SCH, AT, PDIR>), g, blk, 0, st, a, pin, ring,
+                       slot_stride, m, kiter, z, q, n, H, sys, part, probe, wq, real);
 }
 
-template <bool FUSED, class PT, class ZT, class CT, int SCH, class AT = CT>
+template <bool FUSED, class PT, class ZT, class CT, int SCH, class AT = CT, bool PDIR = false>
 void launch_stencil_t(int B, int n, int c, const AT* a, const PT* pin, PT* ring, long long slot_stride, int m,
                       const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
                       hipStream_t st, int wq = 1, const RealState* real = nullptr) {
   const int V = stencil_choice_V(c), H = stencil_choice_H(c);
   if (stencil_choice_D(c) == 2)
-    launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH, AT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                    probe, wq, real, st);
+    launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH, AT, PDIR>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q,
+                                                          sys, part, probe, wq, real, st);
   else
-    launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH, AT>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q, sys, part,
-                                                    probe, wq, real, st);
+    launch_stencil_d<FUSED, PT, ZT, 1, CT, SCH, AT, PDIR>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q,
+                                                          sys, part, probe, wq, real, st);
+}
+
+template <class PT, int SCH, bool PDIR>
+void launch_stencil_fused_m(const Work& w, int probe, hipStream_t st) {
+  const long long slot = (long long)w.S * w.N2;
+  // two-valued fields: one byte per cell instead of eight
+  if (w.a8)
+    launch_stencil_t<true, PT, PT, double, SCH, uint8_t, PDIR>(w.B, w.n, w.stencil, w.a8, (const PT*)nullptr,
+                                                               (PT*)w.pring, slot, w.m_ring, w.kiter, (const PT*)w.z,
+                                                               w.q, w.sys, w.part_pq, probe, st, !w.qfree, w.real);
+  else
+    launch_stencil_t<true, PT, PT, double, SCH, double, PDIR>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr,
+                                                              (PT*)w.pring, slot, w.m_ring, w.kiter, (const PT*)w.z,
+                                                              w.q, w.sys, w.part_pq, probe, st, !w.qfree, w.real);
 }
 
 template <class PT, int SCH>
 void launch_stencil_fused_s(const Work& w, int probe, hipStream_t st) {
-  const long long slot = (long long)w.S * w.N2;
-  // two-valued fields: one byte per cell instead of eight
-  if (w.a8)
-    launch_stencil_t<true, PT, PT, double, SCH, uint8_t>(w.B, w.n, w.stencil, w.a8, (const PT*)nullptr,
-                                                         (PT*)w.pring, slot, w.m_ring, w.kiter, (const PT*)w.z, w.q,
-                                                         w.sys, w.part_pq, probe, st, !w.qfree, w.real);
-  else
-    launch_stencil_t<true, PT, PT, double, SCH>(w.B, w.n, w.stencil, w.a, (const PT*)nullptr, (PT*)w.pring, slot,
-                                                w.m_ring, w.kiter, (const PT*)w.z, w.q, w.sys, w.part_pq, probe, st,
-                                                !w.qfree);
+  if (w.pdirect) launch_stencil_fused_m<PT, SCH, true>(w, probe, st);
+  else launch_stencil_fused_m<PT, SCH, false>(w, probe, st);
 }
 
 template <class PT>
@@ -1536,6 +1551,14 @@ void launch_scalar_alpha(const Work& w, hipStream_t st) {
 void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_conv, dim3(w.S), dim3(kWave), 0, st, w.sys, w.part_rr, w.P_rr, tol, maxit,
                      w.count, (const int*)w.kiter, (int)(w.mixed == 3), sqrt((double)w.N2));
+}
+
+__global__ void k_advance(int* kiter) {
+  if (threadIdx.x == 0) kiter[0] += 1;
+}
+
+void launch_advance(int* kiter, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kWave), 0, st, kiter);
 }
 
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st, int* advance) {

@@ -32,6 +32,15 @@ struct Work {
   // lengths alpha_hist[S][m_ring].
   void* pring = nullptr;
   int m_ring = 2;
+  // pdirect = 1 (2D, 16-bit tile transforms, standard beta, FP64 apply): the
+  // last transform forms the new direction p_{k+1} = z_{k+1} + beta_k p_k in
+  // its epilogue (beta is known once the scaling transform's r.z partials are
+  // summed) and writes it to ring slot k+1 mod m_ring; the operator apply then
+  // reads p_k alone instead of z_k and p_{k-1}. The ring then has
+  // RVE_DIRECTION_RING + 1 slots, since p_{k+1} is written one iteration
+  // before the fold of the chunk that ends at k.
+  int pdirect = 0;
+  int pdir_first = 0;   // pdirect: the apply before the first iteration (p_0 = z_0 into slot k mod m)
   double* alpha_hist = nullptr;
   double* q = nullptr;       // A p
   void* z = nullptr;
@@ -94,6 +103,8 @@ void launch_scalar_alpha(const Work& w, hipStream_t st);
 // stopping test of iteration k; counts the systems that go on in count[k]
 void launch_scalar_conv(const Work& w, double tol, int maxit, hipStream_t st);
 void launch_scalar_beta(const Work& w, int flexible, int first, hipStream_t st, int* advance = nullptr);
+// the shared iteration counter += 1 (one thread)
+void launch_advance(int* kiter, hipStream_t st);
 void launch_round_lo(const Work& w, hipStream_t st);
 // Fused direction step + operator apply of the current PCG iteration in the
 // shape w.stencil (w.P_st must equal stencil_tiles_per_realization(n,
@@ -223,6 +234,9 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
 int precond_phases(const Work& w);
 int gemm_tiles_per_system3(int n);
 bool gemm_variant_valid(int n, int prec, int variant);
+// the 16-bit tile variants, whose last transform can write the next search
+// direction (Work::pdirect)
+bool gemm_variant_writes_direction(int n, int prec, int variant);
 int gemm_tiles_per_system(int n, int prec, int variant);
 int gemm_tiles_per_system_max(int n);
 

@@ -99,6 +99,7 @@ struct rve_ctx {
   int force_stencil = -1;             // operator-apply shape to use instead of the tuner's (-1: none)
   int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
   int small_solver = 1;               // single-workgroup PCG where it fits (n = 64, FP64)
+  int direction_update = 1;           // the last transform forms the next direction where it can
   std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
@@ -359,8 +360,11 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   L.off_f = o; o += sprec ? vec : 0;
   L.off_x = o; o += vec;
   L.off_r = o; o += vec;
-  L.off_ring = o; o += (size_t)kRing * pzvec;   // direction ring
-  L.off_ahist = o; o += align_up((size_t)S * kRing * 8);
+  // direction ring: one slot more in 2D, for the last transform writing the
+  // next direction before the chunk's fold (Work::pdirect)
+  const int ring_slots = dim == 2 ? kRing + 1 : kRing;
+  L.off_ring = o; o += (size_t)ring_slots * pzvec;
+  L.off_ahist = o; o += align_up((size_t)S * ring_slots * 8);
   L.off_q = o; o += vec;
   L.off_z = o; o += pzvec;
   L.off_rlo = o; o += prec == RVE_FP64 ? 0 : uvec;
@@ -605,6 +609,27 @@ void precond_timed(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt, 
   }
 }
 
+// The preconditioner apply of one batch followed by beta (and, for the last
+// batch of an iteration, the counter advance). With pdirect the four
+// transforms are split around beta: the scaling transform's r.z partials
+// give beta, and the last transform then writes p = z + beta p_old.
+void precond_beta(rve_ctx* ctx, const Work& w, int prec, const GemmTables& gt, int flexible, int first,
+                  hipStream_t st, int* advance) {
+  if (!w.pdirect) {
+    precond_timed(ctx, w, prec, gt, st);
+    launch_scalar_beta(w, flexible, first, st, advance);
+    return;
+  }
+  Work v = w;
+  v.pdir_first = first;
+  for (int ph = 0; ph < 4; ++ph) {
+    if (ph == 2) launch_scalar_beta(v, flexible, first, st, nullptr);
+    Timed t(ctx, 1 + ph);
+    launch_precond(v, prec, gt, st, ph);
+  }
+  if (advance) launch_advance(advance, st);
+}
+
 // One equal-n batch of a solve: its inputs and outputs (device) and its
 // workspace region.
 struct Batch {
@@ -648,9 +673,8 @@ void run_chunk(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int flex
         launch_update_r(b.w, flexible, st);
       }
       launch_scalar_conv(b.w, o->tol, o->maxit, st);
-      precond_timed(ctx, b.w, b.prec, b.gt, st);
-      // the last batch's beta also advances the shared iteration counter
-      launch_scalar_beta(b.w, flexible, 0, st, &b == &bs.back() ? bs[0].w.kiter : nullptr);
+      // the last batch also advances the shared iteration counter
+      precond_beta(ctx, b.w, b.prec, b.gt, flexible, 0, st, &b == &bs.back() ? bs[0].w.kiter : nullptr);
     }
   }
 }
@@ -665,7 +689,7 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
                          (long long)bs.size()});
   for (auto& b : bs)
     key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant,
-                           b.w.a8 != nullptr});
+                           b.w.a8 != nullptr, b.w.pdirect});
   auto it = ctx->graph_cache.find(key);
   if (it != ctx->graph_cache.end()) {
     *out = it->second;
@@ -778,8 +802,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     Work& w = b.w;
     const int n = b.n;
     if (b.dim == 3) {   // one operator-apply shape and one transform variant
-      precond_timed(ctx, w, prec, b.gt, st);
-      launch_scalar_beta(w, flexible, 1, st);
+      precond_beta(ctx, w, prec, b.gt, flexible, 1, st, nullptr);
       continue;
     }
     const int bb = batch_bucket(b.B);
@@ -809,8 +832,12 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     }
     if (ctx->force_gemm >= 0 && gemm_variant_valid(n, prec, ctx->force_gemm)) w.gemm_variant = ctx->force_gemm;
     w.P_gemm = gemm_tiles_per_system(n, prec, w.gemm_variant);
-    precond_timed(ctx, w, prec, b.gt, st);
-    launch_scalar_beta(w, flexible, 1, st);
+    // the last transform forms the next direction (standard beta, FP64 apply,
+    // 16-bit tile transforms): bit-identical to the apply forming it
+    w.pdirect = ctx->direction_update && !flexible && !w.sprec &&
+                gemm_variant_writes_direction(n, prec, w.gemm_variant) ? 1 : 0;
+    w.m_ring = w.pdirect ? kRing + 1 : kRing;
+    precond_beta(ctx, w, prec, b.gt, flexible, 1, st, nullptr);
     int sc = stencil_choice_default(n);
     if (ctx->autotune) {
       std::vector<int> vc;
@@ -1480,11 +1507,17 @@ int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_
 }
 
 int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
-  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 6) return RVE_EINVAL;
+  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 7) return RVE_EINVAL;
   // a well-formed shape code (every shape tiles the largest supported grid)
   if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
   c->force_stencil = stencil_choice;
   c->force_gemm = gemm_variant;
+  return RVE_OK;
+}
+
+int rve_set_direction_update(rve_ctx* c, int mode) {
+  if (!c || (mode != 0 && mode != 1)) return RVE_EINVAL;
+  c->direction_update = mode;
   return RVE_OK;
 }
 

@@ -94,7 +94,7 @@ def test_host_argument_validation(lib):
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
     # variant overrides: GEMM variant out of range, malformed operator-apply shape
-    assert lib.rve_force_variants(fake, -1, 7) == N.EINVAL
+    assert lib.rve_force_variants(fake, -1, 8) == N.EINVAL
     assert lib.rve_force_variants(fake, 5, -1) == N.EINVAL
     assert lib.rve_force_variants(None, -1, -1) == N.EINVAL
     assert lib.rve_set_small_solver(None, 1) == N.EINVAL

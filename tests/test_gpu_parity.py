@@ -67,7 +67,7 @@ def test_preconditioner_matches_oracle_fft(dev, n, prec, tol):
             assert np.linalg.norm(zc - ref) <= tol * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("n", [256, 512])
 def test_bf16_transform_variants_match_oracle_fft(dev, n, variant):
     # 128-row tiles (1; 3 with the operands loaded straight into LDS; 4 with
@@ -440,7 +440,7 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
     r = rng.standard_normal((2, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     E = q1.symbol(n)
-    for variant in (0, 1, 3, 4, 5, 6):
+    for variant in (0, 1, 3, 4, 5, 6, 7):
         ctx = rve.Context(0)
         ctx.force_variants(gemm=variant)
         z = rve.apply_precond(_to(a, dev), _to(r, dev), 3, ctx=ctx).cpu().numpy()
@@ -481,7 +481,7 @@ def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     r = rng.standard_normal((3, 2, n, n))
     r -= r.mean(axis=(2, 3), keepdims=True)
     out = {}
-    variants = (1, 3, 4, 5, 6) if n % 256 == 0 else (1, 3)
+    variants = (1, 3, 4, 5, 6, 7) if n % 256 == 0 else (1, 3)
     for variant in variants:
         ctx = rve.Context(0)
         ctx.set_autotune(False)
@@ -522,7 +522,7 @@ def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
     r -= r.mean(axis=(2, 3), keepdims=True)
     ad, rd = _to(a, dev), _to(r, dev)
     out = {}
-    for variant in (1, 5, 6):
+    for variant in (1, 5, 6, 7):
         ctx = rve.Context(0)
         ctx.set_autotune(False)
         ctx.force_variants(gemm=variant)
@@ -531,7 +531,7 @@ def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
         assert res.code == 0
         out[variant] = (z, res.ahom.cpu().numpy(), res.iters.cpu().numpy())
         ctx.close()
-    for v in (5, 6):
+    for v in (5, 6, 7):
         for x1, xv in zip(out[1], out[v]):
             assert np.array_equal(x1, xv), v
     assert out[5][2].min() < out[5][2].max()   # systems did converge at different iterations
@@ -663,3 +663,30 @@ def test_two_valued_byte_coefficients_exact(dev, prec):
         assert torch.equal(getattr(ra, k)[:2], getattr(rb, k)[:2]), k
     bound = 1e-10 if prec == 0 else 1e-8
     assert rel2(rb.ahom.cpu().numpy()[2], oa.solve(b[2], tol=1e-13).ahom) <= bound
+
+
+@pytest.mark.parametrize("prec,variant", [(2, 1), (2, 5), (3, 6), (2, 7)])
+def test_direction_in_last_transform_identical(dev, prec, variant):
+    # the next search direction formed in the last transform's epilogue (with
+    # a ring of one more slot) or in the operator apply: the same arithmetic,
+    # so solves agree to the last bit, also when systems stop at different
+    # iterations, and across a chunk boundary and a poll every 24 iterations
+    rve = _rve()
+    n = 256
+    a = np.concatenate([_fields(n, 2, 65), _fields(n, 2, 66, contrast=2.0)])
+    out = []
+    for mode in (True, False):
+        ctx = rve.Context(0)
+        ctx.set_autotune(False)
+        ctx.force_variants(gemm=variant)
+        ctx.set_direction_update(mode)
+        for opts in (rve.Options(tol=1e-10, prec=prec), rve.Options(tol=1e-10, prec=prec, check_every=24)):
+            out.append(rve.solve_batch(_to(a, dev), 0.125, opts, ctx=ctx))
+        ctx.close()
+    for r1, r0 in ((out[0], out[2]), (out[1], out[3])):
+        assert r1.code == 0 and r0.code == 0
+        assert _same(r1, r0)
+    its = out[0].iters.cpu().numpy()
+    assert its.min() < its.max()
+    for b in (0, 3):
+        assert rel2(out[0].ahom.cpu().numpy()[b], oa.solve(a[b], tol=1e-13).ahom) <= 1e-8
