@@ -83,13 +83,16 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
     return (t1 - t0), it, tim, codes
 
 
-def bytes_per_node(prec_name, flexible, coef_bytes=8):
+def bytes_per_node(prec_name, flexible, coef_bytes=8, pdirect=False):
     """Algorithmic HBM bytes per node of each kernel, per corrector system
     (the operator apply: per realization, both systems).
 
     coef_bytes: bytes per cell of the coefficients the operator kernels read:
     8 (FP64), or 1 when every field of the batch is two-valued (the library
     then reads one byte per cell, decoded exactly).
+    pdirect: the last transform forms the next direction (16-bit tile
+    transforms with the standard beta): it reads p_old and writes p instead of
+    z, and the apply reads p alone.
 
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
@@ -117,17 +120,17 @@ def bytes_per_node(prec_name, flexible, coef_bytes=8):
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": 2 * (sp + sp + sp) + coef_bytes,
+        "stencil": (2 * sp if pdirect else 2 * (sp + sp + sp)) + coef_bytes,
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
-        "gemm4": sg + sp + (0 if sg == 2 else first_in),
+        "gemm4": sg + sp + (sp if pdirect else 0) + (0 if sg == 2 else first_in),
         "update_r": 8 + sp + coef_bytes / 2 + 8 + lo + (sp if flexible else 0),
         "fold_x": sp,
     }
 
 
-def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8):
+def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8, pdirect=False):
     """Per-kernel algorithmic bytes (and flops) summed over the timed launches.
 
     it_all: (steps, B, 2) iteration counts. A realization takes part in the
@@ -142,7 +145,7 @@ def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8):
     real_iters = float(it_all.max(dim=2).values.sum())
     sys_iters = float(it_all.sum())
     folds = float(sum(math.ceil(v / DIRECTION_RING) for v in it_all.flatten().tolist()))
-    bpn = bytes_per_node(prec_name, flexible, coef_bytes)
+    bpn = bytes_per_node(prec_name, flexible, coef_bytes, pdirect)
     units = {"stencil": real_iters, "gemm1": sys_iters, "gemm2": sys_iters, "gemm3": sys_iters,
              "gemm4": sys_iters, "update_r": sys_iters, "fold_x": sys_iters}
     out = {}
@@ -351,7 +354,11 @@ def main():
     two_valued = all(bool(np.all((x == x.min(axis=(1, 2), keepdims=True)) | (x == x.max(axis=(1, 2), keepdims=True))))
                      for x in host)
     coef_bytes = 1 if two_valued else 8
-    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False, coef_bytes=coef_bytes)
+    # the last transform forms the next direction with the 16-bit tile
+    # variants (every one but 0 and the folded 2) and the standard beta
+    tuned = ctx.tuned(n, rve.MIX_BF16, B)
+    pdirect = tuned["gemm_variant"] not in (0, 2, -1)
+    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False, coef_bytes=coef_bytes, pdirect=pdirect)
     dom = max(ent, key=lambda k: ent[k]["ms"])
     roof = roofline_for(dom, ent[dom], "bf16", n)
     roof["traffic"] = measured_traffic(dom)
@@ -393,7 +400,7 @@ def main():
                    "L": L, "n": n, "batch": B, "contrast": args.contrast, "tol": args.tol,
                    "precision": "mixed-bf16"},
         "iters_mean": float(it_mix.mean()),
-        "tuned": ctx.tuned(n, rve.MIX_BF16, B),
+        "tuned": tuned,
         "mixed_fp16_transforms": {"value": v16, "ms_per_step": 1e3 * t16 / args.steps,
                                   "iters_mean": float(it16.mean())},
         "fp64_batched": {"value": v64, "ms_per_step": 1e3 * t64 / args.fp64_steps,
@@ -408,6 +415,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "coefficient_bytes_per_cell": coef_bytes,
+        "direction_in_last_transform": pdirect,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
