@@ -344,8 +344,11 @@ const char* rve_status_string(int status);
  * Autotuner. With mode 1 (the default), the first solve of each
  * (n, precision, floor(log2 B)) times the candidate kernel variants on the
  * live data and keeps the fastest: the shape of the operator apply (V = 1, 2
- * or 4 grid columns per lane, H = 16 or 64 rows per wave strip, D = 1 or 2
- * rows of loads in flight per wave) and the transform-GEMM variant (64 x 64
+ * or 4 grid columns per lane, H = 16 or 64 rows per wave strip, D = 1, 2 or 4
+ * rows of loads in flight per wave), the shape of the residual update that
+ * recomputes A p (FP64 apply, two dimensions; same shape set, timed on
+ * passes that leave the residual unchanged) and the transform-GEMM
+ * variant (64 x 64
  * tiles, or for BF16 128 x 128 tiles when n % 128 == 0; the even/odd-folded
  * variant is used only through rve_force_variants, since its saving per
  * apply is outweighed by extra iterations). Choices are cached in the context
@@ -354,15 +357,18 @@ const char* rve_status_string(int status);
  * defaults. The 16-bit transform tile variants the tuner chooses among
  * (1, 4, 5, 6; the 64 x 64 kernel only where none of them fits) give
  * identical results, so that choice never changes a solve; the operator-apply
- * shape sets the summation order of the PCG dot products' partial sums, so
- * its choice changes results at rounding level only.
+ * and residual-update shapes set the summation order of the PCG dot
+ * products' partial sums, so their choice changes results at rounding level
+ * only.
  *
  * rve_get_tuned: *choice for kind 0 (FP64 operator-apply shape, encoded as
- * V + 8 (H / 16) + 64 (D - 1)), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128,
- * 2 = folded 128 x 128, 3 = 128 x 128 loaded straight into LDS, 4 = 256 x
- * 128, 5 = 256 x 256, 6 = 256 x 256 from 8 waves), 2 (FP32
- * operator-apply shape) or 3 (five-point
- * operator-apply shape), the last two encoded as kind 0, of a shape,
+ * V + 8 (H / 16) + 64 (D - 1) for D = 1, 2 and V + 8 (H / 16) + 128 for
+ * D = 4), 1 (GEMM variant: 0 = 64 x 64, 1 = 128 x 128, 2 = folded
+ * 128 x 128, 3 = 128 x 128 loaded straight into LDS, 4 = 256 x 128,
+ * 5 = 256 x 256, 6 = 256 x 256 from 8 waves), 2 (FP32 operator-apply
+ * shape), 3 (five-point operator-apply shape), 4 (shape of the recomputing
+ * residual update, nine-point) or 5 (the same, five-point), every shape
+ * encoded as kind 0, of a shape,
  * or -1 with return value RVE_NOT_CONVERGED if not tuned yet. Cached choices
  * that are not valid for a shape are ignored and tuned again.
  */
@@ -456,7 +462,9 @@ uint32_t rve_occupancy_threshold(double mu);
 
 /* Use these kernel variants instead of the autotuner's or default choice
  * (-1: no override): an operator-apply shape as encoded for rve_get_tuned
- * kind 0 / 2, and a transform-GEMM variant (0: 64 x 64 tiles; 1: 128 x 128
+ * kind 0 / 2; a shape for the recomputing residual update (the same codes;
+ * -1 with an operator-apply shape given: that shape); and a transform-GEMM
+ * variant (0: 64 x 64 tiles; 1: 128 x 128
  * 16-bit tiles, n % 128 == 0; 2: even/odd-folded 128 x 128 BF16 tiles, half
  * the MFMA work, n % 256 == 0; 3: 128 x 128 16-bit tiles with the operands
  * loaded straight into LDS, n % 128 == 0, the same results as 1; 4: 256 x 128
@@ -468,7 +476,7 @@ uint32_t rve_occupancy_threshold(double mu);
  * n % 256 == 0, the same z as 5). An
  * override that is not valid for a shape is
  * ignored for that shape. Applies to rve_solve_* and rve_apply_precond. */
-int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant);
+int rve_force_variants(rve_ctx* ctx, int stencil_choice, int gemm_variant, int update_choice);
 
 /* Single-workgroup solver (default on): when every batch of a solve has
  * n = 64 in two dimensions with FP64 transforms and the FP64 apply, each

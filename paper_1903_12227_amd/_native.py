@@ -81,7 +81,7 @@ def _declare(lib):
     lib.rve_set_graphs.argtypes = [_vp, _i]
     lib.rve_set_small_solver.argtypes = [_vp, _i]
     lib.rve_set_direction_update.argtypes = [_vp, _i]
-    lib.rve_force_variants.argtypes = [_vp, _i, _i]
+    lib.rve_force_variants.argtypes = [_vp, _i, _i, _i]
     lib.rve_dos_moments.argtypes = [_vp, _i, _i, _i, _vp, _i, _vp, _d, _i, _vp]
     lib.rve_dos_eval.argtypes = [_vp, _i, _i, _i, _vp, _d, _d, _i, _i, _vp, _vp]
     lib.rve_sample_lattice.argtypes = [_vp, _i, _i, _i, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,

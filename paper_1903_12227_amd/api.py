@@ -81,14 +81,17 @@ class Context:
     def set_autotune(self, enable: bool):
         N.check(self._lib.rve_set_autotune(self.handle, int(bool(enable))), "rve_set_autotune")
 
-    def force_variants(self, stencil: int = -1, gemm: int = -1):
+    def force_variants(self, stencil: int = -1, gemm: int = -1, update: int = -1):
         """Use these kernel variants instead of the autotuner's (-1: no
-        override): an operator-apply shape code (see tuned()) and a
+        override): an operator-apply shape code (see tuned()), a
         transform-GEMM variant (0: 64 x 64, 1: 128 x 128 16-bit, 2: even/odd
         folded 128 x 128 BF16, 3: 128 x 128 16-bit with the operands loaded
         straight into LDS, 4: 256 x 128 16-bit, 5: 256 x 256 16-bit, 6: 256 x 256
-        16-bit from 8 waves)."""
-        N.check(self._lib.rve_force_variants(self.handle, int(stencil), int(gemm)), "rve_force_variants")
+        16-bit from 8 waves, 7: as 6 through a four-stage LDS ring), and a
+        shape code for the residual update that recomputes A p (-1 with a
+        stencil shape given: that shape)."""
+        N.check(self._lib.rve_force_variants(self.handle, int(stencil), int(gemm), int(update)),
+                "rve_force_variants")
 
     def set_small_solver(self, enable: bool):
         """Single-workgroup PCG for n = 64 FP64 solves (on by default)."""
@@ -111,15 +114,17 @@ class Context:
         wave strip and rows of loads in flight per wave of the operator
         apply, and the transform-GEMM tile variant (-1: not tuned)."""
         got = []
-        for kind in (2 if stencil_prec else 0, 1):
+        for kind in (2 if stencil_prec else 0, 1, 4):
             c = ctypes.c_int(-1)
             self._lib.rve_get_tuned(self.handle, kind, int(n), int(prec), int(B), ctypes.byref(c))
             got.append(c.value)
-        st = got[0]
-        return {"stencil_columns_per_lane": st & 7 if st >= 0 else -1,
-                "stencil_rows_per_strip": 16 * ((st >> 3) & 7) if st >= 0 else -1,
-                "stencil_prefetch_rows": 1 + ((st >> 6) & 1) if st >= 0 else -1,
-                "gemm_variant": got[1]}
+        out = {}
+        for name, st in (("stencil", got[0]), ("update", got[2])):
+            out[f"{name}_columns_per_lane"] = st & 7 if st >= 0 else -1
+            out[f"{name}_rows_per_strip"] = 16 * ((st >> 3) & 7) if st >= 0 else -1
+            out[f"{name}_prefetch_rows"] = (4 if st & 128 else 1 + ((st >> 6) & 1)) if st >= 0 else -1
+        out["gemm_variant"] = got[1]
+        return out
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -81,4 +81,75 @@ __device__ inline void block_sum(double (&v)[NV], double* sh) {
 __device__ inline int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ inline int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 
+// One n x n block (a system's vector or a realization's coefficients) read and
+// written through a buffer resource: the block's base and size sit in scalar
+// registers, a row is addressed by a wave-uniform byte offset (scalar) and a
+// column by a per-lane 32-bit byte offset that stays fixed down a strip, so no
+// access needs per-lane 64-bit address arithmetic. An access beyond the block
+// reads 0 and writes nothing. NT: streaming (non-temporal) access.
+// AUX: the cache policy bits (2: non-temporal).
+template <int NB, int AUX>
+__device__ inline auto buf_load_bytes(__amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned so) {
+  if constexpr (NB == 1) return __builtin_amdgcn_raw_buffer_load_b8(rs, vo, so, AUX);
+  else if constexpr (NB == 2) return __builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, AUX);
+  else if constexpr (NB == 4) return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, AUX);
+  else if constexpr (NB == 8) return __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, AUX);
+  else return __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, AUX);
+}
+template <int AUX, class W>
+__device__ inline void buf_store_bytes(W v, __amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned so) {
+  constexpr int NB = (int)sizeof(W);
+  if constexpr (NB == 1) __builtin_amdgcn_raw_buffer_store_b8(__builtin_bit_cast(unsigned char, v), rs, vo, so, AUX);
+  else if constexpr (NB == 2) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), rs, vo, so, AUX);
+  else if constexpr (NB == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, vo, so, AUX);
+  else if constexpr (NB == 8) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, vo, so, AUX);
+  } else {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, vo, so, AUX);
+  }
+}
+
+template <class T>
+struct Plane {
+  template <int C> struct alignas(sizeof(T) * C) Run { T e[C]; };
+  __amdgpu_buffer_rsrc_t rs;
+  unsigned row_bytes;
+  __device__ Plane(const T* base, int n)
+      : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, n * n * (int)sizeof(T), 0x00020000)),
+        row_bytes((unsigned)n * (unsigned)sizeof(T)) {}
+  // element at byte offset col of row `row`
+  __device__ T get(int row, unsigned col) const {
+    return __builtin_bit_cast(T, buf_load_bytes<sizeof(T), 0>(rs, col, (unsigned)row * row_bytes));
+  }
+  // V consecutive elements from byte offset col of row `row`, in loads of at
+  // most 16 bytes
+  template <int V, bool NT = false>
+  __device__ void load(int row, unsigned col, T* v) const {
+    constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;
+#pragma unroll
+    for (int k = 0; k < V; k += C) {
+      const Run<C> t = __builtin_bit_cast(
+          Run<C>, buf_load_bytes<sizeof(T) * C, NT ? 2 : 0>(rs, col + k * (unsigned)sizeof(T), (unsigned)row * row_bytes));
+#pragma unroll
+      for (int e = 0; e < C; ++e) v[k + e] = t.e[e];
+    }
+  }
+  template <int V, bool NT = false>
+  __device__ void store(int row, unsigned col, const T* v) const {
+    constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;
+#pragma unroll
+    for (int k = 0; k < V; k += C) {
+      Run<C> t;
+#pragma unroll
+      for (int e = 0; e < C; ++e) t.e[e] = v[k + e];
+      buf_store_bytes<NT ? 2 : 0>(t, rs, col + k * (unsigned)sizeof(T), (unsigned)row * row_bytes);
+    }
+  }
+};
+
+// The wave's index within its workgroup, as a wave-uniform (scalar) value.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)); }
+
 }  // namespace rve

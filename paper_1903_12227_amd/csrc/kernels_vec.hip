@@ -91,6 +91,10 @@ struct CoefDec {
     if constexpr (std::is_same<AT, uint8_t>::value) {
       lo = (CT)real[b].a_min;
       hi = (CT)real[b].a_max;
+      // the larger value is held in vector registers (the empty statement
+      // only pins it there), so a decode is one select per 32-bit half that
+      // reads the smaller value from scalar registers, with no copies
+      asm("" : "+v"(hi));
     }
   }
   __device__ CT operator()(AT v) const {
@@ -354,20 +358,6 @@ template <int V> struct VecIO<float, V> {
   }
 };
 
-// Loads of V consecutive values into registers of their own type (no
-// conversion, so the values may stay in flight while other work proceeds).
-template <class T, int V> struct alignas(sizeof(T) * V) Pack { T e[V]; };
-template <class T, int V>
-__device__ inline void raw_load(const T* p, T* v) {
-  constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;   // elements per load
-#pragma unroll
-  for (int k = 0; k < V; k += C) {
-    const Pack<T, C> t = *reinterpret_cast<const Pack<T, C>*>(p + k);
-#pragma unroll
-    for (int e = 0; e < C; ++e) v[k + e] = t.e[e];
-  }
-}
-
 // Streaming accesses (read once, written once per iteration, no reuse
 // within a launch): non-temporal, so they do not displace reused lines in L2.
 template <class T, int V>
@@ -395,9 +385,10 @@ __device__ inline void store_nt(T* p, const T* v) {
 // realization. A workgroup covers 64V columns x 4H rows; each of its four
 // waves slides a three-row register window down an H-row strip, so every
 // value is loaded about once (plus two halo rows per strip) and the +-1
-// columns come from the cache lines just loaded. With D = 2 the loads of the
-// next row are issued one row ahead of their use (two row buffers that swap
-// roles), so each wave keeps two rows of loads in flight.
+// columns come from the cache lines just loaded. The loads of a row are
+// issued D - 1 rows ahead of their use (a ring of D row buffers), so each
+// wave keeps D rows of loads in flight (D = 1: each row is loaded just
+// before it is used).
 // FUSED: the operand is the new search direction
 // p_k = z_k + beta_{k-1} p_{k-1} (p_0 = z_0), formed on the fly for the V
 // nodes and their neighbours; p_k goes to a ring slot other than p_{k-1}'s
@@ -431,7 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
                                                        const ZT* __restrict__ z, CT* __restrict__ q, int n,
                                                        int H, const SysState* sys, double* __restrict__ part,
                                                        int probe, int wq, const RealState* real) {
-  static_assert(D == 1 || D == 2, "prefetch depth");
+  static_assert(D == 1 || D == 2 || D == 4, "prefetch depth");
   static_assert(FUSED || !PDIR, "PDIR is a mode of the fused apply");
   constexpr bool FORM = FUSED && !PDIR;   // p_k formed here from z_k and p_{k-1}
   __shared__ double sh[4 * 2];
@@ -457,41 +448,49 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   if (!act0 && !act1) return;   // uniform over the workgroup
   const double be[2] = {FORM && !first ? sys[s0].beta : 0.0, FORM && !first ? sys[s1].beta : 0.0};
   const int act[2] = {act0, act1};
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = wave_id();
   const long long N2 = (long long)n * n;
   const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = by * 4 * H + w * H;
-  const AT* A = a + (long long)b * N2;
   const CoefDec<CT, AT> dec(real, b);
-  const PT* Pold[2] = {p_old + (long long)s0 * N2, p_old + (long long)s1 * N2};
-  const ZT* Zs[2] = {FORM ? z + (long long)s0 * N2 : nullptr, FORM ? z + (long long)s1 * N2 : nullptr};
   const bool need_p = !FORM || !first;
+  // the n x n blocks this workgroup reads and writes; rows are wave-uniform,
+  // and the byte offsets of columns c0, c0-1 and c0+V are fixed per lane
+  const Plane<AT> Ap(a + (long long)b * N2, n);
+  const Plane<PT> Pold[2] = {Plane<PT>(p_old + (long long)s0 * N2, n), Plane<PT>(p_old + (long long)s1 * N2, n)};
+  const Plane<PT> Pnew[2] = {Plane<PT>(p_new + (long long)s0 * N2, n), Plane<PT>(p_new + (long long)s1 * N2, n)};
+  const Plane<ZT> Zs[2] = {Plane<ZT>(z + (long long)s0 * N2, n), Plane<ZT>(z + (long long)s1 * N2, n)};
+  const Plane<CT> Qs[2] = {Plane<CT>(q + (long long)s0 * N2, n), Plane<CT>(q + (long long)s1 * N2, n)};
+  const unsigned pc0 = c0 * sizeof(PT), pcl = cl * sizeof(PT), pcr = cr * sizeof(PT);
+  const unsigned zc0 = c0 * sizeof(ZT), zcl = cl * sizeof(ZT), zcr = cr * sizeof(ZT);
+  const unsigned ac0 = c0 * sizeof(AT), acl = cl * sizeof(AT);
+  const unsigned qc0 = c0 * sizeof(CT);
 
-  // raw operand row o (V + 2 values per system: column c0-1, c0..c0+V-1,
-  // c0+V) and coefficient row oa (V + 1 values: c0-1 .. c0+V-1)
+  // raw operand row ro (V + 2 values per system: column c0-1, c0..c0+V-1,
+  // c0+V) and coefficient row ra (V + 1 values: c0-1 .. c0+V-1)
   struct Raw {
     ZT z[2][V + 2];
     PT p[2][V + 2];
     AT a[V + 1];
   };
-  auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a) {
+  auto load_raw = [&](Raw& R, int ro, int ra, bool with_a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if constexpr (FORM) {
-        raw_load<ZT, V>(Zs[i] + o + c0, &R.z[i][1]);
-        R.z[i][0] = Zs[i][o + cl];
-        R.z[i][V + 1] = Zs[i][o + cr];
+        Zs[i].template load<V>(ro, zc0, &R.z[i][1]);
+        R.z[i][0] = Zs[i].get(ro, zcl);
+        R.z[i][V + 1] = Zs[i].get(ro, zcr);
       }
       if (need_p) {
-        raw_load<PT, V>(Pold[i] + o + c0, &R.p[i][1]);
-        R.p[i][0] = Pold[i][o + cl];
-        R.p[i][V + 1] = Pold[i][o + cr];
+        Pold[i].template load<V>(ro, pc0, &R.p[i][1]);
+        R.p[i][0] = Pold[i].get(ro, pcl);
+        R.p[i][V + 1] = Pold[i].get(ro, pcr);
       }
     }
     if (with_a) {
-      R.a[0] = A[oa + cl];
-      raw_load<AT, V>(A + oa + c0, &R.a[1]);
+      R.a[0] = Ap.get(ra, acl);
+      Ap.template load<V>(ra, ac0, &R.a[1]);
     }
   };
   // operand values of system i from a raw row
@@ -515,33 +514,32 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
 
   const int rm = wrap_dec(row0, n);
   CT um[2][V + 2], uc[2][V + 2], am[V + 1];
-  Raw R0, R1;
+  Raw R[D];
   {
-    load_raw(R0, (long long)rm * n, (long long)rm * n, true);
-    load_raw(R1, (long long)row0 * n, 0, false);
+    Raw Ra, Rb;
+    load_raw(Ra, rm, rm, true);
+    load_raw(Rb, row0, 0, false);
+    // the rows of the first D - 1 steps go in flight at once
+#pragma unroll
+    for (int u = 0; u + 1 < D; ++u) load_raw(R[u], wrap_inc(row0 + u, n), row0 + u, true);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      cook(R0, i, um[i]);
-      cook(R1, i, uc[i]);
+      cook(Ra, i, um[i]);
+      cook(Rb, i, uc[i]);
     }
 #pragma unroll
-    for (int k = 0; k < V + 1; ++k) am[k] = dec(R0.a[k]);   // a[row-1][c0-1 .. c0+V-1]
+    for (int k = 0; k < V + 1; ++k) am[k] = dec(Ra.a[k]);   // a[row-1][c0-1 .. c0+V-1]
   }
-  if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true);
 
   double d[2] = {0.0, 0.0};
-  // node row `row`: `use` holds (or receives, D = 1) operand row row+1 and
-  // coefficient row `row`; with D = 2 `fill` receives the next ones
+  // node row `row`: `use` holds operand row row+1 and coefficient row `row`
+  // (with D = 1 it receives them here); `fill` (the buffer of the step
+  // before) receives those of step j + D - 1
   auto step = [&](int j, Raw& use, Raw& fill) {
     const int row = row0 + j;
-    const long long oc = (long long)row * n;
-    if constexpr (D == 1) {
-      load_raw(use, (long long)wrap_inc(row, n) * n, oc, true);
-    } else {
-      if (j + 1 < H) {
-        const int r1 = wrap_inc(row, n);
-        load_raw(fill, (long long)wrap_inc(r1, n) * n, (long long)r1 * n, true);
-      }
+    if (j + D - 1 < H) {
+      const int rc = row + D - 1;   // < n: the strip lies inside the grid
+      load_raw(fill, wrap_inc(rc, n), rc, true);
     }
     CT up[2][V + 2];
 #pragma unroll
@@ -563,12 +561,12 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
           qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc, sp);
       }
       if (act[i]) {
-        if (wq) VecIO<CT, V>::store(q + (long long)(s0 + i) * N2 + oc + c0, qv);
+        if (wq) Qs[i].template store<V>(row, qc0, qv);
         if constexpr (FORM) {
           PT pn[V];
 #pragma unroll
           for (int k = 0; k < V; ++k) pn[k] = (PT)uc[i][k + 1];
-          store_nt<PT, V>(p_new + (long long)(s0 + i) * N2 + oc + c0, pn);
+          Pnew[i].template store<V, true>(row, pc0, pn);
         }
       }
 #pragma unroll
@@ -582,13 +580,9 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
 #pragma unroll
     for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
   };
-  if constexpr (D == 1) {
-    for (int j = 0; j < H; ++j) step(j, R0, R0);
-  } else {
-    for (int j = 0; j < H; j += 2) {   // H is even; the two buffers swap roles
-      step(j, R0, R1);
-      step(j + 1, R1, R0);
-    }
+  for (int j = 0; j < H; j += D) {   // H is a multiple of D
+#pragma unroll
+    for (int u = 0; u < D; ++u) step(j + u, R[u], R[(u + D - 1) % D]);
   }
   if constexpr (FUSED) {
     block_sum<2>(d, sh);
@@ -603,9 +597,9 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
 
 // V values of the GEMM-precision residual copy (scaled for FP16).
 template <class LoT, int V>
-__device__ inline void store_lo_v(LoT* p, const double* v, double sc) {
+__device__ inline void lo_round_v(LoT* out, const double* v, double sc) {
 #pragma unroll
-  for (int k = 0; k < V; ++k) p[k] = (LoT)(float)(kScaledLo<LoT> ? v[k] * sc : v[k]);
+  for (int k = 0; k < V; ++k) out[k] = (LoT)(float)(kScaledLo<LoT> ? v[k] * sc : v[k]);
 }
 
 // Residual update in the operator apply's tile shape, with A p_k recomputed:
@@ -619,6 +613,10 @@ __device__ inline void store_lo_v(LoT* p, const double* v, double sc) {
 // coefficients (shared by both systems) instead of q. Tiles, XCD remap and
 // the sliding three-row window as in k_stencil_v; each row's r (and z) is
 // loaded with the coefficient row, one row ahead with D = 2.
+//
+// probe = 1 (autotuner timing, before iteration 0): r is rewritten unchanged
+// (A p is computed but not applied); the GEMM copy and the partials it writes
+// are rewritten by the real iteration 0.
 template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH, class AT = CT>
 __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a, const PT* ring,
                                                          long long slot_stride, int m, const int* kiter,
@@ -626,8 +624,8 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
                                                          LoT* __restrict__ rlo, int n, int H, const SysState* sys,
                                                          double* __restrict__ part_rr,
                                                          double* __restrict__ part_rzo, int flexible,
-                                                         const RealState* real) {
-  static_assert(D == 1 || D == 2, "prefetch depth");
+                                                         const RealState* real, int probe) {
+  static_assert(D == 1 || D == 2 || D == 4, "prefetch depth");
   __shared__ double sh[4 * 4];
   const PT* __restrict__ pk = ring + (long long)(kiter[0] % m) * slot_stride;
   const int gx = n / (kWave * V), gy = n / (4 * H);
@@ -641,16 +639,23 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
   if (!act[0] && !act[1]) return;   // uniform over the workgroup
   const double al[2] = {sys[s0].alpha, sys[s1].alpha};
   const double sc[2] = {lo_scale_of<LoT>(sys[s0]), lo_scale_of<LoT>(sys[s1])};
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = wave_id();
   const long long N2 = (long long)n * n;
   const int c0 = (bx * kWave + lane) * V;
   const int cl = wrap_dec(c0, n), cr = c0 + V == n ? 0 : c0 + V;
   const int row0 = by * 4 * H + w * H;
-  const AT* A = a + (long long)b * N2;
   const CoefDec<CT, AT> dec(real, b);
-  const PT* P[2] = {pk + (long long)s0 * N2, pk + (long long)s1 * N2};
+  // the n x n blocks (rows wave-uniform, column byte offsets fixed per lane)
+  const Plane<AT> Ap(a + (long long)b * N2, n);
+  const Plane<PT> P[2] = {Plane<PT>(pk + (long long)s0 * N2, n), Plane<PT>(pk + (long long)s1 * N2, n)};
+  const Plane<double> Rs[2] = {Plane<double>(r + (long long)s0 * N2, n), Plane<double>(r + (long long)s1 * N2, n)};
+  const Plane<ZT> Zs[2] = {Plane<ZT>(z + (long long)s0 * N2, n), Plane<ZT>(z + (long long)s1 * N2, n)};
+  const Plane<LoT> Ls[2] = {Plane<LoT>(rlo + (long long)s0 * N2, n), Plane<LoT>(rlo + (long long)s1 * N2, n)};
+  const unsigned pc0 = c0 * sizeof(PT), pcl = cl * sizeof(PT), pcr = cr * sizeof(PT);
+  const unsigned ac0 = c0 * sizeof(AT), acl = cl * sizeof(AT);
+  const unsigned rc0 = c0 * sizeof(double), zc0 = c0 * sizeof(ZT), lc0 = c0 * sizeof(LoT);
 
-  // operand row o (V + 2 values per system), coefficient row oa (V + 1
+  // operand row ro (V + 2 values per system), coefficient row ra (V + 1
   // values) and, with_r, that row's r (and z for the flexible beta)
   struct Raw {
     PT p[2][V + 2];
@@ -658,23 +663,23 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
     double r[2][V];
     ZT z[2][V];
   };
-  auto load_raw = [&](Raw& R, long long o, long long oa, bool with_a, bool with_r) {
+  auto load_raw = [&](Raw& R, int ro, int ra, bool with_a, bool with_r) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      raw_load<PT, V>(P[i] + o + c0, &R.p[i][1]);
-      R.p[i][0] = P[i][o + cl];
-      R.p[i][V + 1] = P[i][o + cr];
+      P[i].template load<V>(ro, pc0, &R.p[i][1]);
+      R.p[i][0] = P[i].get(ro, pcl);
+      R.p[i][V + 1] = P[i].get(ro, pcr);
     }
     if (with_a) {
-      R.a[0] = A[oa + cl];
-      raw_load<AT, V>(A + oa + c0, &R.a[1]);
+      R.a[0] = Ap.get(ra, acl);
+      Ap.template load<V>(ra, ac0, &R.a[1]);
     }
     if (with_r) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         if (act[i]) {
-          load_nt<double, V>(r + (long long)(s0 + i) * N2 + oa + c0, R.r[i]);
-          if (flexible) raw_load<ZT, V>(z + (long long)(s0 + i) * N2 + oa + c0, R.z[i]);
+          Rs[i].template load<V, true>(ra, rc0, R.r[i]);
+          if (flexible) Zs[i].template load<V>(ra, zc0, R.z[i]);
         }
     }
   };
@@ -685,31 +690,28 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
 
   const int rm = wrap_dec(row0, n);
   CT um[2][V + 2], uc[2][V + 2], am[V + 1];
-  Raw R0, R1;
+  Raw R[D];
   {
-    load_raw(R0, (long long)rm * n, (long long)rm * n, true, false);
-    load_raw(R1, (long long)row0 * n, 0, false, false);
+    Raw Ra, Rb;
+    load_raw(Ra, rm, rm, true, false);
+    load_raw(Rb, row0, 0, false, false);
+#pragma unroll
+    for (int u = 0; u + 1 < D; ++u) load_raw(R[u], wrap_inc(row0 + u, n), row0 + u, true, true);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      cook(R0, i, um[i]);
-      cook(R1, i, uc[i]);
+      cook(Ra, i, um[i]);
+      cook(Rb, i, uc[i]);
     }
 #pragma unroll
-    for (int k = 0; k < V + 1; ++k) am[k] = dec(R0.a[k]);
+    for (int k = 0; k < V + 1; ++k) am[k] = dec(Ra.a[k]);
   }
-  if constexpr (D == 2) load_raw(R0, (long long)wrap_inc(row0, n) * n, (long long)row0 * n, true, true);
 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};   // r.r and r.z_old of both systems
   auto step = [&](int j, Raw& use, Raw& fill) {
     const int row = row0 + j;
-    const long long oc = (long long)row * n;
-    if constexpr (D == 1) {
-      load_raw(use, (long long)wrap_inc(row, n) * n, oc, true, true);
-    } else {
-      if (j + 1 < H) {
-        const int r1 = wrap_inc(row, n);
-        load_raw(fill, (long long)wrap_inc(r1, n) * n, (long long)r1 * n, true, true);
-      }
+    if (j + D - 1 < H) {
+      const int rc = row + D - 1;
+      load_raw(fill, wrap_inc(rc, n), rc, true, true);
     }
     CT up[2][V + 2];
 #pragma unroll
@@ -734,11 +736,17 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
         double rv[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-          rv[k] = fma(-al[i], (double)qv[k], use.r[i][k]);
+          // a probe keeps r exactly (the ring slot it reads may not hold a
+          // direction yet, so q is not used at all)
+          rv[k] = probe ? use.r[i][k] : fma(-al[i], (double)qv[k], use.r[i][k]);
           acc[i] += rv[k] * rv[k];
         }
-        store_nt<double, V>(r + (long long)(s0 + i) * N2 + oc + c0, rv);
-        if constexpr (LO) store_lo_v<LoT, V>(rlo + (long long)(s0 + i) * N2 + oc + c0, rv, sc[i]);
+        Rs[i].template store<V, true>(row, rc0, rv);
+        if constexpr (LO) {
+          LoT lv[V];
+          lo_round_v<LoT, V>(lv, rv, sc[i]);
+          Ls[i].template store<V>(row, lc0, lv);
+        }
         if (flexible) {
 #pragma unroll
           for (int k = 0; k < V; ++k) acc[2 + i] += rv[k] * (double)use.z[i][k];
@@ -753,13 +761,9 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
 #pragma unroll
     for (int k = 0; k < V + 1; ++k) am[k] = ac[k];
   };
-  if constexpr (D == 1) {
-    for (int j = 0; j < H; ++j) step(j, R0, R0);
-  } else {
-    for (int j = 0; j < H; j += 2) {   // H is even; the two buffers swap roles
-      step(j, R0, R1);
-      step(j + 1, R1, R0);
-    }
+  for (int j = 0; j < H; j += D) {   // H is a multiple of D
+#pragma unroll
+    for (int u = 0; u < D; ++u) step(j + u, R[u], R[(u + D - 1) % D]);
   }
   block_sum<4>(acc, sh);
   if (threadIdx.x == 0) {
@@ -1302,9 +1306,10 @@ void launch_scalar_fnorm(const Work& w, hipStream_t st) {
 // grid, 16-row strips.
 int stencil_choice_default(int n) { return (n % 256 == 0 ? 4 : n % 128 == 0 ? 2 : 1) + 8 * (kStrip / 16); }
 bool stencil_choice_valid(int n, int c) {
-  const int V = stencil_choice_V(c), H = stencil_choice_H(c), D = stencil_choice_D(c);
-  if (c < 0 || c >= 128 || !(V == 1 || V == 2 || V == 4) || !(H == 16 || H == 32 || H == 64)) return false;
-  return (D == 1 || D == 2) && n % (kWave * V) == 0 && n % (4 * H) == 0;
+  if (c < 0 || c >= 256 || (c & 192) == 192) return false;
+  const int V = stencil_choice_V(c), H = stencil_choice_H(c);
+  if (!(V == 1 || V == 2 || V == 4) || !(H == 16 || H == 32 || H == 64)) return false;
+  return n % (kWave * V) == 0 && n % (4 * H) == 0;
 }
 
 template <bool FUSED, class PT, class ZT, int D, class CT, int SCH, class AT, bool PDIR>
@@ -1327,8 +1332,11 @@ template <bool FUSED, class PT, class ZT, class CT, int SCH, class AT = CT, bool
 void launch_stencil_t(int B, int n, int c, const AT* a, const PT* pin, PT* ring, long long slot_stride, int m,
                       const int* kiter, const ZT* z, CT* q, const SysState* sys, double* part, int probe,
                       hipStream_t st, int wq = 1, const RealState* real = nullptr) {
-  const int V = stencil_choice_V(c), H = stencil_choice_H(c);
-  if (stencil_choice_D(c) == 2)
+  const int V = stencil_choice_V(c), H = stencil_choice_H(c), D = stencil_choice_D(c);
+  if (D == 4)
+    launch_stencil_d<FUSED, PT, ZT, 4, CT, SCH, AT, PDIR>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q,
+                                                          sys, part, probe, wq, real, st);
+  else if (D == 2)
     launch_stencil_d<FUSED, PT, ZT, 2, CT, SCH, AT, PDIR>(B, n, V, H, a, pin, ring, slot_stride, m, kiter, z, q,
                                                           sys, part, probe, wq, real, st);
   else
@@ -1384,8 +1392,8 @@ int stencil_tiles_per_realization(int n, int c) {
 }
 
 template <class PT, class LoT, bool LO, int D, int SCH, class AT>
-void launch_update_r_st_a(const Work& w, const AT* a, int flexible, hipStream_t st) {
-  const int V = stencil_choice_V(w.stencil), H = stencil_choice_H(w.stencil);
+void launch_update_r_st_a(const Work& w, const AT* a, int flexible, int probe, hipStream_t st) {
+  const int V = stencil_choice_V(w.ustencil), H = stencil_choice_H(w.ustencil);
   const dim3 g((unsigned)((w.n / (kWave * V)) * (w.n / (4 * H)) * w.B)), blk(kBlock);
   const long long slot = (long long)w.S * w.N2;
   const PT* ring = (const PT*)w.pring;
@@ -1394,43 +1402,46 @@ void launch_update_r_st_a(const Work& w, const AT* a, int flexible, hipStream_t 
   if (V == 4)
     hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
                        w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real);
+                       w.real, probe);
   else if (V == 2)
     hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
                        w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real);
+                       w.real, probe);
   else
     hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
                        w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real);
+                       w.real, probe);
 }
 
 template <class PT, class LoT, bool LO, int D, int SCH>
-void launch_update_r_st_d(const Work& w, int flexible, hipStream_t st) {
-  if (w.a8) launch_update_r_st_a<PT, LoT, LO, D, SCH, uint8_t>(w, w.a8, flexible, st);
-  else launch_update_r_st_a<PT, LoT, LO, D, SCH, double>(w, w.a, flexible, st);
+void launch_update_r_st_d(const Work& w, int flexible, int probe, hipStream_t st) {
+  if (w.a8) launch_update_r_st_a<PT, LoT, LO, D, SCH, uint8_t>(w, w.a8, flexible, probe, st);
+  else launch_update_r_st_a<PT, LoT, LO, D, SCH, double>(w, w.a, flexible, probe, st);
+}
+
+template <class PT, class LoT, bool LO, int SCH>
+void launch_update_r_st_s(const Work& w, int flexible, int probe, hipStream_t st) {
+  const int D = stencil_choice_D(w.ustencil);
+  if (D == 4) launch_update_r_st_d<PT, LoT, LO, 4, SCH>(w, flexible, probe, st);
+  else if (D == 2) launch_update_r_st_d<PT, LoT, LO, 2, SCH>(w, flexible, probe, st);
+  else launch_update_r_st_d<PT, LoT, LO, 1, SCH>(w, flexible, probe, st);
 }
 
 template <class PT, class LoT, bool LO>
-void launch_update_r_st_l(const Work& w, int flexible, hipStream_t st) {
-  const bool d2 = stencil_choice_D(w.stencil) == 2;
-  if (w.scheme == 1) {
-    if (d2) launch_update_r_st_d<PT, LoT, LO, 2, 1>(w, flexible, st);
-    else launch_update_r_st_d<PT, LoT, LO, 1, 1>(w, flexible, st);
-  } else {
-    if (d2) launch_update_r_st_d<PT, LoT, LO, 2, 0>(w, flexible, st);
-    else launch_update_r_st_d<PT, LoT, LO, 1, 0>(w, flexible, st);
-  }
+void launch_update_r_st_l(const Work& w, int flexible, int probe, hipStream_t st) {
+  if (w.scheme == 1) launch_update_r_st_s<PT, LoT, LO, 1>(w, flexible, probe, st);
+  else launch_update_r_st_s<PT, LoT, LO, 0>(w, flexible, probe, st);
 }
 
 // the residual update with A p_k recomputed (w.qfree: FP64 operator apply,
-// two dimensions); r.r and r.z_old partials per apply tile (w.P_rr = w.P_st)
+// two dimensions) in its own tile shape w.ustencil; r.r and r.z_old partials
+// per tile of that shape (w.P_rr)
 template <class PT>
-void launch_update_r_st_p(const Work& w, int flexible, hipStream_t st) {
-  if (w.mixed == 0) launch_update_r_st_l<PT, double, false>(w, flexible, st);
-  else if (w.mixed == 1) launch_update_r_st_l<PT, float, true>(w, flexible, st);
-  else if (w.mixed == 3) launch_update_r_st_l<PT, _Float16, true>(w, flexible, st);
-  else launch_update_r_st_l<PT, __bf16, true>(w, flexible, st);
+void launch_update_r_st_p(const Work& w, int flexible, int probe, hipStream_t st) {
+  if (w.mixed == 0) launch_update_r_st_l<PT, double, false>(w, flexible, probe, st);
+  else if (w.mixed == 1) launch_update_r_st_l<PT, float, true>(w, flexible, probe, st);
+  else if (w.mixed == 3) launch_update_r_st_l<PT, _Float16, true>(w, flexible, probe, st);
+  else launch_update_r_st_l<PT, __bf16, true>(w, flexible, probe, st);
 }
 
 template <class QT>
@@ -1451,10 +1462,10 @@ void launch_update_r_q(const Work& w, int flexible, hipStream_t st) {
                        (__bf16*)w.rlo, w.sys, w.N2, w.part_rr, w.part_rzo, flexible);
 }
 
-void launch_update_r(const Work& w, int flexible, hipStream_t st) {
+void launch_update_r(const Work& w, int flexible, hipStream_t st, int probe) {
   if (w.qfree) {
-    if (w.mixed == 0) launch_update_r_st_p<double>(w, flexible, st);
-    else launch_update_r_st_p<float>(w, flexible, st);
+    if (w.mixed == 0) launch_update_r_st_p<double>(w, flexible, probe, st);
+    else launch_update_r_st_p<float>(w, flexible, probe, st);
     return;
   }
   // q = A p is FP32 with the FP32 operator apply

@@ -55,6 +55,7 @@ struct Work {
   const float* a32 = nullptr;
   double* f = nullptr;
   int stencil = 0;           // operator-apply shape (stencil_choice_*)
+  int ustencil = 0;          // shape of the recomputing residual update (qfree)
   int gemm_variant = 0;      // 0: 64 x 64 transform tiles; 1: 128 x 128 (16-bit, n % 128 == 0);
                              // 2: even/odd-folded 128 x 128 (BF16, n % 256 == 0);
                              // 3: as 1 with the operands loaded straight into LDS;
@@ -76,8 +77,9 @@ struct Work {
   int P_st = 0;     // workgroups per realization of the operator apply
   int P_vec = 0;    // workgroups per system of the vector kernels
   // qfree = 1 (two dimensions, FP64 operator apply): the fused apply does not
-  // store q = A p and the residual update recomputes it in the apply's tile
-  // shape; its r.r / r.z_old partials then number P_st per system, else P_vec
+  // store q = A p and the residual update recomputes it, in a tile shape of
+  // its own (ustencil); its r.r / r.z_old partials then number
+  // stencil_tiles_per_realization(n, ustencil) per system, else P_vec
   int qfree = 0;
   int P_rr = 0;
   int P_gemm = 0;   // output tiles per system of the transform GEMMs
@@ -112,17 +114,19 @@ void launch_round_lo(const Work& w, hipStream_t st);
 // previous direction's ring slot like a later iteration (outputs are then
 // rewritten by the real iteration 0).
 void launch_stencil_fused(const Work& w, hipStream_t st, int probe = 0);
-// Operator-apply shapes, encoded as c = V + 8 (H / 16) + 64 (D - 1): V in
-// {1, 2, 4} columns per lane, H in {16, 32, 64} rows per wave strip, D in
-// {1, 2} rows of loads in flight per wave; valid when the 64V x 4H
-// workgroup tile divides the n x n grid.
+// Operator-apply shapes, encoded as c = V + 8 (H / 16) + 64 (D - 1) for D in
+// {1, 2} and V + 8 (H / 16) + 128 for D = 4: V in {1, 2, 4} columns per lane,
+// H in {16, 32, 64} rows per wave strip, D rows of loads in flight per wave;
+// valid when the 64V x 4H workgroup tile divides the n x n grid.
 int stencil_choice_default(int n);
 bool stencil_choice_valid(int n, int c);
 inline int stencil_choice_V(int c) { return c & 7; }
 inline int stencil_choice_H(int c) { return 16 * ((c >> 3) & 7); }
-inline int stencil_choice_D(int c) { return 1 + ((c >> 6) & 1); }
+inline int stencil_choice_D(int c) { return (c & 128) ? 4 : 1 + ((c >> 6) & 1); }
 int stencil_tiles_per_realization(int n, int c);
-void launch_update_r(const Work& w, int flexible, hipStream_t st);
+// probe = 1 (recomputing update only, before iteration 0, for timing): r is
+// rewritten unchanged
+void launch_update_r(const Work& w, int flexible, hipStream_t st, int probe = 0);
 // residual replacement r = f - A x (FP64) of the FP32 operator apply
 void launch_replace_r(const Work& w, hipStream_t st);
 void launch_to_f32(const double* in, float* out, long long total, hipStream_t st);

@@ -97,6 +97,8 @@ struct rve_ctx {
   hipStream_t cap_stream = nullptr;   // private stream the iteration chunks are captured on
   int graphs = 1;                     // replay captured chunks (1) or launch them one by one (0)
   int force_stencil = -1;             // operator-apply shape to use instead of the tuner's (-1: none)
+  int force_update = -1;              // shape of the recomputing residual update (-1: the tuner's, or
+                                      // force_stencil when that is set)
   int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
   int small_solver = 1;               // single-workgroup PCG where it fits (n = 64, FP64)
   int direction_update = 1;           // the last transform forms the next direction where it can
@@ -395,6 +397,7 @@ Layout plan(int B, int n, int prec, int sprec, int scheme, int dim, Work* w) {
   w->P_gemm = P_gemm;
   w->mixed = gp;   // GemmPrec: 0 FP64, 1 FP32, 2 BF16, 3 FP16
   w->stencil = sc;
+  w->ustencil = sc;
   w->m_ring = kRing;
   w->sprec = sprec;
   w->scheme = scheme;
@@ -688,8 +691,8 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
   key.insert(key.end(), {(long long)(uintptr_t)ctx->ws, tolbits, o->maxit, flexible, o->stencil_prec, o->scheme,
                          (long long)bs.size()});
   for (auto& b : bs)
-    key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.gemm_variant,
-                           b.w.a8 != nullptr, b.w.pdirect});
+    key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.ustencil,
+                           b.w.gemm_variant, b.w.a8 != nullptr, b.w.pdirect});
   auto it = ctx->graph_cache.find(key);
   if (it != ctx->graph_cache.end()) {
     *out = it->second;
@@ -839,14 +842,15 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     w.m_ring = w.pdirect ? kRing + 1 : kRing;
     precond_beta(ctx, w, prec, b.gt, flexible, 1, st, nullptr);
     int sc = stencil_choice_default(n);
+    // operator-apply shapes: V in {1, 2, 4}, H in {16, 64}, D in {1, 2, 4}
+    std::vector<int> vc;
+    for (int v : {1, 2, 4})
+      for (int hs : {16, 64})
+        for (int dc : {0, 64, 128}) {
+          const int c = v + 8 * (hs / 16) + dc;
+          if (stencil_choice_valid(n, c)) vc.push_back(c);
+        }
     if (ctx->autotune) {
-      std::vector<int> vc;
-      for (int v : {1, 2, 4})
-        for (int hs : {16, 64})
-          for (int d : {1, 2}) {
-            const int c = v + 8 * (hs / 16) + 64 * (d - 1);
-            if (stencil_choice_valid(n, c)) vc.push_back(c);
-          }
       // candidates are timed on probes of iteration 0 that also read the
       // previous direction's slot (zeroed here), i.e. do a later iteration's
       // work; iteration 0 then rewrites everything they wrote
@@ -865,10 +869,24 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     if (ctx->force_stencil >= 0 && stencil_choice_valid(n, ctx->force_stencil)) sc = ctx->force_stencil;
     w.stencil = sc;
     w.P_st = stencil_tiles_per_realization(n, sc);
-    // the residual update recomputes A p in the apply's tile shape (FP64 apply)
+    // FP64 apply: the residual update recomputes A p, in a tile shape of its
+    // own (it streams r in and out besides the operand, so its best shape is
+    // not the apply's); timed on probes that rewrite r unchanged
     if (!w.sprec) {
       w.qfree = 1;
-      w.P_rr = w.P_st;
+      const TuneKey kup(w.scheme ? 5 : 4, n, o->prec, bb);
+      int uc = sc;
+      const bool forced = ctx->force_update >= 0 || ctx->force_stencil >= 0;
+      if (ctx->autotune && !forced && (ctx->tune.count(kup) || count_active(ctx, w) > 0))
+        uc = tune_pick(ctx, kup, vc, [&](int c) {
+          Work t2 = w;
+          t2.ustencil = c;
+          t2.P_rr = stencil_tiles_per_realization(n, c);
+          launch_update_r(t2, flexible, st, 1);
+        });
+      if (ctx->force_update >= 0 && stencil_choice_valid(n, ctx->force_update)) uc = ctx->force_update;
+      w.ustencil = uc;
+      w.P_rr = stencil_tiles_per_realization(n, uc);
     }
   }
 
@@ -1506,12 +1524,14 @@ int rve_sample_lattice(rve_ctx* c, int B, int n, int side, uint64_t seed, int64_
   return RVE_OK;
 }
 
-int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant) {
-  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 7) return RVE_EINVAL;
-  // a well-formed shape code (every shape tiles the largest supported grid)
+int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant, int update_choice) {
+  if (!c || stencil_choice < -1 || gemm_variant < -1 || gemm_variant > 7 || update_choice < -1) return RVE_EINVAL;
+  // well-formed shape codes (every shape tiles the largest supported grid)
   if (stencil_choice >= 0 && !stencil_choice_valid(kMaxN, stencil_choice)) return RVE_EINVAL;
+  if (update_choice >= 0 && !stencil_choice_valid(kMaxN, update_choice)) return RVE_EINVAL;
   c->force_stencil = stencil_choice;
   c->force_gemm = gemm_variant;
+  c->force_update = update_choice >= 0 ? update_choice : stencil_choice;
   return RVE_OK;
 }
 
@@ -1540,7 +1560,7 @@ int rve_set_autotune(rve_ctx* c, int mode) {
 }
 
 int rve_get_tuned(rve_ctx* c, int kind, int n, int prec, int B, int* choice) {
-  if (!c || !choice || kind < 0 || kind > 3 || B < 1) return RVE_EINVAL;
+  if (!c || !choice || kind < 0 || kind > 5 || B < 1) return RVE_EINVAL;
   auto it = c->tune.find(TuneKey(kind, n, prec, batch_bucket(B)));
   if (it == c->tune.end()) {
     *choice = -1;

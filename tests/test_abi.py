@@ -94,9 +94,11 @@ def test_host_argument_validation(lib):
     assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,
                                None, None) == N.EINVAL
     # variant overrides: GEMM variant out of range, malformed operator-apply shape
-    assert lib.rve_force_variants(fake, -1, 8) == N.EINVAL
-    assert lib.rve_force_variants(fake, 5, -1) == N.EINVAL
-    assert lib.rve_force_variants(None, -1, -1) == N.EINVAL
+    assert lib.rve_force_variants(fake, -1, 8, -1) == N.EINVAL
+    assert lib.rve_force_variants(fake, 5, -1, -1) == N.EINVAL
+    assert lib.rve_force_variants(fake, -1, -1, 5) == N.EINVAL
+    assert lib.rve_force_variants(fake, 9 + 64 + 128, -1, -1) == N.EINVAL   # two prefetch depths at once
+    assert lib.rve_force_variants(None, -1, -1, -1) == N.EINVAL
     assert lib.rve_set_small_solver(None, 1) == N.EINVAL
     assert lib.rve_set_small_solver(fake, 2) == N.EINVAL
     for bad in (N.RveOpts(1e-10, 10, 0, -1, 0, 0, 2), N.RveOpts(1e-10, 10, 0, -1, 0, 1, 1)):

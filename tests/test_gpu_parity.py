@@ -421,10 +421,13 @@ def test_autotuner_choices_and_cache(dev, tmp_path, monkeypatch):
         assert rel2(got[b], ref[b]) <= 1e-12
     ch = tuned_ctx.tuned(n, 2, B)
     assert ch["stencil_columns_per_lane"] in (1, 2, 4) and ch["stencil_rows_per_strip"] in (16, 64)
-    assert ch["stencil_prefetch_rows"] in (1, 2)
+    assert ch["stencil_prefetch_rows"] in (1, 2, 4)
+    assert ch["update_columns_per_lane"] in (1, 2, 4) and ch["update_rows_per_strip"] in (16, 64)
+    assert ch["update_prefetch_rows"] in (1, 2, 4)
     assert ch["gemm_variant"] in (0, 1, 4, 5, 6)
     lines = cache.read_text().strip().splitlines()
-    assert len(lines) == 2 and all(line.startswith('{"kind"') for line in lines)
+    # operator apply, transform GEMM and residual update
+    assert len(lines) == 3 and all(line.startswith('{"kind"') for line in lines)
     reload_ctx = rve.Context(0)          # reads the cache at creation
     assert reload_ctx.tuned(n, 2, B) == ch
 

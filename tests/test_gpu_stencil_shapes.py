@@ -1,9 +1,11 @@
 """Every operator-apply shape of the fused PCG step (V columns per lane,
-H rows per wave strip, D rows of loads in flight), forced through the C ABI,
-against the oracles: the Q1 operator with FP64 and FP32 directions and with
-the FP32 apply, and the five-point operator.
+H rows per wave strip, D rows of loads in flight), forced through the C ABI
+for the apply and the residual update that recomputes A p, against the
+oracles: the Q1 operator with FP64 and FP32 directions and with the FP32
+apply, and the five-point operator; and apply and update in different
+shapes.
 
-n = 256 admits all twelve shapes (the 64V x 4H tile divides the grid); two
+n = 256 admits all eighteen shapes (the 64V x 4H tile divides the grid); two
 realizations per solve. Bars: A_hom within 1e-10 (FP64 transforms) or 1e-8
 (BF16 transforms) of the oracle's, relative to max(|A_11|, |A_22|), and the
 true residual of every corrector within twice the tolerance (the stopping
@@ -26,12 +28,16 @@ pytestmark = pytest.mark.gpu
 N, B, H_GRID, TOL = 256, 2, 1.0 / 8, 1e-10
 
 
+def _code(v, hs, d):
+    return v + 8 * (hs // 16) + (128 if d == 4 else 64 * (d - 1))
+
+
 def _shapes():
     out = []
     for v in (1, 2, 4):
         for hs in (16, 64):
-            for d in (1, 2):
-                out.append((v + 8 * (hs // 16) + 64 * (d - 1), f"V{v}-H{hs}-D{d}"))
+            for d in (1, 2, 4):
+                out.append((_code(v, hs, d), f"V{v}-H{hs}-D{d}"))
     return out
 
 
@@ -51,15 +57,13 @@ def _rel2(A, R):
 CONFIGS = [(0, 0, 0, 1e-10), (2, 0, 0, 1e-8), (2, 1, 0, 1e-8), (0, 0, 1, 1e-10)]
 
 
-@pytest.mark.parametrize("code,name", _shapes(), ids=[s[1] for s in _shapes()])
-def test_every_shape_matches_oracle(dev, code, name):
+def _check(dev, a, ref_q1, ref_fd5, name, stencil, update, configs):
     import paper_1903_12227_amd as rve
-    a, ref_q1, ref_fd5 = _case()
     ad = torch.from_numpy(a).to(dev)
-    for prec, sprec, scheme, bar in CONFIGS:
+    for prec, sprec, scheme, bar in configs:
         ctx = rve.Context(0)
         ctx.set_autotune(False)
-        ctx.force_variants(stencil=code)
+        ctx.force_variants(stencil=stencil, update=update)
         res = rve.solve_batch(ad, H_GRID, rve.Options(tol=TOL, prec=prec, stencil_prec=sprec, scheme=scheme),
                               ctx=ctx)
         ctx.close()
@@ -75,3 +79,21 @@ def test_every_shape_matches_oracle(dev, code, name):
                 f = f - f.mean()
                 rr = np.linalg.norm(f.ravel() - K @ x[b, i].ravel()) / np.linalg.norm(f)
                 assert rr <= 2 * TOL, (name, prec, sprec, scheme, b, i, rr)
+
+
+@pytest.mark.parametrize("code,name", _shapes(), ids=[s[1] for s in _shapes()])
+def test_every_shape_matches_oracle(dev, code, name):
+    a, ref_q1, ref_fd5 = _case()
+    _check(dev, a, ref_q1, ref_fd5, name, code, -1, CONFIGS)
+
+
+# apply and residual update in different shapes (the update's r.r partials
+# then number its own tiles); the FP32 apply has no recomputing update
+MIXED = [((4, 64, 4), (1, 16, 2)), ((1, 16, 2), (4, 64, 4)), ((2, 16, 1), (1, 64, 4))]
+
+
+@pytest.mark.parametrize("pair", MIXED, ids=[f"apply{p[0]}-update{p[1]}" for p in MIXED])
+def test_apply_and_update_in_different_shapes(dev, pair):
+    a, ref_q1, ref_fd5 = _case()
+    _check(dev, a, ref_q1, ref_fd5, str(pair), _code(*pair[0]), _code(*pair[1]),
+           [c for c in CONFIGS if c[1] == 0])
