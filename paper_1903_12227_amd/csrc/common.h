@@ -111,6 +111,11 @@ __device__ inline void buf_store_bytes(W v, __amdgpu_buffer_rsrc_t rs, unsigned 
   }
 }
 
+// A byte offset past the end of every block: a load there returns 0 and a
+// store there is dropped, without a memory access (used to switch accesses
+// off without a branch around them).
+constexpr unsigned kPastBlock = 0x80000000u;
+
 template <class T>
 struct Plane {
   template <int C> struct alignas(sizeof(T) * C) Run { T e[C]; };

@@ -534,11 +534,15 @@ __global__ void __launch_bounds__(kBlock) k_stencil_v(const AT* __restrict__ a, 
   double d[2] = {0.0, 0.0};
   // node row `row`: `use` holds operand row row+1 and coefficient row `row`
   // (with D = 1 it receives them here); `fill` (the buffer of the step
-  // before) receives those of step j + D - 1
+  // before) receives those of step j + D - 1. Past the strip's end that step
+  // does not exist and the strip's last rows are loaded again (cache hits,
+  // never used): every pass of the loop then issues the same loads, so the
+  // waits for a row's data count exactly the loads issued after it instead
+  // of draining all of them.
   auto step = [&](int j, Raw& use, Raw& fill) {
     const int row = row0 + j;
-    if (j + D - 1 < H) {
-      const int rc = row + D - 1;   // < n: the strip lies inside the grid
+    {
+      const int rc = row0 + min(j + D - 1, H - 1);   // < n: the strip lies inside the grid
       load_raw(fill, wrap_inc(rc, n), rc, true);
     }
     CT up[2][V + 2];
@@ -617,13 +621,15 @@ __device__ inline void lo_round_v(LoT* out, const double* v, double sc) {
 // probe = 1 (autotuner timing, before iteration 0): r is rewritten unchanged
 // (A p is computed but not applied); the GEMM copy and the partials it writes
 // are rewritten by the real iteration 0.
-template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH, class AT = CT>
+// FLEX: the flexible beta's r.z_old partials (a template parameter, so the
+// loop carries no branch around the loads of z).
+template <class PT, class ZT, class LoT, bool LO, int V, int D, class CT, int SCH, class AT = CT, bool FLEX = false>
 __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a, const PT* ring,
                                                          long long slot_stride, int m, const int* kiter,
                                                          const ZT* __restrict__ z, double* __restrict__ r,
                                                          LoT* __restrict__ rlo, int n, int H, const SysState* sys,
                                                          double* __restrict__ part_rr,
-                                                         double* __restrict__ part_rzo, int flexible,
+                                                         double* __restrict__ part_rzo,
                                                          const RealState* real, int probe) {
   static_assert(D == 1 || D == 2 || D == 4, "prefetch depth");
   __shared__ double sh[4 * 4];
@@ -654,6 +660,11 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
   const unsigned pc0 = c0 * sizeof(PT), pcl = cl * sizeof(PT), pcr = cr * sizeof(PT);
   const unsigned ac0 = c0 * sizeof(AT), acl = cl * sizeof(AT);
   const unsigned rc0 = c0 * sizeof(double), zc0 = c0 * sizeof(ZT), lc0 = c0 * sizeof(LoT);
+  // a system that has stopped iterating has its r (and z, and the GEMM copy)
+  // neither read nor written: its accesses go past the block instead of
+  // sitting behind a branch, so every step issues the same memory
+  // instructions and the waits for a row count exactly the ones after it
+  const unsigned off_i[2] = {act[0] ? 0u : kPastBlock, act[1] ? 0u : kPastBlock};
 
   // operand row ro (V + 2 values per system), coefficient row ra (V + 1
   // values) and, with_r, that row's r (and z for the flexible beta)
@@ -663,7 +674,7 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
     double r[2][V];
     ZT z[2][V];
   };
-  auto load_raw = [&](Raw& R, int ro, int ra, bool with_a, bool with_r) {
+  auto load_raw = [&](Raw& R, int ro, int ra, bool with_a, bool with_r, unsigned past) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       P[i].template load<V>(ro, pc0, &R.p[i][1]);
@@ -676,11 +687,10 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
     }
     if (with_r) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (act[i]) {
-          Rs[i].template load<V, true>(ra, rc0, R.r[i]);
-          if (flexible) Zs[i].template load<V>(ra, zc0, R.z[i]);
-        }
+      for (int i = 0; i < 2; ++i) {
+        Rs[i].template load<V, true>(ra, rc0 + (off_i[i] | past), R.r[i]);
+        if constexpr (FLEX) Zs[i].template load<V>(ra, zc0 + (off_i[i] | past), R.z[i]);
+      }
     }
   };
   auto cook = [&](const Raw& R, int i, CT* u) {
@@ -693,10 +703,10 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
   Raw R[D];
   {
     Raw Ra, Rb;
-    load_raw(Ra, rm, rm, true, false);
-    load_raw(Rb, row0, 0, false, false);
+    load_raw(Ra, rm, rm, true, false, 0);
+    load_raw(Rb, row0, 0, false, false, 0);
 #pragma unroll
-    for (int u = 0; u + 1 < D; ++u) load_raw(R[u], wrap_inc(row0 + u, n), row0 + u, true, true);
+    for (int u = 0; u + 1 < D; ++u) load_raw(R[u], wrap_inc(row0 + u, n), row0 + u, true, true, 0);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       cook(Ra, i, um[i]);
@@ -709,9 +719,13 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
   double acc[4] = {0.0, 0.0, 0.0, 0.0};   // r.r and r.z_old of both systems
   auto step = [&](int j, Raw& use, Raw& fill) {
     const int row = row0 + j;
-    if (j + D - 1 < H) {
-      const int rc = row + D - 1;
-      load_raw(fill, wrap_inc(rc, n), rc, true, true);
+    // as in k_stencil_v, the loads of step j + D - 1 are issued on every
+    // step; past the strip's end the rows of p and a are loaded again (cache
+    // hits) and those of r and z not at all (their offsets go past the block)
+    {
+      const bool past = j + D - 1 >= H;
+      const int rc = row0 + min(j + D - 1, H - 1);
+      load_raw(fill, wrap_inc(rc, n), rc, true, true, past ? kPastBlock : 0u);
     }
     CT up[2][V + 2];
 #pragma unroll
@@ -732,24 +746,26 @@ __global__ void __launch_bounds__(kBlock) k_update_r_st(const AT* __restrict__ a
         else
           qv[k] = q1_apply<CT>(am[k], am[k + 1], ac[k], ac[k + 1], sm, sc3, sp);
       }
-      if (act[i]) {
+      {
         double rv[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
           // a probe keeps r exactly (the ring slot it reads may not hold a
           // direction yet, so q is not used at all)
           rv[k] = probe ? use.r[i][k] : fma(-al[i], (double)qv[k], use.r[i][k]);
-          acc[i] += rv[k] * rv[k];
+          if (act[i]) acc[i] += rv[k] * rv[k];
         }
-        Rs[i].template store<V, true>(row, rc0, rv);
+        Rs[i].template store<V, true>(row, rc0 + off_i[i], rv);
         if constexpr (LO) {
           LoT lv[V];
           lo_round_v<LoT, V>(lv, rv, sc[i]);
-          Ls[i].template store<V>(row, lc0, lv);
+          Ls[i].template store<V>(row, lc0 + off_i[i], lv);
         }
-        if (flexible) {
+        if constexpr (FLEX) {
+          if (act[i]) {
 #pragma unroll
-          for (int k = 0; k < V; ++k) acc[2 + i] += rv[k] * (double)use.z[i][k];
+            for (int k = 0; k < V; ++k) acc[2 + i] += rv[k] * (double)use.z[i][k];
+          }
         }
       }
 #pragma unroll
@@ -1391,8 +1407,8 @@ int stencil_tiles_per_realization(int n, int c) {
   return (n / (kWave * stencil_choice_V(c))) * (n / (4 * stencil_choice_H(c)));
 }
 
-template <class PT, class LoT, bool LO, int D, int SCH, class AT>
-void launch_update_r_st_a(const Work& w, const AT* a, int flexible, int probe, hipStream_t st) {
+template <class PT, class LoT, bool LO, int D, int SCH, class AT, bool FLEX>
+void launch_update_r_st_a(const Work& w, const AT* a, int probe, hipStream_t st) {
   const int V = stencil_choice_V(w.ustencil), H = stencil_choice_H(w.ustencil);
   const dim3 g((unsigned)((w.n / (kWave * V)) * (w.n / (4 * H)) * w.B)), blk(kBlock);
   const long long slot = (long long)w.S * w.N2;
@@ -1400,48 +1416,53 @@ void launch_update_r_st_a(const Work& w, const AT* a, int flexible, int probe, h
   const PT* z = (const PT*)w.z;
   LoT* rlo = (LoT*)w.rlo;
   if (V == 4)
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
-                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real, probe);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 4, D, double, SCH, AT, FLEX>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, w.real,
+                       probe);
   else if (V == 2)
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
-                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real, probe);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 2, D, double, SCH, AT, FLEX>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, w.real,
+                       probe);
   else
-    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH, AT>), g, blk, 0, st, a, ring, slot,
-                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, flexible,
-                       w.real, probe);
+    hipLaunchKernelGGL((k_update_r_st<PT, PT, LoT, LO, 1, D, double, SCH, AT, FLEX>), g, blk, 0, st, a, ring, slot,
+                       w.m_ring, (const int*)w.kiter, z, w.r, rlo, w.n, H, w.sys, w.part_rr, w.part_rzo, w.real,
+                       probe);
 }
 
-template <class PT, class LoT, bool LO, int D, int SCH>
-void launch_update_r_st_d(const Work& w, int flexible, int probe, hipStream_t st) {
-  if (w.a8) launch_update_r_st_a<PT, LoT, LO, D, SCH, uint8_t>(w, w.a8, flexible, probe, st);
-  else launch_update_r_st_a<PT, LoT, LO, D, SCH, double>(w, w.a, flexible, probe, st);
+template <class PT, class LoT, bool LO, int D, int SCH, bool FLEX>
+void launch_update_r_st_d(const Work& w, int probe, hipStream_t st) {
+  if (w.a8) launch_update_r_st_a<PT, LoT, LO, D, SCH, uint8_t, FLEX>(w, w.a8, probe, st);
+  else launch_update_r_st_a<PT, LoT, LO, D, SCH, double, FLEX>(w, w.a, probe, st);
 }
 
-template <class PT, class LoT, bool LO, int SCH>
-void launch_update_r_st_s(const Work& w, int flexible, int probe, hipStream_t st) {
+template <class PT, class LoT, bool LO, int SCH, bool FLEX>
+void launch_update_r_st_s(const Work& w, int probe, hipStream_t st) {
   const int D = stencil_choice_D(w.ustencil);
-  if (D == 4) launch_update_r_st_d<PT, LoT, LO, 4, SCH>(w, flexible, probe, st);
-  else if (D == 2) launch_update_r_st_d<PT, LoT, LO, 2, SCH>(w, flexible, probe, st);
-  else launch_update_r_st_d<PT, LoT, LO, 1, SCH>(w, flexible, probe, st);
+  if (D == 4) launch_update_r_st_d<PT, LoT, LO, 4, SCH, FLEX>(w, probe, st);
+  else if (D == 2) launch_update_r_st_d<PT, LoT, LO, 2, SCH, FLEX>(w, probe, st);
+  else launch_update_r_st_d<PT, LoT, LO, 1, SCH, FLEX>(w, probe, st);
 }
 
 template <class PT, class LoT, bool LO>
 void launch_update_r_st_l(const Work& w, int flexible, int probe, hipStream_t st) {
-  if (w.scheme == 1) launch_update_r_st_s<PT, LoT, LO, 1>(w, flexible, probe, st);
-  else launch_update_r_st_s<PT, LoT, LO, 0>(w, flexible, probe, st);
+  if (w.scheme == 1) {
+    if (flexible) launch_update_r_st_s<PT, LoT, LO, 1, true>(w, probe, st);
+    else launch_update_r_st_s<PT, LoT, LO, 1, false>(w, probe, st);
+  } else {
+    if (flexible) launch_update_r_st_s<PT, LoT, LO, 0, true>(w, probe, st);
+    else launch_update_r_st_s<PT, LoT, LO, 0, false>(w, probe, st);
+  }
 }
 
 // the residual update with A p_k recomputed (w.qfree: FP64 operator apply,
 // two dimensions) in its own tile shape w.ustencil; r.r and r.z_old partials
-// per tile of that shape (w.P_rr)
-template <class PT>
-void launch_update_r_st_p(const Work& w, int flexible, int probe, hipStream_t st) {
-  if (w.mixed == 0) launch_update_r_st_l<PT, double, false>(w, flexible, probe, st);
-  else if (w.mixed == 1) launch_update_r_st_l<PT, float, true>(w, flexible, probe, st);
-  else if (w.mixed == 3) launch_update_r_st_l<PT, _Float16, true>(w, flexible, probe, st);
-  else launch_update_r_st_l<PT, __bf16, true>(w, flexible, probe, st);
+// per tile of that shape (w.P_rr). FP64 directions go with the FP64 GEMM
+// copy-free path, FP32 ones with an FP32, FP16 or BF16 copy of r.
+void launch_update_r_st(const Work& w, int flexible, int probe, hipStream_t st) {
+  if (w.mixed == 0) launch_update_r_st_l<double, double, false>(w, flexible, probe, st);
+  else if (w.mixed == 1) launch_update_r_st_l<float, float, true>(w, flexible, probe, st);
+  else if (w.mixed == 3) launch_update_r_st_l<float, _Float16, true>(w, flexible, probe, st);
+  else launch_update_r_st_l<float, __bf16, true>(w, flexible, probe, st);
 }
 
 template <class QT>
@@ -1464,8 +1485,7 @@ void launch_update_r_q(const Work& w, int flexible, hipStream_t st) {
 
 void launch_update_r(const Work& w, int flexible, hipStream_t st, int probe) {
   if (w.qfree) {
-    if (w.mixed == 0) launch_update_r_st_p<double>(w, flexible, probe, st);
-    else launch_update_r_st_p<float>(w, flexible, probe, st);
+    launch_update_r_st(w, flexible, probe, st);
     return;
   }
   // q = A p is FP32 with the FP32 operator apply
