@@ -421,6 +421,27 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+STORED_ORACLE = os.path.join(ROOT, "tests", "golden", "config_sizes.json")
+
+
+def stored_oracle_error(name, field, A):
+    """Relative error (max |dA_ij| / max_i |A_ii|) of one result against the
+    oracle's A_hom for the same input, stored by
+    tests/golden/make_config_sizes.py (which calls only the oracle; about a
+    minute of host time per item at these sizes). None when the stored input
+    is not this field."""
+    import hashlib
+
+    import numpy as np
+    with open(STORED_ORACLE) as f:
+        g = json.load(f)[name]
+    h = hashlib.sha256(np.ascontiguousarray(field, dtype=np.float64).tobytes()).hexdigest()[:16]
+    if h != g["field_sha256_16"]:
+        return None
+    R, A = np.array(g["ahom"]), np.asarray(A)
+    return float(np.max(np.abs(A - R)) / np.max(np.abs(np.diagonal(R))))
+
+
 def survey(rve, torch, dev):
     """One JSON line per workload: wall time per call (after one warm-up call
     of the same shape, so tuning and graph capture are excluded), mean PCG
@@ -484,9 +505,11 @@ def survey(rve, torch, dev):
         if prec == rve.FP64:
             ref = r.ahom
 
-    # 1024 realizations of L in {8, 16, 32, 64}, contrast 100, FP64 vs FP32 operator apply
+    # 1024 realizations of L in {8, 16, 32, 64}, contrast 100, FP64 vs FP32 operator apply;
+    # the first L = 32 and L = 64 items are inputs whose oracle A_hom is stored
     mix = uneven_batch([8, 16, 32, 64], m0=8, a_in=100.0, a_bg=1.0, config=3, per_size=256)
     ft = [torch.from_numpy(f).to(dev) for _, f in mix]
+    stored3 = [(f"c3_n{8 * L}_contrast100", next(k for k, (LL, _) in enumerate(mix) if LL == L)) for L in (32, 64)]
     ref = None
     for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16")):
         for sprec, sname in ((0, "fp64"), (1, "fp32")):
@@ -494,12 +517,16 @@ def survey(rve, torch, dev):
             dt, r = timed(lambda: rve.solve_uneven(ft, 1 / 8, o))
             if ref is None:
                 ref = r.ahom
+            Ah = r.ahom.cpu().numpy()
+            errs = {nm: stored_oracle_error(nm, mix[k][1], Ah[k]) for nm, k in stored3}
             emit("1024 realizations, L in {8,16,32,64} (n 64..512), contrast 100", gemm=pname, stencil=sname,
                  ms=1e3 * dt, realizations_s=len(ft) / dt, iters_mean=float(r.iters.double().mean()),
-                 ahom_rel_dev_vs_fp64=dev_rel(r.ahom, ref), code=r.code)
+                 ahom_rel_err_vs_oracle=errs, ahom_rel_dev_vs_fp64=dev_rel(r.ahom, ref), code=r.code)
 
-    # 16 realizations at L = 128, h = 1/16 (n = 2048)
-    a = fields(128, 16, 10.0, 16, 14)
+    # 16 realizations at L = 128, h = 1/16 (n = 2048); the first is the input
+    # whose oracle A_hom is stored
+    a = fields(128, 16, 10.0, 16, 4)
+    a0 = a[0].cpu().numpy()
     r64 = rve.solve_batch(a, 1 / 16, rve.Options(prec=rve.FP64), want_phi=False)
     ctx4 = rve.Context(0)
     for prec, pname in ((rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16"), (rve.MIX_FP32, "fp32"), (rve.FP64, "fp64")):
@@ -515,8 +542,9 @@ def survey(rve, torch, dev):
         gfl = float(rt.iters.double().sum()) * 4 * 2.0 * 2048.0 ** 3
         tfs = gfl / (gms * 1e-3) / 1e12
         emit("L=128 h=1/16 n=2048, 16 realizations", gemm=pname, ms=1e3 * dt, realizations_s=16 / dt,
-             iters_mean=float(r.iters.double().mean()), ahom_rel_dev_vs_fp64=dev_rel(r.ahom, r64.ahom),
-             gemm_TFLOPs=tfs, gemm_peak_frac=tfs / MFMA_PEAK_TFS[pname])
+             iters_mean=float(r.iters.double().mean()),
+             ahom_rel_err_vs_oracle={"c4_n2048": stored_oracle_error("c4_n2048", a0, r.ahom[0].cpu().numpy())},
+             ahom_rel_dev_vs_fp64=dev_rel(r.ahom, r64.ahom), gemm_TFLOPs=tfs, gemm_peak_frac=tfs / MFMA_PEAK_TFS[pname])
     ctx4.close()
     del a, r64
 
@@ -712,7 +740,9 @@ def survey_3d(rve, torch, dev, emit):
     for L, B in ((8, 64), (16, 8)):
         n = 8 * L
         N3 = float(n) ** 3
-        a = torch.from_numpy(batch_3d(BooleanModel3D(L=L, m0=8, a_in=10.0), 90 + L, B)).to(dev)
+        # (L = 16: the first realization is the input whose oracle A_hom is stored)
+        a = torch.from_numpy(batch_3d(BooleanModel3D(L=L, m0=8, a_in=10.0), 80 + L, B)).to(dev)
+        a0 = a[0].cpu().numpy()
         ref = None
         for prec, pname in ((rve.FP64, "fp64"), (rve.MIX_BF16, "bf16"), (rve.MIX_FP16, "fp16")):
             opts = rve.Options(tol=1e-10, prec=prec)
@@ -746,8 +776,10 @@ def survey_3d(rve, torch, dev, emit):
                     per = 4 if k == "gemm3" else 1
                     e["TFLOPs"] = round(sys_it * per * 2.0 * n * N3 / (ms * 1e-3) / 1e12, 1)
                 kern[k] = e
+            oerr = {"3d_n128": stored_oracle_error("3d_n128", a0, A[0])} if n == 128 else None
             emit(f"3D L={L} n={n}, {B} realizations (3 correctors + 3x3 A_hom)", gemm=pname, ms=1e3 * dt,
-                 realizations_s=B / dt, iters_mean=float(its.mean()), ahom_rel_dev_vs_fp64=dev_rel,
+                 realizations_s=B / dt, iters_mean=float(its.mean()), ahom_rel_err_vs_oracle=oerr,
+                 ahom_rel_dev_vs_fp64=dev_rel,
                  code=int(res.code), mean_a11=float(A[:, 0, 0].mean()), kernels=kern)
     ctx.close()
 
