@@ -141,9 +141,15 @@ struct Plane {
       for (int e = 0; e < C; ++e) v[k + e] = t.e[e];
     }
   }
+  // V consecutive elements to byte offset col of row `row`, in stores of at
+  // most 8 bytes. (A buffer store of more than 8 bytes with the row offset
+  // in a scalar register needs a wait state before its data registers are
+  // overwritten, which the compiler does not insert for that form on this
+  // target; the two stencil passes then stored values rewritten by the
+  // following instruction. Stores of 8 bytes have no such hazard.)
   template <int V, bool NT = false>
   __device__ void store(int row, unsigned col, const T* v) const {
-    constexpr int C = (int)(16 / sizeof(T)) < V ? (int)(16 / sizeof(T)) : V;
+    constexpr int C = (int)(8 / sizeof(T)) < V ? (int)(8 / sizeof(T)) : V;
 #pragma unroll
     for (int k = 0; k < V; k += C) {
       Run<C> t;

@@ -6,7 +6,7 @@ apply, and the five-point operator; and apply and update in different
 shapes.
 
 n = 256 admits all eighteen shapes (the 64V x 4H tile divides the grid); two
-realizations per solve. Bars: A_hom within 1e-10 (FP64 transforms) or 1e-8
+realizations per solve, in FP64, BF16, scaled FP16 and FP32 transforms. Bars: A_hom within 1e-10 (FP64 transforms) or 1e-8
 (BF16 transforms) of the oracle's, relative to max(|A_11|, |A_22|), and the
 true residual of every corrector within twice the tolerance (the stopping
 test is on the recursive residual, which tracks f - A x to FP64 rounding;
@@ -53,8 +53,11 @@ def _rel2(A, R):
     return float(np.max(np.abs(A - R)) / max(abs(R[0, 0]), abs(R[1, 1])))
 
 
-# (transform precision, operator apply precision, scheme, A_hom bar)
-CONFIGS = [(0, 0, 0, 1e-10), (2, 0, 0, 1e-8), (2, 1, 0, 1e-8), (0, 0, 1, 1e-10)]
+# (transform precision, operator apply precision, scheme, A_hom bar); the
+# scaled FP16 and the FP32 transforms give the residual update other
+# instantiations (GEMM-copy types), so every shape runs with each
+CONFIGS = [(0, 0, 0, 1e-10), (2, 0, 0, 1e-8), (3, 0, 0, 1e-8), (1, 0, 0, 1e-8), (2, 1, 0, 1e-8),
+           (0, 0, 1, 1e-10)]
 
 
 def _check(dev, a, ref_q1, ref_fd5, name, stencil, update, configs):
