@@ -682,12 +682,12 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       // loads of the scaling epilogue to the top)
       if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
       const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
+      if constexpr (EPI == kEpiZ) {
 #pragma unroll
-      for (int i = 0; i < BI; ++i) {
-        const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
-        const long long o = (long long)s * N2 + l * n + m;
-        const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
-        if constexpr (EPI == kEpiZ) {
+        for (int i = 0; i < BI; ++i) {
+          const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
+          const long long o = (long long)s * N2 + l * n + m;
+          const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
           ZT* out = (pnew ? pnew : reinterpret_cast<ZT*>(out_v)) + o;
           ZT zs[4];
 #pragma unroll
@@ -715,7 +715,20 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 #pragma unroll
             for (int e = 0; e < 4; ++e) out[e] = zs[e];
           }
-        } else {
+        }
+      } else {
+        // 16-bit output of block (i, j), rounded (and scaled by f / E in the
+        // scaling transform, which adds its products to the r.z partial), as
+        // two words. The empty asm pins the rounded bits: every later use
+        // (store, lane swap, r.z product) reads them, so the compiler cannot
+        // redo a conversion with another instruction sequence, and every tile
+        // shape stores the same bits.
+        typedef T v4t __attribute__((ext_vector_type(4)));
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        auto block = [&](int i) {
+          const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
+          const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
           float v[4] = {r[0], r[1], r[2], r[3]};
           if constexpr (EPI == kEpiEinv) {
             const float sl = sin2[l];
@@ -726,15 +739,64 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
               const float E = 4.f * (sl + sm[e]) - cq * sl * sm[e];
               v[e] *= E > 0.f ? fscale * __builtin_amdgcn_rcpf(E) : 0.f;
             }
+            // (the scaled values are rounded to FP32 before the conversion:
+            // left free, the compiler fuses some of the FP16 multiplies and
+            // conversions into one rounding and not others, differently in
+            // each tile shape)
+            asm("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
           }
-          typedef T v4t __attribute__((ext_vector_type(4)));
           v4t pk;
 #pragma unroll
           for (int e = 0; e < 4; ++e) pk[e] = (T)v[e];
-          *reinterpret_cast<v4t*>(reinterpret_cast<T*>(out_v) + o) = pk;
+          u2 bits = __builtin_bit_cast(u2, pk);
+          asm("" : "+v"(bits));
           if constexpr (EPI == kEpiEinv) {
+            const v4t q = __builtin_bit_cast(v4t, bits);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dot[i >> 2] += (double)r[e] * (double)(float)pk[e];
+            for (int e = 0; e < 4; ++e) dot[i >> 2] += (double)r[e] * (double)(float)q[e];
+          }
+          return bits;
+        };
+        // Blocks i and i + 1 are stored together, 16 bytes per lane: lane
+        // group g = lane / 16 holds four values of block i at column offset
+        // 4 g and four of block i + 1 at 16 + 4 g. Even groups swap their
+        // block-(i + 1) values for the block-i values of the odd group above
+        // (lane + 16), so group 0 stores columns 0-7 of block i, group 2
+        // columns 8-15, group 1 columns 16-23 (block i + 1) and group 3
+        // 24-31: each row gets 64 contiguous bytes per instruction, which
+        // the memory system writes about 1.5 times faster than the 32-byte
+        // pieces of 8-byte stores (measured with the same tile pattern).
+        // The 16-wave scaling transform has no registers for the swap (128
+        // per lane) and keeps one 8-byte store per block.
+        constexpr bool kPair = !(EPI == kEpiEinv && NW == 16);
+        const bool odd = (lane >> 4) & 1;
+        if constexpr (!kPair) {
+#pragma unroll
+          for (int i = 0; i < BI; ++i) {
+            const u2 w2 = block(i);
+            const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
+            *reinterpret_cast<u2*>(reinterpret_cast<T*>(out_v) + (long long)s * N2 + l * n + m) = w2;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < BI; i += 2) {
+            // (keeps each pair's symbol loads with the pair in the scaling
+            // transform, whose tall tiles otherwise spill)
+            if constexpr (EPI == kEpiEinv) __builtin_amdgcn_sched_barrier(0);
+            const u2 a = block(i);
+            const u2 b = block(i + 1);
+            const u2 send = odd ? a : b;
+            u2 got;
+            got.x = __shfl_xor(send.x, 16, kWave);
+            got.y = __shfl_xor(send.y, 16, kWave);
+            // words 0-1: the lower four columns, 2-3: the upper four
+            u4 o4;
+            o4.x = odd ? got.x : a.x;
+            o4.y = odd ? got.y : a.y;
+            o4.z = odd ? b.x : got.x;
+            o4.w = odd ? b.y : got.y;
+            const long long m = (long long)mb * TMR + wm * WR + i * 16 + (odd ? 16 : 0) + 8 * (lane >> 5);
+            *reinterpret_cast<u4*>(reinterpret_cast<T*>(out_v) + (long long)s * N2 + l * n + m) = o4;
           }
         }
       }

@@ -1,12 +1,14 @@
-"""The vector kernels' gfx950 code has no buffer store of more than 8 bytes
-whose data registers the next instruction overwrites.
+"""The vector and transform kernels' gfx950 code has no store of more than 8
+bytes whose data registers the next instruction overwrites.
 
 Such a store (its row offset in a scalar register) reads its data a cycle
 after issue; the compiler inserts no wait state for that form, so a value
 written by the following instruction is what lands in memory. The stencil
 passes once stored the residual scaled for its FP16 copy that way (the
-solves then stalled). Their stores are now at most 8 bytes wide; this test
-compiles the source to gfx950 assembly (no GPU needed) and scans it.
+solves then stalled). Their stores are now at most 8 bytes wide. The 16-bit
+transforms store 16 bytes per lane with global stores, for which the
+compiler does insert the wait. This test compiles both sources to gfx950
+assembly (no GPU needed) and scans them.
 """
 import os
 import re
@@ -16,7 +18,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_1903_12227_amd", "csrc", "kernels_vec.hip")
+SRCS = [os.path.join(ROOT, "paper_1903_12227_amd", "csrc", f) for f in ("kernels_vec.hip", "kernels_gemm.hip")]
 
 
 def _hipcc():
@@ -61,15 +63,19 @@ def test_scanner_finds_the_pattern():
 
 
 @pytest.mark.timeout(900)
-def test_vector_kernels_have_no_wide_store_data_hazard(tmp_path):
+def test_kernels_have_no_wide_store_data_hazard(tmp_path):
     hipcc = _hipcc()
     if hipcc is None:
         pytest.skip("hipcc not found")
-    out = tmp_path / "kernels_vec.s"
-    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out), SRC]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    assert res.returncode == 0, res.stderr[-2000:]
-    with open(out) as f:
-        hits = wide_store_hazards(f.readlines())
-    assert hits == [], hits[:5]
+    jobs = []
+    for src in SRCS:
+        out = tmp_path / (os.path.basename(src) + ".s")
+        cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+               "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out), src]
+        jobs.append((src, out, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    for src, out, proc in jobs:
+        _, err = proc.communicate()
+        assert proc.returncode == 0, (src, err[-2000:])
+        with open(out) as f:
+            hits = wide_store_hazards(f.readlines())
+        assert hits == [], (src, hits[:5])
