@@ -676,47 +676,107 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
     // row nb TNR + 64 wn + 16 j + l % 16 at the four consecutive columns
     // mb TMR + WR wm + 16 i + 4 (l / 16) + e
     const int lr = lane & 15, m4 = 4 * (lane >> 4);
+    if constexpr (EPI == kEpiZ) {
+      // z of block (i, j) (scaled FP16 operands: times 1 / (sigma E_min a0))
+      // rounded to its type, plus beta_k p_k when this transform forms the
+      // next direction
+      ZT* const zo = pnew ? pnew : reinterpret_cast<ZT*>(out_v);
+      auto zoff = [&](int i, int j) {
+        return (long long)s * N2 + ((long long)nb * TNR + wn * 64 + j * 16 + lr) * n +
+               (long long)mb * TMR + wm * WR + i * 16 + m4;
+      };
+      const ZT kNoP[4] = {0, 0, 0, 0};
+      auto zput = [&](int i, int j, bool with_p, const ZT (&po)[4]) {
+        const long long o = zoff(i, j);
+        ZT zs[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (scaled) zs[e] = (ZT)((double)acc[i][j][e] * es.z);
+          else zs[e] = (ZT)acc[i][j][e];
+        }
+        if (with_p) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) zs[e] = (ZT)fma(pbeta, (double)po[e], (double)zs[e]);
+        }
+        if constexpr (sizeof(ZT) == 4) {
+          float4 st;
+          st.x = zs[0]; st.y = zs[1]; st.z = zs[2]; st.w = zs[3];
+          *reinterpret_cast<float4*>(zo + o) = st;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) zo[o + e] = zs[e];
+        }
+      };
+      // (the scaled FP16 path in the 16-wave tile keeps one p_k load per
+      // block: at 128 registers the row form spills)
+      constexpr bool kRows = sizeof(ZT) == 4 && !(scaled && NW == 16);
+      if constexpr (kRows) {
+        if (pold) {
+          // p_k is loaded a block row at a time (one branch for the whole
+          // epilogue), and where the registers allow, row j + 1 before the
+          // stores of row j: a wait for loads issued after a store waits for
+          // the store too (one in-order counter). Loaded block by block, each
+          // block was a full round trip. (The scaled FP16 path, with its FP64
+          // products, and the 16-wave tile, at 128 registers, would spill
+          // with two rows of p_k in flight.)
+          constexpr bool kAhead = !scaled && NW <= 8;
+          float4 po[2][BI];
+          auto fetch = [&](int j, float4 (&dst)[BI]) {
+#pragma unroll
+            for (int i = 0; i < BI; ++i) dst[i] = *reinterpret_cast<const float4*>(pold + zoff(i, j));
+          };
+          if constexpr (kAhead) fetch(0, po[0]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            // (one block row at a time: hoisting the next rows' address and
+            // FP64 work spills the tighter tiles)
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kAhead) {
+              if (j + 1 < 4) fetch(j + 1, po[(j + 1) & 1]);
+            } else {
+              fetch(j, po[j & 1]);
+            }
+#pragma unroll
+            for (int i = 0; i < BI; ++i) {
+              const float4 pv = po[j & 1][i];
+              const ZT pk4[4] = {pv.x, pv.y, pv.z, pv.w};
+              zput(i, j, true, pk4);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < BI; ++i) zput(i, j, false, kNoP);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < BI; ++i) {
+            ZT pk4[4] = {0, 0, 0, 0};
+            if (pold) {
+              if constexpr (sizeof(ZT) == 4) {
+                const float4 pv = *reinterpret_cast<const float4*>(pold + zoff(i, j));
+                pk4[0] = pv.x; pk4[1] = pv.y; pk4[2] = pv.z; pk4[3] = pv.w;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pk4[e] = pold[zoff(i, j) + e];
+              }
+            }
+            zput(i, j, pold != nullptr, pk4);
+          }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       // (the 16-wave tile has no registers to spare for hoisting every block's
       // loads of the scaling epilogue to the top)
       if constexpr (EPI == kEpiEinv && NW == 16) __builtin_amdgcn_sched_barrier(0);
       const long long l = (long long)nb * TNR + wn * 64 + j * 16 + lr;
-      if constexpr (EPI == kEpiZ) {
-#pragma unroll
-        for (int i = 0; i < BI; ++i) {
-          const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
-          const long long o = (long long)s * N2 + l * n + m;
-          const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
-          ZT* out = (pnew ? pnew : reinterpret_cast<ZT*>(out_v)) + o;
-          ZT zs[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if constexpr (scaled) zs[e] = (ZT)((double)r[e] * es.z);
-            else zs[e] = (ZT)r[e];
-          }
-          if (pold) {
-            ZT po[4];
-            if constexpr (sizeof(ZT) == 4) {
-              const float4 pv = *reinterpret_cast<const float4*>(pold + o);
-              po[0] = pv.x; po[1] = pv.y; po[2] = pv.z; po[3] = pv.w;
-            } else {
-#pragma unroll
-              for (int e = 0; e < 4; ++e) po[e] = pold[o + e];
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) zs[e] = (ZT)fma(pbeta, (double)po[e], (double)zs[e]);
-          }
-          if constexpr (sizeof(ZT) == 4) {
-            float4 st;
-            st.x = zs[0]; st.y = zs[1]; st.z = zs[2]; st.w = zs[3];
-            *reinterpret_cast<float4*>(out) = st;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) out[e] = zs[e];
-          }
-        }
-      } else {
+      if constexpr (EPI != kEpiZ) {
         // 16-bit output of block (i, j), rounded (and scaled by f / E in the
         // scaling transform, which adds its products to the r.z partial), as
         // two words. The empty asm pins the rounded bits: every later use
