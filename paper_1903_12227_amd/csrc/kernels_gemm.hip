@@ -770,6 +770,20 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           }
       }
     }
+    // The scaling transform's symbol values depend on the output row (one
+    // per block row j) and on the four output columns of block i. The 8-wave
+    // tiles load all of them before the first store: loaded per block, each
+    // block pair waited for its loads and with them (one in-order counter)
+    // for the previous pair's store.
+    constexpr bool kPreSym = EPI == kEpiEinv && BI == 8;
+    float sl_pre[kPreSym ? 4 : 1];
+    float4 sm_pre[kPreSym ? BI : 1];
+    if constexpr (kPreSym) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sl_pre[j] = sin2[nb * TNR + wn * 64 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) sm_pre[i] = *reinterpret_cast<const float4*>(sin2 + mb * TMR + wm * WR + i * 16 + m4);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       // (the 16-wave tile has no registers to spare for hoisting every block's
@@ -791,8 +805,15 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           const float r[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
           float v[4] = {r[0], r[1], r[2], r[3]};
           if constexpr (EPI == kEpiEinv) {
-            const float sl = sin2[l];
-            const float4 sm4 = *reinterpret_cast<const float4*>(sin2 + m);
+            float sl;
+            float4 sm4;
+            if constexpr (kPreSym) {
+              sl = sl_pre[j];
+              sm4 = sm_pre[i];
+            } else {
+              sl = sin2[l];
+              sm4 = *reinterpret_cast<const float4*>(sin2 + m);
+            }
             const float sm[4] = {sm4.x, sm4.y, sm4.z, sm4.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
