@@ -847,38 +847,26 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
         // 24-31: each row gets 64 contiguous bytes per instruction, which
         // the memory system writes about 1.5 times faster than the 32-byte
         // pieces of 8-byte stores (measured with the same tile pattern).
-        // The 16-wave scaling transform has no registers for the swap (128
-        // per lane) and keeps one 8-byte store per block.
-        constexpr bool kPair = !(EPI == kEpiEinv && NW == 16);
         const bool odd = (lane >> 4) & 1;
-        if constexpr (!kPair) {
 #pragma unroll
-          for (int i = 0; i < BI; ++i) {
-            const u2 w2 = block(i);
-            const long long m = (long long)mb * TMR + wm * WR + i * 16 + m4;
-            *reinterpret_cast<u2*>(reinterpret_cast<T*>(out_v) + (long long)s * N2 + l * n + m) = w2;
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < BI; i += 2) {
-            // (keeps each pair's symbol loads with the pair in the scaling
-            // transform, whose tall tiles otherwise spill)
-            if constexpr (EPI == kEpiEinv) __builtin_amdgcn_sched_barrier(0);
-            const u2 a = block(i);
-            const u2 b = block(i + 1);
-            const u2 send = odd ? a : b;
-            u2 got;
-            got.x = __shfl_xor(send.x, 16, kWave);
-            got.y = __shfl_xor(send.y, 16, kWave);
-            // words 0-1: the lower four columns, 2-3: the upper four
-            u4 o4;
-            o4.x = odd ? got.x : a.x;
-            o4.y = odd ? got.y : a.y;
-            o4.z = odd ? b.x : got.x;
-            o4.w = odd ? b.y : got.y;
-            const long long m = (long long)mb * TMR + wm * WR + i * 16 + (odd ? 16 : 0) + 8 * (lane >> 5);
-            *reinterpret_cast<u4*>(reinterpret_cast<T*>(out_v) + (long long)s * N2 + l * n + m) = o4;
-          }
+        for (int i = 0; i < BI; i += 2) {
+          // (keeps each pair's symbol loads with the pair in the scaling
+          // transform, whose tall tiles otherwise spill)
+          if constexpr (EPI == kEpiEinv) __builtin_amdgcn_sched_barrier(0);
+          const u2 a = block(i);
+          const u2 b = block(i + 1);
+          const u2 send = odd ? a : b;
+          u2 got;
+          got.x = __shfl_xor(send.x, 16, kWave);
+          got.y = __shfl_xor(send.y, 16, kWave);
+          // words 0-1: the lower four columns, 2-3: the upper four
+          u4 o4;
+          o4.x = odd ? got.x : a.x;
+          o4.y = odd ? got.y : a.y;
+          o4.z = odd ? b.x : got.x;
+          o4.w = odd ? b.y : got.y;
+          const long long m = (long long)mb * TMR + wm * WR + i * 16 + (odd ? 16 : 0) + 8 * (lane >> 5);
+          *reinterpret_cast<u4*>(reinterpret_cast<T*>(out_v) + (long long)s * N2 + l * n + m) = o4;
         }
       }
     }
