@@ -347,6 +347,20 @@ def main():
     torch.cuda.synchronize()
     v_plain = args.plain / (time.perf_counter() - t0)
 
+    # flux form against energy form for each realization of the first timed
+    # batch, headline options, outside every timed region: the gap is set by
+    # the correctors' accuracy, and the flux form's asymmetry is what the
+    # paper tabulates against the tolerance (Sec. 4.1, Table conv_Symmet_thresh)
+    rf = rve.solve_batch(batches[0], h, mixed, want_phi=False, want_flux=True)
+    Ae, Af = rf.ahom.cpu().numpy(), rf.ahom_flux.cpu().numpy()
+    fscale = np.maximum(np.abs(Ae[:, 0, 0]), np.abs(Ae[:, 1, 1]))
+    fgap = np.abs(Af - Ae).reshape(len(fscale), -1).max(axis=1) / fscale
+    fasym = np.abs(Af[:, 0, 1] - Af[:, 1, 0]) / fscale
+    flux_gap = {"realizations": int(len(fscale)), "tol": args.tol, "max_rel": float(fgap.max()),
+                "median_rel": float(np.median(fgap)), "flux_asym_max_rel": float(fasym.max()),
+                "flux_asym_median_rel": float(np.median(fasym))}
+    del rf
+
     # roofline of the dominant kernel (largest total event time) of the headline leg
     # every field here takes two values only, so the operator kernels read
     # one byte per cell (the library's rule: each cell equals its field's
@@ -412,6 +426,7 @@ def main():
         "speedup_vs_plain_fp64": value / v_plain,
         "speedup_vs_fp64_batched": value / v64,
         "ahom_rel_err_vs_oracle": oracle_err,
+        "flux_energy_gap": flux_gap,
         "roofline": roof,
         "kernels": kernels,
         "coefficient_bytes_per_cell": coef_bytes,
