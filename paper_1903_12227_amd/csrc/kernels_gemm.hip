@@ -324,8 +324,10 @@ __global__ void __launch_bounds__(kBlock) k_hartley(const InT* __restrict__ X, c
 // Both accumulate over k in the same order (ascending 32-wide MFMA steps),
 // so they give identical outputs. The output (transposed) is stored straight
 // from the accumulators: each lane holds four consecutive output columns of
-// one output row per MFMA block, so a wave's store covers 16 rows x 32 bytes
-// (16-bit) or 64 bytes (FP32 z), and no LDS round trip or barrier is needed.
+// one output row per MFMA block; for 16-bit output lanes 16 apart swap half
+// of each block pair, so a wave's store covers 16 rows x 64 bytes (as the
+// FP32 z does with four values per lane), and no LDS round trip or barrier
+// is needed.
 // Three waves per SIMD (142 VGPRs with PIPE 0) hide more of the load latency
 // than two; four with 32-wide register-staged slices measured slower.
 constexpr int TM = 128, TN = 128, TK = 64, TLDA = TK + 8, TLDC = TM + 4;
