@@ -719,9 +719,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           // stores of row j: a wait for loads issued after a store waits for
           // the store too (one in-order counter). Loaded block by block, each
           // block was a full round trip. (The scaled FP16 path, with its FP64
-          // products, and the 16-wave tile, at 128 registers, would spill
-          // with two rows of p_k in flight.)
-          constexpr bool kAhead = !scaled && NW <= 8;
+          // products, would spill with two rows of p_k in flight.)
+          constexpr bool kAhead = !scaled;
           float4 po[2][BI];
           auto fetch = [&](int j, float4 (&dst)[BI]) {
 #pragma unroll
