@@ -258,7 +258,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the realizations are independent and this build runs "
+        print("bench.py measures one GPU: the realizations are independent and the library runs "
               "on a single MI355X; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
