@@ -470,14 +470,15 @@ def test_fp16_transforms_128_tiles_and_fewer_iterations(dev, n):
 
 
 @pytest.mark.parametrize("prec", [2, 3])
-@pytest.mark.parametrize("n", [384, 512])
+@pytest.mark.parametrize("n", [384, 512, 1024])
 def test_lds_loaded_transforms_identical_to_register_staged(dev, prec, n):
     # the 16-bit transform variants (1: 128 x 128 register-staged, 3: LDS
     # loaded, 4: 256 x 128 for three of the four transforms, 5: 256 x 256
     # for all four, 6: the same from 8 waves; 4, 5 and 6 need n % 256 == 0)
     # accumulate every output and every r.z partial in the same order, so
     # the preconditioner and whole solves agree bit for bit (n = 384: three
-    # tiles per axis, twelve K slices, no XCD remap of the tile order)
+    # tiles per axis, twelve K slices, no XCD remap of the tile order; n =
+    # 1024: four 256 x 256 tiles per axis, 96 tiles remapped over the XCDs)
     rve = _rve()
     rng = np.random.default_rng(n + 7 * prec)
     a = _fields(n, 3, 56)
