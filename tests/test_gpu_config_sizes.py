@@ -6,13 +6,15 @@
   eqns. wg03, wg01; Sec. 2, eqn. Stoch-decomp);
 * L = 128, h = 1/16 (n = 2048): one realization in every transform
   precision against the oracle's A_hom (Sec. 3.5, Lemma Cond_Number);
+* the largest grid the library takes, n = 4096 (L = 256, h = 1/16): one
+  realization with FP16, BF16 and FP64 transforms against the oracle;
 * three dimensions at n = 128: the operator element by element against the
   oracle's assembled matrix, and A_hom against the oracle's (Sec. 2 for
   d = 3, eqn. As_Kron_d);
 * an uneven batch holding n = 256 and n = 512 items at contrast 100.
 
-The oracle's A_hom at n = 2048, for the contrast-100 items and in three
-dimensions (about a minute of host time each) is stored in
+The oracle's A_hom at n = 2048 and n = 4096, for the contrast-100 items and
+in three dimensions (one to several minutes of host time each) is stored in
 tests/golden/config_sizes.json by tests/golden/make_config_sizes.py, which
 calls only the oracle; each entry carries a hash of its input field, checked
 here. Relative error of a d x d result: max |dA_ij| / max_i |A_ii|.
@@ -174,6 +176,23 @@ def test_n2048_every_precision_against_oracle(dev):
     ref = _gold("c4_n2048", a)
     ad = _to(a, dev).unsqueeze(0).contiguous()
     for prec, bound in ((rve.MIX_BF16, 1e-8), (rve.MIX_FP16, 1e-8), (rve.MIX_FP32, 1e-8), (rve.FP64, 1e-10)):
+        res = rve.solve_batch(ad, 1.0 / 16, rve.Options(tol=1e-10, prec=prec), want_phi=False)
+        assert res.code == 0, prec
+        assert rel(res.ahom.cpu().numpy()[0], ref) <= bound, (prec, rel(res.ahom.cpu().numpy()[0], ref))
+
+
+# ------------------------------------------------- the largest grid, n = 4096
+
+
+@pytest.mark.timeout(900)
+def test_n4096_largest_grid_against_oracle(dev):
+    # L = 256, h = 1/16: the largest n the library takes (16.7 million nodes
+    # per corrector), every 16-bit tile transform and the FP64 ones
+    rve = _rve()
+    a = realization(BooleanModel(L=256, m0=16, a_in=10.0), 7, 0)
+    ref = _gold("max_n4096", a)
+    ad = _to(a, dev).unsqueeze(0).contiguous()
+    for prec, bound in ((rve.MIX_FP16, 1e-8), (rve.MIX_BF16, 1e-8), (rve.FP64, 1e-10)):
         res = rve.solve_batch(ad, 1.0 / 16, rve.Options(tol=1e-10, prec=prec), want_phi=False)
         assert res.code == 0, prec
         assert rel(res.ahom.cpu().numpy()[0], ref) <= bound, (prec, rel(res.ahom.cpu().numpy()[0], ref))
