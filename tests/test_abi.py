@@ -82,9 +82,17 @@ def test_host_argument_validation(lib):
     # null context, bad n (not a multiple of 64 / too small), bad h, bad opts
     assert lib.rve_solve_batch(None, 1, 64, 0.125, fake, ctypes.byref(o), None, fake, None, None, None,
                                None) == N.EINVAL
-    for n in (0, 32, 96, 8192):
+    for n in (0, 32, 96, 4160, 8192):         # 4096 is the largest grid
         assert lib.rve_solve_batch(fake, 1, n, 0.125, fake, ctypes.byref(o), None, fake, None, None,
                                    None, None) == N.EINVAL
+    # an empty or negative batch is an error, not a no-op
+    other = ctypes.c_void_p(2)
+    for B in (0, -1):
+        assert lib.rve_solve_batch(fake, B, 64, 0.125, fake, ctypes.byref(o), None, fake, None, None,
+                                   None, None) == N.EINVAL
+        assert lib.rve_apply_operator(fake, B, 64, fake, fake, other, 0) == N.EINVAL
+        assert lib.rve_apply_precond(fake, B, 64, fake, fake, other, 0, 0) == N.EINVAL
+        assert lib.rve_stats(fake, B, 8.0, fake, other) == N.EINVAL
     assert lib.rve_solve_batch(fake, 1, 64, -1.0, fake, ctypes.byref(o), None, fake, None, None, None,
                                None) == N.EINVAL
     bad = N.RveOpts(-1.0, 10, 0, -1, 0)
