@@ -160,6 +160,35 @@ struct Plane {
   }
 };
 
+// Neighbour columns from the neighbouring lanes. Lane l of a wave holds
+// columns c0 .. c0 + V - 1 of a row, with c0 = (64 band + l) V; column c0 - 1
+// is the last column of lane l - 1 and column c0 + V the first of lane
+// l + 1, which a DPP wave shift brings over. Lanes 0 and 63, whose
+// neighbours lie in another band, keep `halo` (kHaloBelow: lane 0 takes the
+// lower neighbour; kHaloAbove: lane 63 the upper one).
+constexpr int kHaloBelow = 0x138;   // DPP wave_shr:1, lane l reads lane l - 1
+constexpr int kHaloAbove = 0x130;   // DPP wave_shl:1, lane l reads lane l + 1
+template <int CTRL, class T>
+__device__ inline T shift_in(T halo, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, halo), __builtin_bit_cast(int, v),
+                                                             CTRL, 0xf, 0xf, false));
+  } else {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    const i2 h = __builtin_bit_cast(i2, halo), x = __builtin_bit_cast(i2, v);
+    i2 r;
+    r.x = __builtin_amdgcn_update_dpp(h.x, x.x, CTRL, 0xf, 0xf, false);
+    r.y = __builtin_amdgcn_update_dpp(h.y, x.y, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, r);
+  }
+}
+// The byte offset a lane reads a row's neighbour columns from: column c0 - 1
+// in lane 0, c0 + V in lane 63, past the block (no access) in every other.
+__device__ inline unsigned halo_offset(int lane, unsigned below, unsigned above) {
+  return lane == 0 ? below : lane == kWave - 1 ? above : kPastBlock;
+}
+
 // The wave's index within its workgroup, as a wave-uniform (scalar) value.
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)); }
 
