@@ -83,7 +83,7 @@ def timed_steps(rve, torch, batches_dev, h, opts, G, contrast, L, warmup, steps,
     return (t1 - t0), it, tim, codes
 
 
-def bytes_per_node(prec_name, flexible, coef_bytes=8, pdirect=False):
+def bytes_per_node(prec_name, flexible, coef_bytes=8, pdirect=False, dir_bytes=None):
     """Algorithmic HBM bytes per node of each kernel, per corrector system
     (the operator apply: per realization, both systems).
 
@@ -93,6 +93,8 @@ def bytes_per_node(prec_name, flexible, coef_bytes=8, pdirect=False):
     pdirect: the last transform forms the next direction (16-bit tile
     transforms with the standard beta): it reads p_old and writes p instead of
     z, and the apply reads p alone.
+    dir_bytes: bytes per value of the directions p where they differ from
+    s_p (2: stored in BF16 where the last transform forms them).
 
     FP64 path: every vector FP64. Mixed paths: the directions p and z are
     stored in FP32 (s_p = 4) and the residual has a copy in the GEMM
@@ -117,20 +119,23 @@ def bytes_per_node(prec_name, flexible, coef_bytes=8, pdirect=False):
     """
     sg = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
+    # the directions p (BF16 where the last transform forms them, unless
+    # switched off; z, never stored then, does not appear)
+    sd = sp if dir_bytes is None else dir_bytes
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {
-        "stencil": (2 * sp if pdirect else 2 * (sp + sp + sp)) + coef_bytes,
+        "stencil": (2 * sd if pdirect else 2 * (sp + sp + sp)) + coef_bytes,
         "gemm1": first_in + sg,
         "gemm2": 2 * sg,
         "gemm3": 2 * sg,
-        "gemm4": sg + sp + (sp if pdirect else 0) + (0 if sg == 2 else first_in),
-        "update_r": 8 + sp + coef_bytes / 2 + 8 + lo + (sp if flexible else 0),
-        "fold_x": sp,
+        "gemm4": sg + (2 * sd if pdirect else sp) + (0 if sg == 2 else first_in),
+        "update_r": 8 + sd + coef_bytes / 2 + 8 + lo + (sp if flexible else 0),
+        "fold_x": sd,
     }
 
 
-def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8, pdirect=False):
+def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8, pdirect=False, dir_bytes=None):
     """Per-kernel algorithmic bytes (and flops) summed over the timed launches.
 
     it_all: (steps, B, 2) iteration counts. A realization takes part in the
@@ -145,7 +150,7 @@ def kernel_entries(tim, it_all, n, prec_name, flexible, coef_bytes=8, pdirect=Fa
     real_iters = float(it_all.max(dim=2).values.sum())
     sys_iters = float(it_all.sum())
     folds = float(sum(math.ceil(v / DIRECTION_RING) for v in it_all.flatten().tolist()))
-    bpn = bytes_per_node(prec_name, flexible, coef_bytes, pdirect)
+    bpn = bytes_per_node(prec_name, flexible, coef_bytes, pdirect, dir_bytes)
     units = {"stencil": real_iters, "gemm1": sys_iters, "gemm2": sys_iters, "gemm3": sys_iters,
              "gemm4": sys_iters, "update_r": sys_iters, "fold_x": sys_iters}
     out = {}
@@ -372,7 +377,10 @@ def main():
     # variants (every one but 0 and the folded 2) and the standard beta
     tuned = ctx.tuned(n, rve.MIX_BF16, B)
     pdirect = tuned["gemm_variant"] not in (0, 2, -1)
-    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False, coef_bytes=coef_bytes, pdirect=pdirect)
+    # ... and stores it in BF16 (the library's default)
+    dir_bytes = 2 if pdirect else None
+    ent = kernel_entries(tim_mix, it_mix_t, n, "bf16", flexible=False, coef_bytes=coef_bytes, pdirect=pdirect,
+                         dir_bytes=dir_bytes)
     dom = max(ent, key=lambda k: ent[k]["ms"])
     roof = roofline_for(dom, ent[dom], "bf16", n)
     roof["traffic"] = measured_traffic(dom)
@@ -431,6 +439,7 @@ def main():
         "kernels": kernels,
         "coefficient_bytes_per_cell": coef_bytes,
         "direction_in_last_transform": pdirect,
+        "direction_bytes": dir_bytes or 4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -733,6 +742,9 @@ def bytes_per_node_3d(prec_name):
     together, gemm4 the last (writes z, re-reads the residual copy)."""
     sg = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
+    # the directions p (BF16 where the last transform forms them, unless
+    # switched off; z, never stored then, does not appear)
+    sd = sp if dir_bytes is None else dir_bytes
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {"stencil": 3 * sp + 8 + 8, "gemm1": first_in + sg, "gemm2": 2 * sg, "gemm3": 4 * 2 * sg,

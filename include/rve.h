@@ -498,9 +498,24 @@ int rve_set_small_solver(rve_ctx* ctx, int mode);
  * the FP64 operator apply are used (beta is summed between the second and
  * the third transform; the operator apply then reads p_k alone); mode 0
  * always in the operator apply, from z_k and p_{k-1}. Both round p to its
- * storage type in the same way, so results are identical to the last bit.
- * Anything else: RVE_EINVAL. */
+ * storage type in the same way, so results are identical to the last bit
+ * (with rve_set_direction_bf16 mode 0; see there). Anything else:
+ * RVE_EINVAL. */
 int rve_set_direction_update(rve_ctx* ctx, int mode);
+
+/* Storage type of the search directions where the last transform forms
+ * them (rve_set_direction_update mode 1, 16-bit transforms, n <= 512): mode
+ * 1 (the default) BF16, p_{k+1} = z_{k+1} + beta_k p_k formed in FP64 and rounded
+ * once; mode 0 FP32, as the operator apply forms them. Sec. 3.5's PCG with
+ * the direction rounded before use: x += alpha p and r -= alpha A p see the
+ * same rounded p, so r = f - A x holds to FP64 rounding and the stopping
+ * test and A_hom keep their accuracy; only the conjugacy of successive
+ * directions is perturbed (a few percent more iterations), against 2 bytes
+ * less per node and system in each of four passes over them. Larger grids
+ * keep FP32 directions: over their longer iterations the perturbation adds
+ * up (n = 4096 with BF16 transforms stalled near a relative residual of
+ * 2e-7). Anything else: RVE_EINVAL. */
+int rve_set_direction_bf16(rve_ctx* ctx, int mode);
 
 /* Chunks of PCG iterations: mode 1 (the default) captures each distinct
  * chunk (same batches, pointers, kernel choices and options) once as a HIP

@@ -29,7 +29,7 @@ EXPORTS = (
     "rve_set_graphs", "rve_force_variants", "rve_sample_lattice", "rve_dos_moments", "rve_dos_eval",
     "rve_solve_batch_3d", "rve_apply_operator_3d", "rve_apply_precond_3d", "rve_set_small_solver",
     "rve_solve", "rve_field_from_mask", "rve_dos_plan", "rve_dos_probes", "rve_occupancy_threshold",
-    "rve_grad_noalloc", "rve_sample_fixed_count", "rve_set_direction_update",
+    "rve_grad_noalloc", "rve_sample_fixed_count", "rve_set_direction_update", "rve_set_direction_bf16",
 )
 
 
@@ -81,6 +81,7 @@ def _declare(lib):
     lib.rve_set_graphs.argtypes = [_vp, _i]
     lib.rve_set_small_solver.argtypes = [_vp, _i]
     lib.rve_set_direction_update.argtypes = [_vp, _i]
+    lib.rve_set_direction_bf16.argtypes = [_vp, _i]
     lib.rve_force_variants.argtypes = [_vp, _i, _i, _i]
     lib.rve_dos_moments.argtypes = [_vp, _i, _i, _i, _vp, _i, _vp, _d, _i, _vp]
     lib.rve_dos_eval.argtypes = [_vp, _i, _i, _i, _vp, _d, _d, _i, _i, _vp, _vp]

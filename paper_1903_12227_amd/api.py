@@ -101,9 +101,14 @@ class Context:
     def set_direction_update(self, in_transform: bool):
         """Form the next search direction in the last transform's epilogue
         where possible (the default) or always in the operator apply; the
-        results are identical."""
+        results are identical (with BF16 directions off)."""
         N.check(self._lib.rve_set_direction_update(self.handle, int(bool(in_transform))),
                 "rve_set_direction_update")
+
+    def set_direction_bf16(self, enable: bool):
+        """Store the directions the last transform forms in BF16 (the
+        default) or FP32 (16-bit transforms, n <= 512 only)."""
+        N.check(self._lib.rve_set_direction_bf16(self.handle, int(bool(enable))), "rve_set_direction_bf16")
 
     def set_graphs(self, enable: bool):
         """Replay each chunk of PCG iterations from a captured HIP graph (the

@@ -170,8 +170,11 @@ constexpr int kHaloBelow = 0x138;   // DPP wave_shr:1, lane l reads lane l - 1
 constexpr int kHaloAbove = 0x130;   // DPP wave_shl:1, lane l reads lane l + 1
 template <int CTRL, class T>
 __device__ inline T shift_in(T halo, T v) {
-  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
-  if constexpr (sizeof(T) == 4) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "16-, 32- or 64-bit values");
+  if constexpr (sizeof(T) == 2) {
+    const int h = __builtin_bit_cast(unsigned short, halo), x = __builtin_bit_cast(unsigned short, v);
+    return __builtin_bit_cast(T, (unsigned short)__builtin_amdgcn_update_dpp(h, x, CTRL, 0xf, 0xf, false));
+  } else if constexpr (sizeof(T) == 4) {
     return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, halo), __builtin_bit_cast(int, v),
                                                              CTRL, 0xf, 0xf, false));
   } else {

@@ -690,6 +690,22 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       const ZT kNoP[4] = {0, 0, 0, 0};
       auto zput = [&](int i, int j, bool with_p, const ZT (&po)[4]) {
         const long long o = zoff(i, j);
+        if constexpr (sizeof(ZT) == 2) {
+          // BF16 directions: p = z + beta p_k in FP64, rounded once
+          struct alignas(8) Z4 { ZT e[4]; } st;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double zd = scaled ? (double)acc[i][j][e] * es.z : (double)acc[i][j][e];
+            // rounded to FP32, then to BF16: the empty asm keeps the two
+            // roundings apart (left free, the compiler merged them into one
+            // for some elements and not others, differently per tile shape)
+            float f = (float)(with_p ? fma(pbeta, (double)po[e], zd) : zd);
+            asm("" : "+v"(f));
+            st.e[e] = (ZT)f;
+          }
+          *reinterpret_cast<Z4*>(zo + o) = st;
+          return;
+        }
         ZT zs[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -711,7 +727,19 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
       };
       // (the scaled FP16 path in the 16-wave tile keeps one p_k load per
       // block: at 128 registers the row form spills)
-      constexpr bool kRows = sizeof(ZT) == 4 && !(scaled && NW == 16);
+      constexpr bool kRows = (sizeof(ZT) == 4 || sizeof(ZT) == 2) && !(scaled && NW == 16);
+      // four values of p_k in one load: 16 bytes (FP32) or 8 (BF16)
+      using P4 = typename std::conditional<sizeof(ZT) == 4, float4, uint2>::type;
+      auto p4dec = [](const P4& v, ZT (&o)[4]) {
+        if constexpr (sizeof(ZT) == 4) {
+          o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+        } else {
+          struct Z4 { ZT e[4]; };
+          const Z4 t = __builtin_bit_cast(Z4, v);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) o[e] = t.e[e];
+        }
+      };
       if constexpr (kRows) {
         if (pold) {
           // p_k is loaded a block row at a time (one branch for the whole
@@ -721,10 +749,10 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           // block was a full round trip. (The scaled FP16 path, with its FP64
           // products, would spill with two rows of p_k in flight.)
           constexpr bool kAhead = !scaled;
-          float4 po[2][BI];
-          auto fetch = [&](int j, float4 (&dst)[BI]) {
+          P4 po[2][BI];
+          auto fetch = [&](int j, P4 (&dst)[BI]) {
 #pragma unroll
-            for (int i = 0; i < BI; ++i) dst[i] = *reinterpret_cast<const float4*>(pold + zoff(i, j));
+            for (int i = 0; i < BI; ++i) dst[i] = *reinterpret_cast<const P4*>(pold + zoff(i, j));
           };
           if constexpr (kAhead) fetch(0, po[0]);
 #pragma unroll
@@ -739,8 +767,8 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
             }
 #pragma unroll
             for (int i = 0; i < BI; ++i) {
-              const float4 pv = po[j & 1][i];
-              const ZT pk4[4] = {pv.x, pv.y, pv.z, pv.w};
+              ZT pk4[4];
+              p4dec(po[j & 1][i], pk4);
               zput(i, j, true, pk4);
             }
           }
@@ -1360,7 +1388,19 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
   } else if (prec == kGemmF32) {
     run_precond<TrF32, float>(w, t, st, phase);
   } else if (prec == kGemmF16) {
-    if (w.gemm_variant == 1)
+    if (w.pdir16 && w.gemm_variant == 1)
+      run_precond_h16<_Float16, __bf16, 0>(w, t, st, phase);
+    else if (w.pdir16 && w.gemm_variant == 3)
+      run_precond_h16<_Float16, __bf16, 1>(w, t, st, phase);
+    else if (w.pdir16 && w.gemm_variant == 7)
+      run_precond_h16<_Float16, __bf16, 2, 2, 4, 8>(w, t, st, phase);
+    else if (w.pdir16 && w.gemm_variant == 4)
+      run_precond_h16<_Float16, __bf16, 0, 4>(w, t, st, phase);
+    else if (w.pdir16 && w.gemm_variant == 5)
+      run_precond_h16<_Float16, __bf16, 0, 4, 4>(w, t, st, phase);
+    else if (w.pdir16 && w.gemm_variant == 6)
+      run_precond_h16<_Float16, __bf16, 0, 2, 4, 8>(w, t, st, phase);
+    else if (w.gemm_variant == 1)
       run_precond_h16<_Float16, float, 0>(w, t, st, phase);
     else if (w.gemm_variant == 3)
       run_precond_h16<_Float16, float, 1>(w, t, st, phase);
@@ -1376,6 +1416,18 @@ void launch_precond(const Work& w, int prec, const GemmTables& t, hipStream_t st
       run_precond<TrF16, float>(w, t, st, phase);
   } else if (w.gemm_variant == 2) {
     run_precond_bf16_sym<float>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 1) {
+    run_precond_h16<__bf16, __bf16, 0>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 3) {
+    run_precond_h16<__bf16, __bf16, 1>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 7) {
+    run_precond_h16<__bf16, __bf16, 2, 2, 4, 8>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 4) {
+    run_precond_h16<__bf16, __bf16, 0, 4>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 5) {
+    run_precond_h16<__bf16, __bf16, 0, 4, 4>(w, t, st, phase);
+  } else if (w.pdir16 && w.gemm_variant == 6) {
+    run_precond_h16<__bf16, __bf16, 0, 2, 4, 8>(w, t, st, phase);
   } else if (w.gemm_variant == 1) {
     run_precond_h16<__bf16, float, 0>(w, t, st, phase);
   } else if (w.gemm_variant == 3) {

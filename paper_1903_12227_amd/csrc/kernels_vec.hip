@@ -104,12 +104,15 @@ struct CoefDec {
 };
 
 // code[b][e] = 1 where a = max a of realization b, 0 where a = min a; a cell
-// with any other value sets *not_two_valued (one atomic per workgroup).
+// with any other value sets bit 0 of *not_two_valued (one atomic per
+// workgroup), a realization whose contrast max a / min a exceeds
+// kDir16MaxContrast bit 1.
 __global__ void __launch_bounds__(kBlock) k_encode_two_valued(const double* __restrict__ a,
                                                                const RealState* __restrict__ real, long long N2,
                                                                uint8_t* __restrict__ code, int* not_two_valued) {
   const int b = blockIdx.y;
   const double lo = real[b].a_min, hi = real[b].a_max;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(hi <= kDir16MaxContrast * lo)) atomicOr(not_two_valued, 2);
   const long long off = (long long)b * N2;
   const long long stride = (long long)gridDim.x * kBlock * 4;
   int bad = 0;
@@ -1422,6 +1425,10 @@ void launch_stencil_fused(const Work& w, hipStream_t st, int probe) {
   // reads p_{k-1} from the previous slot
   if (w.mixed == 0)
     launch_stencil_fused_p<double>(w, probe, st);
+  else if (w.pdir16 && w.scheme == 1)
+    launch_stencil_fused_m<__bf16, 1, true>(w, probe, st);
+  else if (w.pdir16)
+    launch_stencil_fused_m<__bf16, 0, true>(w, probe, st);
   else
     launch_stencil_fused_p<float>(w, probe, st);
 }
@@ -1483,6 +1490,8 @@ void launch_update_r_st_l(const Work& w, int flexible, int probe, hipStream_t st
 // copy-free path, FP32 ones with an FP32, FP16 or BF16 copy of r.
 void launch_update_r_st(const Work& w, int flexible, int probe, hipStream_t st) {
   if (w.mixed == 0) launch_update_r_st_l<double, double, false>(w, flexible, probe, st);
+  else if (w.pdir16 && w.mixed == 3) launch_update_r_st_l<__bf16, _Float16, true>(w, 0, probe, st);
+  else if (w.pdir16) launch_update_r_st_l<__bf16, __bf16, true>(w, 0, probe, st);
   else if (w.mixed == 1) launch_update_r_st_l<float, float, true>(w, flexible, probe, st);
   else if (w.mixed == 3) launch_update_r_st_l<float, _Float16, true>(w, flexible, probe, st);
   else launch_update_r_st_l<float, __bf16, true>(w, flexible, probe, st);
@@ -1579,6 +1588,9 @@ void launch_fold_x(const Work& w, int final, hipStream_t st) {
   const long long slot = (long long)w.S * w.N2;
   if (w.mixed == 0)
     hipLaunchKernelGGL((k_fold_x<double>), g, blk, 0, st, w.x, (const double*)w.pring, slot, w.m_ring,
+                       w.alpha_hist, w.sys, w.N2, (const int*)w.kiter, final);
+  else if (w.pdir16)
+    hipLaunchKernelGGL((k_fold_x<__bf16>), g, blk, 0, st, w.x, (const __bf16*)w.pring, slot, w.m_ring,
                        w.alpha_hist, w.sys, w.N2, (const int*)w.kiter, final);
   else
     hipLaunchKernelGGL((k_fold_x<float>), g, blk, 0, st, w.x, (const float*)w.pring, slot, w.m_ring,

@@ -40,6 +40,10 @@ struct Work {
   // RVE_DIRECTION_RING + 1 slots, since p_{k+1} is written one iteration
   // before the fold of the chunk that ends at k.
   int pdirect = 0;
+  // pdirect with 16-bit transforms: the directions in the ring are BF16
+  // instead of FP32 (the apply, the residual update and the fold read them
+  // so; the last transform rounds p_{k+1} = z_{k+1} + beta_k p_k to BF16 once)
+  int pdir16 = 0;
   int pdir_first = 0;   // pdirect: the apply before the first iteration (p_0 = z_0 into slot k mod m)
   double* alpha_hist = nullptr;
   double* q = nullptr;       // A p
@@ -136,6 +140,12 @@ void launch_to_f32(const double* in, float* out, long long total, hipStream_t st
 // iteration (directions since the last multiple of m).
 void launch_fold_x(const Work& w, int final, hipStream_t st);
 constexpr int kRing = 8;   // direction ring length (iterations per x update)
+// BF16 directions (Work::pdir16) on grids up to kDir16MaxN and for fields of
+// contrast (max a / min a) up to kDir16MaxContrast: beyond either the longer
+// iteration accumulates the lost conjugacy (n = 4096: a stall near 2e-7;
+// contrast 100: 12 % more iterations, as much as the bytes save)
+constexpr int kDir16MaxN = 512;
+constexpr double kDir16MaxContrast = 10.0;
 void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);

@@ -102,6 +102,7 @@ struct rve_ctx {
   int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
   int small_solver = 1;               // single-workgroup PCG where it fits (n = 64, FP64)
   int direction_update = 1;           // the last transform forms the next direction where it can
+  int direction_bf16 = 1;             // ... and stores it in BF16 (16-bit transforms, n <= kDir16MaxN)
   std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
@@ -692,7 +693,7 @@ int chunk_graph(rve_ctx* ctx, std::vector<Batch>& bs, const rve_opts* o, int fle
                          (long long)bs.size()});
   for (auto& b : bs)
     key.insert(key.end(), {b.B, b.n, b.dim, b.prec, (long long)b.base, b.w.stencil, b.w.ustencil,
-                           b.w.gemm_variant, b.w.a8 != nullptr, b.w.pdirect});
+                           b.w.gemm_variant, b.w.a8 != nullptr, b.w.pdirect, b.w.pdir16});
   auto it = ctx->graph_cache.find(key);
   if (it != ctx->graph_cache.end()) {
     *out = it->second;
@@ -788,11 +789,15 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       launch_to_f32(b.w.a, const_cast<float*>(b.w.a32), (long long)b.B * b.w.N2, st);
     }
   }
+  // (bit 1 of the flag: a field of the solve exceeds the contrast of BF16
+  // directions)
+  bool low_contrast = false;
   if (encode) {
     HIP_TRY(hipMemcpyAsync(ctx->h_count + 2, not_two_valued, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (ctx->h_count[2] == 0)
+    if ((ctx->h_count[2] & 1) == 0)
       for (auto& b : bs) b.w.a8 = reinterpret_cast<const uint8_t*>(ws + b.base + b.L.off_a8);
+    low_contrast = (ctx->h_count[2] & 2) == 0;
   }
 
   if (small) {
@@ -840,6 +845,12 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     w.pdirect = ctx->direction_update && !flexible && !w.sprec &&
                 gemm_variant_writes_direction(n, prec, w.gemm_variant) ? 1 : 0;
     w.m_ring = w.pdirect ? kRing + 1 : kRing;
+    // the directions the last transform forms are stored in BF16 (16-bit
+    // transforms; they only steer the iteration: x and q = A p see the same
+    // rounded p, so r = f - A x still holds to FP64 rounding), on grids up to
+    // kDir16MaxN and for fields of contrast up to kDir16MaxContrast
+    w.pdir16 = w.pdirect && ctx->direction_bf16 && (w.mixed == 2 || w.mixed == 3) && n <= kDir16MaxN &&
+                       low_contrast ? 1 : 0;
     precond_beta(ctx, w, prec, b.gt, flexible, 1, st, nullptr);
     int sc = stencil_choice_default(n);
     // operator-apply shapes: V in {1, 2, 4}, H in {16, 64}, D in {1, 2, 4}
@@ -855,7 +866,7 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       // previous direction's slot (zeroed here), i.e. do a later iteration's
       // work; iteration 0 then rewrites everything they wrote
       if (tune_now && !ctx->tune.count(kst)) {
-        const size_t slot = (size_t)w.S * w.N2 * (w.mixed ? 4 : 8);
+        const size_t slot = (size_t)w.S * w.N2 * (w.pdir16 ? 2 : w.mixed ? 4 : 8);
         HIP_TRY(hipMemsetAsync(static_cast<char*>(w.pring) + (kRing - 1) * slot, 0, slot, st));
       }
       if (ctx->tune.count(kst) || tune_now)
@@ -1538,6 +1549,12 @@ int rve_force_variants(rve_ctx* c, int stencil_choice, int gemm_variant, int upd
 int rve_set_direction_update(rve_ctx* c, int mode) {
   if (!c || (mode != 0 && mode != 1)) return RVE_EINVAL;
   c->direction_update = mode;
+  return RVE_OK;
+}
+
+int rve_set_direction_bf16(rve_ctx* c, int mode) {
+  if (!c || (mode != 0 && mode != 1)) return RVE_EINVAL;
+  c->direction_bf16 = mode;
   return RVE_OK;
 }
 

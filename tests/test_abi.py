@@ -109,6 +109,9 @@ def test_host_argument_validation(lib):
     assert lib.rve_force_variants(None, -1, -1, -1) == N.EINVAL
     assert lib.rve_set_small_solver(None, 1) == N.EINVAL
     assert lib.rve_set_small_solver(fake, 2) == N.EINVAL
+    assert lib.rve_set_direction_bf16(None, 1) == N.EINVAL
+    assert lib.rve_set_direction_bf16(fake, 2) == N.EINVAL
+    assert lib.rve_set_direction_bf16(fake, -1) == N.EINVAL
     for bad in (N.RveOpts(1e-10, 10, 0, -1, 0, 0, 2), N.RveOpts(1e-10, 10, 0, -1, 0, 1, 1)):
         # unknown scheme; five-point with the FP32 apply
         assert lib.rve_solve_batch(fake, 1, 64, 0.125, fake, ctypes.byref(bad), None, fake, None, None,

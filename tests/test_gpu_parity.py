@@ -548,6 +548,54 @@ def test_persistent_256_tiles_match_per_tile_grid(dev, prec):
         assert np.linalg.norm(zc - ref) <= (3e-2 if prec == 2 else 3e-3) * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("prec,variant,n", [(2, 1, 256), (3, 5, 256), (2, 6, 512), (3, 6, 512), (2, 7, 256)])
+def test_bf16_directions_against_fp32_and_oracle(dev, prec, variant, n):
+    # directions formed in the last transform and stored in BF16 (the
+    # default) or FP32: A_hom of both agree with the oracle to 1e-8 and
+    # with each other to 1e-10, the true residual ||f - A phi|| stays within
+    # 2 tol (x and A p see the same rounded direction), and the rounding
+    # costs at most a few iterations; a solve holding a field of contrast
+    # above 10 keeps FP32 directions (the same bits either way)
+    rve = _rve()
+    a = _fields(n, 3, 67)
+    res = {}
+    for bf in (True, False):
+        ctx = rve.Context(0)
+        ctx.set_autotune(False)
+        ctx.force_variants(gemm=variant)
+        ctx.set_direction_bf16(bf)
+        res[bf] = rve.solve_batch(_to(a, dev), 0.125, rve.Options(tol=1e-10, prec=prec), ctx=ctx)
+        ctx.close()
+        assert res[bf].code == 0
+    A16, A32 = res[True].ahom.cpu().numpy(), res[False].ahom.cpu().numpy()
+    it16, it32 = res[True].iters.cpu().numpy(), res[False].iters.cpu().numpy()
+    assert np.all(it16 <= it32 + np.maximum(3, np.ceil(0.1 * it32))), (it16, it32)
+    for b in range(3):
+        assert rel2(A16[b], A32[b]) <= 1e-10
+    phi = res[True].phi.cpu().numpy()
+    for b in (0, 2) if n == 256 else (0,):
+        ref = oa.solve(a[b], tol=1e-13)
+        assert rel2(A16[b], ref.ahom) <= 1e-8
+        A = q1.assemble(a[b])
+        f1, f2 = q1.rhs(a[b])
+        for i, f in enumerate((f1, f2)):
+            f = (f - f.mean()).ravel()
+            # phi is the corrector in physical units (grid units times h)
+            u = phi[b, i].ravel() / 0.125
+            assert np.linalg.norm(f - A @ u) <= 2e-10 * np.linalg.norm(f)
+    if n == 256:
+        hi = np.concatenate([a[:1], _fields(n, 1, 68, contrast=100.0)])
+        out = []
+        for bf in (True, False):
+            ctx = rve.Context(0)
+            ctx.set_autotune(False)
+            ctx.force_variants(gemm=variant)
+            ctx.set_direction_bf16(bf)
+            out.append(rve.solve_batch(_to(hi, dev), 0.125, rve.Options(tol=1e-10, prec=prec), ctx=ctx))
+            ctx.close()
+        assert out[0].code == 0 and _same(out[0], out[1])
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_small_solver_matches_batched_path_and_oracle(dev, scheme):
     # n = 64, FP64: the single-workgroup solver (default) against the batched
@@ -684,6 +732,7 @@ def test_direction_in_last_transform_identical(dev, prec, variant):
         ctx.set_autotune(False)
         ctx.force_variants(gemm=variant)
         ctx.set_direction_update(mode)
+        ctx.set_direction_bf16(False)   # the apply forms FP32 directions
         for opts in (rve.Options(tol=1e-10, prec=prec), rve.Options(tol=1e-10, prec=prec, check_every=24)):
             out.append(rve.solve_batch(_to(a, dev), 0.125, opts, ctx=ctx))
         ctx.close()
