@@ -742,9 +742,6 @@ def bytes_per_node_3d(prec_name):
     together, gemm4 the last (writes z, re-reads the residual copy)."""
     sg = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[prec_name]
     sp = 8 if prec_name == "fp64" else 4
-    # the directions p (BF16 where the last transform forms them, unless
-    # switched off; z, never stored then, does not appear)
-    sd = sp if dir_bytes is None else dir_bytes
     lo = 0 if prec_name == "fp64" else sg
     first_in = 8 if prec_name == "fp64" else sg
     return {"stencil": 3 * sp + 8 + 8, "gemm1": first_in + sg, "gemm2": 2 * sg, "gemm3": 4 * 2 * sg,

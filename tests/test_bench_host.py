@@ -27,6 +27,15 @@ def test_bytes_per_node_matches_the_kernels_accesses():
     # BF16 copy (2); the fold reads each direction once (4)
     b = bench.bytes_per_node("bf16", flexible=False, coef_bytes=1, pdirect=True)
     assert b == {"stencil": 9, "gemm1": 4, "gemm2": 4, "gemm3": 4, "gemm4": 10, "update_r": 22.5, "fold_x": 4}
+    # the same with the directions stored in BF16: 2 bytes less in each of
+    # the apply's reads (both systems), the last transform's write and read,
+    # the update's read and the fold's read
+    b = bench.bytes_per_node("bf16", flexible=False, coef_bytes=1, pdirect=True, dir_bytes=2)
+    assert b == {"stencil": 5, "gemm1": 4, "gemm2": 4, "gemm3": 4, "gemm4": 6, "update_r": 20.5, "fold_x": 2}
+    # three dimensions: one system per apply workgroup (a read per system),
+    # six transforms (gemm3: the four plain ones), FP32 directions
+    assert bench.bytes_per_node_3d("bf16") == {"stencil": 28, "gemm1": 4, "gemm2": 4, "gemm3": 16, "gemm4": 8,
+                                               "update_r": 26, "fold_x": 4}
     # the apply fused with the direction step: reads z and p_old, writes p_new
     assert bench.bytes_per_node("bf16", False, 1)["stencil"] == 25
     assert bench.bytes_per_node("bf16", False, 8)["stencil"] == 32
