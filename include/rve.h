@@ -504,17 +504,20 @@ int rve_set_small_solver(rve_ctx* ctx, int mode);
 int rve_set_direction_update(rve_ctx* ctx, int mode);
 
 /* Storage type of the search directions where the last transform forms
- * them (rve_set_direction_update mode 1, 16-bit transforms, n <= 512): mode
+ * them (rve_set_direction_update mode 1, 16-bit transforms, n <= 512,
+ * contrast <= 20): mode
  * 1 (the default) BF16, p_{k+1} = z_{k+1} + beta_k p_k formed in FP64 and rounded
  * once; mode 0 FP32, as the operator apply forms them. Sec. 3.5's PCG with
  * the direction rounded before use: x += alpha p and r -= alpha A p see the
  * same rounded p, so r = f - A x holds to FP64 rounding and the stopping
  * test and A_hom keep their accuracy; only the conjugacy of successive
  * directions is perturbed (a few percent more iterations), against 2 bytes
- * less per node and system in each of four passes over them. Larger grids
- * keep FP32 directions: over their longer iterations the perturbation adds
- * up (n = 4096 with BF16 transforms stalled near a relative residual of
- * 2e-7). Anything else: RVE_EINVAL. */
+ * less per node and system in each of four passes over them. Larger grids,
+ * and solves holding a field of contrast max a / min a above 20, keep FP32
+ * directions: over their longer iterations the perturbation adds up (n =
+ * 4096 with BF16 transforms stalled near a relative residual of 2e-7; at
+ * contrast 100 the extra iterations cost more than the bytes save).
+ * Anything else: RVE_EINVAL. */
 int rve_set_direction_bf16(rve_ctx* ctx, int mode);
 
 /* Chunks of PCG iterations: mode 1 (the default) captures each distinct

@@ -107,7 +107,8 @@ class Context:
 
     def set_direction_bf16(self, enable: bool):
         """Store the directions the last transform forms in BF16 (the
-        default) or FP32 (16-bit transforms, n <= 512 only)."""
+        default) or FP32 (16-bit transforms, n <= 512 and contrast <= 20
+        only)."""
         N.check(self._lib.rve_set_direction_bf16(self.handle, int(bool(enable))), "rve_set_direction_bf16")
 
     def set_graphs(self, enable: bool):

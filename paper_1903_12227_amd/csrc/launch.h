@@ -142,10 +142,11 @@ void launch_fold_x(const Work& w, int final, hipStream_t st);
 constexpr int kRing = 8;   // direction ring length (iterations per x update)
 // BF16 directions (Work::pdir16) on grids up to kDir16MaxN and for fields of
 // contrast (max a / min a) up to kDir16MaxContrast: beyond either the longer
-// iteration accumulates the lost conjugacy (n = 4096: a stall near 2e-7;
-// contrast 100: 12 % more iterations, as much as the bytes save)
+// iteration accumulates the lost conjugacy (n = 4096: a stall near 2e-7; at
+// n = 512 whole solves gain 6-8 % at contrast 10, 4-6 % at 20, 1-6 % at 30
+// and lose 5-12 % at 100)
 constexpr int kDir16MaxN = 512;
-constexpr double kDir16MaxContrast = 10.0;
+constexpr double kDir16MaxContrast = 20.0;
 void launch_widen(const float* in, double* out, long long total, hipStream_t st);
 void launch_ahom(const Work& w, hipStream_t st);
 void launch_scalar_ahom(const Work& w, double* ahom, double* ahom_flux, hipStream_t st);

@@ -555,7 +555,7 @@ def test_bf16_directions_against_fp32_and_oracle(dev, prec, variant, n):
     # with each other to 1e-10, the true residual ||f - A phi|| stays within
     # 2 tol (x and A p see the same rounded direction), and the rounding
     # costs at most a few iterations; a solve holding a field of contrast
-    # above 10 keeps FP32 directions (the same bits either way)
+    # above 20 keeps FP32 directions (the same bits either way)
     rve = _rve()
     a = _fields(n, 3, 67)
     res = {}
