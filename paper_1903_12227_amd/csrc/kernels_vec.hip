@@ -1487,7 +1487,9 @@ void launch_update_r_st_l(const Work& w, int flexible, int probe, hipStream_t st
 // the residual update with A p_k recomputed (w.qfree: FP64 operator apply,
 // two dimensions) in its own tile shape w.ustencil; r.r and r.z_old partials
 // per tile of that shape (w.P_rr). FP64 directions go with the FP64 GEMM
-// copy-free path, FP32 ones with an FP32, FP16 or BF16 copy of r.
+// copy-free path, FP32 ones with an FP32, FP16 or BF16 copy of r; BF16
+// ones (only where the last transform forms them, so never with the
+// flexible beta) with a BF16 or FP16 copy.
 void launch_update_r_st(const Work& w, int flexible, int probe, hipStream_t st) {
   if (w.mixed == 0) launch_update_r_st_l<double, double, false>(w, flexible, probe, st);
   else if (w.pdir16 && w.mixed == 3) launch_update_r_st_l<__bf16, _Float16, true>(w, 0, probe, st);

@@ -102,7 +102,7 @@ struct rve_ctx {
   int force_gemm = -1;                // transform-GEMM variant to use instead of the tuner's (-1: none)
   int small_solver = 1;               // single-workgroup PCG where it fits (n = 64, FP64)
   int direction_update = 1;           // the last transform forms the next direction where it can
-  int direction_bf16 = 1;             // ... and stores it in BF16 (16-bit transforms, n <= kDir16MaxN)
+  int direction_bf16 = 1;             // ... in BF16 (16-bit transforms; n, contrast: kDir16Max*)
   std::map<std::vector<long long>, hipGraphExec_t> graph_cache;
   int autotune = 1;
   std::map<TuneKey, int> tune;
@@ -849,8 +849,8 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
     // transforms; they only steer the iteration: x and q = A p see the same
     // rounded p, so r = f - A x still holds to FP64 rounding), on grids up to
     // kDir16MaxN and for fields of contrast up to kDir16MaxContrast
-    w.pdir16 = w.pdirect && ctx->direction_bf16 && (w.mixed == 2 || w.mixed == 3) && n <= kDir16MaxN &&
-                       low_contrast ? 1 : 0;
+    w.pdir16 =
+        w.pdirect && ctx->direction_bf16 && (w.mixed == 2 || w.mixed == 3) && n <= kDir16MaxN && low_contrast ? 1 : 0;
     precond_beta(ctx, w, prec, b.gt, flexible, 1, st, nullptr);
     int sc = stencil_choice_default(n);
     // operator-apply shapes: V in {1, 2, 4}, H in {16, 64}, D in {1, 2, 4}
