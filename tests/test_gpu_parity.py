@@ -596,6 +596,31 @@ def test_bf16_directions_against_fp32_and_oracle(dev, prec, variant, n):
         assert out[0].code == 0 and _same(out[0], out[1])
 
 
+def test_bf16_direction_limits(dev):
+    # BF16 directions are used up to contrast 20 on grids up to n = 512:
+    # there the switch changes the iterates; above either limit the solve
+    # keeps FP32 directions and the switch changes nothing
+    rve = _rve()
+
+    def both(a, h):
+        out = []
+        for bf in (True, False):
+            ctx = rve.Context(0)
+            ctx.set_direction_bf16(bf)
+            out.append(rve.solve_batch(_to(a, dev), h, rve.Options(tol=1e-10, prec=rve.MIX_BF16), ctx=ctx))
+            ctx.close()
+            assert out[-1].code == 0
+        return out
+
+    r16, r32 = both(_fields(256, 1, 69, contrast=20.0), 0.125)
+    assert not torch.equal(r16.phi, r32.phi)
+    assert rel2(r16.ahom.cpu().numpy()[0], r32.ahom.cpu().numpy()[0]) <= 1e-10
+    r16, r32 = both(_fields(256, 1, 69, contrast=21.0), 0.125)
+    assert _same(r16, r32)
+    r16, r32 = both(_fields(1024, 1, 70), 0.125)
+    assert _same(r16, r32)
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_small_solver_matches_batched_path_and_oracle(dev, scheme):
     # n = 64, FP64: the single-workgroup solver (default) against the batched
