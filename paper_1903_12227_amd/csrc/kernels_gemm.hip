@@ -688,22 +688,49 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
                (long long)mb * TMR + wm * WR + i * 16 + m4;
       };
       const ZT kNoP[4] = {0, 0, 0, 0};
-      auto zput = [&](int i, int j, bool with_p, const ZT (&po)[4]) {
-        const long long o = zoff(i, j);
+      // BF16 directions: p = z + beta p_k of block (i, j) in FP64, rounded
+      // to FP32, then to BF16 (the empty asm keeps the two roundings apart:
+      // left free, the compiler merged them into one for some elements and
+      // not others, differently per tile shape), as two words
+      typedef unsigned u2 __attribute__((ext_vector_type(2)));
+      typedef unsigned u4 __attribute__((ext_vector_type(4)));
+      struct alignas(8) Z4 { ZT e[4]; };
+      auto pbits = [&](int i, int j, bool with_p, const ZT (&po)[4]) {
+        u2 bits = {0u, 0u};
         if constexpr (sizeof(ZT) == 2) {
-          // BF16 directions: p = z + beta p_k in FP64, rounded once
-          struct alignas(8) Z4 { ZT e[4]; } st;
+          Z4 st;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const double zd = scaled ? (double)acc[i][j][e] * es.z : (double)acc[i][j][e];
-            // rounded to FP32, then to BF16: the empty asm keeps the two
-            // roundings apart (left free, the compiler merged them into one
-            // for some elements and not others, differently per tile shape)
             float f = (float)(with_p ? fma(pbeta, (double)po[e], zd) : zd);
             asm("" : "+v"(f));
             st.e[e] = (ZT)f;
           }
-          *reinterpret_cast<Z4*>(zo + o) = st;
+          bits = __builtin_bit_cast(u2, st);
+        }
+        return bits;
+      };
+      // BF16 directions, blocks i and i + 1 of block row j stored together,
+      // 16 bytes per lane (lanes 16 apart swap half their words, as in the
+      // 16-bit transforms' epilogue: 64 contiguous bytes per row and store)
+      auto ppair = [&](int i, int j, bool with_p, const ZT (&pa)[4], const ZT (&pb)[4]) {
+        const bool odd = (lane >> 4) & 1;
+        const u2 a = pbits(i, j, with_p, pa), b = pbits(i + 1, j, with_p, pb);
+        const u2 send = odd ? a : b;
+        u2 got;
+        got.x = __shfl_xor(send.x, 16, kWave);
+        got.y = __shfl_xor(send.y, 16, kWave);
+        u4 o4;
+        o4.x = odd ? got.x : a.x;
+        o4.y = odd ? got.y : a.y;
+        o4.z = odd ? b.x : got.x;
+        o4.w = odd ? b.y : got.y;
+        *reinterpret_cast<u4*>(zo + (zoff(i, j) - m4 + (odd ? 16 : 0) + 8 * (lane >> 5))) = o4;
+      };
+      auto zput = [&](int i, int j, bool with_p, const ZT (&po)[4]) {
+        const long long o = zoff(i, j);
+        if constexpr (sizeof(ZT) == 2) {
+          *reinterpret_cast<u2*>(zo + o) = pbits(i, j, with_p, po);
           return;
         }
         ZT zs[4];
@@ -765,19 +792,34 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
             } else {
               fetch(j, po[j & 1]);
             }
+            if constexpr (sizeof(ZT) == 2) {
 #pragma unroll
-            for (int i = 0; i < BI; ++i) {
-              ZT pk4[4];
-              p4dec(po[j & 1][i], pk4);
-              zput(i, j, true, pk4);
+              for (int i = 0; i < BI; i += 2) {
+                ZT pa[4], pb[4];
+                p4dec(po[j & 1][i], pa);
+                p4dec(po[j & 1][i + 1], pb);
+                ppair(i, j, true, pa, pb);
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < BI; ++i) {
+                ZT pk4[4];
+                p4dec(po[j & 1][i], pk4);
+                zput(i, j, true, pk4);
+              }
             }
           }
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (sizeof(ZT) == 2) {
 #pragma unroll
-            for (int i = 0; i < BI; ++i) zput(i, j, false, kNoP);
+              for (int i = 0; i < BI; i += 2) ppair(i, j, false, kNoP, kNoP);
+            } else {
+#pragma unroll
+              for (int i = 0; i < BI; ++i) zput(i, j, false, kNoP);
+            }
           }
         }
       } else {
