@@ -778,8 +778,33 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
           constexpr bool kAhead = !scaled;
           P4 po[2][BI];
           auto fetch = [&](int j, P4 (&dst)[BI]) {
+            if constexpr (sizeof(ZT) == 2) {
+              // BF16: 16 bytes per lane at the position the pair store
+              // writes (64 contiguous bytes per row), lane halves swapped
+              // back when the row is used (pget)
+              const bool odd = (lane >> 4) & 1;
 #pragma unroll
-            for (int i = 0; i < BI; ++i) dst[i] = *reinterpret_cast<const P4*>(pold + zoff(i, j));
+              for (int i = 0; i < BI; i += 2) {
+                const u4 v = *reinterpret_cast<const u4*>(pold + (zoff(i, j) - m4 + (odd ? 16 : 0) + 8 * (lane >> 5)));
+                dst[i] = P4{v.x, v.y};
+                dst[i + 1] = P4{v.z, v.w};
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < BI; ++i) dst[i] = *reinterpret_cast<const P4*>(pold + zoff(i, j));
+            }
+          };
+          // BF16: this lane's values of blocks i and i + 1 from a pair load
+          // (even lanes hold their own block-i values and their partner's,
+          // odd lanes their partner's block-(i + 1) values and their own)
+          auto pget = [&](const P4& lo, const P4& hi, ZT (&pa)[4], ZT (&pb)[4]) {
+            const bool odd = (lane >> 4) & 1;
+            const P4 send = odd ? lo : hi;
+            P4 got;
+            got.x = __shfl_xor(send.x, 16, kWave);
+            got.y = __shfl_xor(send.y, 16, kWave);
+            p4dec(odd ? got : lo, pa);
+            p4dec(odd ? hi : got, pb);
           };
           if constexpr (kAhead) fetch(0, po[0]);
 #pragma unroll
@@ -796,8 +821,7 @@ k_hartley_h16(const T* __restrict__ X, const T* __restrict__ Qm, void* __restric
 #pragma unroll
               for (int i = 0; i < BI; i += 2) {
                 ZT pa[4], pb[4];
-                p4dec(po[j & 1][i], pa);
-                p4dec(po[j & 1][i + 1], pb);
+                pget(po[j & 1][i], po[j & 1][i + 1], pa, pb);
                 ppair(i, j, true, pa, pb);
               }
             } else {
