@@ -546,9 +546,13 @@ void save_tune_entry(rve_ctx* ctx, const TuneKey& k, int choice, const std::vect
 
 // Best of three event-timed runs of `launch` for each candidate; the
 // launches must be idempotent (they are: the first PCG direction step and a
-// preconditioner apply to a fixed residual).
-template <class F>
-int tune_pick(rve_ctx* ctx, const TuneKey& key, const std::vector<int>& cands, F launch) {
+// preconditioner apply to a fixed residual). `pre` runs before each of them,
+// outside the timed region.
+struct NoPre {
+  void operator()() const {}
+};
+template <class F, class P = NoPre>
+int tune_pick(rve_ctx* ctx, const TuneKey& key, const std::vector<int>& cands, F launch, P pre = P()) {
   auto it = ctx->tune.find(key);
   // a cached choice is used only if it is a candidate for this shape
   if (it != ctx->tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
@@ -563,9 +567,11 @@ int tune_pick(rve_ctx* ctx, const TuneKey& key, const std::vector<int>& cands, F
   int best = cands[0];
   float best_ms = 1e30f;
   for (int c : cands) {
+    pre();
     launch(c);   // warm-up (code load, caches)
     float cbest = 1e30f;
     for (int r = 0; r < 3; ++r) {
+      pre();
       ignore(hipEventRecord(e0, ctx->stream));
       launch(c);
       ignore(hipEventRecord(e1, ctx->stream));
@@ -861,6 +867,16 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
           const int c = v + 8 * (hs / 16) + dc;
           if (stencil_choice_valid(n, c)) vc.push_back(c);
         }
+    // Each probe of the two stencil passes follows the preconditioner's last
+    // transform, as in the solve (rerun here on the first apply's
+    // intermediate: it writes the same p_0 or z again), so the operand comes
+    // from where the solve finds it; timed alone, shapes without row
+    // prefetch probed as fast as the rest, then ran 15 % slower in the solve.
+    auto follow_last = [&]() {
+      Work v = w;
+      v.pdir_first = 1;
+      launch_precond(v, prec, b.gt, st, 3);
+    };
     if (ctx->autotune) {
       // candidates are timed on probes of iteration 0 that also read the
       // previous direction's slot (zeroed here), i.e. do a later iteration's
@@ -870,12 +886,15 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
         HIP_TRY(hipMemsetAsync(static_cast<char*>(w.pring) + (kRing - 1) * slot, 0, slot, st));
       }
       if (ctx->tune.count(kst) || tune_now)
-        sc = tune_pick(ctx, kst, vc, [&](int c) {
-          Work t2 = w;
-          t2.stencil = c;
-          t2.P_st = stencil_tiles_per_realization(n, c);
-          launch_stencil_fused(t2, st, 1);
-        });
+        sc = tune_pick(
+            ctx, kst, vc,
+            [&](int c) {
+              Work t2 = w;
+              t2.stencil = c;
+              t2.P_st = stencil_tiles_per_realization(n, c);
+              launch_stencil_fused(t2, st, 1);
+            },
+            follow_last);
     }
     if (ctx->force_stencil >= 0 && stencil_choice_valid(n, ctx->force_stencil)) sc = ctx->force_stencil;
     w.stencil = sc;
@@ -889,12 +908,15 @@ int solve_batches(rve_ctx* ctx, std::vector<Batch>& bs, double h, const rve_opts
       int uc = sc;
       const bool forced = ctx->force_update >= 0 || ctx->force_stencil >= 0;
       if (ctx->autotune && !forced && (ctx->tune.count(kup) || count_active(ctx, w) > 0))
-        uc = tune_pick(ctx, kup, vc, [&](int c) {
-          Work t2 = w;
-          t2.ustencil = c;
-          t2.P_rr = stencil_tiles_per_realization(n, c);
-          launch_update_r(t2, flexible, st, 1);
-        });
+        uc = tune_pick(
+            ctx, kup, vc,
+            [&](int c) {
+              Work t2 = w;
+              t2.ustencil = c;
+              t2.P_rr = stencil_tiles_per_realization(n, c);
+              launch_update_r(t2, flexible, st, 1);
+            },
+            follow_last);
       if (ctx->force_update >= 0 && stencil_choice_valid(n, ctx->force_update)) uc = ctx->force_update;
       w.ustencil = uc;
       w.P_rr = stencil_tiles_per_realization(n, uc);
